@@ -1,0 +1,174 @@
+"""Picard (source) iteration, DIRK stages and the explicit time-step bound.
+
+* DIRK (Sec. 3.5, eq. dirk, eq. dirk-stages, eq. q-stages,
+  eq. dirk-recursive-def): each stage s solves the steady problem
+  eq. bgk-ss with sigma = nu + 1/(dt A_ss) and
+  q^(s) = (f^k + dt sum_{r<s} A_sr F^(r)) / (dt A_ss);
+  F^(s) = (f^(s) - f^k - dt sum_{r<s} A_sr F^(r)) / (dt A_ss);
+  f^{k+1} = f^k + dt sum_s b_s F^(s).
+* Picard (Sec. 4, eq. bgk-ss-picard): the Maxwellian and nu are lagged at
+  iterate l, the sweep gives f^{l+1}, the moments of f^{l+1} give the next
+  Maxwellian.  Stage 1 starts from f^k and stage s > 1 from the converged
+  f^(s-1) (design note A3; the printed "s = 0" case is read as s = 1).
+* Stopping rule (eq. convergence-criteria, design note A13):
+  max_m |U^{l+1,m} - U^{l,m}| / max(|U^{l,m}|, |U^{l,0}| s_m)
+      < tau / max(1, max_i nu_i dt),
+  with s_0 = s_2 = 0 and s_1 = 1 (guards the zero momentum of a gas at
+  rest), unweighted l2 norms over DG nodes, momentum measured with the
+  Euclidean norm of each node's vector.  After l_max iterations the stage
+  fails (the GPU library reports BGK_E_NOT_CONVERGED).
+* Time step (eq. explicit-dt): dt_e = (1/d) (1/(2k+1)) h_min / max_j |v_j|
+  with h_min = (min cell measure)^{1/d}; dt = C dt_e.
+* Tableaus (App. A): backward Euler; the L-stable two-stage DIRK with
+  gamma = 1 - sqrt(2)/2; the L-stable three-stage DIRK with gamma the root
+  of x^3 - 3x^2 + 3x/2 - 1/6 near 0.4359 (its printed 6-digit constants are
+  derived exactly from gamma); the two-stage B-stable DIRK with
+  gamma = (3 + sqrt(3))/6.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import kinetic, transport
+from .geometry import Geometry
+
+
+def tableau(name: str):
+    if name == "BE":
+        return np.array([[1.0]]), np.array([1.0]), np.array([1.0])
+    if name == "DIRK2":
+        g = 1.0 - math.sqrt(2.0) / 2.0
+        A = np.array([[g, 0.0], [math.sqrt(2.0) / 2.0, g]])
+        return A, A[-1].copy(), A.sum(axis=1)
+    if name == "DIRK3":
+        # root of x^3 - 3x^2 + 3x/2 - 1/6 in (0.4, 0.5) by bisection
+        lo, hi = 0.4, 0.5
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if (mid ** 3 - 3 * mid ** 2 + 1.5 * mid - 1.0 / 6.0) > 0:
+                lo = mid
+            else:
+                hi = mid
+        g = 0.5 * (lo + hi)
+        b1 = -(6 * g * g - 16 * g + 1) / 4.0
+        b2 = (6 * g * g - 20 * g + 5) / 4.0
+        A = np.array([[g, 0, 0], [(1 - g) / 2.0, g, 0], [b1, b2, g]])
+        return A, A[-1].copy(), A.sum(axis=1)
+    if name == "BDIRK2":
+        g = (3.0 + math.sqrt(3.0)) / 6.0
+        A = np.array([[g, 0.0], [1.0 - 2.0 * g, g]])
+        return A, np.array([0.5, 0.5]), A.sum(axis=1)
+    raise ValueError(name)
+
+
+def explicit_dt(geo: Geometry, V: np.ndarray, cfl: float) -> float:
+    h_min = float(np.min(geo.vol)) ** (1.0 / geo.dim)
+    vmax = float(np.max(np.linalg.norm(V, axis=1)))
+    return cfl * (1.0 / geo.dim) * (1.0 / (2 * geo.order + 1)) * h_min / vmax
+
+
+def relative_changes(U_new: np.ndarray, U_old: np.ndarray, dim: int) -> np.ndarray:
+    """The three ratios of eq. convergence-criteria with the A13 guard."""
+    blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
+    n0 = np.linalg.norm(U_old[..., 0])
+    out = np.zeros(3)
+    for m, sl in enumerate(blocks):
+        num = np.linalg.norm(U_new[..., sl] - U_old[..., sl])
+        den = np.linalg.norm(U_old[..., sl])
+        if m == 1:
+            den = max(den, n0)
+        out[m] = num / den
+    return out
+
+
+def maxwellian_coefficients(U, V, w, mode: str, L: float):
+    dim = V.shape[1]
+    if mode == "DIRECT":
+        n, u, th = kinetic.primitive(U, dim)
+        return kinetic.direct_coefficients(n, u, th), 0
+    if mode == "MATCHED":
+        return kinetic.matched_coefficients(U, V, w)
+    if mode == "LINEAR":
+        return kinetic.linear_coefficients(U, L, dim), 0
+    raise ValueError(mode)
+
+
+def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged, *, dt,
+                 mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10,
+                 lmax=2000, fixed_iters=None, U_init=None, L=0.0):
+    """Picard iteration for one DIRK stage.  Returns (f, U, iterations, history)."""
+    dim = geo.dim
+    f = f_init
+    U = kinetic.moments(f, V, w) if U_init is None else U_init
+    hist = []
+    nfb = 0
+    for ell in range(lmax):
+        nu = kinetic.collision_frequency(U, dim, nu_model, nu_const, kn)
+        if np.any(nu != 0.0):
+            coef, fb = maxwellian_coefficients(U, V, w, mode, L)
+            nfb += fb
+            Mv = kinetic.coef_values(coef, V)
+        else:                      # collision term vanishes: no Maxwellian needed
+            Mv = np.zeros_like(q)
+        f_new = transport.sweep(geo, V, nu + sigma_shift, nu, Mv, q, gbc, gens, lagged, f)
+        U_new = kinetic.moments(f_new, V, w)
+        ratio = relative_changes(U_new, U, dim)
+        hist.append(float(ratio.max()))
+        f, U = f_new, U_new
+        if fixed_iters is not None:
+            if ell + 1 >= fixed_iters:
+                return f, U, ell + 1, hist, nfb
+            continue
+        if ratio.max() < tau / max(1.0, float(np.max(nu)) * dt):
+            return f, U, ell + 1, hist, nfb
+    raise RuntimeError("Picard iteration did not converge")
+
+
+def bgk_step(geo: Geometry, V, w, f, gbc, dt, gens, lagged=None, *, scheme="BE",
+             mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10, lmax=2000,
+             fixed_iters=None, U_guess=None, L=0.0):
+    """One DIRK time step of the discretised BGK equation.
+
+    ``gbc`` is either the boundary data [n_bf][n_fp][N_v] or a callable
+    gbc(stage_index) returning it.  ``U_guess`` (optional) replaces the
+    moments of f^k as the first stage's initial Picard iterate.
+    Returns (f^{k+1}, stats dict).
+    """
+    A, b, _ = tableau(scheme)
+    S = A.shape[0]
+    Fs = []
+    stage_f = f
+    iters, hists, nfb_tot = [], [], 0
+    for s in range(S):
+        acc = f.copy()
+        for r in range(s):
+            acc = acc + dt * A[s, r] * Fs[r]
+        q = acc / (dt * A[s, s])
+        g = gbc(s) if callable(gbc) else gbc
+        f_s, U_s, it, hist, nfb = picard_stage(
+            geo, V, w, q, g, 1.0 / (dt * A[s, s]), stage_f, gens, lagged, dt=dt, mode=mode,
+            nu_model=nu_model, nu_const=nu_const, kn=kn, tau=tau, lmax=lmax,
+            fixed_iters=fixed_iters, U_init=U_guess if s == 0 else None, L=L)
+        Fs.append((f_s - acc) / (dt * A[s, s]))
+        stage_f = f_s
+        iters.append(it)
+        hists.append(hist)
+        nfb_tot += nfb
+    f_new = f.copy()
+    for s in range(S):
+        f_new = f_new + dt * b[s] * Fs[s]
+    return f_new, {"iters": iters, "hist": hists, "fallbacks": nfb_tot, "U": U_s}
+
+
+def initial_condition(geo: Geometry, V, state) -> np.ndarray:
+    """Nodal interpolation of the initial Maxwellians (design note A7)."""
+    n, u, th = state.params(geo.node_x.reshape(-1, geo.dim))
+    return kinetic.maxwellian_values(n, u, th, V).reshape(geo.n_cells, geo.n_p, -1)
+
+
+def boundary_values(geo: Geometry, V, state) -> np.ndarray:
+    """Inflow data: the state's Maxwellian at each boundary facet node (A8)."""
+    n, u, th = state.params(geo.bnode_x.reshape(-1, geo.dim))
+    return kinetic.maxwellian_values(n, u, th, V).reshape(geo.bnode_x.shape[0], geo.n_fp, -1)

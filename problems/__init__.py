@@ -1,0 +1,352 @@
+"""Seeded synthetic problem generators.
+
+This module defines *problems*, not the method: meshes (vertex coordinates and
+simplex connectivity), discrete velocity sets (nodes and quadrature weights as
+stated by each workload), and the macroscopic states (n, u, theta) that define
+initial and inflow data as functions of position.  It is the only code shared
+by the CPU oracle and the GPU path; it contains none of the method's
+arithmetic (no element matrices, sweeps, moments or Maxwellians).
+
+Workloads follow the paper's Sod-type test problems (Sec. 5.1: left state
+(1, 0, 1), right state (0.125, 0, 0.8), inflow data equal to the initial
+equilibrium) on synthetic seeded Delaunay meshes that stand in for the
+paper's meshes, which are not public.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.spatial import Delaunay
+
+__all__ = [
+    "Mesh", "VelocityGrid", "State", "Problem",
+    "jittered_square_mesh", "graded_square_mesh", "jittered_cube_mesh",
+    "structured_square_mesh",
+    "tensor_velocity_grid",
+    "sod_state", "planar_riemann_state", "fourier_state", "uniform_state",
+    "config_c1", "config_c2", "config_c3", "config_c4_instances", "small_problem",
+]
+
+
+@dataclass
+class Mesh:
+    """Simplicial mesh: ``vert`` f64[n_vert][dim], ``cells`` i32[n_cells][dim+1]."""
+    vert: np.ndarray
+    cells: np.ndarray
+
+    @property
+    def dim(self) -> int:
+        return int(self.vert.shape[1])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cells.shape[0])
+
+
+@dataclass
+class VelocityGrid:
+    """Discrete velocities ``v`` f64[n_v][dim] with weights ``w`` f64[n_v].
+
+    Ordering is the row-major tensor index with the first axis slowest.
+    ``nodes_1d``/``weights_1d`` hold the per-axis factors for tensor grids.
+    """
+    v: np.ndarray
+    w: np.ndarray
+    nodes_1d: np.ndarray | None = None
+    weights_1d: np.ndarray | None = None
+    L: float = 0.0
+
+    @property
+    def n_v(self) -> int:
+        return int(self.v.shape[0])
+
+    @property
+    def dim(self) -> int:
+        return int(self.v.shape[1])
+
+
+@dataclass
+class State:
+    """A macroscopic state field: ``params(x)`` -> (n, u[dim], theta) arrays."""
+    kind: str
+    data: dict = field(default_factory=dict)
+
+    def params(self, x: np.ndarray):
+        x = np.asarray(x, dtype=np.float64)
+        npts, dim = x.shape
+        if self.kind == "uniform":
+            n = np.full(npts, self.data["n"])
+            u = np.tile(np.asarray(self.data["u"], dtype=np.float64), (npts, 1))
+            th = np.full(npts, self.data["theta"])
+            return n, u, th
+        if self.kind == "plane":
+            nrm = np.asarray(self.data["normal"], dtype=np.float64)
+            c = np.asarray(self.data["center"], dtype=np.float64)
+            left = (x - c) @ nrm < 0.0
+            nl, ul, tl = self.data["left"]
+            nr, ur, tr = self.data["right"]
+            n = np.where(left, nl, nr).astype(np.float64)
+            u = np.where(left[:, None], np.asarray(ul, dtype=np.float64)[None, :dim],
+                         np.asarray(ur, dtype=np.float64)[None, :dim])
+            th = np.where(left, tl, tr).astype(np.float64)
+            return n, u, th
+        if self.kind == "fourier":
+            out = []
+            for name in ["n"] + [f"u{a}" for a in range(dim)] + ["theta"]:
+                k, amp, phase, base, rel = (self.data[name][key] for key in
+                                            ("k", "amp", "phase", "base", "relative"))
+                s = np.zeros(npts)
+                for m in range(len(amp)):
+                    s += amp[m] * np.sin(2.0 * math.pi * (x @ k[m]) + phase[m])
+                out.append(base * (1.0 + s) if rel else base + s)
+            n = out[0]
+            u = np.stack(out[1:1 + dim], axis=1)
+            th = out[1 + dim]
+            return n, u, th
+        raise ValueError(f"unknown state kind {self.kind}")
+
+
+@dataclass
+class Problem:
+    """One workload instance: mesh, polynomial order, velocities, state, physics."""
+    mesh: Mesh
+    order: int
+    vgrid: VelocityGrid
+    state: State
+    nu_model: str = "const"         # "const" or "kn"
+    nu_const: float = 1.0
+    kn: float = 1.0
+    tableau: str = "BE"             # "BE" or "DIRK2"
+    cfl: float = 10.0
+    n_steps: int = 1
+    tau: float = 1e-10
+    name: str = ""
+
+
+# ----------------------------------------------------------------------------
+# meshes
+# ----------------------------------------------------------------------------
+
+def _delaunay(points: np.ndarray) -> np.ndarray:
+    tri = Delaunay(points, qhull_options="Qbb Qc Qz Q12")
+    return np.ascontiguousarray(tri.simplices.astype(np.int32))
+
+
+def _simplex_measures(vert: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    x0 = vert[cells[:, 0]]
+    J = np.stack([vert[cells[:, k + 1]] - x0 for k in range(vert.shape[1])], axis=2)
+    return np.abs(np.linalg.det(J)) / math.factorial(vert.shape[1])
+
+
+def _drop_degenerate(vert, cells, rel=1e-9):
+    vol = _simplex_measures(vert, cells)
+    keep = vol > rel * vol.mean()
+    if not np.all(keep):
+        raise RuntimeError(f"Delaunay produced {np.count_nonzero(~keep)} degenerate simplices")
+    return cells
+
+
+def jittered_square_mesh(n_side: int, jitter: float, seed: int) -> Mesh:
+    """(n_side+1)^2 lattice on [0,1]^2, interior points jittered by U(-jitter*h, jitter*h)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n_side
+    g = np.linspace(0.0, 1.0, n_side + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    interior = (pts[:, 0] > 0) & (pts[:, 0] < 1) & (pts[:, 1] > 0) & (pts[:, 1] < 1)
+    pts[interior] += rng.uniform(-jitter * h, jitter * h, size=(np.count_nonzero(interior), 2))
+    cells = _drop_degenerate(pts, _delaunay(pts))
+    expected = 2 * n_side * n_side
+    if cells.shape[0] != expected:
+        raise RuntimeError(f"expected {expected} triangles, got {cells.shape[0]}")
+    return Mesh(pts, cells)
+
+
+def structured_square_mesh(n_side: int) -> Mesh:
+    """Right-triangle mesh of [0,1]^2: each lattice square split along its (0,0)-(1,1) diagonal."""
+    g = np.linspace(0.0, 1.0, n_side + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    idx = lambda i, j: i * (n_side + 1) + j  # noqa: E731
+    cells = []
+    for i in range(n_side):
+        for j in range(n_side):
+            a, b, c, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+            cells.append((a, b, c))
+            cells.append((a, c, d))
+    return Mesh(pts, np.asarray(cells, dtype=np.int32))
+
+
+def graded_square_mesh(n_side: int, jitter: float, seed: int, ratio: float = 4.0) -> Mesh:
+    """Jittered lattice warped per axis by g(s) = s + a sin(2 pi s)/(2 pi).
+
+    With a = (ratio-1)/(ratio+1) the spacing at the centre is ``ratio`` times
+    finer than at the boundary.  2*n_side^2 triangles.
+    """
+    rng = np.random.default_rng(seed)
+    a = (ratio - 1.0) / (ratio + 1.0)
+    h = 1.0 / n_side
+    g = np.linspace(0.0, 1.0, n_side + 1)
+    S, T = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([S.ravel(), T.ravel()], axis=1)
+    interior = (pts[:, 0] > 0) & (pts[:, 0] < 1) & (pts[:, 1] > 0) & (pts[:, 1] < 1)
+    pts[interior] += rng.uniform(-jitter * h, jitter * h, size=(np.count_nonzero(interior), 2))
+    pts = pts + a * np.sin(2.0 * math.pi * pts) / (2.0 * math.pi)
+    pts[np.isclose(pts, 0.0, atol=1e-15)] = 0.0
+    pts[np.isclose(pts, 1.0, atol=1e-15)] = 1.0
+    cells = _drop_degenerate(pts, _delaunay(pts))
+    return Mesh(pts, cells)
+
+
+def jittered_cube_mesh(n_side: int, jitter: float, seed: int) -> Mesh:
+    """(n_side+1)^3 lattice on [0,1]^3.  Interior points are jittered in all
+    directions; boundary points only tangentially (edges along the edge,
+    corners fixed), so the cube stays exact and no boundary square is
+    cocircular."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n_side
+    g = np.linspace(0.0, 1.0, n_side + 1)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    free = (pts > 0) & (pts < 1)
+    pts = pts + np.where(free, rng.uniform(-jitter * h, jitter * h, size=pts.shape), 0.0)
+    cells = _drop_degenerate(pts, _delaunay(pts))
+    return Mesh(pts, cells)
+
+
+# ----------------------------------------------------------------------------
+# velocity grids
+# ----------------------------------------------------------------------------
+
+def tensor_velocity_grid(n_1d: int, L: float, dim: int) -> VelocityGrid:
+    """n_1d equispaced nodes v_k = -L + 2Lk/(n_1d-1) per axis with trapezoid
+    weights h*(1/2, 1, ..., 1, 1/2), h = 2L/(n_1d-1); tensor product with the
+    first axis slowest and product weights, as the workloads state."""
+    x = np.linspace(-L, L, n_1d)
+    hv = 2.0 * L / (n_1d - 1)
+    w1 = np.full(n_1d, hv)
+    w1[0] *= 0.5
+    w1[-1] *= 0.5
+    grids = np.meshgrid(*([x] * dim), indexing="ij")
+    v = np.stack([gg.ravel() for gg in grids], axis=1)
+    wg = np.meshgrid(*([w1] * dim), indexing="ij")
+    w = np.ones(v.shape[0])
+    for gg in wg:
+        w = w * gg.ravel()
+    return VelocityGrid(np.ascontiguousarray(v), w, x, w1, L)
+
+
+# ----------------------------------------------------------------------------
+# states
+# ----------------------------------------------------------------------------
+
+SOD_LEFT = (1.0, (0.0, 0.0, 0.0), 1.0)
+SOD_RIGHT = (0.125, (0.0, 0.0, 0.0), 0.8)
+
+
+def uniform_state(n=1.0, u=(0.0, 0.0, 0.0), theta=1.0, dim=2) -> State:
+    return State("uniform", {"n": n, "u": list(u)[:dim], "theta": theta})
+
+
+def sod_state(dim: int) -> State:
+    """Sod split at x_1 = 0.5: left (x_1 < 0.5) = (1,0,1), right = (0.125,0,0.8)."""
+    nrm = np.zeros(dim)
+    nrm[0] = 1.0
+    return State("plane", {"normal": nrm, "center": np.full(dim, 0.5),
+                           "left": SOD_LEFT, "right": SOD_RIGHT})
+
+
+def planar_riemann_state(dim: int, seed: int) -> State:
+    """Sod states split by the plane through the domain centre with a seeded random normal."""
+    rng = np.random.default_rng(seed)
+    nrm = rng.normal(size=dim)
+    nrm /= np.linalg.norm(nrm)
+    return State("plane", {"normal": nrm, "center": np.full(dim, 0.5),
+                           "left": SOD_LEFT, "right": SOD_RIGHT})
+
+
+def fourier_state(dim: int, seed: int, modes: int = 8, amplitude: float = 0.1) -> State:
+    """Smooth seeded perturbation of (1, 0, 1): each field gets a sum of
+    ``modes`` sines with integer wave vectors in [1,4]^dim, scaled so the
+    worst-case amplitude is ``amplitude`` (relative for n and theta,
+    absolute for u)."""
+    rng = np.random.default_rng(seed)
+    data = {}
+    names = ["n"] + [f"u{a}" for a in range(dim)] + ["theta"]
+    for name in names:
+        k = rng.integers(1, 5, size=(modes, dim)).astype(np.float64)
+        amp = rng.uniform(0.2, 1.0, size=modes)
+        amp *= amplitude / amp.sum()
+        phase = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+        rel = name in ("n", "theta")
+        data[name] = {"k": k, "amp": amp, "phase": phase, "base": 1.0 if rel else 0.0,
+                      "relative": rel}
+    return State("fourier", data)
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def config_c1() -> Problem:
+    """512-triangle jittered Delaunay square, P1, 16x16 velocities on [-6,6]^2,
+    nu = 1, Sod, backward Euler at CFL 10, 5 steps, tau = 1e-10."""
+    mesh = jittered_square_mesh(16, 0.25, seed=1000)
+    return Problem(mesh, 1, tensor_velocity_grid(16, 6.0, 2), sod_state(2),
+                   nu_model="const", nu_const=1.0, tableau="BE", cfl=10.0,
+                   n_steps=5, tau=1e-10, name="c1_sod_p1_512tri_16x16")
+
+
+def config_c2(n_side: int = 316) -> Problem:
+    """~200k-triangle graded Delaunay square (4x finer at the centre), P2,
+    32x32 velocities on [-8,8]^2, nu = n theta^{-1/2}/Kn with Kn = 1e-2,
+    seeded 8-mode Fourier perturbation of (1,0,1), 2-stage L-stable DIRK,
+    CFL 10, 20 steps."""
+    mesh = graded_square_mesh(n_side, 0.2, seed=2000)
+    return Problem(mesh, 2, tensor_velocity_grid(32, 8.0, 2), fourier_state(2, seed=2001),
+                   nu_model="kn", kn=1e-2, tableau="DIRK2", cfl=10.0, n_steps=20,
+                   tau=1e-10, name=f"c2_fourier_p2_{2 * n_side * n_side}tri_32x32")
+
+
+def config_c3(kn: float = 1e-2, n_side: int = 20) -> Problem:
+    """~5e4-tet jittered Delaunay cube, P1, 16^3 velocities on [-6,6]^3,
+    planar Riemann problem with a seeded normal, backward Euler, CFL 10."""
+    mesh = jittered_cube_mesh(n_side, 0.2, seed=3000)
+    return Problem(mesh, 1, tensor_velocity_grid(16, 6.0, 3), planar_riemann_state(3, seed=3001),
+                   nu_model="kn", kn=kn, tableau="BE", cfl=10.0, n_steps=10, tau=1e-10,
+                   name=f"c3_riemann_p1_{mesh.n_cells}tet_16^3_kn{kn:g}")
+
+
+def config_c4_instances(count: int = 64, seed0: int = 4000, max_tri: int = 50000):
+    """Uneven batch: meshes of 1e3..max_tri triangles (log-uniform), P1/P2,
+    n_1d in [8, 32] on [-8,8]^2, Kn log-uniform in [1e-4, 1], planar Riemann."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        ntri = math.exp(rng.uniform(math.log(1000.0), math.log(max_tri)))
+        n_side = max(4, int(round(math.sqrt(ntri / 2.0))))
+        order = int(rng.integers(1, 3))
+        n1 = int(rng.integers(8, 33))
+        kn = math.exp(rng.uniform(math.log(1e-4), 0.0))
+        mesh = jittered_square_mesh(n_side, 0.2, seed=seed0 + 1000 + i)
+        out.append(Problem(mesh, order, tensor_velocity_grid(n1, 8.0, 2),
+                           planar_riemann_state(2, seed=seed0 + 2000 + i), nu_model="kn", kn=kn,
+                           tableau="DIRK2", cfl=10.0, n_steps=5, tau=1e-10,
+                           name=f"c4_{i}"))
+    return out
+
+
+def small_problem(dim=2, order=1, n_side=4, n_1d=6, L=6.0, seed=7, state="sod",
+                  nu_model="const", nu_const=1.0, kn=1.0, tableau="BE", jitter=0.25) -> Problem:
+    """A tiny instance for oracle pins and parity tests."""
+    if dim == 2:
+        mesh = jittered_square_mesh(n_side, jitter, seed)
+    else:
+        mesh = jittered_cube_mesh(n_side, min(jitter, 0.2), seed)
+    st = {"sod": lambda: sod_state(dim), "riemann": lambda: planar_riemann_state(dim, seed + 1),
+          "fourier": lambda: fourier_state(dim, seed + 2),
+          "uniform": lambda: uniform_state(dim=dim)}[state]()
+    return Problem(mesh, order, tensor_velocity_grid(n_1d, L, dim), st, nu_model=nu_model,
+                   nu_const=nu_const, kn=kn, tableau=tableau, name="small")
