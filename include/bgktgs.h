@@ -1,0 +1,268 @@
+/*
+ * bgktgs.h -- C ABI of the MI355X (gfx950) topological-generation sweep
+ * library for the implicit BGK equation.
+ *
+ * The library implements the hot path of the sweep-based implicit BGK
+ * method: per-velocity upwind DAGs grouped into generations (Sec. 4.1), the
+ * upwind DG transport-plus-relaxation solve of every (velocity, cell) pair in
+ * generation order (eq. bgk-ss-picard), the velocity-moment reduction
+ * (eq. moments) and the discrete Maxwellian rebuild it alternates with
+ * (eq. Maxwellian-projection), DIRK stages (Sec. 3.5, App. A) and the Picard
+ * stopping rule (eq. convergence-criteria).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns BGK_OK (0) or a negative BGK_E_* code; the text
+ *    of the last error on the calling thread is bgk_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Device pointers are hipMalloc'ed (or torch-owned) memory on the device
+ *    that was current when the DAG was built; host pointers are ordinary
+ *    host memory.  Each argument says which.
+ *  - Kernels run asynchronously on the caller's hipStream_t (0 = the null
+ *    stream).  Only build_mesh_dag, bgk_step and the host-output query
+ *    functions synchronise.
+ *  - The caller owns every data buffer.  The library owns the opaque handles
+ *    (tgs_dag, bgk_solver, bgk_mlp) and the device workspaces inside them;
+ *    they are freed by the matching *_destroy call.
+ *  - Precision: FP64 unless a field says otherwise.
+ *
+ * Layouts
+ * -------
+ *  - Cells are the caller's simplices, numbered 0..n_cells-1 ("user order").
+ *  - DG nodes per cell: P1 = the d+1 vertices in the order of the cell's
+ *    vertex list; P2 (triangles) = vertices 0,1,2 then the midpoints of
+ *    edges (0,1), (1,2), (2,0).  Node i of cell c has nodal index c*n_p + i.
+ *  - Facet k of a cell is the facet opposite its vertex k; facet nodes are
+ *    the cell's nodes on it in ascending local index.
+ *  - Boundary facets are numbered in ascending (cell, facet) order; boundary
+ *    data is indexed [boundary facet][facet node].
+ *  - Velocities: the order of tgs_vgrid_desc.v (for tensor grids the
+ *    row-major tensor index, first axis slowest).
+ *  - "Canonical" phase-space layout: f[cell][node][velocity], velocity
+ *    fastest, user cell order.
+ *  - "Sweep" phase-space layout: the library's internal velocity-major
+ *    layout in which every velocity's cells are stored in its generation
+ *    order.  tgs_sweep, moments and bgk_step take phase-space arrays in
+ *    sweep layout; tgs_pack / tgs_unpack convert.  Its size is
+ *    n_v * n_cells * n_p doubles, like the canonical layout.
+ *  - Nodal arrays (U, Maxwellian coefficients, nu) are [node][...] in user
+ *    order with node = cell*n_p + local node.
+ *  - Maxwellians are carried as exponential-family coefficients
+ *    (a, b_1..b_d, c): M(v) = exp(a + b.v + c|v|^2).
+ */
+#ifndef BGKTGS_H
+#define BGKTGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bgk_stream_t; /* same object as hipStream_t */
+
+enum {
+  BGK_OK = 0,
+  BGK_E_INVALID = -1,       /* bad argument, degenerate or non-conforming mesh */
+  BGK_E_HIP = -2,           /* a HIP runtime call failed */
+  BGK_E_NOMEM = -3,         /* device allocation failed */
+  BGK_E_NOT_CONVERGED = -4, /* Picard iteration reached l_max */
+  BGK_E_NONPHYSICAL = -5,   /* n <= 0 or theta <= 0 (or non-finite) at a node */
+  BGK_E_UNSUPPORTED = -6    /* element type or option not implemented */
+};
+
+/* Text of the last error raised on this thread ("" if none). */
+const char* bgk_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Mesh, velocity grid and the per-velocity sweep DAGs (Sec. 3.1, Sec. 4.1)   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int dim;                /* 2 (triangles) or 3 (tetrahedra) */
+  int order;              /* DG degree: 1 (d = 2, 3) or 2 (d = 2) */
+  int64_t n_vert;
+  const double* vert;     /* host [n_vert][dim], copied */
+  int64_t n_cells;
+  const int32_t* cells;   /* host [n_cells][dim+1] vertex ids, copied */
+} tgs_mesh_desc;
+
+typedef struct {
+  int n_v;
+  const double* v;        /* host [n_v][dim], copied */
+  const double* w;        /* host [n_v] quadrature weights, copied */
+  int n_1d;               /* > 0 declares a tensor grid: v and w are the tensor
+                             product of nodes_1d / weights_1d (checked) */
+  const double* nodes_1d; /* host [n_1d] or NULL */
+  const double* weights_1d;
+  double L;               /* half-width of the velocity box (LINEAR mode) */
+} tgs_vgrid_desc;
+
+typedef struct {
+  /* Optional host bitmask [n_v][n_cells] (user cell order): bit k set forces
+     facet k of that cell to take its inflow from the previous Picard iterate
+     (the lagged part of the inflow boundary, Sec. 4).  NULL = lag only what
+     cycle breaking requires. */
+  const uint8_t* lagged;
+  /* Threads per workgroup of the sweep kernel (64..1024, multiple of 64);
+     0 = the library's choice. */
+  int sweep_threads;
+} tgs_dag_opts;
+
+typedef struct tgs_dag tgs_dag;
+
+/* Builds cell geometry and facet connectivity on the host, then every
+ * velocity's upwind DAG and its longest-path generations on the GPU
+ * (Sec. 4.1).  An edge a->b exists when b's facet shared with a has
+ * v.n < 0 from b's side; facets with v.n == 0 carry no edge.  When a
+ * velocity's graph has a cycle (never the case on Delaunay meshes) the
+ * builder releases the lowest-numbered unreleased cell into the next
+ * generation and lags its unreleased in-edges (exported by
+ * tgs_dag_lagged).  Synchronises `stream`.
+ * Errors: BGK_E_INVALID (degenerate cell, facet shared by more than two
+ * cells, malformed tensor grid), BGK_E_UNSUPPORTED (element type),
+ * BGK_E_NOMEM, BGK_E_HIP. */
+int build_mesh_dag(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vgrid,
+                   const tgs_dag_opts* opts, bgk_stream_t stream, tgs_dag** out);
+
+int tgs_dag_destroy(tgs_dag* dag);
+
+/* sizes[0..8] = dim, order, n_p, n_fp, n_cells, n_v, n_bfaces, max_G, n_lagged. */
+int tgs_dag_sizes(const tgs_dag* dag, int64_t sizes[9]);
+
+/* Host outputs (any may be NULL): gen [n_v][n_cells] in user cell order,
+ * G [n_v] generation counts.  Synchronises. */
+int tgs_dag_generations(const tgs_dag* dag, int32_t* gen, int32_t* G);
+
+/* Host output [n_v][n_cells] (user order) lagged-facet bitmasks. */
+int tgs_dag_lagged(const tgs_dag* dag, uint8_t* lagged);
+
+/* Host outputs (any may be NULL): node_x [n_cells][n_p][dim] node
+ * coordinates, bnode_x [n_bfaces][n_fp][dim] boundary facet node
+ * coordinates, vol [n_cells] cell measures. */
+int tgs_dag_geometry(const tgs_dag* dag, double* node_x, double* bnode_x, double* vol);
+
+/* Canonical -> sweep layout and back (device pointers, no aliasing). */
+int tgs_pack(const tgs_dag* dag, const double* f_canonical, double* f_sweep, bgk_stream_t stream);
+int tgs_unpack(const tgs_dag* dag, const double* f_sweep, double* f_canonical, bgk_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* One transport sweep (eq. bgk-ss-picard)                                   */
+/* ------------------------------------------------------------------------ */
+
+enum { TGS_FP64 = 0, TGS_FP32_CORRECTION = 1 };
+
+typedef struct {
+  int precision;          /* TGS_FP64: solve for f in FP64.
+                             TGS_FP32_CORRECTION: form the FP64 residual of
+                             f_prev per cell, solve for the correction in FP32
+                             with upwind correction traces, add it in FP64. */
+  double sigma_shift;     /* 1/(dt A_ss): sigma_i = nu_i + sigma_shift */
+  double q_scale;         /* the stage source enters as q_scale * q */
+  const double* nu;       /* device [n_nodes] collision frequency */
+  const double* mcoef;    /* device [n_nodes][dim+2] Maxwellian coefficients */
+  const double* q;        /* device, sweep layout */
+  const double* bc_coef;  /* device [n_bfaces][n_fp][dim+2] inflow Maxwellians, or NULL */
+  const double* bc_dense; /* device canonical [n_bfaces][n_fp][n_v] inflow values, or NULL */
+  const double* f_prev;   /* device, sweep layout: previous iterate; required when
+                             lagged facets exist or for TGS_FP32_CORRECTION */
+  double* f_out;          /* device, sweep layout; must not alias f_prev */
+} tgs_sweep_io;
+
+/* Solves, for every velocity j and every cell K in generation order,
+ *   A f_K = b,
+ *   A = M_K diag(sigma) - |det J| sum_b (J^-1 v_j)_b S_b + sum_{v.n>0} (v.n) M_e
+ *   b = M_K (nu*M_j + q_scale*q) + sum_{v.n<0} |v.n| M_e fhat
+ * with fhat the upwind neighbour's new value, the lagged f_prev, or the
+ * boundary value (exactly one of bc_coef / bc_dense non-NULL).  Exactly one
+ * sweep; no convergence logic.  Asynchronous on `stream`. */
+int tgs_sweep(const tgs_dag* dag, const tgs_sweep_io* io, bgk_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Moments and Maxwellians (eq. moments, eq. convergence-criteria)           */
+/* ------------------------------------------------------------------------ */
+
+/* U[node][m] = sum_j w_j e_m(v_j) f_j(node), e = (1, v, |v|^2/2); f in sweep
+ * layout, U device [n_nodes][dim+2].  When U_prev is non-NULL, rel3 (device
+ * double[3]) receives the three ratios of eq. convergence-criteria,
+ * |U^m - U_prev^m| / max(|U_prev^m|, s_m |U_prev^0|), s = (0, 1, 0).
+ * Reductions run in a fixed order (bitwise reproducible). */
+int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
+            double* rel3, bgk_stream_t stream);
+
+enum { BGK_MAXW_DIRECT = 0, BGK_MAXW_MATCHED = 1, BGK_MAXW_LINEAR = 2 };
+enum { BGK_NU_CONST = 0, BGK_NU_KN = 1 };
+
+typedef struct {
+  int kind;               /* BGK_NU_CONST: nu = nu_const; BGK_NU_KN: nu = n theta^-1/2 / kn */
+  double nu_const;
+  double kn;
+} tgs_nu_model;
+
+/* From nodal moments U (device [n_nodes][dim+2]) computes the Maxwellian
+ * coefficients mcoef (device [n_nodes][dim+2]) and nu (device [n_nodes]):
+ * DIRECT = the Maxwellian of (n, u, theta); MATCHED = the nodal Gaussian
+ * whose discrete moments equal U (Newton from DIRECT, residual <= 1e-14|U|,
+ * at most 30 steps, else that node falls back to DIRECT and is counted);
+ * LINEAR = n/|V| (the simplified linear Maxwellian).  Optional outputs:
+ * M_dense (device canonical [n_nodes][n_v]) and status (device int32[2]:
+ * fallback count, non-physical count; accumulated, caller zeroes). */
+int maxwellian(const tgs_dag* dag, int mode, const double* U, const tgs_nu_model* nu_model,
+               double* mcoef, double* nu, double* M_dense, int32_t* status, bgk_stream_t stream);
+
+/* Coefficients of M_{n,u,theta} for n_pts primitive states prim (device
+ * [n_pts][dim+2] = (n, u, theta)) into coef (device [n_pts][dim+2]). */
+int maxwellian_coef_from_primitive(int dim, int64_t n_pts, const double* prim, double* coef,
+                                   bgk_stream_t stream);
+
+/* f = exp(coef . (1, v, |v|^2)) at every node and velocity: coef device
+ * [n_nodes][dim+2]; f device, sweep layout (initial conditions). */
+int tgs_eval_maxwellian(const tgs_dag* dag, const double* coef, double* f_sweep,
+                        bgk_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Implicit time step: DIRK stages with Picard iteration (Sec. 3.5, Sec. 4)  */
+/* ------------------------------------------------------------------------ */
+
+enum { BGK_TAB_BE = 0, BGK_TAB_DIRK2 = 1, BGK_TAB_DIRK3 = 2, BGK_TAB_BDIRK2 = 3 };
+enum { BGK_GUESS_PREVIOUS = 0, BGK_GUESS_USER = 1 };
+
+typedef struct {
+  int tableau;            /* BGK_TAB_* (App. A) */
+  double dt;
+  double tau;             /* Picard tolerance of eq. convergence-criteria */
+  int l_max;              /* iteration cap per stage (BGK_E_NOT_CONVERGED) */
+  int fixed_iters;        /* > 0: run exactly this many Picard iterations per stage */
+  int precision;          /* TGS_FP64 or TGS_FP32_CORRECTION */
+  int maxw_mode;          /* BGK_MAXW_* */
+  tgs_nu_model nu_model;
+  const double* bc_coef;  /* device [n_bfaces][n_fp][dim+2] time-independent inflow */
+} bgk_solver_opts;
+
+typedef struct {
+  int stages;
+  int iters[4];           /* Picard iterations per stage */
+  int total_iters;
+  double last_ratio[4];   /* final max_m ratio per stage */
+  int maxw_fallbacks;
+  double seconds;         /* host wall time of the step */
+} bgk_step_stats;
+
+typedef struct bgk_solver bgk_solver;
+
+int bgk_solver_create(const tgs_dag* dag, const bgk_solver_opts* opts, bgk_solver** out);
+int bgk_solver_destroy(bgk_solver* solver);
+
+/* One DIRK step.  f (device, sweep layout) holds f^k on entry and f^{k+1}
+ * on exit.  U_guess (device [n_nodes][dim+2] or NULL) replaces the moments
+ * of f^k as the first stage's initial Picard iterate (learned guess); U_out
+ * (device or NULL) receives the converged moments of f^{k+1}.
+ * Synchronises `stream` once per Picard iteration to test convergence.
+ * Errors: BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_HIP. */
+int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out,
+             bgk_step_stats* stats, bgk_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGKTGS_H */

@@ -1,0 +1,323 @@
+"""Python binding of libbgktgs.so, the MI355X topological-generation sweep library.
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels; PyTorch provides device memory and streams.  Entry points carry the
+C names (build_mesh_dag, tgs_sweep, moments, maxwellian, bgk_step, ...).
+The library must have been built (``python -m paper_2608_19150_amd.build``);
+importing this package without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbgktgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_19150_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+BGK_OK, BGK_E_INVALID, BGK_E_HIP, BGK_E_NOMEM = 0, -1, -2, -3
+BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_UNSUPPORTED = -4, -5, -6
+TGS_FP64, TGS_FP32_CORRECTION = 0, 1
+MAXW = {"DIRECT": 0, "MATCHED": 1, "LINEAR": 2}
+NU = {"const": 0, "kn": 1}
+TABLEAU = {"BE": 0, "DIRK2": 1, "DIRK3": 2, "BDIRK2": 3}
+
+EXPORTED = [
+    "bgk_last_error", "build_mesh_dag", "tgs_dag_destroy", "tgs_dag_sizes",
+    "tgs_dag_generations", "tgs_dag_lagged", "tgs_dag_geometry", "tgs_pack", "tgs_unpack",
+    "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
+    "tgs_eval_maxwellian", "bgk_solver_create", "bgk_solver_destroy", "bgk_step",
+]
+
+
+class BGKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib.bgk_last_error.restype = C.c_char_p
+
+
+def _check(rc):
+    if rc != BGK_OK:
+        raise BGKError(rc, _lib.bgk_last_error().decode())
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("order", C.c_int), ("n_vert", C.c_int64),
+                ("vert", C.c_void_p), ("n_cells", C.c_int64), ("cells", C.c_void_p)]
+
+
+class VGridDesc(C.Structure):
+    _fields_ = [("n_v", C.c_int), ("v", C.c_void_p), ("w", C.c_void_p), ("n_1d", C.c_int),
+                ("nodes_1d", C.c_void_p), ("weights_1d", C.c_void_p), ("L", C.c_double)]
+
+
+class DagOpts(C.Structure):
+    _fields_ = [("lagged", C.c_void_p), ("sweep_threads", C.c_int)]
+
+
+class SweepIO(C.Structure):
+    _fields_ = [("precision", C.c_int), ("sigma_shift", C.c_double), ("q_scale", C.c_double),
+                ("nu", C.c_void_p), ("mcoef", C.c_void_p), ("q", C.c_void_p),
+                ("bc_coef", C.c_void_p), ("bc_dense", C.c_void_p), ("f_prev", C.c_void_p),
+                ("f_out", C.c_void_p)]
+
+
+class NuModel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nu_const", C.c_double), ("kn", C.c_double)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("tableau", C.c_int), ("dt", C.c_double), ("tau", C.c_double),
+                ("l_max", C.c_int), ("fixed_iters", C.c_int), ("precision", C.c_int),
+                ("maxw_mode", C.c_int), ("nu_model", NuModel), ("bc_coef", C.c_void_p)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("stages", C.c_int), ("iters", C.c_int * 4), ("total_iters", C.c_int),
+                ("last_ratio", C.c_double * 4), ("maxw_fallbacks", C.c_int),
+                ("seconds", C.c_double)]
+
+
+def _p(t):
+    """Device or host pointer of a tensor/array (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(t))
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype=torch.float64):
+    t = torch.as_tensor(x, dtype=dtype)
+    return t.to("cuda").contiguous()
+
+
+_lib.build_mesh_dag.argtypes = [C.POINTER(MeshDesc), C.POINTER(VGridDesc), C.POINTER(DagOpts),
+                                C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.tgs_dag_destroy.argtypes = [C.c_void_p]
+_lib.tgs_dag_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+_lib.tgs_dag_generations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tgs_dag_lagged.argtypes = [C.c_void_p, C.c_void_p]
+_lib.tgs_dag_geometry.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tgs_pack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tgs_unpack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tgs_sweep.argtypes = [C.c_void_p, C.POINTER(SweepIO), C.c_void_p]
+_lib.moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.maxwellian.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(NuModel), C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.maxwellian_coef_from_primitive.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
+                                                C.c_void_p]
+_lib.tgs_eval_maxwellian.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.bgk_solver_create.argtypes = [C.c_void_p, C.POINTER(SolverOpts), C.POINTER(C.c_void_p)]
+_lib.bgk_solver_destroy.argtypes = [C.c_void_p]
+_lib.bgk_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(StepStats),
+                          C.c_void_p]
+
+
+class Dag:
+    """Handle returned by build_mesh_dag (mesh geometry + per-velocity DAGs)."""
+
+    def __init__(self, vert, cells, order, v, w, *, n_1d=0, nodes_1d=None, weights_1d=None,
+                 L=0.0, lagged=None, sweep_threads=0, stream=None):
+        vert = np.ascontiguousarray(vert, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._keep = [vert, cells, v, w]
+        md = MeshDesc(vert.shape[1], order, vert.shape[0], vert.ctypes.data, cells.shape[0],
+                      cells.ctypes.data)
+        n1 = np.ascontiguousarray(nodes_1d, dtype=np.float64) if n_1d else None
+        w1 = np.ascontiguousarray(weights_1d, dtype=np.float64) if n_1d else None
+        self._keep += [n1, w1]
+        vd = VGridDesc(v.shape[0], v.ctypes.data, w.ctypes.data, int(n_1d),
+                       n1.ctypes.data if n_1d else None, w1.ctypes.data if n_1d else None,
+                       float(L))
+        lag = None
+        if lagged is not None:
+            lag = np.ascontiguousarray(lagged, dtype=np.uint8)
+            self._keep.append(lag)
+        opts = DagOpts(lag.ctypes.data if lag is not None else None, int(sweep_threads))
+        h = C.c_void_p()
+        _check(_lib.build_mesh_dag(C.byref(md), C.byref(vd), C.byref(opts), _stream(stream),
+                                   C.byref(h)))
+        self.h = h
+        s = (C.c_int64 * 9)()
+        _check(_lib.tgs_dag_sizes(h, s))
+        (self.dim, self.order, self.n_p, self.n_fp, self.n_cells, self.n_v, self.n_bfaces,
+         self.max_G, self.n_lagged) = [int(x) for x in s]
+        self.n_nodes = self.n_cells * self.n_p
+        self.v = torch.as_tensor(v)
+        self.w = torch.as_tensor(w)
+        self.L = float(L)
+
+    @classmethod
+    def from_problem(cls, pr, **kw):
+        vg = pr.vgrid
+        tensor = vg.nodes_1d is not None
+        return cls(pr.mesh.vert, pr.mesh.cells, pr.order, vg.v, vg.w,
+                   n_1d=len(vg.nodes_1d) if tensor else 0, nodes_1d=vg.nodes_1d,
+                   weights_1d=vg.weights_1d, L=vg.L, **kw)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _lib.tgs_dag_destroy(h)
+            self.h = None
+
+    @property
+    def f_shape(self):
+        return (self.n_cells, self.n_p, self.n_v)
+
+    def f_numel(self):
+        return self.n_cells * self.n_p * self.n_v
+
+    def generations(self):
+        gen = np.zeros((self.n_v, self.n_cells), dtype=np.int32)
+        G = np.zeros(self.n_v, dtype=np.int32)
+        _check(_lib.tgs_dag_generations(self.h, gen.ctypes.data, G.ctypes.data))
+        return gen, G
+
+    def lagged(self):
+        out = np.zeros((self.n_v, self.n_cells), dtype=np.uint8)
+        _check(_lib.tgs_dag_lagged(self.h, out.ctypes.data))
+        return out
+
+    def geometry(self):
+        nx = np.zeros((self.n_cells, self.n_p, self.dim))
+        bx = np.zeros((self.n_bfaces, self.n_fp, self.dim))
+        vol = np.zeros(self.n_cells)
+        _check(_lib.tgs_dag_geometry(self.h, nx.ctypes.data, bx.ctypes.data, vol.ctypes.data))
+        return nx, bx, vol
+
+    def pack(self, f_canonical, out=None, stream=None):
+        out = torch.empty(self.f_numel(), dtype=torch.float64, device="cuda") if out is None else out
+        _check(_lib.tgs_pack(self.h, _p(f_canonical), _p(out), _stream(stream)))
+        return out
+
+    def unpack(self, f_sweep, out=None, stream=None):
+        out = torch.empty(self.f_shape, dtype=torch.float64, device="cuda") if out is None else out
+        _check(_lib.tgs_unpack(self.h, _p(f_sweep), _p(out), _stream(stream)))
+        return out
+
+    def eval_maxwellian(self, coef, out=None, stream=None):
+        out = torch.empty(self.f_numel(), dtype=torch.float64, device="cuda") if out is None else out
+        _check(_lib.tgs_eval_maxwellian(self.h, _p(coef), _p(out), _stream(stream)))
+        return out
+
+    def explicit_dt(self, cfl):
+        """dt = C (1/d) (1/(2k+1)) h_min / max|v| with h_min = (min |K|)^(1/d) (eq. explicit-dt)."""
+        _, _, vol = self.geometry()
+        hmin = float(vol.min()) ** (1.0 / self.dim)
+        vmax = float(torch.linalg.norm(self.v, dim=1).max())
+        return cfl * (1.0 / self.dim) * (1.0 / (2 * self.order + 1)) * hmin / vmax
+
+
+def tgs_sweep(dag, *, q, nu, mcoef, f_out, sigma_shift, q_scale=1.0, bc_coef=None,
+              bc_dense=None, f_prev=None, precision=TGS_FP64, stream=None):
+    io = SweepIO(precision, float(sigma_shift), float(q_scale), _p(nu), _p(mcoef), _p(q),
+                 _p(bc_coef), _p(bc_dense), _p(f_prev), _p(f_out))
+    _check(_lib.tgs_sweep(dag.h, C.byref(io), _stream(stream)))
+    return f_out
+
+
+def moments(dag, f, U=None, U_prev=None, stream=None):
+    """Returns U (and the three convergence ratios when U_prev is given)."""
+    U = torch.empty((dag.n_nodes, dag.dim + 2), dtype=torch.float64, device="cuda") if U is None else U
+    rel = torch.empty(3, dtype=torch.float64, device="cuda") if U_prev is not None else None
+    _check(_lib.moments(dag.h, _p(f), _p(U), _p(U_prev), _p(rel), _stream(stream)))
+    return (U, rel) if U_prev is not None else U
+
+
+def maxwellian(dag, U, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, dense=False,
+               stream=None):
+    """Returns (coef [n_nodes][d+2], nu [n_nodes], M_dense or None, status[2])."""
+    coef = torch.empty((dag.n_nodes, dag.dim + 2), dtype=torch.float64, device="cuda")
+    nu = torch.empty(dag.n_nodes, dtype=torch.float64, device="cuda")
+    Md = torch.empty((dag.n_nodes, dag.n_v), dtype=torch.float64, device="cuda") if dense else None
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    nm = NuModel(NU[nu_model], float(nu_const), float(kn))
+    _check(_lib.maxwellian(dag.h, MAXW[mode], _p(U), C.byref(nm), _p(coef), _p(nu), _p(Md),
+                           _p(status), _stream(stream)))
+    return coef, nu, Md, status
+
+
+def maxwellian_coef_from_primitive(prim, dim, stream=None):
+    prim = prim.contiguous()
+    coef = torch.empty_like(prim)
+    _check(_lib.maxwellian_coef_from_primitive(int(dim), int(prim.shape[0]), _p(prim), _p(coef),
+                                               _stream(stream)))
+    return coef
+
+
+def state_coefficients(dag, state, where="nodes"):
+    """Maxwellian coefficients of a problems.State at the DG nodes or at the
+    boundary facet nodes (the state's (n, u, theta) is sampled on the host,
+    the conversion runs on the GPU)."""
+    nx, bx, _ = dag.geometry()
+    pts = nx.reshape(-1, dag.dim) if where == "nodes" else bx.reshape(-1, dag.dim)
+    n, u, th = state.params(pts)
+    prim = _dev(np.concatenate([n[:, None], u, th[:, None]], axis=1))
+    return maxwellian_coef_from_primitive(prim, dag.dim)
+
+
+class Solver:
+    """bgk_solver: DIRK stages with sweep-based Picard iteration."""
+
+    def __init__(self, dag, *, dt, bc_coef, tableau="BE", tau=1e-10, l_max=2000, fixed_iters=0,
+                 precision=TGS_FP64, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0):
+        self.dag = dag
+        self.bc_coef = bc_coef
+        o = SolverOpts(TABLEAU[tableau], float(dt), float(tau), int(l_max), int(fixed_iters),
+                       int(precision), MAXW[mode], NuModel(NU[nu_model], float(nu_const), float(kn)),
+                       _p(bc_coef))
+        h = C.c_void_p()
+        _check(_lib.bgk_solver_create(dag.h, C.byref(o), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _lib.bgk_solver_destroy(h)
+            self.h = None
+
+    def step(self, f, U_guess=None, U_out=None, stream=None):
+        st = StepStats()
+        _check(_lib.bgk_step(self.h, _p(f), _p(U_guess), _p(U_out), C.byref(st), _stream(stream)))
+        return {"iters": list(st.iters[:st.stages]), "total_iters": st.total_iters,
+                "last_ratio": list(st.last_ratio[:st.stages]), "fallbacks": st.maxw_fallbacks,
+                "seconds": st.seconds}
+
+
+def exported_symbols():
+    """Names of the C entry points the binding uses (all must resolve)."""
+    return [n for n in EXPORTED if hasattr(_lib, n)]
+
+
+def problem_setup(pr, dag=None, **dag_kw):
+    """Device-side setup of a problems.Problem: DAG, initial f (sweep layout),
+    boundary coefficients and dt = C dt_e."""
+    dag = Dag.from_problem(pr, **dag_kw) if dag is None else dag
+    f0 = dag.eval_maxwellian(state_coefficients(dag, pr.state, "nodes"))
+    bc = state_coefficients(dag, pr.state, "boundary")
+    return dag, f0, bc, dag.explicit_dt(pr.cfl)
+
+
+__all__ = ["Dag", "Solver", "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
+           "state_coefficients", "problem_setup", "BGKError", "exported_symbols", "math"]

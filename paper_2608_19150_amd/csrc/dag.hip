@@ -1,0 +1,717 @@
+// build_mesh_dag: host geometry and connectivity, then per-velocity upwind
+// DAGs and longest-path generations on the GPU (Sec. 4.1).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "device_common.h"
+
+namespace bgk {
+
+namespace {
+
+constexpr int DAG_THREADS = 256;
+
+// ----------------------------------------------------------------------------
+// host geometry
+// ----------------------------------------------------------------------------
+struct HostMesh {
+  int dim, order, n_p, n_fp;
+  int64_t n_cells;
+  std::vector<double> geo;          // user order, [c][dim*dim+1]
+  std::vector<int32_t> nb;          // user order, [c][dim+1]: user nbr or -(1+bface)
+  std::vector<int32_t> nb_face;     // [c][dim+1]
+  std::vector<int32_t> nb_node;     // [c][dim+1][n_fp]
+  std::vector<double> node_x;       // [c][n_p][dim]
+  std::vector<double> bnode_x;      // [bf][n_fp][dim]
+  std::vector<double> vol;          // [c]
+  std::vector<double> centroid;     // [c][dim]
+  int64_t n_bfaces = 0;
+};
+
+// local nodes on facet k (ascending), node key helpers
+void facet_nodes(int dim, int order, int k, std::vector<int>& out) {
+  out.clear();
+  for (int a = 0; a <= dim; ++a)
+    if (a != k) out.push_back(a);
+  if (order == 2) {
+    const int ii[3] = {0, 1, 2}, jj[3] = {1, 2, 0};
+    for (int m = 0; m < 3; ++m)
+      if (ii[m] != k && jj[m] != k) out.push_back(3 + m);
+  }
+}
+
+// global identity of local node a of a cell: vertex id, or the sorted pair of
+// an edge midpoint
+std::array<int32_t, 2> node_key(const int32_t* cv, int a) {
+  if (a < 3 || cv == nullptr) return {cv[a], -1};
+  const int ii[3] = {0, 1, 2}, jj[3] = {1, 2, 0};
+  int32_t x = cv[ii[a - 3]], y = cv[jj[a - 3]];
+  return {std::min(x, y), std::max(x, y)};
+}
+
+int build_host_mesh(const tgs_mesh_desc* m, HostMesh& H) {
+  const int dim = m->dim, order = m->order;
+  BGK_CHECK(dim == 2 || dim == 3, BGK_E_UNSUPPORTED, "dim must be 2 or 3");
+  BGK_CHECK(order == 1 || (order == 2 && dim == 2), BGK_E_UNSUPPORTED,
+            "supported elements: P1 triangles/tetrahedra, P2 triangles");
+  BGK_CHECK(m->n_cells > 0 && m->n_vert > dim && m->vert && m->cells, BGK_E_INVALID,
+            "empty mesh");
+  BGK_CHECK(m->n_cells < (int64_t)1 << 30, BGK_E_INVALID, "too many cells");
+  H.dim = dim;
+  H.order = order;
+  H.n_p = order == 1 ? dim + 1 : 6;
+  H.n_fp = order == 1 ? dim : 3;
+  H.n_cells = m->n_cells;
+  const int64_t nc = m->n_cells, nf = dim + 1;
+  const int gs = dim * dim + 1;
+  H.geo.assign(nc * gs, 0.0);
+  H.vol.assign(nc, 0.0);
+  H.centroid.assign(nc * dim, 0.0);
+  H.node_x.assign(nc * H.n_p * dim, 0.0);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int32_t* cv = m->cells + c * nf;
+    double X[4][3] = {};
+    for (int a = 0; a < nf; ++a) {
+      BGK_CHECK(cv[a] >= 0 && cv[a] < m->n_vert, BGK_E_INVALID, "vertex id out of range");
+      for (int d = 0; d < dim; ++d) X[a][d] = m->vert[(int64_t)cv[a] * dim + d];
+    }
+    double J[3][3] = {};  // columns X_{k+1} - X_0
+    double hmax = 0.0;
+    for (int r = 0; r < dim; ++r)
+      for (int k = 0; k < dim; ++k) {
+        J[r][k] = X[k + 1][r] - X[0][r];
+        hmax = std::max(hmax, std::fabs(J[r][k]));
+      }
+    double det, inv[3][3];
+    if (dim == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      inv[0][0] = J[1][1] / det;
+      inv[0][1] = -J[0][1] / det;
+      inv[1][0] = -J[1][0] / det;
+      inv[1][1] = J[0][0] / det;
+    } else {
+      const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      inv[0][0] = c00 / det;
+      inv[1][0] = c01 / det;
+      inv[2][0] = c02 / det;
+      inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    const double adet = std::fabs(det);
+    BGK_CHECK(std::isfinite(det) && adet > 1e-13 * std::pow(hmax, dim), BGK_E_INVALID,
+              "degenerate cell " + std::to_string(c));
+    double* g = &H.geo[c * gs];
+    for (int r = 0; r < dim; ++r)
+      for (int k = 0; k < dim; ++k) g[r * dim + k] = adet * inv[r][k];
+    g[dim * dim] = adet / (dim == 2 ? 2.0 : 6.0);
+    H.vol[c] = g[dim * dim];
+    for (int d = 0; d < dim; ++d) {
+      double s = 0;
+      for (int a = 0; a < nf; ++a) s += X[a][d];
+      H.centroid[c * dim + d] = s / nf;
+    }
+    for (int a = 0; a < H.n_p; ++a)
+      for (int d = 0; d < dim; ++d) {
+        double x;
+        if (a < nf) {
+          x = X[a][d];
+        } else {
+          const int ii[3] = {0, 1, 2}, jj[3] = {1, 2, 0};
+          x = 0.5 * (X[ii[a - 3]][d] + X[jj[a - 3]][d]);
+        }
+        H.node_x[(c * H.n_p + a) * dim + d] = x;
+      }
+  }
+  // facet matching by sorted vertex ids
+  struct FKey {
+    int32_t v[3];
+    int32_t cell, k;
+  };
+  std::vector<FKey> keys(nc * nf);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nf; ++k) {
+      FKey& f = keys[c * nf + k];
+      int p = 0;
+      f.v[2] = -1;
+      for (int a = 0; a < nf; ++a)
+        if (a != k) f.v[p++] = m->cells[c * nf + a];
+      std::sort(f.v, f.v + dim);
+      f.cell = (int32_t)c;
+      f.k = k;
+    }
+  std::sort(keys.begin(), keys.end(), [](const FKey& a, const FKey& b) {
+    if (a.v[0] != b.v[0]) return a.v[0] < b.v[0];
+    if (a.v[1] != b.v[1]) return a.v[1] < b.v[1];
+    if (a.v[2] != b.v[2]) return a.v[2] < b.v[2];
+    if (a.cell != b.cell) return a.cell < b.cell;
+    return a.k < b.k;
+  });
+  H.nb.assign(nc * nf, INT32_MIN);
+  H.nb_face.assign(nc * nf, -1);
+  auto same = [&](const FKey& a, const FKey& b) {
+    return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.v[2] == b.v[2];
+  };
+  for (size_t i = 0; i < keys.size();) {
+    size_t e = i + 1;
+    while (e < keys.size() && same(keys[i], keys[e])) ++e;
+    BGK_CHECK(e - i <= 2, BGK_E_INVALID, "facet shared by more than two cells");
+    if (e - i == 2) {
+      const FKey &a = keys[i], &b = keys[i + 1];
+      BGK_CHECK(a.cell != b.cell, BGK_E_INVALID, "cell with repeated vertices");
+      H.nb[(int64_t)a.cell * nf + a.k] = b.cell;
+      H.nb_face[(int64_t)a.cell * nf + a.k] = b.k;
+      H.nb[(int64_t)b.cell * nf + b.k] = a.cell;
+      H.nb_face[(int64_t)b.cell * nf + b.k] = a.k;
+    }
+    i = e;
+  }
+  // boundary facets in ascending (cell, facet) order; node maps
+  H.nb_node.assign(nc * nf * H.n_fp, -1);
+  H.bnode_x.clear();
+  std::vector<int> fn, fn2;
+  int64_t nbf = 0;
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nf; ++k) {
+      facet_nodes(dim, order, k, fn);
+      const int64_t idx = c * nf + k;
+      if (H.nb[idx] == INT32_MIN) {
+        H.nb[idx] = -(int32_t)(1 + nbf);
+        ++nbf;
+        for (int p = 0; p < H.n_fp; ++p)
+          for (int d = 0; d < dim; ++d)
+            H.bnode_x.push_back(H.node_x[(c * H.n_p + fn[p]) * dim + d]);
+        continue;
+      }
+      const int32_t c2 = H.nb[idx];
+      const int k2 = H.nb_face[idx];
+      facet_nodes(dim, order, k2, fn2);
+      for (int p = 0; p < H.n_fp; ++p) {
+        auto key = order == 1 ? std::array<int32_t, 2>{m->cells[c * nf + fn[p]], -1}
+                              : node_key(m->cells + c * nf, fn[p]);
+        int found = -1;
+        for (int q = 0; q < H.n_fp; ++q) {
+          auto k2key = order == 1 ? std::array<int32_t, 2>{m->cells[(int64_t)c2 * nf + fn2[q]], -1}
+                                  : node_key(m->cells + (int64_t)c2 * nf, fn2[q]);
+          if (k2key == key) found = fn2[q];
+        }
+        BGK_CHECK(found >= 0, BGK_E_INVALID, "non-conforming facet");
+        H.nb_node[idx * H.n_fp + p] = found;
+      }
+    }
+  H.n_bfaces = nbf;
+  return BGK_OK;
+}
+
+uint64_t spread_bits(uint64_t x, int dim) {
+  // interleave the low bits of x with (dim-1) zero bits between them
+  uint64_t r = 0;
+  const int nb = dim == 2 ? 31 : 21;
+  for (int b = 0; b < nb; ++b) r |= ((x >> b) & 1ull) << (b * dim);
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// GPU: per-velocity Kahn levels + stable counting sort by generation
+// ----------------------------------------------------------------------------
+struct DagArgs {
+  const double* geo;
+  const FacetRec* facet;
+  const double* v;
+  const uint8_t* user_lag;   // [n_v][n_cells] internal order, or null
+  uint8_t* lag;              // [n_v][n_cells] output lag bits, or null
+  int32_t* perm;             // [n_v][n_cells]
+  int32_t* pos;              // [n_v][n_cells]
+  int32_t* scratch_cnt;      // [batch][n_cells+1]  generation offsets (batch-local)
+  int32_t* scratch_cur;      // [batch][n_cells+1]  in-degrees, then cursors
+  int32_t* G;                // [n_v]
+  unsigned long long* n_lagged;
+  int n_cells;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
+  const int jb = blockIdx.x, j = j0 + jb, tid = threadIdx.x, bs = blockDim.x;
+  const int nc = a.n_cells;
+  double v[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) v[d] = a.v[(size_t)j * DIM + d];
+  int32_t* indeg = a.scratch_cur + (size_t)jb * (nc + 1);
+  int32_t* cnt = a.scratch_cnt + (size_t)jb * (nc + 1);
+  int32_t* queue = a.perm + (size_t)j * nc;
+  int32_t* gen = a.pos + (size_t)j * nc;
+  const uint8_t* ulag = a.user_lag ? a.user_lag + (size_t)j * nc : nullptr;
+  uint8_t* lag = a.lag ? a.lag + (size_t)j * nc : nullptr;
+
+  __shared__ int s_tail, s_min;
+  __shared__ int s_scan[DAG_THREADS];
+  if (tid == 0) s_tail = 0;
+  __syncthreads();
+  // in-degrees and sources
+  for (int K = tid; K < nc; K += bs) {
+    const int ul = ulag ? ulag[K] : 0;
+    const int bits = inflow_bits<DIM>(a.geo, a.facet, K, v, ul);
+    indeg[K] = __popc(bits);
+    gen[K] = -1;
+    if (lag) lag[K] = (uint8_t)ul;
+  }
+  __syncthreads();
+  for (int K = tid; K < nc; K += bs)
+    if (indeg[K] == 0) {
+      const int p = atomicAdd(&s_tail, 1);
+      queue[p] = K;
+      gen[K] = 0;
+    }
+  __syncthreads();
+  int head = 0, tail = s_tail, g = 0;
+  while (head < nc) {
+    if (head == tail) {
+      // the remaining cells form cycles: release the lowest-numbered one and
+      // lag its in-edges from unreleased cells
+      if (tid == 0) s_min = INT32_MAX;
+      __syncthreads();
+      int mymin = INT32_MAX;
+      for (int K = tid; K < nc; K += bs)
+        if (gen[K] < 0) mymin = min(mymin, K);
+      atomicMin(&s_min, mymin);
+      __syncthreads();
+      const int K = s_min;
+      if (K == INT32_MAX) break;  // inconsistent bookkeeping: stop (G < cells flags it)
+      if (tid == 0) {
+        const int ul = ulag ? ulag[K] : 0;
+        const int bits = inflow_bits<DIM>(a.geo, a.facet, K, v, ul);
+        int extra = 0;
+        for (int k = 0; k <= DIM; ++k)
+          if ((bits >> k) & 1) {
+            const int nbk = a.facet[(size_t)K * (DIM + 1) + k].nb;
+            if (gen[nbk] < 0) extra |= 1 << k;
+          }
+        if (lag) lag[K] = (uint8_t)(ul | extra);
+        atomicAdd(a.n_lagged, (unsigned long long)__popc(extra));
+        indeg[K] = 0;
+        queue[tail] = K;
+        gen[K] = g;
+        s_tail = tail + 1;
+      }
+      __syncthreads();
+      tail = s_tail;
+    }
+    __syncthreads();
+    if (tid == 0) s_tail = tail;
+    __syncthreads();
+    for (int idx = head + tid; idx < tail; idx += bs) {
+      const int K = queue[idx];
+#pragma unroll
+      for (int k = 0; k <= DIM; ++k) {
+        const FacetRec fr = a.facet[(size_t)K * (DIM + 1) + k];
+        if (fr.nb < 0) continue;
+        const int b = fr.nb, kb = fr.pack & 3;
+        const int ul = ulag ? ulag[b] : 0;
+        const int bits = inflow_bits<DIM>(a.geo, a.facet, b, v, ul);
+        if (!((bits >> kb) & 1)) continue;
+        if (atomicSub(&indeg[b], 1) == 1) {
+          const int p = atomicAdd(&s_tail, 1);
+          queue[p] = b;
+          gen[b] = g + 1;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    head = tail;
+    tail = s_tail;
+    ++g;
+    __syncthreads();
+  }
+  if (head < nc) {  // not every cell was released: report, touch nothing else
+    if (tid == 0) a.G[j] = -1;
+    return;
+  }
+  const int G = g;
+  if (tid == 0) a.G[j] = G;
+  // histogram of generations
+  for (int i = tid; i <= G; i += bs) cnt[i] = 0;
+  __syncthreads();
+  for (int K = tid; K < nc; K += bs) atomicAdd(&cnt[gen[K]], 1);
+  __threadfence_block();
+  __syncthreads();
+  // exclusive scan of cnt[0..G] (cnt[G] = 0 -> becomes nc)
+  int carry = 0;
+  for (int base = 0; base <= G; base += bs) {
+    const int i = base + tid;
+    const int x = i <= G ? cnt[i] : 0;
+    s_scan[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < bs; off <<= 1) {
+      const int y = tid >= off ? s_scan[tid - off] : 0;
+      __syncthreads();
+      s_scan[tid] += y;
+      __syncthreads();
+    }
+    if (i <= G) {
+      cnt[i] = carry + s_scan[tid] - x;
+      indeg[i] = cnt[i];  // cursor
+    }
+    carry += s_scan[bs - 1];
+    __syncthreads();
+  }
+  __threadfence_block();
+  __syncthreads();
+  // stable scatter in internal (Morton) order by one wavefront: within each
+  // 64-cell chunk, equal generations keep their order via ballots
+  if (tid < 64) {
+    const int lane = tid;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int base = 0; base < nc; base += 64) {
+      const int K = base + lane;
+      const bool act = K < nc;
+      const int gk = act ? gen[K] : -1;
+      unsigned long long remaining = __ballot(act);
+      int slot = 0;
+      while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const int gl = __shfl(gk, leader);
+        const unsigned long long m = __ballot(act && gk == gl);
+        int cur = 0;
+        if (lane == leader) cur = atomicAdd(&indeg[gl], (int)__popcll(m));
+        cur = __shfl(cur, leader);
+        if (act && gk == gl) slot = cur + __popcll(m & below);
+        remaining &= ~m;
+      }
+      if (act) {
+        queue[slot] = K;
+        gen[K] = slot;
+      }
+    }
+  }
+}
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(BGK_E_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return BGK_OK;
+}
+
+}  // namespace
+
+void free_dag(tgs_dag* d) {
+  if (!d) return;
+  void* ptrs[] = {d->d_geo,  d->d_uid, d->d_facet, d->d_v,    d->d_w,    d->d_nodes1d,
+                  d->d_weights1d, d->d_perm, d->d_pos, d->d_goff, d->d_gbase, d->d_G,
+                  d->d_lag, d->d_vorder};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete d;
+}
+
+int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tgs_dag_opts* opts,
+                   hipStream_t stream, tgs_dag* D) {
+  HostMesh H;
+  int rc = build_host_mesh(mesh, H);
+  if (rc) return rc;
+  const int dim = H.dim;
+  BGK_CHECK(vg && vg->n_v > 0 && vg->v && vg->w, BGK_E_INVALID, "empty velocity grid");
+  BGK_HIP(hipGetDevice(&D->device));
+  D->dim = dim;
+  D->order = H.order;
+  D->n_p = H.n_p;
+  D->n_fp = H.n_fp;
+  D->n_cells = H.n_cells;
+  D->n_vert = mesh->n_vert;
+  D->n_bfaces = H.n_bfaces;
+  D->n_nodes = H.n_cells * H.n_p;
+  D->n_v = vg->n_v;
+  D->L = vg->L;
+  D->v_host.assign(vg->v, vg->v + (size_t)vg->n_v * dim);
+  D->w_host.assign(vg->w, vg->w + vg->n_v);
+  if (opts && opts->sweep_threads) {
+    BGK_CHECK(opts->sweep_threads >= 64 && opts->sweep_threads <= 1024 &&
+                  opts->sweep_threads % 64 == 0,
+              BGK_E_INVALID, "sweep_threads must be a multiple of 64 in [64, 1024]");
+    D->sweep_threads = opts->sweep_threads;
+  }
+  // tensor grid declaration
+  D->n_1d = vg->n_1d;
+  if (vg->n_1d > 0) {
+    BGK_CHECK(vg->nodes_1d && vg->weights_1d, BGK_E_INVALID, "tensor grid without 1D factors");
+    int64_t expect = 1;
+    for (int d = 0; d < dim; ++d) expect *= vg->n_1d;
+    BGK_CHECK(expect == vg->n_v, BGK_E_INVALID, "n_v != n_1d^dim");
+    D->nodes_1d.assign(vg->nodes_1d, vg->nodes_1d + vg->n_1d);
+    D->weights_1d.assign(vg->weights_1d, vg->weights_1d + vg->n_1d);
+    for (int j = 0; j < vg->n_v; ++j) {
+      int rem = j;
+      double w = 1.0;
+      int idx[3];
+      for (int d = dim - 1; d >= 0; --d) {
+        idx[d] = rem % vg->n_1d;
+        rem /= vg->n_1d;
+      }
+      for (int d = 0; d < dim; ++d) {
+        w *= vg->weights_1d[idx[d]];
+        BGK_CHECK(vg->v[(size_t)j * dim + d] == vg->nodes_1d[idx[d]], BGK_E_INVALID,
+                  "velocity grid is not the declared tensor product");
+      }
+      BGK_CHECK(std::fabs(w - vg->w[j]) <= 1e-13 * std::fabs(w), BGK_E_INVALID,
+                "weights are not the declared tensor product");
+    }
+  }
+  const int64_t nc = H.n_cells;
+  const int nf = dim + 1;
+  // Morton order of centroids -> internal numbering
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t c = 0; c < nc; ++c)
+    for (int d = 0; d < dim; ++d) {
+      lo[d] = std::min(lo[d], H.centroid[c * dim + d]);
+      hi[d] = std::max(hi[d], H.centroid[c * dim + d]);
+    }
+  std::vector<std::pair<uint64_t, int32_t>> mk(nc);
+  const double scale = dim == 2 ? 2147483647.0 : 2097151.0;
+  for (int64_t c = 0; c < nc; ++c) {
+    uint64_t code = 0;
+    for (int d = 0; d < dim; ++d) {
+      const double t = (H.centroid[c * dim + d] - lo[d]) / std::max(hi[d] - lo[d], 1e-300);
+      code |= spread_bits((uint64_t)(t * scale), dim) << d;
+    }
+    mk[c] = {code, (int32_t)c};
+  }
+  std::stable_sort(mk.begin(), mk.end(),
+                   [](const auto& a, const auto& b) { return a.first < b.first; });
+  D->uid_host.resize(nc);
+  D->iid_host.resize(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    D->uid_host[i] = mk[i].second;
+    D->iid_host[mk[i].second] = (int32_t)i;
+  }
+  // internal-order device records
+  const int gs = dim * dim + 1;
+  std::vector<double> geo_i(nc * gs);
+  std::vector<FacetRec> fac_i(nc * nf);
+  for (int64_t i = 0; i < nc; ++i) {
+    const int64_t u = D->uid_host[i];
+    std::copy(&H.geo[u * gs], &H.geo[u * gs] + gs, &geo_i[i * gs]);
+    for (int k = 0; k < nf; ++k) {
+      const int32_t nb = H.nb[u * nf + k];
+      FacetRec r;
+      r.nb = nb >= 0 ? D->iid_host[nb] : nb;
+      int pack = nb >= 0 ? (H.nb_face[u * nf + k] & 3) : 0;
+      if (nb >= 0)
+        for (int p = 0; p < H.n_fp; ++p) pack |= (H.nb_node[(u * nf + k) * H.n_fp + p] & 15) << (4 * (p + 1));
+      r.pack = pack;
+      fac_i[i * nf + k] = r;
+    }
+  }
+  D->node_x = std::move(H.node_x);
+  D->bnode_x = std::move(H.bnode_x);
+  D->vol_user = std::move(H.vol);
+  const int nv = vg->n_v;
+  if ((rc = dalloc(&D->d_geo, geo_i.size()))) return rc;
+  if ((rc = dalloc(&D->d_uid, nc))) return rc;
+  if ((rc = dalloc(&D->d_facet, fac_i.size()))) return rc;
+  if ((rc = dalloc(&D->d_v, (size_t)nv * dim))) return rc;
+  if ((rc = dalloc(&D->d_w, (size_t)nv))) return rc;
+  if ((rc = dalloc(&D->d_perm, (size_t)nv * nc))) return rc;
+  if ((rc = dalloc(&D->d_pos, (size_t)nv * nc))) return rc;
+  if ((rc = dalloc(&D->d_G, (size_t)nv))) return rc;
+  if ((rc = dalloc(&D->d_gbase, (size_t)nv))) return rc;
+  if ((rc = dalloc(&D->d_vorder, (size_t)nv))) return rc;
+  if ((rc = dalloc(&D->d_lag, (size_t)nv * nc))) return rc;
+  BGK_HIP(hipMemcpyAsync(D->d_geo, geo_i.data(), geo_i.size() * sizeof(double),
+                         hipMemcpyHostToDevice, stream));
+  BGK_HIP(hipMemcpyAsync(D->d_uid, D->uid_host.data(), nc * sizeof(int32_t),
+                         hipMemcpyHostToDevice, stream));
+  BGK_HIP(hipMemcpyAsync(D->d_facet, fac_i.data(), fac_i.size() * sizeof(FacetRec),
+                         hipMemcpyHostToDevice, stream));
+  BGK_HIP(hipMemcpyAsync(D->d_v, D->v_host.data(), D->v_host.size() * sizeof(double),
+                         hipMemcpyHostToDevice, stream));
+  BGK_HIP(hipMemcpyAsync(D->d_w, D->w_host.data(), D->w_host.size() * sizeof(double),
+                         hipMemcpyHostToDevice, stream));
+  if (D->n_1d > 0) {
+    if ((rc = dalloc(&D->d_nodes1d, D->n_1d))) return rc;
+    if ((rc = dalloc(&D->d_weights1d, D->n_1d))) return rc;
+    BGK_HIP(hipMemcpyAsync(D->d_nodes1d, D->nodes_1d.data(), D->n_1d * sizeof(double),
+                           hipMemcpyHostToDevice, stream));
+    BGK_HIP(hipMemcpyAsync(D->d_weights1d, D->weights_1d.data(), D->n_1d * sizeof(double),
+                           hipMemcpyHostToDevice, stream));
+  }
+  uint8_t* d_ulag = nullptr;
+  std::vector<uint8_t> ulag_i;
+  if (opts && opts->lagged) {
+    ulag_i.resize((size_t)nv * nc);
+    for (int j = 0; j < nv; ++j)
+      for (int64_t i = 0; i < nc; ++i)
+        ulag_i[(size_t)j * nc + i] = opts->lagged[(size_t)j * nc + D->uid_host[i]] & ((1 << nf) - 1);
+    if ((rc = dalloc(&d_ulag, ulag_i.size()))) return rc;
+    BGK_HIP(hipMemcpyAsync(d_ulag, ulag_i.data(), ulag_i.size(), hipMemcpyHostToDevice, stream));
+  }
+  // batches of velocities bounded by ~1 GiB of scratch
+  const size_t per_v = (size_t)2 * (nc + 1) * sizeof(int32_t);
+  int batch = (int)std::max<size_t>(1, std::min<size_t>(nv, ((size_t)1 << 30) / per_v));
+  int32_t *s_cnt = nullptr, *s_cur = nullptr;
+  unsigned long long* d_nlag = nullptr;
+  if ((rc = dalloc(&s_cnt, (size_t)batch * (nc + 1)))) return rc;
+  if ((rc = dalloc(&s_cur, (size_t)batch * (nc + 1)))) return rc;
+  if ((rc = dalloc(&d_nlag, 1))) return rc;
+  BGK_HIP(hipMemsetAsync(d_nlag, 0, sizeof(unsigned long long), stream));
+  DagArgs a{D->d_geo, D->d_facet, D->d_v, d_ulag, D->d_lag, D->d_perm, D->d_pos,
+            s_cnt, s_cur, D->d_G, d_nlag, (int)nc};
+  D->G_host.resize(nv);
+  D->gbase_host.resize(nv);
+  int64_t total_goff = 0;
+  // first pass: levels per batch; offsets copied to host per batch
+  std::vector<int32_t> goff_host;
+  for (int j0 = 0; j0 < nv; j0 += batch) {
+    const int nb = std::min(batch, nv - j0);
+    if (dim == 2)
+      hipLaunchKernelGGL(k_dag_levels<2>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
+    else
+      hipLaunchKernelGGL(k_dag_levels<3>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
+    BGK_HIP(hipGetLastError());
+    BGK_HIP(hipMemcpyAsync(D->G_host.data() + j0, D->d_G + j0, nb * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream));
+    BGK_HIP(hipStreamSynchronize(stream));
+    std::vector<int32_t> cnt_host((size_t)nb * (nc + 1));
+    BGK_HIP(hipMemcpy(cnt_host.data(), s_cnt, cnt_host.size() * sizeof(int32_t),
+                      hipMemcpyDeviceToHost));
+    for (int jb = 0; jb < nb; ++jb) {
+      const int j = j0 + jb;
+      D->gbase_host[j] = total_goff;
+      const int G = D->G_host[j];
+      BGK_CHECK(G > 0, BGK_E_INVALID, "generation construction failed for velocity " + std::to_string(j));
+      goff_host.insert(goff_host.end(), cnt_host.begin() + (size_t)jb * (nc + 1),
+                       cnt_host.begin() + (size_t)jb * (nc + 1) + G + 1);
+      total_goff += G + 1;
+    }
+  }
+  if ((rc = dalloc(&D->d_goff, (size_t)total_goff))) return rc;
+  BGK_HIP(hipMemcpyAsync(D->d_goff, goff_host.data(), total_goff * sizeof(int32_t),
+                         hipMemcpyHostToDevice, stream));
+  BGK_HIP(hipMemcpyAsync(D->d_gbase, D->gbase_host.data(), nv * sizeof(int64_t),
+                         hipMemcpyHostToDevice, stream));
+  unsigned long long nlag = 0;
+  BGK_HIP(hipMemcpyAsync(&nlag, d_nlag, sizeof(nlag), hipMemcpyDeviceToHost, stream));
+  BGK_HIP(hipStreamSynchronize(stream));
+  (void)hipFree(s_cnt);
+  (void)hipFree(s_cur);
+  (void)hipFree(d_nlag);
+  if (d_ulag) (void)hipFree(d_ulag);
+  int64_t user_lag_bits = 0;
+  for (uint8_t b : ulag_i) user_lag_bits += __builtin_popcount(b);
+  D->n_lagged = (int64_t)nlag + user_lag_bits;
+  if (D->n_lagged == 0) {
+    (void)hipFree(D->d_lag);
+    D->d_lag = nullptr;
+  }
+  D->max_G = 0;
+  for (int j = 0; j < nv; ++j) D->max_G = std::max(D->max_G, D->G_host[j]);
+  // sweep block order: longest generation chains first
+  std::vector<int32_t> vorder(nv);
+  std::iota(vorder.begin(), vorder.end(), 0);
+  std::stable_sort(vorder.begin(), vorder.end(),
+                   [&](int32_t x, int32_t y) { return D->G_host[x] > D->G_host[y]; });
+  BGK_HIP(hipMemcpyAsync(D->d_vorder, vorder.data(), nv * sizeof(int32_t), hipMemcpyHostToDevice,
+                         stream));
+  BGK_HIP(hipStreamSynchronize(stream));
+  return BGK_OK;
+}
+
+}  // namespace bgk
+
+using namespace bgk;
+
+extern "C" int build_mesh_dag(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vgrid,
+                              const tgs_dag_opts* opts, bgk_stream_t stream, tgs_dag** out) {
+  if (!mesh || !vgrid || !out) return fail(BGK_E_INVALID, "null argument");
+  *out = nullptr;
+  if (vgrid->n_v <= 0) return fail(BGK_E_INVALID, "n_v must be positive");
+  tgs_dag* D = new (std::nothrow) tgs_dag();
+  if (!D) return fail(BGK_E_NOMEM, "host allocation failed");
+  int rc;
+  try {
+    rc = build_dag_impl(mesh, vgrid, opts, (hipStream_t)stream, D);
+  } catch (const std::exception& e) {
+    rc = fail(BGK_E_NOMEM, std::string("host exception: ") + e.what());
+  }
+  if (rc) {
+    free_dag(D);
+    return rc;
+  }
+  *out = D;
+  return BGK_OK;
+}
+
+extern "C" int tgs_dag_destroy(tgs_dag* dag) {
+  free_dag(dag);
+  return BGK_OK;
+}
+
+extern "C" int tgs_dag_sizes(const tgs_dag* d, int64_t s[9]) {
+  if (!d || !s) return fail(BGK_E_INVALID, "null argument");
+  s[0] = d->dim;
+  s[1] = d->order;
+  s[2] = d->n_p;
+  s[3] = d->n_fp;
+  s[4] = d->n_cells;
+  s[5] = d->n_v;
+  s[6] = d->n_bfaces;
+  s[7] = d->max_G;
+  s[8] = d->n_lagged;
+  return BGK_OK;
+}
+
+extern "C" int tgs_dag_generations(const tgs_dag* d, int32_t* gen, int32_t* G) {
+  if (!d) return fail(BGK_E_INVALID, "null dag");
+  if (G) std::copy(d->G_host.begin(), d->G_host.end(), G);
+  if (!gen) return BGK_OK;
+  const int64_t nc = d->n_cells;
+  std::vector<int32_t> perm((size_t)d->n_v * nc);
+  std::vector<int32_t> goff;
+  BGK_HIP(hipMemcpy(perm.data(), d->d_perm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int64_t total = 0;
+  for (int j = 0; j < d->n_v; ++j) total += d->G_host[j] + 1;
+  goff.resize(total);
+  BGK_HIP(hipMemcpy(goff.data(), d->d_goff, total * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int j = 0; j < d->n_v; ++j) {
+    const int32_t* go = goff.data() + d->gbase_host[j];
+    for (int g = 0; g < d->G_host[j]; ++g)
+      for (int s = go[g]; s < go[g + 1]; ++s)
+        gen[(size_t)j * nc + d->uid_host[perm[(size_t)j * nc + s]]] = g;
+  }
+  return BGK_OK;
+}
+
+extern "C" int tgs_dag_lagged(const tgs_dag* d, uint8_t* lagged) {
+  if (!d || !lagged) return fail(BGK_E_INVALID, "null argument");
+  const int64_t nc = d->n_cells;
+  if (!d->d_lag) {
+    std::memset(lagged, 0, (size_t)d->n_v * nc);
+    return BGK_OK;
+  }
+  std::vector<uint8_t> tmp((size_t)d->n_v * nc);
+  BGK_HIP(hipMemcpy(tmp.data(), d->d_lag, tmp.size(), hipMemcpyDeviceToHost));
+  for (int j = 0; j < d->n_v; ++j)
+    for (int64_t i = 0; i < nc; ++i) lagged[(size_t)j * nc + d->uid_host[i]] = tmp[(size_t)j * nc + i];
+  return BGK_OK;
+}
+
+extern "C" int tgs_dag_geometry(const tgs_dag* d, double* node_x, double* bnode_x, double* vol) {
+  if (!d) return fail(BGK_E_INVALID, "null dag");
+  if (node_x) std::copy(d->node_x.begin(), d->node_x.end(), node_x);
+  if (bnode_x) std::copy(d->bnode_x.begin(), d->bnode_x.end(), bnode_x);
+  if (vol) std::copy(d->vol_user.begin(), d->vol_user.end(), vol);
+  return BGK_OK;
+}

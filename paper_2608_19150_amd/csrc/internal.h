@@ -1,0 +1,261 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bgktgs.h"
+
+namespace bgk {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define BGK_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::bgk::fail(BGK_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define BGK_CHECK(cond, code, msg)       \
+  do {                                   \
+    if (!(cond)) return ::bgk::fail(code, msg); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Reference-element matrices, evaluated at compile time.
+//
+// Basis functions are polynomials in the barycentric coordinates
+// lambda_0..lambda_d (P1: lambda_a; P2 triangle: lambda_k(2 lambda_k - 1) at
+// vertices, 4 lambda_i lambda_j at edge midpoints (0,1),(1,2),(2,0)).  On a
+// simplex of measure |K|,
+//     int_K prod_i lambda_i^a_i = |K| d! prod_i a_i! / (sum a + d)!,
+// which makes every element integral an exact rational; the tables hold
+// those rationals rounded to double by the compiler.
+// ---------------------------------------------------------------------------
+struct Term {
+  double c;
+  int e[4];
+};
+struct Poly {
+  int n = 0;
+  Term t[24] = {};
+};
+
+constexpr double cfact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+constexpr Poly p_mul(const Poly& a, const Poly& b) {
+  Poly r;
+  for (int i = 0; i < a.n; ++i)
+    for (int j = 0; j < b.n; ++j) {
+      Term t{a.t[i].c * b.t[j].c, {0, 0, 0, 0}};
+      for (int k = 0; k < 4; ++k) t.e[k] = a.t[i].e[k] + b.t[j].e[k];
+      r.t[r.n++] = t;
+    }
+  return r;
+}
+constexpr Poly p_dlam(const Poly& a, int var) {  // d/d lambda_var
+  Poly r;
+  for (int i = 0; i < a.n; ++i)
+    if (a.t[i].e[var] > 0) {
+      Term t = a.t[i];
+      t.c *= t.e[var];
+      t.e[var] -= 1;
+      r.t[r.n++] = t;
+    }
+  return r;
+}
+// d/d xi_beta (beta = 1..d) with lambda_0 = 1 - sum xi, lambda_beta = xi_beta
+constexpr Poly p_dxi(const Poly& a, int beta) {
+  Poly r = p_dlam(a, beta);
+  Poly m = p_dlam(a, 0);
+  for (int i = 0; i < m.n; ++i) {
+    Term t = m.t[i];
+    t.c = -t.c;
+    r.t[r.n++] = t;
+  }
+  return r;
+}
+// integral over a dim-simplex divided by its measure
+constexpr double p_int_norm(const Poly& p, int dim) {
+  double s = 0.0;
+  for (int i = 0; i < p.n; ++i) {
+    double num = 1.0;
+    int deg = 0;
+    for (int k = 0; k < 4; ++k) {
+      num *= cfact(p.t[i].e[k]);
+      deg += p.t[i].e[k];
+    }
+    s += p.t[i].c * cfact(dim) * num / cfact(deg + dim);
+  }
+  return s;
+}
+// integral over facet `drop` (lambda_drop = 0) divided by the facet measure
+constexpr double p_int_facet_norm(const Poly& p, int dim, int drop) {
+  double s = 0.0;
+  for (int i = 0; i < p.n; ++i) {
+    if (p.t[i].e[drop] != 0) continue;
+    double num = 1.0;
+    int deg = 0;
+    for (int k = 0; k < 4; ++k) {
+      num *= cfact(p.t[i].e[k]);
+      deg += p.t[i].e[k];
+    }
+    s += p.t[i].c * cfact(dim - 1) * num / cfact(deg + dim - 1);
+  }
+  return s;
+}
+constexpr Poly p_lam(int i) {
+  Poly r;
+  r.n = 1;
+  r.t[0] = Term{1.0, {0, 0, 0, 0}};
+  r.t[0].e[i] = 1;
+  return r;
+}
+
+template <int DIM, int ORDER>
+struct Elem;
+
+template <int DIM, int ORDER>
+struct ElemBuild {
+  static constexpr int NP = (ORDER == 1) ? DIM + 1 : 6;
+  static constexpr int NF = DIM + 1;
+  static constexpr int NFP = (ORDER == 1) ? DIM : 3;
+  struct Tables {
+    double mass[NP][NP] = {};             // (1/|K|) int phi_a phi_b
+    double stiff[DIM][NP][NP] = {};       // int_ref phi_b d(phi_a)/d(xi_beta)
+    double fmass[NF][NP][NP] = {};        // (1/|F_k|) int_{F_k} phi_a phi_b
+    int fnode[NF][NFP] = {};              // local nodes on facet k, ascending
+  };
+  static constexpr Poly basis(int a) {
+    if (ORDER == 1) return p_lam(a);
+    // P2 triangle
+    if (a < 3) {
+      Poly r;
+      r.n = 2;
+      r.t[0] = Term{2.0, {0, 0, 0, 0}};
+      r.t[0].e[a] = 2;
+      r.t[1] = Term{-1.0, {0, 0, 0, 0}};
+      r.t[1].e[a] = 1;
+      return r;
+    }
+    const int ii[3] = {0, 1, 2}, jj[3] = {1, 2, 0};
+    Poly r;
+    r.n = 1;
+    r.t[0] = Term{4.0, {0, 0, 0, 0}};
+    r.t[0].e[ii[a - 3]] = 1;
+    r.t[0].e[jj[a - 3]] += 1;
+    return r;
+  }
+  // node a lies on facet k (lambda_k = 0 at the node)
+  static constexpr bool on_facet(int a, int k) {
+    if (a <= DIM) return a != k;  // vertices (and P2 vertices 0..2)
+    const int ii[3] = {0, 1, 2}, jj[3] = {1, 2, 0};
+    return ii[a - 3] != k && jj[a - 3] != k;
+  }
+  static constexpr Tables make() {
+    Tables T;
+    for (int a = 0; a < NP; ++a)
+      for (int b = 0; b < NP; ++b) T.mass[a][b] = p_int_norm(p_mul(basis(a), basis(b)), DIM);
+    for (int be = 0; be < DIM; ++be)
+      for (int a = 0; a < NP; ++a)
+        for (int b = 0; b < NP; ++b)
+          T.stiff[be][a][b] =
+              p_int_norm(p_mul(basis(b), p_dxi(basis(a), be + 1)), DIM) / cfact(DIM);
+    for (int k = 0; k < NF; ++k) {
+      int p = 0;
+      for (int a = 0; a < NP; ++a)
+        if (on_facet(a, k)) T.fnode[k][p++] = a;
+      for (int a = 0; a < NP; ++a)
+        for (int b = 0; b < NP; ++b)
+          if (on_facet(a, k) && on_facet(b, k))
+            T.fmass[k][a][b] = p_int_facet_norm(p_mul(basis(a), basis(b)), DIM, k);
+    }
+    return T;
+  }
+};
+
+template <int DIM, int ORDER>
+struct Elem {
+  using B = ElemBuild<DIM, ORDER>;
+  static constexpr int NP = B::NP, NF = B::NF, NFP = B::NFP;
+  static constexpr typename B::Tables T = B::make();
+  // facet flux factor: v.N_k = |e_k| v.n_k = s_k * (D v) with D = |det J| J^-1:
+  //   k = 0: +sum_b w_b / (d-1)!,  k >= 1: -w_{k-1} / (d-1)!
+  static constexpr double INV_FACT_DM1 = 1.0 / cfact(DIM - 1);
+};
+
+// ---------------------------------------------------------------------------
+// geometry record per internal cell (doubles):
+//   D[DIM][DIM] = |det J| J^{-1}, vol = |K|
+// internal cells are numbered in Morton order of their centroids
+// ---------------------------------------------------------------------------
+template <int DIM>
+struct GeoLayout {
+  static constexpr int STRIDE = DIM * DIM + 1;  // doubles
+};
+
+// facet record: x = neighbour internal cell id, or -(1 + boundary facet id);
+// y = bits 0..1 neighbour's facet index, bits 4*(p+1).. neighbour local node
+// of facet node p (4 bits each)
+struct FacetRec {
+  int nb;
+  int pack;
+};
+
+struct DeviceBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace bgk
+
+struct tgs_dag {
+  int device = 0;
+  int dim = 0, order = 0, n_p = 0, n_fp = 0;
+  int64_t n_cells = 0, n_vert = 0, n_bfaces = 0, n_nodes = 0;
+  int n_v = 0;
+  int max_G = 0;
+  int64_t n_lagged = 0;
+  int sweep_threads = 256;
+  // host copies
+  std::vector<double> v_host, w_host;       // [n_v][dim], [n_v]
+  int n_1d = 0;
+  std::vector<double> nodes_1d, weights_1d;
+  double L = 0.0;
+  std::vector<int32_t> uid_host;            // internal -> user cell
+  std::vector<int32_t> iid_host;            // user -> internal cell
+  std::vector<double> node_x, bnode_x, vol_user;  // exports (user order)
+  std::vector<int32_t> G_host;              // [n_v]
+  std::vector<int64_t> gbase_host;          // [n_v]
+  // device arrays
+  double* d_geo = nullptr;        // [n_cells][GeoLayout::STRIDE]
+  int32_t* d_uid = nullptr;       // [n_cells] internal -> user
+  bgk::FacetRec* d_facet = nullptr;  // [n_cells][dim+1]
+  double* d_v = nullptr;          // [n_v][dim]
+  double* d_w = nullptr;          // [n_v]
+  double* d_nodes1d = nullptr;    // [n_1d]
+  double* d_weights1d = nullptr;  // [n_1d]
+  int32_t* d_perm = nullptr;      // [n_v][n_cells] slot -> internal cell
+  int32_t* d_pos = nullptr;       // [n_v][n_cells] internal cell -> slot
+  int32_t* d_goff = nullptr;      // flat generation offsets
+  int64_t* d_gbase = nullptr;     // [n_v] base index of velocity j's offsets
+  int32_t* d_G = nullptr;         // [n_v]
+  uint8_t* d_lag = nullptr;       // [n_v][n_cells] lagged facet bits (internal), or null
+  int32_t* d_vorder = nullptr;    // [n_v] velocity processed by sweep block b
+};
+
+namespace bgk {
+inline size_t f_elems(const tgs_dag* d) { return (size_t)d->n_v * d->n_cells * d->n_p; }
+}  // namespace bgk

@@ -1,0 +1,578 @@
+// Velocity moments (eq. moments), the Picard stopping ratios
+// (eq. convergence-criteria) and the discrete Maxwellian
+// (eq. Maxwellian-projection) with the collision frequency.
+#include <cmath>
+
+#include "device_common.h"
+
+namespace bgk {
+
+// ----------------------------------------------------------------------------
+// moments: U[node][m] = sum_j w_j e_m(v_j) f_j(node)
+//
+// A block holds CB consecutive internal cells x VL velocity lanes (CB*VL =
+// 256, cells fastest so a wavefront reads 64 consecutive entries of pos[j]).
+// Lane l sums velocities j = l, l+VL, ... in increasing order; the VL partial
+// sums are then added in lane order through LDS, so the result is bitwise
+// reproducible.  Optionally the per-block pieces of the convergence norms
+// are written for a fixed-order final reduction.
+// ----------------------------------------------------------------------------
+constexpr int MOM_THREADS = 256;
+
+struct MomArgs {
+  const double* f;
+  const int32_t* pos;
+  const int32_t* uid;
+  const double* v;
+  const double* w;
+  double* U;
+  const double* U_prev;
+  double* partial;  // [gridDim][6]: |dU_m|^2 (m = 0,1,2), |U_prev_m|^2
+  int n_cells;
+  int n_v;
+};
+
+template <int DIM, int NP, int VL>
+__global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
+  constexpr int CB = MOM_THREADS / VL, NM = DIM + 2;
+  __shared__ double s_red[MOM_THREADS / 64 > 0 ? (VL > 1 ? (VL - 1) * CB * NP * NM : 1) : 1];
+  __shared__ double s_norm[6][CB];
+  const int tid = threadIdx.x, c = tid % CB, lane = tid / CB;
+  const int K = blockIdx.x * CB + c;
+  const bool valid = K < a.n_cells;
+  double acc[NP][NM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+  if (valid) {
+    for (int j = lane; j < a.n_v; j += VL) {
+      const size_t slot = (size_t)a.pos[(size_t)j * a.n_cells + K];
+      const double* fp = a.f + ((size_t)j * a.n_cells + slot) * NP;
+      const double wj = a.w[j];
+      double e[NM];
+      double v2 = 0.0;
+      e[0] = wj;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double vd = a.v[(size_t)j * DIM + d];
+        e[1 + d] = wj * vd;
+        v2 = fma(vd, vd, v2);
+      }
+      e[NM - 1] = 0.5 * wj * v2;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const double fv = fp[p];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[p][m] = fma(e[m], fv, acc[p][m]);
+      }
+    }
+  }
+  if (VL > 1) {
+    if (lane > 0) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) s_red[(((lane - 1) * CB + c) * NP + p) * NM + m] = acc[p][m];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      for (int l = 1; l < VL; ++l)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int m = 0; m < NM; ++m) acc[p][m] += s_red[(((l - 1) * CB + c) * NP + p) * NM + m];
+    }
+  }
+  if (lane == 0) {
+    double nrm[6] = {0, 0, 0, 0, 0, 0};
+    if (valid) {
+      const size_t u = (size_t)a.uid[K];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        double* Up = a.U + (u * NP + p) * NM;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) Up[m] = acc[p][m];
+        if (a.U_prev) {
+          const double* Uo = a.U_prev + (u * NP + p) * NM;
+#pragma unroll
+          for (int m = 0; m < NM; ++m) {
+            const int blk = m == 0 ? 0 : (m == NM - 1 ? 2 : 1);
+            const double dd = acc[p][m] - Uo[m];
+            nrm[blk] = fma(dd, dd, nrm[blk]);
+            nrm[3 + blk] = fma(Uo[m], Uo[m], nrm[3 + blk]);
+          }
+        }
+      }
+    }
+    if (a.U_prev)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) s_norm[i][c] = nrm[i];
+  }
+  if (a.U_prev) {
+    __syncthreads();
+    // fixed-order tree over the CB cells of the block
+    for (int off = CB / 2; off > 0; off >>= 1) {
+      if (tid < off)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s_norm[i][tid] += s_norm[i][tid + off];
+      __syncthreads();
+    }
+    if (tid < 6) a.partial[(size_t)blockIdx.x * 6 + tid] = s_norm[tid][0];
+  }
+}
+
+// Final reduction of the block pieces in a fixed order; writes
+// out[0..2] = ratios, out[3] = max ratio.
+__global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partial, int nblk,
+                                               double* out) {
+  __shared__ double s[6][256];
+  const int tid = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < nblk; b += 256)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += partial[(size_t)b * 6 + i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i][tid] = acc[i];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) s[i][tid] += s[i][tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double n0 = sqrt(s[3][0]);
+    double mx = 0.0;
+    for (int m = 0; m < 3; ++m) {
+      double den = sqrt(s[3 + m][0]);
+      if (m == 1) den = fmax(den, n0);
+      const double r = sqrt(s[m][0]) / den;
+      out[m] = r;
+      mx = fmax(mx, r);
+    }
+    out[3] = mx;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Maxwellian coefficients and collision frequency, one thread per node.
+// ----------------------------------------------------------------------------
+struct MaxwArgs {
+  const double* U;
+  double* coef;
+  double* nu;
+  double* M_dense;          // canonical [n_nodes][n_v] or null
+  int32_t* status;          // [0] fallbacks, [1] non-physical, or null
+  unsigned long long* numax;  // bit pattern of max nu (nu >= 0), or null
+  const double* v;
+  const double* w;
+  const double* x1;         // tensor 1-D nodes or null
+  const double* w1;
+  int n1;
+  int n_v;
+  int64_t n_nodes;
+  int mode;
+  int nu_kind;
+  double nu_const, kn, L;
+};
+
+template <int N>
+__device__ bool small_solve(double (&A)[N][N], double (&b)[N]) {
+  // Gaussian elimination with partial pivoting on a (d+2)x(d+2) system
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    double best = fabs(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < N; ++i)
+      if (fabs(A[i][k]) > best) {
+        best = fabs(A[i][k]);
+        piv = i;
+      }
+    if (!(best > 0.0) || !isfinite(best)) return false;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (i == piv && piv != k) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const double t = A[k][c];
+          A[k][c] = A[i][c];
+          A[i][c] = t;
+        }
+        const double t = b[k];
+        b[k] = b[i];
+        b[i] = t;
+      }
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const double l = A[i][k] * inv;
+#pragma unroll
+      for (int c = k; c < N; ++c) A[i][c] = fma(-l, A[k][c], A[i][c]);
+      b[i] = fma(-l, b[k], b[i]);
+    }
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = b[i];
+#pragma unroll
+    for (int c = i + 1; c < N; ++c) s = fma(-A[i][c], b[c], s);
+    b[i] = s / A[i][i];
+  }
+  return true;
+}
+
+// F = sum_j w_j e_j M_j and the Jacobian J[r][c] = dF_r/dx_c for
+// M_j = exp(a + b.v_j + c|v_j|^2), x = (a, b, c).
+template <int DIM>
+__device__ void matched_system(const MaxwArgs& p, const double (&x)[DIM + 2],
+                               double (&F)[DIM + 2], double (&J)[DIM + 2][DIM + 2]) {
+  constexpr int NM = DIM + 2;
+  if (p.x1) {
+    // tensor grid: per-axis sums Z[al][k] = sum_i w1_i x_i^k exp(b_al x_i + c x_i^2)
+    double Z[DIM][5];
+#pragma unroll
+    for (int al = 0; al < DIM; ++al)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) Z[al][k] = 0.0;
+    for (int i = 0; i < p.n1; ++i) {
+      const double xi = p.x1[i], wi = p.w1[i];
+#pragma unroll
+      for (int al = 0; al < DIM; ++al) {
+        const double g = wi * exp(fma(x[1 + al], xi, x[1 + DIM] * xi * xi));
+        double t = g;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          Z[al][k] += t;
+          t *= xi;
+        }
+      }
+    }
+    const double ea = exp(x[0]);
+    // moment of v^(k_al) summed: prod over axes of Z[al][k_al]
+    auto P = [&](const int (&k)[DIM]) {
+      double r = ea;
+#pragma unroll
+      for (int al = 0; al < DIM; ++al) r *= Z[al][k[al]];
+      return r;
+    };
+    // F
+    {
+      int k0[DIM] = {};
+      F[0] = P(k0);
+#pragma unroll
+      for (int be = 0; be < DIM; ++be) {
+        int k[DIM] = {};
+        k[be] = 1;
+        F[1 + be] = P(k);
+      }
+      double e = 0.0;
+#pragma unroll
+      for (int be = 0; be < DIM; ++be) {
+        int k[DIM] = {};
+        k[be] = 2;
+        e += P(k);
+      }
+      F[1 + DIM] = 0.5 * e;
+    }
+    // second moments m2[b][g] = sum w v_b v_g M, third t3[b] = sum w v_b |v|^2 M,
+    // fourth q4 = sum w |v|^4 M
+    double m2[DIM][DIM], t3[DIM], q4 = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+#pragma unroll
+      for (int g = 0; g < DIM; ++g) {
+        int k[DIM] = {};
+        k[b] += 1;
+        k[g] += 1;
+        m2[b][g] = P(k);
+      }
+      double t = 0.0;
+#pragma unroll
+      for (int g = 0; g < DIM; ++g) {
+        int k[DIM] = {};
+        k[b] += 1;
+        k[g] += 2;
+        t += P(k);
+      }
+      t3[b] = t;
+    }
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+      for (int g = 0; g < DIM; ++g) {
+        int k[DIM] = {};
+        k[b] += 2;
+        k[g] += 2;
+        q4 += P(k);
+      }
+    // Jacobian rows: mass, momentum, energy; columns: a, b, c
+    J[0][0] = F[0];
+#pragma unroll
+    for (int be = 0; be < DIM; ++be) J[0][1 + be] = F[1 + be];
+    J[0][1 + DIM] = 2.0 * F[1 + DIM];
+#pragma unroll
+    for (int g = 0; g < DIM; ++g) {
+      J[1 + g][0] = F[1 + g];
+#pragma unroll
+      for (int be = 0; be < DIM; ++be) J[1 + g][1 + be] = m2[g][be];
+      J[1 + g][1 + DIM] = t3[g];
+    }
+    J[1 + DIM][0] = F[1 + DIM];
+#pragma unroll
+    for (int be = 0; be < DIM; ++be) J[1 + DIM][1 + be] = 0.5 * t3[be];
+    J[1 + DIM][1 + DIM] = 0.5 * q4;
+    return;
+  }
+  // general velocity set: direct sums
+#pragma unroll
+  for (int r = 0; r < NM; ++r) {
+    F[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NM; ++c) J[r][c] = 0.0;
+  }
+  for (int j = 0; j < p.n_v; ++j) {
+    double vv[DIM], v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      vv[d] = p.v[(size_t)j * DIM + d];
+      v2 = fma(vv[d], vv[d], v2);
+    }
+    double ex = x[0];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ex = fma(x[1 + d], vv[d], ex);
+    ex = fma(x[1 + DIM], v2, ex);
+    const double wm = p.w[j] * exp(ex);
+    double e[NM], pp[NM];
+    e[0] = 1.0;
+    pp[0] = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) e[1 + d] = pp[1 + d] = vv[d];
+    e[1 + DIM] = 0.5 * v2;
+    pp[1 + DIM] = v2;
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      F[r] = fma(wm, e[r], F[r]);
+#pragma unroll
+      for (int c = 0; c < NM; ++c) J[r][c] = fma(wm * e[r], pp[c], J[r][c]);
+    }
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
+  constexpr int NM = DIM + 2;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= p.n_nodes) return;
+  double U[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) U[m] = p.U[i * NM + m];
+  const double n = U[0];
+  double u[DIM], uu = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    u[d] = U[1 + d] / n;
+    uu = fma(u[d], u[d], uu);
+  }
+  const double th = (2.0 * U[1 + DIM] / n - uu) / DIM;
+  const bool physical = n > 0.0 && th > 0.0 && isfinite(n) && isfinite(th);
+  if (!physical && p.status) atomicAdd(&p.status[1], 1);
+  double nu = p.nu_kind == BGK_NU_CONST ? p.nu_const : n / sqrt(th) / p.kn;
+  if (p.nu) p.nu[i] = nu;
+  if (p.numax && physical) atomicMax(p.numax, (unsigned long long)__double_as_longlong(nu));
+  double x[NM];
+  if (p.mode == BGK_MAXW_LINEAR) {
+    double vol = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vol *= 2.0 * p.L;
+    x[0] = log(n / vol);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) x[1 + d] = 0.0;
+    x[1 + DIM] = 0.0;
+  } else {
+    // DIRECT coefficients
+    x[0] = log(n) - 0.5 * DIM * log(2.0 * M_PI * th) - 0.5 * uu / th;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) x[1 + d] = u[d] / th;
+    x[1 + DIM] = -0.5 / th;
+    if (p.mode == BGK_MAXW_MATCHED && physical) {
+      double Unorm = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) Unorm = fma(U[m], U[m], Unorm);
+      Unorm = sqrt(Unorm);
+      double y[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) y[m] = x[m];
+      bool ok = false;
+      for (int it = 0; it <= 30; ++it) {
+        double F[NM], J[NM][NM];
+        matched_system<DIM>(p, y, F, J);
+        double rn = 0.0;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          F[m] -= U[m];
+          rn = fma(F[m], F[m], rn);
+        }
+        if (sqrt(rn) <= 1e-14 * Unorm) {
+          ok = true;
+          break;
+        }
+        if (!small_solve<NM>(J, F)) break;
+        bool fin = true;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          y[m] -= F[m];
+          fin = fin && isfinite(y[m]);
+        }
+        if (!fin) break;
+      }
+      if (ok && y[1 + DIM] < 0.0) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) x[m] = y[m];
+      } else if (p.status) {
+        atomicAdd(&p.status[0], 1);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NM; ++m) p.coef[i * NM + m] = x[m];
+  if (p.M_dense) {
+    for (int j = 0; j < p.n_v; ++j) {
+      double vv[DIM], v2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        vv[d] = p.v[(size_t)j * DIM + d];
+        v2 = fma(vv[d], vv[d], v2);
+      }
+      p.M_dense[i * p.n_v + j] = maxw_eval<DIM>(x, vv, v2);
+    }
+  }
+}
+
+template <int DIM>
+__global__ void k_coef_from_prim(const double* __restrict__ prim, double* __restrict__ coef,
+                                 int64_t n) {
+  constexpr int NM = DIM + 2;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double nn = prim[i * NM], th = prim[i * NM + 1 + DIM];
+  double uu = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uu = fma(prim[i * NM + 1 + d], prim[i * NM + 1 + d], uu);
+  coef[i * NM] = log(nn) - 0.5 * DIM * log(2.0 * M_PI * th) - 0.5 * uu / th;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) coef[i * NM + 1 + d] = prim[i * NM + 1 + d] / th;
+  coef[i * NM + 1 + DIM] = -0.5 / th;
+}
+
+// velocity lanes per cell for the moment kernel: enough blocks to fill the chip
+int moment_vl(const tgs_dag* d) {
+  const int64_t nc = d->n_cells;
+  if (nc >= 65536) return 1;
+  if (nc >= 16384) return 4;
+  return 16;
+}
+
+int moment_blocks(const tgs_dag* d) {
+  const int vl = moment_vl(d);
+  const int cb = MOM_THREADS / vl;
+  return (int)((d->n_cells + cb - 1) / cb);
+}
+
+int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
+                   double* partial, double* ratio_out, hipStream_t stream) {
+  MomArgs a{f, d->d_pos, d->d_uid, d->d_v, d->d_w, U, U_prev, partial, (int)d->n_cells, d->n_v};
+  const int vl = moment_vl(d);
+  const dim3 grid(moment_blocks(d)), block(MOM_THREADS);
+#define BGK_MOM(D_, P_)                                                                   \
+  do {                                                                                    \
+    if (vl == 1) hipLaunchKernelGGL((k_moments<D_, P_, 1>), grid, block, 0, stream, a);   \
+    else if (vl == 4) hipLaunchKernelGGL((k_moments<D_, P_, 4>), grid, block, 0, stream, a); \
+    else hipLaunchKernelGGL((k_moments<D_, P_, 16>), grid, block, 0, stream, a);          \
+  } while (0)
+  if (d->dim == 2 && d->order == 1)
+    BGK_MOM(2, 3);
+  else if (d->dim == 2)
+    BGK_MOM(2, 6);
+  else
+    BGK_MOM(3, 4);
+#undef BGK_MOM
+  BGK_HIP(hipGetLastError());
+  if (U_prev && ratio_out) {
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, (int)grid.x, ratio_out);
+    BGK_HIP(hipGetLastError());
+  }
+  return BGK_OK;
+}
+
+int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
+                      double* coef, double* nu, double* M_dense, int32_t* status,
+                      unsigned long long* numax, hipStream_t stream) {
+  BGK_CHECK(mode == BGK_MAXW_DIRECT || mode == BGK_MAXW_MATCHED || mode == BGK_MAXW_LINEAR,
+            BGK_E_INVALID, "unknown Maxwellian mode");
+  BGK_CHECK(nm && (nm->kind == BGK_NU_CONST || (nm->kind == BGK_NU_KN && nm->kn > 0)),
+            BGK_E_INVALID, "bad collision-frequency model");
+  BGK_CHECK(mode != BGK_MAXW_LINEAR || d->L > 0, BGK_E_INVALID,
+            "LINEAR mode needs the velocity box half-width L");
+  MaxwArgs p{U,      coef,     nu,          M_dense,       status, numax,
+             d->d_v, d->d_w,   d->d_nodes1d, d->d_weights1d, d->n_1d, d->n_v,
+             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L};
+  const dim3 grid((unsigned)((d->n_nodes + 127) / 128)), block(128);
+  if (d->dim == 2)
+    hipLaunchKernelGGL(k_maxwellian<2>, grid, block, 0, stream, p);
+  else
+    hipLaunchKernelGGL(k_maxwellian<3>, grid, block, 0, stream, p);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+}  // namespace bgk
+
+using namespace bgk;
+
+extern "C" int moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
+                       double* rel3, bgk_stream_t stream) {
+  if (!d || !f || !U) return fail(BGK_E_INVALID, "null argument");
+  if ((U_prev == nullptr) != (rel3 == nullptr))
+    return fail(BGK_E_INVALID, "U_prev and rel3 go together");
+  double* partial = nullptr;
+  double* ratio = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (U_prev) {
+    if (hipMallocAsync((void**)&partial, (size_t)moment_blocks(d) * 6 * sizeof(double), s) !=
+            hipSuccess ||
+        hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)
+      return fail(BGK_E_NOMEM, "scratch allocation failed");
+  }
+  int rc = launch_moments(d, f, U, U_prev, partial, ratio, s);
+  if (rc == BGK_OK && U_prev) {
+    if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      rc = fail(BGK_E_HIP, "copy of ratios failed");
+  }
+  if (partial) (void)hipFreeAsync(partial, s);
+  if (ratio) (void)hipFreeAsync(ratio, s);
+  return rc;
+}
+
+extern "C" int maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
+                          double* coef, double* nu, double* M_dense, int32_t* status,
+                          bgk_stream_t stream) {
+  if (!d || !U || !coef || !nu) return fail(BGK_E_INVALID, "null argument");
+  return launch_maxwellian(d, mode, U, nm, coef, nu, M_dense, status, nullptr,
+                           (hipStream_t)stream);
+}
+
+extern "C" int maxwellian_coef_from_primitive(int dim, int64_t n, const double* prim, double* coef,
+                                              bgk_stream_t stream) {
+  if (!prim || !coef || n < 0 || (dim != 2 && dim != 3))
+    return fail(BGK_E_INVALID, "bad arguments");
+  if (n == 0) return BGK_OK;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_coef_from_prim<2>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
+  else
+    hipLaunchKernelGGL(k_coef_from_prim<3>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}

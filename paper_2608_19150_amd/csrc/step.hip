@@ -1,0 +1,341 @@
+// bgk_step: one DIRK time step (Sec. 3.5, App. A) whose stages are solved by
+// the sweep-based Picard iteration (Sec. 4) with the stopping rule of
+// eq. convergence-criteria.
+//
+// Stage bookkeeping (eq. q-stages, eq. dirk-recursive-def, eq. dirk-n) is
+// carried as linear combinations over {f^k, f^(1), ..., f^(S)}:
+//   F^(r) = f^(r)/(dt A_rr) - q^(r),
+//   q^(s) = (f^k + dt sum_{r<s} A_sr F^(r)) / (dt A_ss),
+//   f^{k+1} = f^k + dt sum_s b_s F^(s)   (= f^(S) for stiffly accurate tableaus).
+// The first stage's source is f^k itself scaled inside the sweep (no extra
+// pass); later stages materialise q^(s) with one fused combination kernel.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "device_common.h"
+
+namespace bgk {
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, float* d32, hipStream_t stream);
+int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
+                   double* partial, double* ratio_out, hipStream_t stream);
+int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
+                      double* coef, double* nu, double* M_dense, int32_t* status,
+                      unsigned long long* numax, hipStream_t stream);
+int moment_blocks(const tgs_dag* d);
+
+// out = sum_i c_i x_i (up to 5 inputs), grid-stride, vectorised by 2
+__global__ void k_combine(double* __restrict__ out, const double* __restrict__ x0,
+                          const double* __restrict__ x1, const double* __restrict__ x2,
+                          const double* __restrict__ x3, const double* __restrict__ x4, double c0,
+                          double c1, double c2, double c3, double c4, int nin, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double s = c0 * x0[i];
+    if (nin > 1) s = fma(c1, x1[i], s);
+    if (nin > 2) s = fma(c2, x2[i], s);
+    if (nin > 3) s = fma(c3, x3[i], s);
+    if (nin > 4) s = fma(c4, x4[i], s);
+    out[i] = s;
+  }
+}
+
+// zero the per-iteration status words (a kernel, so the sequence stays
+// capturable in a graph)
+__global__ void k_reset(int32_t* status, unsigned long long* numax) {
+  if (threadIdx.x == 0) {
+    status[0] = 0;
+    status[1] = 0;
+    *numax = 0ull;
+  }
+}
+
+}  // namespace bgk
+
+using namespace bgk;
+
+struct bgk_solver {
+  const tgs_dag* dag = nullptr;
+  bgk_solver_opts opts{};
+  int S = 1;
+  double A[4][4] = {}, b[4] = {}, c[4] = {};
+  bool stiffly_accurate = true;
+  // linear-combination coefficients over {f^k, f^(1..S)}
+  double qcoef[4][5] = {}, Fcoef[4][5] = {}, ncoef[5] = {};
+  double* fk = nullptr;          // copy of f^k
+  double* fst[4] = {};           // converged stage values
+  double* fping = nullptr;       // previous iterate (lagged facets / FP32 form)
+  double* q = nullptr;           // stage source
+  float* d32 = nullptr;          // FP32 correction traces
+  double* U[2] = {};             // moments ping-pong
+  double* mcoef = nullptr;
+  double* nu = nullptr;
+  double* partial = nullptr;
+  double* ratio = nullptr;       // [4]
+  int32_t* status = nullptr;     // [2]
+  unsigned long long* numax = nullptr;
+  // pinned host mirror: ratio[4], numax bits, status[2]
+  double* h_info = nullptr;
+};
+
+namespace {
+
+int set_tableau(bgk_solver* s, int tab) {
+  std::memset(s->A, 0, sizeof(s->A));
+  if (tab == BGK_TAB_BE) {
+    s->S = 1;
+    s->A[0][0] = 1.0;
+    s->b[0] = 1.0;
+  } else if (tab == BGK_TAB_DIRK2) {
+    const double g = 1.0 - std::sqrt(2.0) / 2.0;
+    s->S = 2;
+    s->A[0][0] = g;
+    s->A[1][0] = std::sqrt(2.0) / 2.0;
+    s->A[1][1] = g;
+    s->b[0] = s->A[1][0];
+    s->b[1] = g;
+  } else if (tab == BGK_TAB_DIRK3) {
+    // gamma: the root of x^3 - 3x^2 + 3x/2 - 1/6 in (0.4, 0.5), by bisection
+    double lo = 0.4, hi = 0.5;
+    for (int i = 0; i < 200; ++i) {
+      const double m = 0.5 * (lo + hi);
+      if (m * m * m - 3 * m * m + 1.5 * m - 1.0 / 6.0 > 0) lo = m; else hi = m;
+    }
+    const double g = 0.5 * (lo + hi);
+    s->S = 3;
+    s->A[0][0] = s->A[1][1] = s->A[2][2] = g;
+    s->A[1][0] = 0.5 * (1.0 - g);
+    s->A[2][0] = -(6 * g * g - 16 * g + 1) / 4.0;
+    s->A[2][1] = (6 * g * g - 20 * g + 5) / 4.0;
+    for (int i = 0; i < 3; ++i) s->b[i] = s->A[2][i];
+  } else if (tab == BGK_TAB_BDIRK2) {
+    const double g = (3.0 + std::sqrt(3.0)) / 6.0;
+    s->S = 2;
+    s->A[0][0] = s->A[1][1] = g;
+    s->A[1][0] = 1.0 - 2.0 * g;
+    s->b[0] = s->b[1] = 0.5;
+  } else {
+    return fail(BGK_E_INVALID, "unknown tableau");
+  }
+  s->stiffly_accurate = true;
+  for (int i = 0; i < s->S; ++i)
+    if (s->b[i] != s->A[s->S - 1][i]) s->stiffly_accurate = false;
+  // combination coefficients
+  const double dt = s->opts.dt;
+  std::memset(s->qcoef, 0, sizeof(s->qcoef));
+  std::memset(s->Fcoef, 0, sizeof(s->Fcoef));
+  std::memset(s->ncoef, 0, sizeof(s->ncoef));
+  for (int st = 0; st < s->S; ++st) {
+    double acc[5] = {1.0, 0, 0, 0, 0};
+    for (int r = 0; r < st; ++r)
+      for (int i = 0; i < 5; ++i) acc[i] += dt * s->A[st][r] * s->Fcoef[r][i];
+    for (int i = 0; i < 5; ++i) s->qcoef[st][i] = acc[i] / (dt * s->A[st][st]);
+    for (int i = 0; i < 5; ++i) s->Fcoef[st][i] = -s->qcoef[st][i];
+    s->Fcoef[st][1 + st] += 1.0 / (dt * s->A[st][st]);
+  }
+  s->ncoef[0] = 1.0;
+  for (int st = 0; st < s->S; ++st)
+    for (int i = 0; i < 5; ++i) s->ncoef[i] += dt * s->b[st] * s->Fcoef[st][i];
+  return BGK_OK;
+}
+
+template <typename T>
+int dmalloc(T** p, size_t n) {
+  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return fail(BGK_E_NOMEM, "solver workspace allocation failed");
+  }
+  return BGK_OK;
+}
+
+int combine(double* out, const double* const* xs, const double* cs, int nin, size_t n,
+            hipStream_t stream) {
+  const double* x[5] = {xs[0], nin > 1 ? xs[1] : xs[0], nin > 2 ? xs[2] : xs[0],
+                        nin > 3 ? xs[3] : xs[0], nin > 4 ? xs[4] : xs[0]};
+  double c[5] = {cs[0], nin > 1 ? cs[1] : 0, nin > 2 ? cs[2] : 0, nin > 3 ? cs[3] : 0,
+                 nin > 4 ? cs[4] : 0};
+  const int grid = (int)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), 0, stream, out, x[0], x[1], x[2], x[3],
+                     x[4], c[0], c[1], c[2], c[3], c[4], nin, n);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+}  // namespace
+
+extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk_solver** out) {
+  if (!d || !o || !out) return fail(BGK_E_INVALID, "null argument");
+  *out = nullptr;
+  if (!(o->dt > 0) || !(o->tau > 0) || o->l_max <= 0)
+    return fail(BGK_E_INVALID, "dt, tau and l_max must be positive");
+  if (!o->bc_coef) return fail(BGK_E_INVALID, "bc_coef is required");
+  if (o->precision != TGS_FP64 && o->precision != TGS_FP32_CORRECTION)
+    return fail(BGK_E_INVALID, "unknown precision");
+  bgk_solver* s = new (std::nothrow) bgk_solver();
+  if (!s) return fail(BGK_E_NOMEM, "host allocation failed");
+  s->dag = d;
+  s->opts = *o;
+  int rc = set_tableau(s, o->tableau);
+  const size_t nf = f_elems(d);
+  const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
+  if (!rc) rc = dmalloc(&s->fk, nf);
+  for (int i = 0; i + 1 < s->S && !rc; ++i) rc = dmalloc(&s->fst[i], nf);
+  if (!rc && !s->stiffly_accurate) rc = dmalloc(&s->fst[s->S - 1], nf);
+  if (!rc && s->S > 1) rc = dmalloc(&s->q, nf);
+  if (!rc && (d->d_lag || o->precision == TGS_FP32_CORRECTION)) rc = dmalloc(&s->fping, nf);
+  if (!rc && o->precision == TGS_FP32_CORRECTION) rc = dmalloc(&s->d32, nf);
+  if (!rc) rc = dmalloc(&s->U[0], nn);
+  if (!rc) rc = dmalloc(&s->U[1], nn);
+  if (!rc) rc = dmalloc(&s->mcoef, nn);
+  if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
+  if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
+  if (!rc) rc = dmalloc(&s->ratio, 4);
+  if (!rc) rc = dmalloc(&s->status, 2);
+  if (!rc) rc = dmalloc(&s->numax, 1);
+  if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
+    rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
+  if (rc) {
+    bgk_solver_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return BGK_OK;
+}
+
+extern "C" int bgk_solver_destroy(bgk_solver* s) {
+  if (!s) return BGK_OK;
+  void* ptrs[] = {s->fk, s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping, s->q, s->d32,
+                  s->U[0], s->U[1], s->mcoef, s->nu, s->partial, s->ratio, s->status, s->numax};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->h_info) (void)hipHostFree(s->h_info);
+  delete s;
+  return BGK_OK;
+}
+
+extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double* U_out,
+                        bgk_step_stats* stats, bgk_stream_t stream_) {
+  if (!s || !f) return fail(BGK_E_INVALID, "null argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  const tgs_dag* d = s->dag;
+  const bgk_solver_opts& o = s->opts;
+  hipStream_t stream = (hipStream_t)stream_;
+  const size_t nf = f_elems(d);
+  const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
+  const bool need_prev = d->d_lag != nullptr || o.precision == TGS_FP32_CORRECTION;
+  bgk_step_stats st{};
+  st.stages = s->S;
+  int rc;
+  // keep f^k; the last stage of a stiffly accurate tableau writes into f
+  BGK_HIP(hipMemcpyAsync(s->fk, f, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  double* fst[4] = {s->fst[0], s->fst[1], s->fst[2], s->fst[3]};
+  if (s->stiffly_accurate) fst[s->S - 1] = f;
+  const double* stage_init = s->fk;   // initial Picard iterate of the stage
+  int ucur = 0;
+  if (U_guess) {
+    BGK_HIP(hipMemcpyAsync(s->U[0], U_guess, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  } else {
+    if ((rc = launch_moments(d, s->fk, s->U[0], nullptr, nullptr, nullptr, stream))) return rc;
+  }
+  for (int stg = 0; stg < s->S; ++stg) {
+    const double shift = 1.0 / (o.dt * s->A[stg][stg]);
+    const double* qsrc;
+    double qscale;
+    if (stg == 0) {
+      qsrc = s->fk;
+      qscale = s->qcoef[0][0];
+    } else {
+      const double* xs[5] = {s->fk, fst[0], fst[1], fst[2], fst[3]};
+      if ((rc = combine(s->q, xs, s->qcoef[stg], stg + 1, nf, stream))) return rc;
+      qsrc = s->q;
+      qscale = 1.0;
+    }
+    double* out = fst[stg];
+    // with lagged facets or the FP32 form the previous iterate is kept in
+    // fping; the first iteration reads the stage's initial iterate
+    const double* prev = stage_init;
+    double* cur_out = out;
+    int it = 0;
+    bool converged = false;
+    double last = 0.0;
+    while (it < o.l_max) {
+      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
+      if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
+                                  nullptr, s->status, s->numax, stream)))
+        return rc;
+      if (need_prev) cur_out = (prev == out) ? s->fping : out;
+      tgs_sweep_io io{};
+      io.precision = o.precision;
+      io.sigma_shift = shift;
+      io.q_scale = qscale;
+      io.nu = s->nu;
+      io.mcoef = s->mcoef;
+      io.q = qsrc;
+      io.bc_coef = o.bc_coef;
+      io.f_prev = need_prev ? prev : nullptr;
+      io.f_out = cur_out;
+      if ((rc = launch_sweep(d, &io, s->d32, stream))) return rc;
+      if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
+                               stream)))
+        return rc;
+      BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             stream));
+      BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, stream));
+      BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             stream));
+      BGK_HIP(hipStreamSynchronize(stream));
+      ++it;
+      ucur ^= 1;
+      prev = cur_out;
+      int32_t stat[2];
+      std::memcpy(stat, s->h_info + 5, sizeof(stat));
+      st.maxw_fallbacks += stat[0];
+      if (stat[1] > 0) {
+        return fail(BGK_E_NONPHYSICAL,
+                    "non-physical moments (n <= 0 or theta <= 0) at " + std::to_string(stat[1]) +
+                        " nodes");
+      }
+      double numax;
+      std::memcpy(&numax, s->h_info + 4, sizeof(double));
+      last = s->h_info[3];
+      if (!std::isfinite(last))
+        return fail(BGK_E_NONPHYSICAL, "non-finite moments in the Picard iteration");
+      if (o.fixed_iters > 0) {
+        if (it >= o.fixed_iters) {
+          converged = true;
+          break;
+        }
+        continue;
+      }
+      if (last < o.tau / std::max(1.0, numax * o.dt)) {
+        converged = true;
+        break;
+      }
+    }
+    if (prev != out) {
+      BGK_HIP(hipMemcpyAsync(out, prev, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+    st.iters[stg] = it;
+    st.last_ratio[stg] = last;
+    st.total_iters += it;
+    if (!converged) {
+      if (stats) *stats = st;
+      return fail(BGK_E_NOT_CONVERGED, "Picard iteration reached l_max in stage " +
+                                           std::to_string(stg + 1));
+    }
+    stage_init = out;
+  }
+  if (!s->stiffly_accurate) {
+    const double* xs[5] = {s->fk, fst[0], fst[1], fst[2], fst[3]};
+    if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
+    if (U_out && (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream)))
+      return rc;
+  }
+  if (U_out)
+    BGK_HIP(hipMemcpyAsync(U_out, s->U[ucur], nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  BGK_HIP(hipStreamSynchronize(stream));
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return BGK_OK;
+}

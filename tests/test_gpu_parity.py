@@ -1,0 +1,285 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Error measure (design note A21): max-norm error over the whole array divided
+by the max norm of the oracle's array; 1e-12 for every FP64 result.
+Generations are integers and must match exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import problems as P
+from oracle import dag as odag
+from oracle import geometry, kinetic, solver, transport
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+import paper_2608_19150_amd as B  # noqa: E402
+
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def _problem(dim, order, n_side, n1, seed=7, state="sod"):
+    return P.small_problem(dim=dim, order=order, n_side=n_side, n_1d=n1, seed=seed, state=state)
+
+
+CASES = [(2, 1, 5, 6), (2, 2, 4, 5), (3, 1, 3, 4)]
+
+
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+def test_generations_match_oracle(dim, order, n_side, n1):
+    say("generations", dim, order, n_side, n1)
+    pr = _problem(dim, order, n_side, n1)
+    d = B.Dag.from_problem(pr)
+    gen, G = d.generations()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, order)
+    ogen, olag = odag.build_all(geo, pr.vgrid.v)
+    assert not olag.any() and d.n_lagged == 0
+    np.testing.assert_array_equal(gen, ogen)
+    np.testing.assert_array_equal(G, ogen.max(axis=1) + 1)
+
+
+def test_generations_c1_match_oracle():
+    pr = P.config_c1()
+    d = B.Dag.from_problem(pr)
+    gen, _ = d.generations()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, 1)
+    ogen, _ = odag.build_all(geo, pr.vgrid.v)
+    np.testing.assert_array_equal(gen, ogen)
+
+
+def test_pack_unpack_roundtrip():
+    pr = _problem(2, 2, 4, 5)
+    d = B.Dag.from_problem(pr)
+    x = torch.randn(d.f_shape, dtype=torch.float64, device="cuda")
+    y = d.unpack(d.pack(x))
+    assert torch.equal(x, y)
+
+
+def _random_sweep_inputs(pr, seed):
+    rng = np.random.default_rng(seed)
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    nv = pr.vgrid.n_v
+    dim = geo.dim
+    q = rng.uniform(0.0, 1.0, (geo.n_cells, geo.n_p, nv))
+    nu = rng.uniform(0.1, 2.0, (geo.n_cells, geo.n_p))
+    n = rng.uniform(0.2, 1.5, (geo.n_cells, geo.n_p))
+    u = rng.uniform(-0.5, 0.5, (geo.n_cells, geo.n_p, dim))
+    th = rng.uniform(0.6, 1.4, (geo.n_cells, geo.n_p))
+    prim = np.concatenate([n[..., None], u, th[..., None]], axis=-1)
+    return geo, q, nu, prim
+
+
+def _gpu_sweep(d, pr, q, nu, prim, shift, qscale, bc_dense=None, f_prev=None, precision=0):
+    qg = d.pack(B._dev(q))
+    mcoef = B.maxwellian_coef_from_primitive(B._dev(prim.reshape(-1, d.dim + 2)), d.dim)
+    bc = None if bc_dense is not None else B.state_coefficients(d, pr.state, "boundary")
+    fo = torch.empty_like(qg)
+    fp = d.pack(B._dev(f_prev)) if f_prev is not None else None
+    B.tgs_sweep(d, q=qg, nu=B._dev(nu.reshape(-1)), mcoef=mcoef, f_out=fo, sigma_shift=shift,
+                q_scale=qscale, bc_coef=bc, bc_dense=None if bc_dense is None else B._dev(bc_dense),
+                f_prev=fp, precision=precision)
+    return d.unpack(fo).cpu().numpy()
+
+
+def _oracle_sweep(geo, pr, q, nu, prim, shift, qscale, gens, lags=None, f_prev=None, gbc=None):
+    V = pr.vgrid.v
+    coef = kinetic.direct_coefficients(prim[..., 0], prim[..., 1:-1], prim[..., -1])
+    Mv = kinetic.coef_values(coef, V)
+    g = solver.boundary_values(geo, V, pr.state) if gbc is None else gbc
+    return transport.sweep(geo, V, nu + shift, nu, Mv, qscale * q, g, gens, lags, f_prev)
+
+
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+def test_sweep_fp64_matches_oracle(dim, order, n_side, n1):
+    say("sweep fp64", dim, order, n_side, n1)
+    pr = _problem(dim, order, n_side, n1, state="riemann")
+    d = B.Dag.from_problem(pr)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 3)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 37.0, 2.5)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 37.0, 2.5, gens)
+    assert rel(f_gpu, f_ref) <= TOL64
+
+
+def test_sweep_fp64_c1_size_matches_oracle():
+    pr = P.config_c1()
+    d = B.Dag.from_problem(pr)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 4)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 191.0, 191.0)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 191.0, 191.0, gens)
+    assert rel(f_gpu, f_ref) <= TOL64
+
+
+def test_sweep_dense_boundary_matches_oracle():
+    pr = _problem(2, 2, 3, 4)
+    d = B.Dag.from_problem(pr)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 5)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    gbc = np.random.default_rng(6).uniform(0, 1, (geo.bnode_x.shape[0], geo.n_fp, pr.vgrid.n_v))
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 5.0, 1.0, bc_dense=gbc)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 5.0, 1.0, gens, gbc=gbc)
+    assert rel(f_gpu, f_ref) <= TOL64
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 1)])
+def test_sweep_with_lagged_facets_matches_oracle(dim, order):
+    say("sweep lagged", dim, order)
+    pr = _problem(dim, order, 3, 4)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 8)
+    V = pr.vgrid.v
+    rng = np.random.default_rng(12)
+    lags = np.zeros((V.shape[0], geo.n_cells, dim + 1), dtype=bool)
+    bits = np.zeros((V.shape[0], geo.n_cells), dtype=np.uint8)
+    for j in range(V.shape[0]):
+        s = odag.facet_speeds(geo, V[j])
+        lags[j] = (s < 0) & (geo.nbr >= 0) & (rng.uniform(size=s.shape) < 0.3)
+        for k in range(dim + 1):
+            bits[j] |= (lags[j][:, k].astype(np.uint8) << k)
+    d = B.Dag.from_problem(pr, lagged=bits)
+    assert d.n_lagged == int(lags.sum())
+    np.testing.assert_array_equal(d.lagged(), bits)
+    gens, _ = odag.build_all(geo, V, lagged=lags)
+    gen_gpu, _ = d.generations()
+    np.testing.assert_array_equal(gen_gpu, gens)
+    f_prev = rng.uniform(0, 1, (geo.n_cells, geo.n_p, V.shape[0]))
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 3.0, 1.0, f_prev=f_prev)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 3.0, 1.0, gens, lags, f_prev)
+    assert rel(f_gpu, f_ref) <= TOL64
+
+
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+def test_moments_and_ratios_match_oracle(dim, order, n_side, n1):
+    pr = _problem(dim, order, n_side, n1)
+    d = B.Dag.from_problem(pr)
+    rng = np.random.default_rng(2)
+    f = rng.uniform(0, 1, d.f_shape)
+    f_old = f * (1 + 1e-3 * rng.normal(size=f.shape))
+    fs = d.pack(B._dev(f))
+    U_old = B.moments(d, d.pack(B._dev(f_old)))
+    U, ratio = B.moments(d, fs, U_prev=U_old)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    Uref = kinetic.moments(f, V, w).reshape(-1, dim + 2)
+    Uold_ref = kinetic.moments(f_old, V, w).reshape(-1, dim + 2)
+    assert rel(U.cpu().numpy(), Uref) <= TOL64
+    rref = solver.relative_changes(Uref, Uold_ref, dim)
+    assert np.allclose(ratio.cpu().numpy(), rref, rtol=1e-9)
+    # bitwise reproducible
+    U2 = B.moments(d, fs)
+    assert torch.equal(U, U2)
+
+
+@pytest.mark.parametrize("mode", ["DIRECT", "MATCHED", "LINEAR"])
+@pytest.mark.parametrize("dim,n1", [(2, 16), (3, 10)])
+def test_maxwellian_matches_oracle(mode, dim, n1):
+    pr = _problem(dim, 1, 2, n1)
+    d = B.Dag.from_problem(pr)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    rng = np.random.default_rng(4)
+    nn = d.n_nodes
+    n = rng.uniform(0.1, 1.5, nn)
+    u = rng.uniform(-1.0, 1.0, (nn, dim))
+    th = rng.uniform(0.5, 2.0, nn)
+    f = kinetic.maxwellian_values(n, u, th, V) * (1 + 0.1 * np.cos(V[:, 0]))[None]
+    U = kinetic.moments(f, V, w)
+    coef, nu, Md, status = B.maxwellian(d, B._dev(U), mode=mode,
+                                        nu_model="kn", kn=0.01, dense=True)
+    ref, nfb = solver.maxwellian_coefficients(U, V, w, mode, pr.vgrid.L)
+    assert nfb == 0 and int(status[0]) == 0 and int(status[1]) == 0
+    assert rel(coef.cpu().numpy(), ref) <= 1e-12
+    assert rel(Md.cpu().numpy(), kinetic.coef_values(ref, V)) <= 1e-12
+    nu_ref = kinetic.collision_frequency(U, dim, "kn", kn=0.01)
+    assert rel(nu.cpu().numpy(), nu_ref) <= 1e-14
+    if mode == "MATCHED":
+        Um = kinetic.moments(Md.cpu().numpy(), V, w)
+        assert rel(Um, U) <= 1e-13
+
+
+def _run_steps(pr, nsteps, *, mode="MATCHED", fixed_iters=0, tau=1e-10, precision=0):
+    d, f0, bc, dt = B.problem_setup(pr)
+    s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=tau, fixed_iters=fixed_iters,
+                 precision=precision, mode=mode, nu_model=pr.nu_model, nu_const=pr.nu_const,
+                 kn=pr.kn)
+    f = f0
+    stats = []
+    for _ in range(nsteps):
+        stats.append(s.step(f))
+    return d, d.unpack(f).cpu().numpy(), stats, dt
+
+
+def _oracle_steps(pr, nsteps, dt, *, mode="MATCHED", fixed_iters=None, tau=1e-10):
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    gens, lags = odag.build_all(geo, V)
+    f = solver.initial_condition(geo, V, pr.state)
+    g = solver.boundary_values(geo, V, pr.state)
+    stats = []
+    for _ in range(nsteps):
+        f, st = solver.bgk_step(geo, V, w, f, g, dt, gens, lags, scheme=pr.tableau, mode=mode,
+                                nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn, tau=tau,
+                                fixed_iters=fixed_iters, L=pr.vgrid.L)
+        stats.append(st)
+    return geo, f, stats
+
+
+def test_bgk_step_c1_fixed_iterations_matches_oracle():
+    say("bgk_step c1 fixed")
+    pr = P.config_c1()
+    d, f, st, dt = _run_steps(pr, 2, fixed_iters=3)
+    geo, fref, _ = _oracle_steps(pr, 2, dt, fixed_iters=3)
+    assert rel(f, fref) <= TOL64
+
+
+def test_bgk_step_c1_converged_matches_oracle():
+    say("bgk_step c1 converged")
+    pr = P.config_c1()
+    d, f, st, dt = _run_steps(pr, 5)
+    geo, fref, ost = _oracle_steps(pr, 5, dt)
+    assert [s["iters"] for s in st] == [s["iters"] for s in ost]
+    assert rel(f, fref) <= TOL64
+
+
+@pytest.mark.parametrize("tableau", ["DIRK2", "DIRK3", "BDIRK2"])
+def test_bgk_step_dirk_kn_matches_oracle(tableau):
+    say("bgk_step", tableau)
+    pr = P.small_problem(order=2, n_side=4, n_1d=8, state="fourier", nu_model="kn", kn=0.05,
+                         tableau=tableau)
+    d, f, st, dt = _run_steps(pr, 2, fixed_iters=4)
+    geo, fref, _ = _oracle_steps(pr, 2, dt, fixed_iters=4)
+    assert rel(f, fref) <= TOL64
+
+
+def test_bgk_step_3d_matches_oracle():
+    pr = P.small_problem(dim=3, order=1, n_side=3, n_1d=6, state="riemann", nu_model="kn", kn=0.1)
+    d, f, st, dt = _run_steps(pr, 2, fixed_iters=3)
+    geo, fref, _ = _oracle_steps(pr, 2, dt, fixed_iters=3)
+    assert rel(f, fref) <= TOL64
+
+
+def test_uniform_maxwellian_preserved_on_gpu():
+    pr = P.small_problem(n_side=4, n_1d=8, state="uniform")
+    d, f0, bc, dt = B.problem_setup(pr)
+    f_init = d.unpack(f0).cpu().numpy()
+    s = B.Solver(d, dt=dt, bc_coef=bc)
+    f = f0
+    for _ in range(5):
+        st = s.step(f)
+        assert st["iters"] == [1]
+    assert rel(d.unpack(f).cpu().numpy(), f_init) <= 1e-13
