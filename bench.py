@@ -1,0 +1,210 @@
+"""Benchmark: DG unknowns swept per second for implicit BGK time steps on one MI355X.
+
+Workload (the 2D x 2D at-scale configuration): a seeded ~200k-triangle
+Delaunay mesh of the unit square, graded 4x finer at the centre; P2 DG
+(6 nodes per cell); 32x32 trapezoid velocity grid on [-8,8]^2; collision
+frequency nu = n theta^{-1/2}/Kn with Kn = 1e-2; initial data a seeded
+8-mode Fourier perturbation (10%) of (1, 0, 1); two-stage L-stable DIRK at
+CFL 10; Picard iteration to tau = 1e-10 on the moments.  Synthetic, seeded
+inputs stand in for the paper's meshes.
+
+A timed "step" is one full DIRK time step (all stages, every Picard
+iteration: Maxwellian rebuild, sweep, moments, stopping test, stage
+bookkeeping) with the state resident in HBM.  value = phase-space unknowns
+swept per second over the timed steps = N_c * N_p * N_v * (sweeps) / time.
+
+Extra JSON fields: the FP32-solve + FP64-refinement form on the same
+workload (its rate, iterations and the moment error against the FP64 run),
+the sweep kernel's roofline (algorithmic 16 B per unknown: read the stage
+source, write the new iterate) from HIP events inside the library, and the
+FP64 CPU oracle's sweep rate on a bounded sample of velocities.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_PER_UNKNOWN = 16.0
+
+
+def _oracle_worker_init(state):
+    global _ORACLE_STATE
+    _ORACLE_STATE = state
+
+
+def _oracle_dag(j):
+    from oracle import dag
+    geo, V = _ORACLE_STATE["geo"], _ORACLE_STATE["V"]
+    order, lag = dag.dfs_order(geo, V[j])
+    return dag.generations(geo, V[j], lag, order)
+
+
+def _oracle_sweep(args):
+    from oracle import transport
+    j, gen = args
+    st = _ORACLE_STATE
+    geo, V = st["geo"], st["V"]
+    rng = np.random.default_rng(j)
+    nc, npn = geo.n_cells, geo.n_p
+    sig = np.full((nc, npn), st["sigma"])
+    nu = np.full((nc, npn), st["nu"])
+    Mv = rng.uniform(0.0, 1.0, (nc, npn, 1))
+    q = rng.uniform(0.0, 1.0, (nc, npn, 1))
+    g = np.zeros((geo.bnode_x.shape[0], geo.n_fp, 1))
+    t0 = time.perf_counter()
+    transport.sweep(geo, V[j:j + 1], sig, nu, Mv, q, g, gen[None])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(pr, n_vel, dt):
+    """The oracle's sweep on `n_vel` sampled velocities of the same mesh, one
+    velocity per worker process; returns unknowns swept per second."""
+    import multiprocessing as mp
+
+    from oracle import geometry
+    cores = min(16, len(os.sched_getaffinity(0)))
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    rng = np.random.default_rng(99)
+    js = np.sort(rng.choice(pr.vgrid.n_v, size=n_vel, replace=False))
+    state = {"geo": geo, "V": pr.vgrid.v, "sigma": 1.0 / dt, "nu": 100.0}
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_oracle_worker_init, initargs=(state,)) as pool:
+        gens = pool.map(_oracle_dag, list(js))
+        t0 = time.perf_counter()
+        times = pool.map(_oracle_sweep, list(zip(js, gens)))
+        wall = time.perf_counter() - t0
+    unknowns = geo.n_cells * geo.n_p * n_vel
+    return {"value": unknowns / wall, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle sweep of {n_vel} sampled velocities on the full mesh "
+                      f"({geo.n_cells} cells, P{pr.order}), one velocity per process; "
+                      f"{sum(times):.1f} s of CPU work"}
+
+
+def run_gpu(pr, steps, warmup, precision, timing=True):
+    import torch
+
+    import paper_2608_19150_amd as B
+    t0 = time.perf_counter()
+    d, f, bc, dt = B.problem_setup(pr)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, precision=precision,
+                 mode="MATCHED", nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn,
+                 timing=timing)
+    for _ in range(warmup):
+        s.step(f)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(s.step(f))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    U = B.moments(d, f)
+    n_unknown = d.n_cells * d.n_p * d.n_v
+    sweeps = sum(st["sweeps"] for st in stats)
+    sweep_ms = sum(st["sweep_ms"] for st in stats)
+    out = {
+        "elapsed": elapsed, "sweeps": sweeps, "n_unknown": n_unknown, "dt": dt,
+        "value": n_unknown * sweeps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+        "iters": [st["iters"] for st in stats], "setup_s": setup_s,
+        "sweep_ms_avg": sweep_ms / max(sweeps, 1),
+        "moments_ms_avg": sum(st["moments_ms"] for st in stats) / max(sweeps, 1),
+        "maxwellian_ms_avg": sum(st["maxwellian_ms"] for st in stats) / max(sweeps, 1),
+        "max_G": d.max_G, "n_cells": d.n_cells, "n_p": d.n_p, "n_v": d.n_v,
+        "fallbacks": sum(st["fallbacks"] for st in stats),
+    }
+    out["U"] = U.cpu().numpy()
+    del s, f, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def moment_error(U, Uref, dim):
+    """Per component: |U_m - Uref_m| / max(|Uref_m|, s_m |Uref_0|), s = (0,1,0)."""
+    blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
+    n0 = np.linalg.norm(Uref[:, 0])
+    errs = []
+    for m, sl in enumerate(blocks):
+        den = np.linalg.norm(Uref[:, sl])
+        if m == 1:
+            den = max(den, n0)
+        errs.append(float(np.linalg.norm(U[:, sl] - Uref[:, sl]) / den))
+    return errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-side", type=int, default=316,
+                    help="mesh lattice size (2*n^2 triangles; 316 -> 199,712)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-velocities", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import problems as P
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    pr = P.config_c2(args.n_side)
+    print(f"[bench] workload {pr.name}: building", file=sys.stderr, flush=True)
+    r64 = run_gpu(pr, args.steps, args.warmup, 0)
+    print(f"[bench] fp64 {r64['value']:.3e} unknowns/s, {r64['ms_per_step']:.1f} ms/step, "
+          f"iters {r64['iters']}", file=sys.stderr, flush=True)
+    fp32 = None
+    if not args.no_fp32:
+        r32 = run_gpu(pr, args.steps, args.warmup, 1)
+        fp32 = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "iters": r32["iters"],
+                "sweep_ms_avg": r32["sweep_ms_avg"],
+                "moment_err_vs_fp64": moment_error(r32["U"], r64["U"], 2)}
+        print(f"[bench] fp32+refine {r32['value']:.3e} unknowns/s, {r32['ms_per_step']:.1f} ms/step",
+              file=sys.stderr, flush=True)
+    sweep_s = r64["sweep_ms_avg"] * 1e-3
+    achieved = SWEEP_BYTES_PER_UNKNOWN * r64["n_unknown"] / sweep_s / 1e9
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(pr, args.cpu_velocities, r64["dt"])
+        print(f"[bench] cpu oracle {cpu['value']:.3e} unknowns/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+    line = {
+        "metric": "DG unknowns swept/s (FP64 vs FP32+refine); outer iters & s/step w/ learned guess",
+        "value": r64["value"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": pr.name, "cells": r64["n_cells"], "dofs_per_cell": r64["n_p"],
+                   "velocities": r64["n_v"], "unknowns": r64["n_unknown"], "tableau": pr.tableau,
+                   "kn": pr.kn, "tau": pr.tau, "max_generations": r64["max_G"],
+                   "parallelism": "single GPU"},
+        "picard_iters": r64["iters"],
+        "kernel_ms": {"sweep": r64["sweep_ms_avg"], "moments": r64["moments_ms_avg"],
+                      "maxwellian": r64["maxwellian_ms_avg"]},
+        "fp32_refine": fp32,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep_fp64<2,2>",
+                     "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

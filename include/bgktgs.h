@@ -237,6 +237,8 @@ typedef struct {
   int maxw_mode;          /* BGK_MAXW_* */
   tgs_nu_model nu_model;
   const double* bc_coef;  /* device [n_bfaces][n_fp][dim+2] time-independent inflow */
+  int timing;             /* 1: time every kernel with HIP events on the step's
+                             stream (bgk_step_stats.*_ms); 0: no events */
 } bgk_solver_opts;
 
 typedef struct {
@@ -246,6 +248,11 @@ typedef struct {
   double last_ratio[4];   /* final max_m ratio per stage */
   int maxw_fallbacks;
   double seconds;         /* host wall time of the step */
+  double sweep_ms;        /* summed device time of the sweep kernels (timing = 1) */
+  double moments_ms;      /* summed device time of the moment kernels */
+  double maxwellian_ms;   /* summed device time of the Maxwellian kernels */
+  double other_ms;        /* DIRK combinations and copies */
+  int sweeps;             /* number of sweep launches */
 } bgk_step_stats;
 
 typedef struct bgk_solver bgk_solver;

@@ -8,7 +8,11 @@ back edge) closes a cycle and is lagged: the downwind cell then takes that
 facet's inflow from the previous Picard iterate.
 
 Readings taken here (design notes A9-A11):
-  * a facet with v.n == 0 carries no edge;
+  * a facet with v.n == 0 carries no edge; "zero" is taken as
+    |v.n| <= 1e-12 |v| (n the unit normal), so that a tangential facet whose
+    computed flux is rounding noise of either sign is classified the same
+    way by any implementation (eq. cell-inflow-outflow-boundaries puts such
+    a facet in neither the inflow nor the outflow boundary);
   * DFS roots are visited in ascending cell index and children in ascending
     local facet order of the current cell;
   * the generation of a cell is 0 when it has no non-lagged in-edge,
@@ -22,9 +26,23 @@ import numpy as np
 from .geometry import Geometry
 
 
+TANGENTIAL_TOL = 1e-12
+
+
 def facet_speeds(geo: Geometry, v: np.ndarray) -> np.ndarray:
-    """s[c][k] = v . n_{c,k} (outward unit normal)."""
-    return geo.normal @ np.asarray(v, dtype=np.float64)
+    """s[c][k] = v . n_{c,k} (outward unit normal); tangential facets
+    (|s| <= 1e-12 |v|) get exactly 0."""
+    v = np.asarray(v, dtype=np.float64)
+    s = geo.normal @ v
+    s[np.abs(s) <= TANGENTIAL_TOL * np.linalg.norm(v)] = 0.0
+    return s
+
+
+def facet_speeds_batch(normals: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """Per item i: s[i][k] = V[i] . normals[i][k] with the same tangential rule."""
+    s = np.einsum("ikd,id->ik", normals, V)
+    s[np.abs(s) <= TANGENTIAL_TOL * np.linalg.norm(V, axis=1)[:, None]] = 0.0
+    return s
 
 
 def dfs_order(geo: Geometry, v: np.ndarray):

@@ -35,6 +35,10 @@ from . import kinetic, transport
 from .geometry import Geometry
 
 
+class NonPhysicalError(RuntimeError):
+    """Moments with n <= 0 or theta <= 0 at some node: no Maxwellian exists."""
+
+
 def tableau(name: str):
     if name == "BE":
         return np.array([[1.0]]), np.array([1.0]), np.array([1.0])
@@ -105,6 +109,14 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
     hist = []
     nfb = 0
     for ell in range(lmax):
+        collisional = not (nu_model == "const" and nu_const == 0.0)
+        needs_theta = not (mode == "LINEAR" and nu_model == "const")
+        n_, _, th_ = kinetic.primitive(U, dim)
+        ok = np.all(n_ > 0) and np.all(np.isfinite(n_))
+        if needs_theta:
+            ok = ok and np.all(th_ > 0) and np.all(np.isfinite(th_))
+        if collisional and not ok:
+            raise NonPhysicalError("non-physical moments (n <= 0 or theta <= 0)")
         nu = kinetic.collision_frequency(U, dim, nu_model, nu_const, kn)
         if np.any(nu != 0.0):
             coef, fb = maxwellian_coefficients(U, V, w, mode, L)

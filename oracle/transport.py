@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dag import facet_speeds
+from .dag import facet_speeds, facet_speeds_batch
 from .geometry import Geometry
 
 
@@ -37,7 +37,7 @@ def cell_matrices(geo: Geometry, cells: np.ndarray, V: np.ndarray, sigma: np.nda
     vt = np.einsum("iab,ib->ia", geo.jinv[cells], V)                     # J^{-1} v
     A = geo.vol[cells, None, None] * ref["mass"][None] * sigma[:, None, :]
     A = A - geo.det[cells, None, None] * np.einsum("ib,bxy->ixy", vt, ref["stiff"])
-    s = np.einsum("ikd,id->ik", geo.normal[cells], V)
+    s = facet_speeds_batch(geo.normal[cells], V)
     for k in range(geo.dim + 1):
         w = np.where(s[:, k] > 0.0, s[:, k], 0.0) * geo.area[cells, k]
         A = A + w[:, None, None] * ref["face_mass"][k][None]

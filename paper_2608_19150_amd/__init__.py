@@ -79,13 +79,15 @@ class NuModel(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("tableau", C.c_int), ("dt", C.c_double), ("tau", C.c_double),
                 ("l_max", C.c_int), ("fixed_iters", C.c_int), ("precision", C.c_int),
-                ("maxw_mode", C.c_int), ("nu_model", NuModel), ("bc_coef", C.c_void_p)]
+                ("maxw_mode", C.c_int), ("nu_model", NuModel), ("bc_coef", C.c_void_p),
+                ("timing", C.c_int)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("stages", C.c_int), ("iters", C.c_int * 4), ("total_iters", C.c_int),
                 ("last_ratio", C.c_double * 4), ("maxw_fallbacks", C.c_int),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("sweep_ms", C.c_double), ("moments_ms", C.c_double),
+                ("maxwellian_ms", C.c_double), ("other_ms", C.c_double), ("sweeps", C.c_int)]
 
 
 def _p(t):
@@ -281,12 +283,13 @@ class Solver:
     """bgk_solver: DIRK stages with sweep-based Picard iteration."""
 
     def __init__(self, dag, *, dt, bc_coef, tableau="BE", tau=1e-10, l_max=2000, fixed_iters=0,
-                 precision=TGS_FP64, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0):
+                 precision=TGS_FP64, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0,
+                 timing=False):
         self.dag = dag
         self.bc_coef = bc_coef
         o = SolverOpts(TABLEAU[tableau], float(dt), float(tau), int(l_max), int(fixed_iters),
                        int(precision), MAXW[mode], NuModel(NU[nu_model], float(nu_const), float(kn)),
-                       _p(bc_coef))
+                       _p(bc_coef), int(bool(timing)))
         h = C.c_void_p()
         _check(_lib.bgk_solver_create(dag.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -302,7 +305,8 @@ class Solver:
         _check(_lib.bgk_step(self.h, _p(f), _p(U_guess), _p(U_out), C.byref(st), _stream(stream)))
         return {"iters": list(st.iters[:st.stages]), "total_iters": st.total_iters,
                 "last_ratio": list(st.last_ratio[:st.stages]), "fallbacks": st.maxw_fallbacks,
-                "seconds": st.seconds}
+                "seconds": st.seconds, "sweep_ms": st.sweep_ms, "moments_ms": st.moments_ms,
+                "maxwellian_ms": st.maxwellian_ms, "sweeps": st.sweeps}
 
 
 def exported_symbols():

@@ -20,7 +20,7 @@ constexpr int DAG_THREADS = 256;
 struct HostMesh {
   int dim, order, n_p, n_fp;
   int64_t n_cells;
-  std::vector<double> geo;          // user order, [c][dim*dim+1]
+  std::vector<double> geo;          // user order, [c][1 + (dim+1)*dim]: vol, normals
   std::vector<int32_t> nb;          // user order, [c][dim+1]: user nbr or -(1+bface)
   std::vector<int32_t> nb_face;     // [c][dim+1]
   std::vector<int32_t> nb_node;     // [c][dim+1][n_fp]
@@ -66,7 +66,7 @@ int build_host_mesh(const tgs_mesh_desc* m, HostMesh& H) {
   H.n_fp = order == 1 ? dim : 3;
   H.n_cells = m->n_cells;
   const int64_t nc = m->n_cells, nf = dim + 1;
-  const int gs = dim * dim + 1;
+  const int gs = 1 + (dim + 1) * dim;
   H.geo.assign(nc * gs, 0.0);
   H.vol.assign(nc, 0.0);
   H.centroid.assign(nc * dim, 0.0);
@@ -110,11 +110,9 @@ int build_host_mesh(const tgs_mesh_desc* m, HostMesh& H) {
     const double adet = std::fabs(det);
     BGK_CHECK(std::isfinite(det) && adet > 1e-13 * std::pow(hmax, dim), BGK_E_INVALID,
               "degenerate cell " + std::to_string(c));
-    double* g = &H.geo[c * gs];
-    for (int r = 0; r < dim; ++r)
-      for (int k = 0; k < dim; ++k) g[r * dim + k] = adet * inv[r][k];
-    g[dim * dim] = adet / (dim == 2 ? 2.0 : 6.0);
-    H.vol[c] = g[dim * dim];
+    (void)inv;
+    H.geo[c * gs] = adet / (dim == 2 ? 2.0 : 6.0);
+    H.vol[c] = H.geo[c * gs];
     for (int d = 0; d < dim; ++d) {
       double s = 0;
       for (int a = 0; a < nf; ++a) s += X[a][d];
@@ -175,6 +173,46 @@ int build_host_mesh(const tgs_mesh_desc* m, HostMesh& H) {
     }
     i = e;
   }
+  // outward area-weighted facet normals N_k = |e_k| n_k: computed from the
+  // lower-numbered cell's facet vertices (ascending local order), edge vector
+  // rotated (2D) or half the cross product (3D), oriented away from the
+  // centroid, and stored negated in the neighbour
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nf; ++k) {
+      const int32_t nbc = H.nb[c * nf + k];
+      if (nbc != INT32_MIN && nbc < c) continue;
+      double P[3][3] = {};
+      int p = 0;
+      for (int a = 0; a < nf; ++a)
+        if (a != k) {
+          for (int d = 0; d < dim; ++d) P[p][d] = m->vert[(int64_t)m->cells[c * nf + a] * dim + d];
+          ++p;
+        }
+      double N[3] = {0, 0, 0}, mid[3] = {0, 0, 0};
+      if (dim == 2) {
+        const double t0 = P[1][0] - P[0][0], t1 = P[1][1] - P[0][1];
+        N[0] = t1;
+        N[1] = -t0;
+      } else {
+        const double a0 = P[1][0] - P[0][0], a1 = P[1][1] - P[0][1], a2 = P[1][2] - P[0][2];
+        const double b0 = P[2][0] - P[0][0], b1 = P[2][1] - P[0][1], b2 = P[2][2] - P[0][2];
+        N[0] = 0.5 * (a1 * b2 - a2 * b1);
+        N[1] = 0.5 * (a2 * b0 - a0 * b2);
+        N[2] = 0.5 * (a0 * b1 - a1 * b0);
+      }
+      double dotc = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        for (int q = 0; q < dim; ++q) mid[d] += P[q][d];
+        mid[d] /= dim;
+        dotc += N[d] * (mid[d] - H.centroid[c * dim + d]);
+      }
+      const double sgn = dotc < 0 ? -1.0 : 1.0;
+      for (int d = 0; d < dim; ++d) H.geo[c * gs + 1 + k * dim + d] = sgn * N[d];
+      if (nbc != INT32_MIN) {
+        const int k2 = H.nb_face[c * nf + k];
+        for (int d = 0; d < dim; ++d) H.geo[(int64_t)nbc * gs + 1 + k2 * dim + d] = -(sgn * N[d]);
+      }
+    }
   // boundary facets in ascending (cell, facet) order; node maps
   H.nb_node.assign(nc * nf * H.n_fp, -1);
   H.bnode_x.clear();
@@ -498,7 +536,7 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
     D->iid_host[mk[i].second] = (int32_t)i;
   }
   // internal-order device records
-  const int gs = dim * dim + 1;
+  const int gs = 1 + (dim + 1) * dim;
   std::vector<double> geo_i(nc * gs);
   std::vector<FacetRec> fac_i(nc * nf);
   for (int64_t i = 0; i < nc; ++i) {

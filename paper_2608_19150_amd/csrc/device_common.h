@@ -5,49 +5,46 @@
 
 namespace bgk {
 
-// Facet fluxes v.N_k (N_k = |e_k| n_k, outward) of one cell from its
-// D = |det J| J^{-1}: with w = D v,
-//   v.N_0 = sum_b w_b / (d-1)!,   v.N_k = -w_{k-1} / (d-1)!   (k >= 1).
-// Explicit fma calls fix the rounding so that the DAG builder and the sweep
-// classify every facet identically (inflow iff v.N_k < 0).
+// Facet fluxes fl_k = v.N_k (N_k = |e_k| n_k, outward) from the stored
+// area-weighted normals, in a fixed operation order so that the DAG builder
+// and the sweep classify every facet identically (inflow iff fl_k < 0).  A
+// tangential facet, |v.n| <= 1e-12 |v|, gets exactly 0 (no edge, no flux):
+// its computed flux is rounding noise whose sign means nothing.
 template <int DIM>
-__device__ __forceinline__ void facet_flux(const double* __restrict__ D, const double* v,
-                                           double* fl) {
-  double w[DIM];
+__device__ __forceinline__ void facet_flux_raw(const double* __restrict__ geo, const double* v,
+                                               double v2, double* fl, double* raw) {
 #pragma unroll
-  for (int r = 0; r < DIM; ++r) {
-    double s = D[r * DIM] * v[0];
+  for (int k = 0; k <= DIM; ++k) {
+    const double* N = geo + 1 + k * DIM;
+    double s = N[0] * v[0];
+    double n2 = N[0] * N[0];
 #pragma unroll
-    for (int c = 1; c < DIM; ++c) s = __fma_rn(D[r * DIM + c], v[c], s);
-    w[r] = s;
+    for (int d = 1; d < DIM; ++d) {
+      s = __fma_rn(N[d], v[d], s);
+      n2 = __fma_rn(N[d], N[d], n2);
+    }
+    raw[k] = s;
+    fl[k] = (s * s <= 1e-24 * v2 * n2) ? 0.0 : s;
   }
-  constexpr double inv = (DIM == 2) ? 1.0 : 0.5;
-  double sum = w[0];
-#pragma unroll
-  for (int r = 1; r < DIM; ++r) sum += w[r];
-  fl[0] = sum * inv;
-#pragma unroll
-  for (int k = 1; k <= DIM; ++k) fl[k] = -w[k - 1] * inv;
 }
 
-// Same as facet_flux but also returns w = D v (the stiffness weights).
 template <int DIM>
-__device__ __forceinline__ void facet_flux_w(const double* __restrict__ D, const double* v,
-                                             double* fl, double* w) {
+__device__ __forceinline__ void facet_flux(const double* __restrict__ geo, const double* v,
+                                           double v2, double* fl) {
+  double raw[DIM + 1];
+  facet_flux_raw<DIM>(geo, v, v2, fl, raw);
+}
+
+// Same, plus the stiffness weights w = |det J| J^{-1} v = -(d-1)! v.N_{b+1},
+// taken from the unthresholded fluxes.
+template <int DIM>
+__device__ __forceinline__ void facet_flux_w(const double* __restrict__ geo, const double* v,
+                                             double v2, double* fl, double* w) {
+  double raw[DIM + 1];
+  facet_flux_raw<DIM>(geo, v, v2, fl, raw);
+  constexpr double f = (DIM == 2) ? -1.0 : -2.0;
 #pragma unroll
-  for (int r = 0; r < DIM; ++r) {
-    double s = D[r * DIM] * v[0];
-#pragma unroll
-    for (int c = 1; c < DIM; ++c) s = __fma_rn(D[r * DIM + c], v[c], s);
-    w[r] = s;
-  }
-  constexpr double inv = (DIM == 2) ? 1.0 : 0.5;
-  double sum = w[0];
-#pragma unroll
-  for (int r = 1; r < DIM; ++r) sum += w[r];
-  fl[0] = sum * inv;
-#pragma unroll
-  for (int k = 1; k <= DIM; ++k) fl[k] = -w[k - 1] * inv;
+  for (int b = 0; b < DIM; ++b) w[b] = f * raw[b + 1];
 }
 
 // bit k set: facet k of cell K is an interior inflow facet that is not
@@ -57,7 +54,10 @@ __device__ __forceinline__ int inflow_bits(const double* __restrict__ geo,
                                            const FacetRec* __restrict__ facet, int K,
                                            const double* v, int user_lag) {
   double fl[DIM + 1];
-  facet_flux<DIM>(geo + (size_t)K * GeoLayout<DIM>::STRIDE, v, fl);
+  double v2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) v2 = __fma_rn(v[d], v[d], v2);
+  facet_flux<DIM>(geo + (size_t)K * GeoLayout<DIM>::STRIDE, v, v2, fl);
   int bits = 0;
 #pragma unroll
   for (int k = 0; k <= DIM; ++k)

@@ -191,19 +191,22 @@ struct Elem {
   using B = ElemBuild<DIM, ORDER>;
   static constexpr int NP = B::NP, NF = B::NF, NFP = B::NFP;
   static constexpr typename B::Tables T = B::make();
-  // facet flux factor: v.N_k = |e_k| v.n_k = s_k * (D v) with D = |det J| J^-1:
-  //   k = 0: +sum_b w_b / (d-1)!,  k >= 1: -w_{k-1} / (d-1)!
-  static constexpr double INV_FACT_DM1 = 1.0 / cfact(DIM - 1);
 };
 
 // ---------------------------------------------------------------------------
 // geometry record per internal cell (doubles):
-//   D[DIM][DIM] = |det J| J^{-1}, vol = |K|
+//   [0] vol = |K|;  [1 + k*DIM + d] = N_k[d], the outward area-weighted
+//   normal |e_k| n_k of facet k (facet opposite vertex k).
+// Each interior facet's normal is computed once, from the lower-numbered
+// cell's vertices, and stored negated in the other cell, so v.N is exactly
+// antisymmetric across a facet.  Since N_k = -(1/(d-1)!) (row k-1 of
+// |det J| J^{-1}) for k >= 1, the stiffness weights w = |det J| J^{-1} v are
+// w_{k-1} = -(d-1)! v.N_k and J^{-1} need not be stored.
 // internal cells are numbered in Morton order of their centroids
 // ---------------------------------------------------------------------------
 template <int DIM>
 struct GeoLayout {
-  static constexpr int STRIDE = DIM * DIM + 1;  // doubles
+  static constexpr int STRIDE = 1 + (DIM + 1) * DIM;  // doubles
 };
 
 // facet record: x = neighbour internal cell id, or -(1 + boundary facet id);

@@ -376,7 +376,19 @@ __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
     uu = fma(u[d], u[d], uu);
   }
   const double th = (2.0 * U[1 + DIM] / n - uu) / DIM;
-  const bool physical = n > 0.0 && th > 0.0 && isfinite(n) && isfinite(th);
+  // theta enters unless the Maxwellian is the linear n/|V| with constant nu
+  const bool needs_theta = !(p.mode == BGK_MAXW_LINEAR && p.nu_kind == BGK_NU_CONST);
+  const bool physical = n > 0.0 && isfinite(n) && (!needs_theta || (th > 0.0 && isfinite(th)));
+  // without collisions (constant nu = 0) no Maxwellian is needed: M = 0
+  const bool collisional = !(p.nu_kind == BGK_NU_CONST && p.nu_const == 0.0);
+  if (!collisional) {
+    if (p.nu) p.nu[i] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) p.coef[i * NM + m] = m == 0 ? -INFINITY : 0.0;
+    if (p.M_dense)
+      for (int j = 0; j < p.n_v; ++j) p.M_dense[i * p.n_v + j] = 0.0;
+    return;
+  }
   if (!physical && p.status) atomicAdd(&p.status[1], 1);
   double nu = p.nu_kind == BGK_NU_CONST ? p.nu_const : n / sqrt(th) / p.kn;
   if (p.nu) p.nu[i] = nu;

@@ -76,6 +76,7 @@ struct bgk_solver {
   unsigned long long* numax = nullptr;
   // pinned host mirror: ratio[4], numax bits, status[2]
   double* h_info = nullptr;
+  hipEvent_t ev[4] = {};  // kernel timing: before maxw, before sweep, before moments, after
 };
 
 namespace {
@@ -194,6 +195,9 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->numax, 1);
   if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
     rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
+  if (!rc && o->timing)
+    for (int i = 0; i < 4 && !rc; ++i)
+      if (hipEventCreate(&s->ev[i]) != hipSuccess) rc = fail(BGK_E_HIP, "hipEventCreate failed");
   if (rc) {
     bgk_solver_destroy(s);
     return rc;
@@ -209,6 +213,8 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_info) (void)hipHostFree(s->h_info);
+  for (hipEvent_t e : s->ev)
+    if (e) (void)hipEventDestroy(e);
   delete s;
   return BGK_OK;
 }
@@ -260,9 +266,11 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     double last = 0.0;
     while (it < o.l_max) {
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
+      if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], stream));
       if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
                                   nullptr, s->status, s->numax, stream)))
         return rc;
+      if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
       if (need_prev) cur_out = (prev == out) ? s->fping : out;
       tgs_sweep_io io{};
       io.precision = o.precision;
@@ -275,9 +283,11 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       io.f_prev = need_prev ? prev : nullptr;
       io.f_out = cur_out;
       if ((rc = launch_sweep(d, &io, s->d32, stream))) return rc;
+      if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
       if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
                                stream)))
         return rc;
+      if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], stream));
       BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
                              stream));
       BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
@@ -285,6 +295,16 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
                              stream));
       BGK_HIP(hipStreamSynchronize(stream));
+      if (o.timing) {
+        float t01, t12, t23;
+        BGK_HIP(hipEventElapsedTime(&t01, s->ev[0], s->ev[1]));
+        BGK_HIP(hipEventElapsedTime(&t12, s->ev[1], s->ev[2]));
+        BGK_HIP(hipEventElapsedTime(&t23, s->ev[2], s->ev[3]));
+        st.maxwellian_ms += t01;
+        st.sweep_ms += t12;
+        st.moments_ms += t23;
+      }
+      ++st.sweeps;
       ++it;
       ucur ^= 1;
       prev = cur_out;

@@ -8,7 +8,8 @@
 // generations.  Velocities are independent, so no grid-wide barrier exists.
 // Each thread assembles its cell's local system
 //   A = |K| mass diag(sigma) - sum_b w_b stiff_b + sum_{v.N_k>0} (v.N_k) fmass_k
-// (w = |det J| J^{-1} v) from compile-time reference matrices and solves it
+// (w = |det J| J^{-1} v, obtained from the facet fluxes) from compile-time
+// reference matrices and solves it
 // in registers by Gaussian elimination without pivoting (the symmetric part
 // of A is positive definite: sigma > 0 plus the upwind facet terms).
 #include "device_common.h"
@@ -129,12 +130,9 @@ __global__ __launch_bounds__(1024) void k_sweep_fp64(SweepArgs a) {
     for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
       const int K = perm[s];
       const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
-      double D[DIM * DIM];
-#pragma unroll
-      for (int i = 0; i < DIM * DIM; ++i) D[i] = gk[i];
-      const double vol = gk[DIM * DIM];
+      const double vol = gk[0];
       double fl[NF], w[DIM];
-      facet_flux_w<DIM>(D, v, fl, w);
+      facet_flux_w<DIM>(gk, v, v2, fl, w);
       const size_t u = (size_t)a.uid[K];
       double sig[NP], src[NP];
 #pragma unroll
@@ -220,12 +218,9 @@ __global__ __launch_bounds__(1024) void k_sweep_fp32c(SweepArgs a) {
     for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
       const int K = perm[s];
       const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
-      double D[DIM * DIM];
-#pragma unroll
-      for (int i = 0; i < DIM * DIM; ++i) D[i] = gk[i];
-      const double vol = gk[DIM * DIM];
+      const double vol = gk[0];
       double fl[NF], w[DIM];
-      facet_flux_w<DIM>(D, v, fl, w);
+      facet_flux_w<DIM>(gk, v, v2, fl, w);
       const size_t u = (size_t)a.uid[K];
       double sig[NP], src[NP], fold[NP];
 #pragma unroll

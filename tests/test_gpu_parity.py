@@ -266,11 +266,24 @@ def test_bgk_step_dirk_kn_matches_oracle(tableau):
     assert rel(f, fref) <= TOL64
 
 
-def test_bgk_step_3d_matches_oracle():
-    pr = P.small_problem(dim=3, order=1, n_side=3, n_1d=6, state="riemann", nu_model="kn", kn=0.1)
+@pytest.mark.parametrize("state", ["fourier", "sod"])
+def test_bgk_step_3d_matches_oracle(state):
+    pr = P.small_problem(dim=3, order=1, n_side=3, n_1d=6, state=state, nu_model="kn", kn=0.1)
     d, f, st, dt = _run_steps(pr, 2, fixed_iters=3)
     geo, fref, _ = _oracle_steps(pr, 2, dt, fixed_iters=3)
     assert rel(f, fref) <= TOL64
+
+
+def test_nonphysical_state_is_reported_like_the_oracle():
+    """A sharp 3D Riemann state on a 6^3 velocity grid drives nodal moments
+    non-physical; the oracle raises and the library returns BGK_E_NONPHYSICAL."""
+    pr = P.small_problem(dim=3, order=1, n_side=3, n_1d=6, state="riemann", nu_model="kn", kn=0.1)
+    with pytest.raises(B.BGKError) as e:
+        _run_steps(pr, 2, fixed_iters=3)
+    assert e.value.code == B.BGK_E_NONPHYSICAL
+    d = B.Dag.from_problem(pr)
+    with pytest.raises(solver.NonPhysicalError):
+        _oracle_steps(pr, 2, d.explicit_dt(pr.cfl), fixed_iters=3)
 
 
 def test_uniform_maxwellian_preserved_on_gpu():
