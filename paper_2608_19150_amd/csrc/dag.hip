@@ -433,6 +433,80 @@ __global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
   }
 }
 
+// Item records for the sweep: per (velocity, slot) the cell and, per facet,
+// where its inflow comes from.  Uses the same facet classification as the
+// level kernel and the sweep (facet_flux), so every inflow facet has a code.
+template <int DIM>
+__global__ void k_records(const double* __restrict__ geo, const FacetRec* __restrict__ facet,
+                          const double* __restrict__ vel, const int32_t* __restrict__ perm,
+                          const int32_t* __restrict__ pos, const uint8_t* __restrict__ lag,
+                          int32_t* __restrict__ rec, int32_t* __restrict__ recx, int n_cells,
+                          int n_fp, int j0, int nb) {
+  const int64_t total = (int64_t)nb * n_cells;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = j0 + (int)(idx / n_cells);
+    const size_t base = (size_t)j * n_cells;
+    const int s = (int)(idx % n_cells);
+    const int K = perm[base + s];
+    double v[DIM], v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      v[d] = vel[(size_t)j * DIM + d];
+      v2 = __fma_rn(v[d], v[d], v2);
+    }
+    double fl[DIM + 1];
+    facet_flux<DIM>(geo + (size_t)K * GeoLayout<DIM>::STRIDE, v, v2, fl);
+    const int lb = lag ? lag[base + K] : 0;
+    int code[4] = {-1, -1, -1, -1};
+    const int nbits = n_fp == 3 && DIM == 2 ? 3 : 2;
+    int packs = 0;
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k) {
+      const FacetRec fr = facet[(size_t)K * (DIM + 1) + k];
+      for (int p = 0; p < n_fp; ++p)
+        packs |= ((fr.pack >> (4 * (p + 1))) & 15) << (nbits * (k * n_fp + p));
+      if (!(fl[k] < 0.0)) continue;
+      if (fr.nb >= 0)
+        code[k] = pos[base + fr.nb] | (((lb >> k) & 1) ? REC_LAG_BIT : 0);
+      else
+        code[k] = -2 - (-fr.nb - 1);
+    }
+    recx[base + s] = packs;
+    int4 r;
+    if (DIM == 2)
+      r = make_int4(K, code[0], code[1], code[2]);
+    else
+      r = make_int4(code[0], code[1], code[2], code[3]);
+    reinterpret_cast<int4*>(rec)[base + s] = r;
+  }
+}
+
+// lowest upwind (non-lagged) slot read by each generation; one block per velocity
+__global__ void k_gen_reach(const int32_t* __restrict__ rec, const int32_t* __restrict__ goff,
+                            const int64_t* __restrict__ gbase, const int32_t* __restrict__ G,
+                            int32_t* __restrict__ gmin, int n_cells, int dim) {
+  const int j = blockIdx.x;
+  const int32_t* go = goff + gbase[j];
+  const size_t base = (size_t)j * n_cells;
+  __shared__ int s_min;
+  for (int g = 0; g < G[j]; ++g) {
+    if (threadIdx.x == 0) s_min = INT32_MAX;
+    __syncthreads();
+    int m = INT32_MAX;
+    for (int s = go[g] + threadIdx.x; s < go[g + 1]; s += blockDim.x) {
+      const int4 r = reinterpret_cast<const int4*>(rec)[base + s];
+      const int c[4] = {r.x, r.y, r.z, r.w};
+      for (int k = (dim == 2 ? 1 : 0); k < 4; ++k)
+        if (c[k] >= 0 && !(c[k] & REC_LAG_BIT)) m = min(m, c[k] & REC_SLOT_MASK);
+    }
+    atomicMin(&s_min, m);
+    __syncthreads();
+    if (threadIdx.x == 0) gmin[gbase[j] + g] = s_min;
+    __syncthreads();
+  }
+}
+
 template <typename T>
 int dalloc(T** p, size_t n) {
   if (n == 0) n = 1;
@@ -450,7 +524,7 @@ void free_dag(tgs_dag* d) {
   if (!d) return;
   void* ptrs[] = {d->d_geo,  d->d_uid, d->d_facet, d->d_v,    d->d_w,    d->d_nodes1d,
                   d->d_weights1d, d->d_perm, d->d_pos, d->d_goff, d->d_gbase, d->d_G,
-                  d->d_lag, d->d_vorder};
+                  d->d_lag, d->d_vorder, d->d_rec, d->d_recx, d->d_gmin};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
@@ -656,11 +730,64 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   }
   D->max_G = 0;
   for (int j = 0; j < nv; ++j) D->max_G = std::max(D->max_G, D->G_host[j]);
-  // sweep block order: longest generation chains first
+  // sweep item records
+  if ((rc = dalloc(&D->d_rec, (size_t)nv * nc * 4))) return rc;
+  if ((rc = dalloc(&D->d_recx, (size_t)nv * nc))) return rc;
+  {
+    const int64_t total = (int64_t)nv * nc;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    if (dim == 2)
+      hipLaunchKernelGGL(k_records<2>, dim3(grid), dim3(256), 0, stream, D->d_geo, D->d_facet,
+                         D->d_v, D->d_perm, D->d_pos, D->d_lag, D->d_rec, D->d_recx, (int)nc,
+                         D->n_fp, 0, nv);
+    else
+      hipLaunchKernelGGL(k_records<3>, dim3(grid), dim3(256), 0, stream, D->d_geo, D->d_facet,
+                         D->d_v, D->d_perm, D->d_pos, D->d_lag, D->d_rec, D->d_recx, (int)nc,
+                         D->n_fp, 0, nv);
+    BGK_HIP(hipGetLastError());
+  }
+  if ((rc = dalloc(&D->d_gmin, (size_t)total_goff))) return rc;
+  hipLaunchKernelGGL(k_gen_reach, dim3(nv), dim3(256), 0, stream, D->d_rec, D->d_goff, D->d_gbase,
+                     D->d_G, D->d_gmin, (int)nc, dim);
+  BGK_HIP(hipGetLastError());
+  // sweep block order.  Workgroups are dispatched round-robin over the 8
+  // XCDs (block b -> XCD b % 8), each with its own L2.  Velocities sorted by
+  // direction are dealt to XCDs in 8 contiguous angular sectors (2D) or by
+  // octant (3D), so the velocities sharing an L2 sweep similar fronts and
+  // reuse each other's cell data.  Within a sector, blocks that run together
+  // are angular neighbours.
   std::vector<int32_t> vorder(nv);
-  std::iota(vorder.begin(), vorder.end(), 0);
-  std::stable_sort(vorder.begin(), vorder.end(),
-                   [&](int32_t x, int32_t y) { return D->G_host[x] > D->G_host[y]; });
+  {
+    std::vector<std::pair<double, int32_t>> key(nv);
+    for (int j = 0; j < nv; ++j) {
+      const double* vj = &D->v_host[(size_t)j * dim];
+      double k;
+      if (dim == 2) {
+        k = std::atan2(vj[1], vj[0]);
+      } else {
+        const int oct = (vj[0] < 0) * 4 + (vj[1] < 0) * 2 + (vj[2] < 0);
+        k = oct * 10.0 + std::atan2(std::fabs(vj[1]), std::fabs(vj[0])) +
+            std::atan2(std::fabs(vj[2]), std::hypot(vj[0], vj[1]));
+      }
+      key[j] = {k, j};
+    }
+    std::stable_sort(key.begin(), key.end());
+    constexpr int NX = 8;
+    // sector x gets sorted positions [x*nv/NX, (x+1)*nv/NX); block b takes
+    // the (b/NX)-th velocity of sector b%NX
+    std::vector<int> used(NX, 0);
+    for (int b = 0; b < nv; ++b) {
+      int x = b % NX;
+      int lo = (int)((int64_t)x * nv / NX), hi = (int)((int64_t)(x + 1) * nv / NX);
+      // sectors can differ in size by one: fall through to the next with room
+      for (int t = 0; t < NX && lo + used[x] >= hi; ++t) {
+        x = (x + 1) % NX;
+        lo = (int)((int64_t)x * nv / NX);
+        hi = (int)((int64_t)(x + 1) * nv / NX);
+      }
+      vorder[b] = key[lo + used[x]++].second;
+    }
+  }
   BGK_HIP(hipMemcpyAsync(D->d_vorder, vorder.data(), nv * sizeof(int32_t), hipMemcpyHostToDevice,
                          stream));
   BGK_HIP(hipStreamSynchronize(stream));

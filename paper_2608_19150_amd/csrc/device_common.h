@@ -65,6 +65,32 @@ __device__ __forceinline__ int inflow_bits(const double* __restrict__ geo,
   return bits & ~user_lag;
 }
 
+// exp(x) by Cody-Waite reduction x = k ln2 + r (ln2 split into a high part
+// with 21 trailing zero bits and a low part, so k*ln2_hi is exact for
+// |k| < 2^11) and the degree-13 Taylor polynomial of exp(r) on
+// |r| <= ln2/2 (truncation below 5e-18 relative), scaled by 2^k with ldexp
+// (which also produces the gradual underflow).  Arguments below -745 give 0.
+__device__ __forceinline__ double bgk_exp(double x) {
+  if (x < -745.5) return 0.0;
+  const double k = rint(x * 1.4426950408889634074);
+  const double r = fma(-k, 1.9082149292705877000e-10, fma(-k, 6.93147180369123816490e-01, x));
+  double p = 1.0 / 6227020800.0;           // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);        // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);         // 1/11!
+  p = fma(p, r, 1.0 / 3628800.0);          // 1/10!
+  p = fma(p, r, 1.0 / 362880.0);           // 1/9!
+  p = fma(p, r, 1.0 / 40320.0);            // 1/8!
+  p = fma(p, r, 1.0 / 5040.0);             // 1/7!
+  p = fma(p, r, 1.0 / 720.0);              // 1/6!
+  p = fma(p, r, 1.0 / 120.0);              // 1/5!
+  p = fma(p, r, 1.0 / 24.0);               // 1/4!
+  p = fma(p, r, 1.0 / 6.0);                // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
 // Maxwellian value exp(a + b.v + c|v|^2) from coefficients
 template <int DIM>
 __device__ __forceinline__ double maxw_eval(const double* __restrict__ coef, const double* v,
@@ -73,7 +99,7 @@ __device__ __forceinline__ double maxw_eval(const double* __restrict__ coef, con
 #pragma unroll
   for (int d = 0; d < DIM; ++d) e = __fma_rn(coef[1 + d], v[d], e);
   e = __fma_rn(coef[1 + DIM], v2, e);
-  return exp(e);
+  return bgk_exp(e);
 }
 
 }  // namespace bgk

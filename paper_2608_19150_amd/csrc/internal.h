@@ -217,10 +217,8 @@ struct FacetRec {
   int pack;
 };
 
-struct DeviceBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
+constexpr int REC_LAG_BIT = 1 << 30;
+constexpr int REC_SLOT_MASK = REC_LAG_BIT - 1;
 
 }  // namespace bgk
 
@@ -231,7 +229,7 @@ struct tgs_dag {
   int n_v = 0;
   int max_G = 0;
   int64_t n_lagged = 0;
-  int sweep_threads = 256;
+  int sweep_threads = 0;   // 0: chosen per element type and precision
   // host copies
   std::vector<double> v_host, w_host;       // [n_v][dim], [n_v]
   int n_1d = 0;
@@ -257,6 +255,19 @@ struct tgs_dag {
   int32_t* d_G = nullptr;         // [n_v]
   uint8_t* d_lag = nullptr;       // [n_v][n_cells] lagged facet bits (internal), or null
   int32_t* d_vorder = nullptr;    // [n_v] velocity processed by sweep block b
+  // sweep item records, [n_v][n_cells][4] int32 per slot: 2D {K, c_0, c_1, c_2},
+  // 3D {c_0, c_1, c_2, c_3} (K from d_perm); facet code c_k: -1 not an inflow
+  // facet; >= 0 upwind neighbour's slot (bit 30 set when lagged); <= -2
+  // boundary facet -2 - c
+  int32_t* d_rec = nullptr;
+  // [n_v][n_cells] facet node maps of the slot's cell: for facet k and facet
+  // node p, the upwind neighbour's local node sits at bit NB*(k*n_fp + p)
+  // with NB = 2 bits (n_p <= 4) or 3 bits (P2)
+  int32_t* d_recx = nullptr;
+  // per (velocity, generation), aligned with d_goff: the lowest slot any
+  // cell of the generation reads a non-lagged upwind value from (INT32_MAX
+  // if none); tells the sweep whether older values must come from HBM
+  int32_t* d_gmin = nullptr;
 };
 
 namespace bgk {

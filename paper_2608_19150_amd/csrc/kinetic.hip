@@ -87,7 +87,7 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
   if (lane == 0) {
     double nrm[6] = {0, 0, 0, 0, 0, 0};
     if (valid) {
-      const size_t u = (size_t)a.uid[K];
+      const size_t u = a.uid ? (size_t)a.uid[K] : (size_t)K;
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         double* Up = a.U + (u * NP + p) * NM;
@@ -478,6 +478,69 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
   coef[i * NM + 1 + DIM] = -0.5 / th;
 }
 
+// Factorised Maxwellian for tensor velocity grids: exp(a + b.v + c|v|^2) =
+// prod_alpha exp([alpha == 0] a + b_alpha x + c x^2) with x the node of axis
+// alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
+// and M(v_j) is the product of d table entries (node fastest, coalesced).
+template <int DIM>
+__global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ x1,
+                              double* __restrict__ tab, int64_t n_nodes, int n1) {
+  constexpr int NM = DIM + 2;
+  const int64_t total = n_nodes * DIM * n1;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = idx % n_nodes;
+    const int64_t r = idx / n_nodes;
+    const int i = (int)(r % n1), al = (int)(r / n1);
+    const double x = x1[i];
+    const double* c = coef + node * NM;
+    double e = __fma_rn(c[1 + DIM], x * x, c[1 + al] * x);
+    if (al == 0) e += c[0];
+    tab[idx] = bgk_exp(e);
+  }
+}
+
+int launch_maxw_tables(const tgs_dag* d, const double* coef, double* tab, hipStream_t stream) {
+  const int64_t total = d->n_nodes * d->dim * d->n_1d;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  if (d->dim == 2)
+    hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, d->d_nodes1d, tab,
+                       d->n_nodes, d->n_1d);
+  else
+    hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, d->d_nodes1d, tab,
+                       d->n_nodes, d->n_1d);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+// nodal rows between user order and internal order: to_internal:
+// dst[K] = src[uid[K]], else dst[uid[K]] = src[K]; rows of `width` doubles
+__global__ void k_nodal_perm(const double* __restrict__ src, double* __restrict__ dst,
+                             const int32_t* __restrict__ uid, int64_t n_cells, int row,
+                             int to_internal) {
+  const int64_t total = n_cells * row;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t K = i / row, r = i % row;
+    const int64_t u = uid[K];
+    if (to_internal)
+      dst[K * row + r] = src[u * row + r];
+    else
+      dst[u * row + r] = src[K * row + r];
+  }
+}
+
+int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,
+                      hipStream_t stream) {
+  const int row = d->n_p * (d->dim + 2);
+  const int64_t total = d->n_cells * row;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_nodal_perm, dim3(grid), dim3(256), 0, stream, src, dst, d->d_uid,
+                     d->n_cells, row, to_internal);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
 // velocity lanes per cell for the moment kernel: enough blocks to fill the chip
 int moment_vl(const tgs_dag* d) {
   const int64_t nc = d->n_cells;
@@ -493,8 +556,9 @@ int moment_blocks(const tgs_dag* d) {
 }
 
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
-                   double* partial, double* ratio_out, hipStream_t stream) {
-  MomArgs a{f, d->d_pos, d->d_uid, d->d_v, d->d_w, U, U_prev, partial, (int)d->n_cells, d->n_v};
+                   double* partial, double* ratio_out, hipStream_t stream, bool user_order) {
+  MomArgs a{f,      d->d_pos, user_order ? d->d_uid : nullptr, d->d_v, d->d_w, U, U_prev, partial,
+            (int)d->n_cells, d->n_v};
   const int vl = moment_vl(d);
   const dim3 grid(moment_blocks(d)), block(MOM_THREADS);
 #define BGK_MOM(D_, P_)                                                                   \
@@ -557,7 +621,7 @@ extern "C" int moments(const tgs_dag* d, const double* f, double* U, const doubl
         hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)
       return fail(BGK_E_NOMEM, "scratch allocation failed");
   }
-  int rc = launch_moments(d, f, U, U_prev, partial, ratio, s);
+  int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
   if (rc == BGK_OK && U_prev) {
     if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
       rc = fail(BGK_E_HIP, "copy of ratios failed");

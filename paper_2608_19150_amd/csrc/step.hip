@@ -16,9 +16,13 @@
 #include "device_common.h"
 
 namespace bgk {
-int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, float* d32, hipStream_t stream);
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+                 const double* mtab, float* d32, hipStream_t stream, int threads);
+int launch_maxw_tables(const tgs_dag* d, const double* coef, double* tab, hipStream_t stream);
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
-                   double* partial, double* ratio_out, hipStream_t stream);
+                   double* partial, double* ratio_out, hipStream_t stream, bool user_order);
+int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,
+                      hipStream_t stream);
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
                       unsigned long long* numax, hipStream_t stream);
@@ -69,6 +73,7 @@ struct bgk_solver {
   float* d32 = nullptr;          // FP32 correction traces
   double* U[2] = {};             // moments ping-pong
   double* mcoef = nullptr;
+  double* mtab = nullptr;        // factorised Maxwellian tables (tensor grids)
   double* nu = nullptr;
   double* partial = nullptr;
   double* ratio = nullptr;       // [4]
@@ -188,6 +193,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->U[0], nn);
   if (!rc) rc = dmalloc(&s->U[1], nn);
   if (!rc) rc = dmalloc(&s->mcoef, nn);
+  if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, (size_t)d->dim * d->n_1d * d->n_nodes);
   if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
   if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
   if (!rc) rc = dmalloc(&s->ratio, 4);
@@ -208,8 +214,9 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
 
 extern "C" int bgk_solver_destroy(bgk_solver* s) {
   if (!s) return BGK_OK;
-  void* ptrs[] = {s->fk, s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping, s->q, s->d32,
-                  s->U[0], s->U[1], s->mcoef, s->nu, s->partial, s->ratio, s->status, s->numax};
+  void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
+                  s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
+                  s->nu,    s->partial, s->ratio, s->status, s->numax};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_info) (void)hipHostFree(s->h_info);
@@ -238,10 +245,13 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
   if (s->stiffly_accurate) fst[s->S - 1] = f;
   const double* stage_init = s->fk;   // initial Picard iterate of the stage
   int ucur = 0;
+  // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
+  // order during the step; U_guess / U_out are in user order
   if (U_guess) {
-    BGK_HIP(hipMemcpyAsync(s->U[0], U_guess, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if ((rc = launch_nodal_perm(d, U_guess, s->U[0], 1, stream))) return rc;
   } else {
-    if ((rc = launch_moments(d, s->fk, s->U[0], nullptr, nullptr, nullptr, stream))) return rc;
+    if ((rc = launch_moments(d, s->fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
+      return rc;
   }
   for (int stg = 0; stg < s->S; ++stg) {
     const double shift = 1.0 / (o.dt * s->A[stg][stg]);
@@ -270,6 +280,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
                                   nullptr, s->status, s->numax, stream)))
         return rc;
+      if (s->mtab && (rc = launch_maxw_tables(d, s->mcoef, s->mtab, stream))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
       if (need_prev) cur_out = (prev == out) ? s->fping : out;
       tgs_sweep_io io{};
@@ -282,10 +293,10 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       io.bc_coef = o.bc_coef;
       io.f_prev = need_prev ? prev : nullptr;
       io.f_out = cur_out;
-      if ((rc = launch_sweep(d, &io, s->d32, stream))) return rc;
+      if ((rc = launch_sweep(d, &io, nullptr, s->mtab, s->d32, stream, 0))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
       if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
-                               stream)))
+                               stream, false)))
         return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], stream));
       BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
@@ -349,11 +360,11 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
   if (!s->stiffly_accurate) {
     const double* xs[5] = {s->fk, fst[0], fst[1], fst[2], fst[3]};
     if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
-    if (U_out && (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream)))
+    if (U_out &&
+        (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false)))
       return rc;
   }
-  if (U_out)
-    BGK_HIP(hipMemcpyAsync(U_out, s->U[ucur], nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (U_out && (rc = launch_nodal_perm(d, s->U[ucur], U_out, 0, stream))) return rc;
   BGK_HIP(hipStreamSynchronize(stream));
   st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = st;

@@ -1,17 +1,30 @@
 // tgs_sweep: the topological-generation sweep (Sec. 4.1) of the Picard
 // iteration eq. bgk-ss-picard, plus layout conversion kernels.
 //
-// Mapping: one workgroup owns one velocity j and walks that velocity's
-// generations in order; the threads of the workgroup take the cells of a
-// generation (a contiguous slot range in the sweep layout, so q and f move
-// through HBM fully coalesced) and a workgroup barrier separates
-// generations.  Velocities are independent, so no grid-wide barrier exists.
-// Each thread assembles its cell's local system
-//   A = |K| mass diag(sigma) - sum_b w_b stiff_b + sum_{v.N_k>0} (v.N_k) fmass_k
-// (w = |det J| J^{-1} v, obtained from the facet fluxes) from compile-time
-// reference matrices and solves it
-// in registers by Gaussian elimination without pivoting (the symmetric part
-// of A is positive definite: sigma > 0 plus the upwind facet terms).
+// Mapping.  One workgroup owns one velocity j and walks that velocity's
+// generations in order; each thread takes one cell of a generation (cells of
+// a generation are a contiguous slot range of the sweep layout, so q and f
+// stream through HBM coalesced).  Velocities are independent: there is no
+// grid-wide barrier, only a workgroup barrier between generations.
+//
+// Per cell the thread assembles
+//   A = |K| mass diag(sigma) - sum_b w_b stiff_b + sum_{v.N_k > 0} (v.N_k) fmass_k
+//   b = |K| mass (nu*M + q_scale*q) + sum_{v.N_k < 0} |v.N_k| fmass_k fhat_k
+// (w = |det J| J^{-1} v from the facet fluxes) with the reference matrices as
+// compile-time integer tables, and solves A f = b in registers by Gaussian
+// elimination without pivoting (A's symmetric part is positive definite:
+// sigma > 0 plus the upwind facet terms).
+//
+// Latency.  Everything a cell needs except its upwind neighbours' new values
+// (record, geometry, Maxwellian, sigma, source) is loaded and evaluated one
+// generation ahead, before the barrier.  New values are also kept in an LDS
+// ring of the last RS slots; upwind reads are served from it when their slot
+// is recent enough, so the per-generation barrier only orders LDS
+// (s_waitcnt lgkmcnt + s_barrier) and global loads stay in flight across it.
+// Older upwind values are read from HBM after a full workgroup fence, which
+// runs only when the ring no longer covers the generation's reach.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace bgk {
@@ -19,34 +32,103 @@ namespace bgk {
 struct SweepArgs {
   const double* geo;
   const FacetRec* facet;
-  const int32_t* uid;
   const double* v;
+  const int32_t* rec;
+  const int32_t* recx;
   const int32_t* perm;
-  const int32_t* pos;
   const int32_t* goff;
+  const int32_t* gmin;
   const int64_t* gbase;
   const int32_t* G;
-  const uint8_t* lag;
   const int32_t* vorder;
+  const int32_t* node_map;   // internal cell -> row of the nodal arrays (null: identity)
   const double* nu;
   const double* mcoef;
+  const double* mtab;        // factorised Maxwellian [dim][n1][n_nodes] (internal order) or null
   const double* q;
   const double* bc_coef;
   const double* bc_dense;
   const double* f_prev;
   double* f_out;
-  float* d32;      // FP32 correction traces (sweep layout), FP32 form only
+  float* d32;                // FP32 corrections (sweep layout), FP32 form only
   double sigma_shift;
   double q_scale;
   int n_cells;
   int n_v;
+  int n1;                    // points per axis of a tensor velocity grid (mtab)
 };
+
+// ---------------------------------------------------------------------------
+// Integer-scaled reference tables.  Every normalised element integral is a
+// rational whose denominator divides MS = (2k+d)!/d! (mass), SS = (2k-1+d)!
+// (stiffness on the reference simplex) or FS = (2k+d-1)!/(d-1)! (facet
+// mass); scaled by these the tables are small exact integers, so the kernel
+// multiplies by integers and applies 1/MS, 1/SS, 1/FS once per cell.
+// ---------------------------------------------------------------------------
+constexpr double c_round(double x) {
+  return x >= 0 ? (double)(long long)(x + 0.5) : -(double)(long long)(-x + 0.5);
+}
+constexpr double c_abs(double x) { return x < 0 ? -x : x; }
+
+template <int DIM, int ORDER>
+struct Scaled {
+  using E = Elem<DIM, ORDER>;
+  static constexpr int NP = E::NP, NF = E::NF, NFP = E::NFP;
+  static constexpr double MS = cfact(2 * ORDER + DIM) / cfact(DIM);
+  static constexpr double SS = cfact(2 * ORDER - 1 + DIM);
+  static constexpr double FS = cfact(2 * ORDER + DIM - 1) / cfact(DIM - 1);
+  struct Tab {
+    double m[NP][NP] = {};
+    double s[DIM][NP][NP] = {};
+    double f[NF][NP][NP] = {};
+    bool exact = true;
+  };
+  static constexpr Tab make() {
+    Tab t;
+    for (int a = 0; a < NP; ++a)
+      for (int b = 0; b < NP; ++b) {
+        const double m = E::T.mass[a][b] * MS;
+        t.m[a][b] = c_round(m);
+        if (c_abs(m - t.m[a][b]) > 1e-9) t.exact = false;
+        for (int be = 0; be < DIM; ++be) {
+          const double s = E::T.stiff[be][a][b] * SS;
+          t.s[be][a][b] = c_round(s);
+          if (c_abs(s - t.s[be][a][b]) > 1e-9) t.exact = false;
+        }
+        for (int k = 0; k < NF; ++k) {
+          const double f = E::T.fmass[k][a][b] * FS;
+          t.f[k][a][b] = c_round(f);
+          if (c_abs(f - t.f[k][a][b]) > 1e-9) t.exact = false;
+        }
+      }
+    return t;
+  }
+  static constexpr Tab T = make();
+  static_assert(T.exact, "scaled reference tables must be integers");
+};
+
+template <int DIM, int ORDER>
+struct SweepCfg {
+  static constexpr int NP = Elem<DIM, ORDER>::NP;
+  static constexpr int RS = (NP * 8 * 1024 <= 32768) ? 1024 : 512;  // LDS ring slots
+};
+
+// 1/x: hardware reciprocal estimate refined by two Newton steps (full
+// double precision for the well-scaled pivots of the local systems).
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <int N, typename T>
 __device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const T inv = T(1) / A[k][k];
+    const T inv = recip(A[k][k]);
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
       const T l = A[i][k] * inv;
@@ -65,245 +147,402 @@ __device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
   }
 }
 
-// Assemble the local matrix A and the volume part of the right-hand side
-// for one (velocity, cell) item.
+// A cell prepared for its solve: everything but the upwind values.
 template <int DIM, int ORDER>
-__device__ __forceinline__ void assemble(const double vol, const double* w, const double* fl,
-                                         const double* sig, const double* src,
+struct Prep {
+  static constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1;
+  int s;            // slot, -1: none
+  int K;
+  int code[NF];
+  int pack;         // facet node maps (see tgs_dag::d_recx)
+  double vol;
+  double fl[NF];
+  double w[DIM];
+  double sig[NP];
+  double src[NP];
+};
+
+template <int DIM>
+__device__ __forceinline__ void load_rec(const SweepArgs& a, size_t base, int s, int& K,
+                                         int (&code)[DIM + 1], int& pack) {
+  const int4 r = reinterpret_cast<const int4*>(a.rec)[base + s];
+  pack = a.recx[base + s];
+  if (DIM == 2) {
+    K = r.x;
+    code[0] = r.y;
+    code[1] = r.z;
+    code[2] = r.w;
+  } else {
+    K = a.perm[base + s];
+    code[0] = r.x;
+    code[1] = r.y;
+    code[2] = r.z;
+    code[DIM] = r.w;
+  }
+}
+
+template <int DIM, int ORDER, bool TAB>
+__device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, double v2,
+                                        size_t base, const double* const (&mrow)[DIM],
+                                        Prep<DIM, ORDER>& P) {
+  constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1, NC = DIM + 2;
+  const double* __restrict__ gk = a.geo + (size_t)P.K * GeoLayout<DIM>::STRIDE;
+  P.vol = gk[0];
+  double raw[NF];
+  facet_flux_raw<DIM>(gk, v, v2, P.fl, raw);
+  constexpr double wf = (DIM == 2) ? -1.0 : -2.0;
+#pragma unroll
+  for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
+  const size_t u = a.node_map ? (size_t)a.node_map[P.K] : (size_t)P.K;
+  const double* __restrict__ nu = a.nu + u * NP;
+  const double* __restrict__ q = a.q + (base + P.s) * NP;
+  double M[NP];
+  if constexpr (TAB) {
+    // tensor grid: M = prod_alpha E_alpha[i_alpha][node]
+#pragma unroll
+    for (int b = 0; b < NP; ++b) M[b] = mrow[0][u * NP + b];
+#pragma unroll
+    for (int al = 1; al < DIM; ++al)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) M[b] *= mrow[al][u * NP + b];
+  } else {
+    const double* __restrict__ mc = a.mcoef + u * NP * NC;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) M[b] = maxw_eval<DIM>(mc + b * NC, v, v2);
+  }
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    const double nub = nu[b];
+    P.sig[b] = nub + a.sigma_shift;
+    P.src[b] = fma(nub, M[b], a.q_scale * q[b]);
+  }
+}
+
+template <int DIM, int ORDER>
+__device__ __forceinline__ void assemble(const Prep<DIM, ORDER>& P,
                                          double (&A)[Elem<DIM, ORDER>::NP][Elem<DIM, ORDER>::NP],
                                          double (&rhs)[Elem<DIM, ORDER>::NP]) {
-  using E = Elem<DIM, ORDER>;
-  constexpr int NP = E::NP, NF = E::NF;
+  using S = Scaled<DIM, ORDER>;
+  constexpr int NP = S::NP, NF = S::NF;
+  const double vm = P.vol * (1.0 / S::MS);
+  double vs[NP], ws[DIM], os[NF];
 #pragma unroll
-  for (int a = 0; a < NP; ++a) {
+  for (int b = 0; b < NP; ++b) vs[b] = vm * P.sig[b];
+#pragma unroll
+  for (int be = 0; be < DIM; ++be) ws[be] = P.w[be] * (1.0 / S::SS);
+#pragma unroll
+  for (int k = 0; k < NF; ++k) os[k] = (P.fl[k] > 0.0 ? P.fl[k] : 0.0) * (1.0 / S::FS);
+#pragma unroll
+  for (int ia = 0; ia < NP; ++ia) {
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       double x = 0.0;
-      if (E::T.mass[a][b] != 0.0) x = (vol * E::T.mass[a][b]) * sig[b];
+      if (S::T.m[ia][b] != 0.0) x = S::T.m[ia][b] * vs[b];
 #pragma unroll
       for (int be = 0; be < DIM; ++be)
-        if (E::T.stiff[be][a][b] != 0.0) x = fma(-E::T.stiff[be][a][b], w[be], x);
-      A[a][b] = x;
+        if (S::T.s[be][ia][b] != 0.0) x = fma(-S::T.s[be][ia][b], ws[be], x);
+#pragma unroll
+      for (int k = 0; k < NF; ++k)
+        if (S::T.f[k][ia][b] != 0.0) x = fma(S::T.f[k][ia][b], os[k], x);
+      A[ia][b] = x;
     }
     double r = 0.0;
 #pragma unroll
     for (int b = 0; b < NP; ++b)
-      if (E::T.mass[a][b] != 0.0) r = fma(E::T.mass[a][b], src[b], r);
-    rhs[a] = vol * r;
+      if (S::T.m[ia][b] != 0.0) r = fma(S::T.m[ia][b], P.src[b], r);
+    rhs[ia] = vm * r;
   }
+}
+
+// upwind trace values of facet k at its nodes (in facet-node order)
+template <int DIM, int ORDER, typename RT>
+__device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM, ORDER>& P,
+                                              int k, size_t base, int j, const double* v,
+                                              double v2, const RT* ring, int ring_lo,
+                                              bool use_prev, double (&fh)[Elem<DIM, ORDER>::NFP]) {
+  constexpr int NP = Elem<DIM, ORDER>::NP, NFP = Elem<DIM, ORDER>::NFP, NC = DIM + 2;
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
+  constexpr int NB = NP <= 4 ? 2 : 3, NM = (1 << NB) - 1;
+  const int c = P.code[k];
+  if (c >= 0) {
+    const int sl = c & REC_SLOT_MASK;
+    const int pk = P.pack >> (NB * k * NFP);
+    if (use_prev || (c & REC_LAG_BIT)) {
+      const double* src = a.f_prev + (base + sl) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+    } else if (sl >= ring_lo) {
+      const RT* src = ring + (sl & (RS - 1)) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = (double)src[(pk >> (NB * p)) & NM];
+    } else {
+      const double* src = a.f_out + (base + sl) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+    }
+  } else {
+    const size_t bf = (size_t)(-2 - c);
+    if (a.bc_coef) {
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = maxw_eval<DIM>(a.bc_coef + (bf * NFP + p) * NC, v, v2);
+    } else {
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = a.bc_dense[(bf * NFP + p) * a.n_v + j];
+    }
+  }
+}
+
+// FP64 solve of a prepared cell; the result goes to HBM and the LDS ring
+template <int DIM, int ORDER>
+__device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORDER>& P,
+                                         size_t base, int j, const double* v, double v2,
+                                         double* ring, int ring_lo) {
+  using S = Scaled<DIM, ORDER>;
+  constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
+  double A[NP][NP], rhs[NP];
+  assemble<DIM, ORDER>(P, A, rhs);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
-    const double out = fl[k] > 0.0 ? fl[k] : 0.0;
+    if (P.code[k] == -1) continue;
+    double fh[NFP];
+    upwind_values<DIM, ORDER, double>(a, P, k, base, j, v, v2, ring, ring_lo, false, fh);
+    const double inflow = -P.fl[k] * (1.0 / S::FS);
 #pragma unroll
-    for (int a = 0; a < NP; ++a)
+    for (int ia = 0; ia < NFP; ++ia) {
+      const int ra = Elem<DIM, ORDER>::T.fnode[k][ia];
+      double r = 0.0;
 #pragma unroll
-      for (int b = 0; b < NP; ++b)
-        if (E::T.fmass[k][a][b] != 0.0) A[a][b] = fma(out, E::T.fmass[k][a][b], A[a][b]);
+      for (int p = 0; p < NFP; ++p)
+        r = fma(S::T.f[k][ra][Elem<DIM, ORDER>::T.fnode[k][p]], fh[p], r);
+      rhs[ra] = fma(inflow, r, rhs[ra]);
+    }
+  }
+  lu_solve<NP, double>(A, rhs);
+  double* fo = a.f_out + (base + P.s) * NP;
+  double* rg = ring + (P.s & (RS - 1)) * NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    fo[b] = rhs[b];
+    rg[b] = rhs[b];
   }
 }
 
+// FP32 defect correction of a prepared cell: FP64 residual of f_prev,
+// FP32 solve for the correction with upwind correction traces, FP64 update.
 template <int DIM, int ORDER>
-__global__ __launch_bounds__(1024) void k_sweep_fp64(SweepArgs a) {
-  using E = Elem<DIM, ORDER>;
-  constexpr int NP = E::NP, NF = E::NF, NFP = E::NFP, NC = DIM + 2;
-  const int j = a.vorder[blockIdx.x];
-  double v[DIM];
-  double v2 = 0.0;
+__device__ __forceinline__ void finish32c(const SweepArgs& a, const Prep<DIM, ORDER>& P,
+                                          size_t base, int j, const double* v, double v2,
+                                          float* ring, int ring_lo) {
+  using S = Scaled<DIM, ORDER>;
+  constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
+  double A[NP][NP], r[NP], fold[NP];
+  assemble<DIM, ORDER>(P, A, r);
+  const double* fp = a.f_prev + (base + P.s) * NP;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    v[d] = a.v[(size_t)j * DIM + d];
-    v2 = fma(v[d], v[d], v2);
-  }
-  const size_t base = (size_t)j * a.n_cells;
-  const int32_t* __restrict__ perm = a.perm + base;
-  const int32_t* __restrict__ pos = a.pos + base;
-  const int32_t* __restrict__ go = a.goff + a.gbase[j];
-  const int G = a.G[j];
-  const double* __restrict__ q = a.q + base * NP;
-  double* fo = a.f_out + base * NP;
-  const double* fp = a.f_prev ? a.f_prev + base * NP : nullptr;
-  const uint8_t* __restrict__ lag = a.lag ? a.lag + base : nullptr;
-  const double qs = a.q_scale, shift = a.sigma_shift;
-
-  for (int g = 0; g < G; ++g) {
-    const int s0 = go[g], s1 = go[g + 1];
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-      const int K = perm[s];
-      const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
-      const double vol = gk[0];
-      double fl[NF], w[DIM];
-      facet_flux_w<DIM>(gk, v, v2, fl, w);
-      const size_t u = (size_t)a.uid[K];
-      double sig[NP], src[NP];
+  for (int b = 0; b < NP; ++b) fold[b] = fp[b];
+  // FP64 inflow of the previous iterate through every inflow facet
 #pragma unroll
-      for (int b = 0; b < NP; ++b) {
-        const double M = maxw_eval<DIM>(a.mcoef + (u * NP + b) * NC, v, v2);
-        const double nub = a.nu[u * NP + b];
-        sig[b] = nub + shift;
-        src[b] = fma(nub, M, qs * q[(size_t)s * NP + b]);
-      }
-      double A[NP][NP], rhs[NP];
-      assemble<DIM, ORDER>(vol, w, fl, sig, src, A, rhs);
-      const int lb = lag ? lag[K] : 0;
+  for (int k = 0; k < NF; ++k) {
+    if (P.code[k] == -1) continue;
+    double fh[NFP];
+    upwind_values<DIM, ORDER, float>(a, P, k, base, j, v, v2, ring, ring_lo, true, fh);
+    const double inflow = -P.fl[k] * (1.0 / S::FS);
 #pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        if (!(fl[k] < 0.0)) continue;
-        const double inflow = -fl[k];
-        const FacetRec fr = a.facet[(size_t)K * NF + k];
-        double fh[NFP];
-        if (fr.nb >= 0) {
-          const size_t sl = (size_t)pos[fr.nb];
-          const double* srcf = ((lb >> k) & 1) ? fp : fo;
+    for (int ia = 0; ia < NFP; ++ia) {
+      const int ra = Elem<DIM, ORDER>::T.fnode[k][ia];
+      double acc = 0.0;
 #pragma unroll
-          for (int p = 0; p < NFP; ++p) fh[p] = srcf[sl * NP + ((fr.pack >> (4 * (p + 1))) & 15)];
-        } else {
-          const size_t bf = (size_t)(-fr.nb - 1);
-          if (a.bc_coef) {
-#pragma unroll
-            for (int p = 0; p < NFP; ++p) fh[p] = maxw_eval<DIM>(a.bc_coef + (bf * NFP + p) * NC, v, v2);
-          } else {
-#pragma unroll
-            for (int p = 0; p < NFP; ++p) fh[p] = a.bc_dense[(bf * NFP + p) * a.n_v + j];
-          }
-        }
-#pragma unroll
-        for (int ia = 0; ia < NFP; ++ia) {
-          const int ra = E::T.fnode[k][ia];
-          double r = 0.0;
-#pragma unroll
-          for (int p = 0; p < NFP; ++p) r = fma(E::T.fmass[k][ra][E::T.fnode[k][p]], fh[p], r);
-          rhs[ra] = fma(inflow, r, rhs[ra]);
-        }
-      }
-      lu_solve<NP, double>(A, rhs);
-#pragma unroll
-      for (int b = 0; b < NP; ++b) fo[(size_t)s * NP + b] = rhs[b];
+      for (int p = 0; p < NFP; ++p)
+        acc = fma(S::T.f[k][ra][Elem<DIM, ORDER>::T.fnode[k][p]], fh[p], acc);
+      r[ra] = fma(inflow, acc, r[ra]);
     }
-    __syncthreads();
+  }
+  float Af[NP][NP], rf[NP];
+#pragma unroll
+  for (int ia = 0; ia < NP; ++ia) {
+    double x = r[ia];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) x = fma(-A[ia][b], fold[b], x);
+    rf[ia] = (float)x;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) Af[ia][b] = (float)A[ia][b];
+  }
+  // FP32 inflow of the corrections through non-lagged interior facets
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int c = P.code[k];
+    if (c < 0 || (c & REC_LAG_BIT)) continue;
+    constexpr int NB = NP <= 4 ? 2 : 3, NM = (1 << NB) - 1;
+    const int sl = c & REC_SLOT_MASK;
+    const int pk = P.pack >> (NB * k * NFP);
+    float dh[NFP];
+    if (sl >= ring_lo) {
+      const float* src = ring + (sl & (RS - 1)) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) dh[p] = src[(pk >> (NB * p)) & NM];
+    } else {
+      const float* src = a.d32 + (base + sl) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) dh[p] = src[(pk >> (NB * p)) & NM];
+    }
+    const float inflow = (float)(-P.fl[k] * (1.0 / S::FS));
+#pragma unroll
+    for (int ia = 0; ia < NFP; ++ia) {
+      const int ra = Elem<DIM, ORDER>::T.fnode[k][ia];
+      float acc = 0.0f;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p)
+        acc = fmaf((float)S::T.f[k][ra][Elem<DIM, ORDER>::T.fnode[k][p]], dh[p], acc);
+      rf[ra] = fmaf(inflow, acc, rf[ra]);
+    }
+  }
+  lu_solve<NP, float>(Af, rf);
+  double* fo = a.f_out + (base + P.s) * NP;
+  float* dg = a.d32 + (base + P.s) * NP;
+  float* rg = ring + (P.s & (RS - 1)) * NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    fo[b] = fold[b] + (double)rf[b];
+    dg[b] = rf[b];
+    rg[b] = rf[b];
   }
 }
 
-// FP32 defect-correction sweep: per cell the FP64 residual of the previous
-// iterate f_prev,
-//   r = M_K(nu*M + q_scale*q) + inflow(f_prev) - A f_prev   (all FP64),
-// then A delta = r + inflow(delta) solved in FP32 with upwind delta traces,
-// and f_out = f_prev + delta stored in FP64.  At a fixed point of the Picard
-// iteration delta -> 0, so the FP64 state converges to the FP64 solution.
-template <int DIM, int ORDER>
-__global__ __launch_bounds__(1024) void k_sweep_fp32c(SweepArgs a) {
-  using E = Elem<DIM, ORDER>;
-  constexpr int NP = E::NP, NF = E::NF, NFP = E::NFP, NC = DIM + 2;
+// Workgroup barrier that orders LDS only: global loads issued before it may
+// stay in flight (the upwind values it protects live in the LDS ring).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int DIM, int ORDER, bool F32, bool TAB>
+__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep(SweepArgs a) {
+  constexpr int NF = DIM + 1;
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
+  using RT = typename std::conditional<F32, float, double>::type;
+  __shared__ RT ring[RS * NP];
+  const int T = blockDim.x, tid = threadIdx.x;
   const int j = a.vorder[blockIdx.x];
-  double v[DIM];
-  double v2 = 0.0;
+  double v[DIM], v2 = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     v[d] = a.v[(size_t)j * DIM + d];
-    v2 = fma(v[d], v[d], v2);
+    v2 = __fma_rn(v[d], v[d], v2);
   }
   const size_t base = (size_t)j * a.n_cells;
-  const int32_t* __restrict__ perm = a.perm + base;
-  const int32_t* __restrict__ pos = a.pos + base;
   const int32_t* __restrict__ go = a.goff + a.gbase[j];
+  const int32_t* __restrict__ gm = a.gmin + a.gbase[j];
   const int G = a.G[j];
-  const double* __restrict__ q = a.q + base * NP;
-  double* fo = a.f_out + base * NP;
-  const double* __restrict__ fp = a.f_prev + base * NP;
-  float* dl = a.d32 + base * NP;
-  const uint8_t* __restrict__ lag = a.lag ? a.lag + base : nullptr;
-  const double qs = a.q_scale, shift = a.sigma_shift;
+  // rows of the factorised Maxwellian tables for this velocity (tensor grids)
+  const double* mrow[DIM];
+  {
+    int rem = j;
+    const size_t nn = (size_t)a.n_cells * NP;
+#pragma unroll
+    for (int al = DIM - 1; al >= 0; --al) {
+      const int i = a.mtab ? rem % a.n1 : 0;
+      rem = a.mtab ? rem / a.n1 : rem;
+      mrow[al] = a.mtab ? a.mtab + ((size_t)al * a.n1 + i) * nn : nullptr;
+    }
+  }
 
+  Prep<DIM, ORDER> P;
+  P.s = -1;
+  if (go[0] + tid < go[1]) {
+    P.s = go[0] + tid;
+    load_rec<DIM>(a, base, P.s, P.K, P.code, P.pack);
+    prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, P);
+  }
+  int ns = -1, nK = 0, ncode[NF], npack = 0;
+  if (G > 1 && go[1] + tid < go[2]) {
+    ns = go[1] + tid;
+    load_rec<DIM>(a, base, ns, nK, ncode, npack);
+  }
+  int synced = 0;  // global stores of slots < synced are complete and visible
   for (int g = 0; g < G; ++g) {
     const int s0 = go[g], s1 = go[g + 1];
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-      const int K = perm[s];
-      const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
-      const double vol = gk[0];
-      double fl[NF], w[DIM];
-      facet_flux_w<DIM>(gk, v, v2, fl, w);
-      const size_t u = (size_t)a.uid[K];
-      double sig[NP], src[NP], fold[NP];
-#pragma unroll
-      for (int b = 0; b < NP; ++b) {
-        const double M = maxw_eval<DIM>(a.mcoef + (u * NP + b) * NC, v, v2);
-        const double nub = a.nu[u * NP + b];
-        sig[b] = nub + shift;
-        src[b] = fma(nub, M, qs * q[(size_t)s * NP + b]);
-        fold[b] = fp[(size_t)s * NP + b];
-      }
-      double A[NP][NP], r[NP];
-      assemble<DIM, ORDER>(vol, w, fl, sig, src, A, r);
-      const int lb = lag ? lag[K] : 0;
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        if (!(fl[k] < 0.0)) continue;
-        const double inflow = -fl[k];
-        const FacetRec fr = a.facet[(size_t)K * NF + k];
-        double fh[NFP];
-        if (fr.nb >= 0) {
-          const size_t sl = (size_t)pos[fr.nb];
-#pragma unroll
-          for (int p = 0; p < NFP; ++p) fh[p] = fp[sl * NP + ((fr.pack >> (4 * (p + 1))) & 15)];
-        } else {
-          const size_t bf = (size_t)(-fr.nb - 1);
-          if (a.bc_coef) {
-#pragma unroll
-            for (int p = 0; p < NFP; ++p) fh[p] = maxw_eval<DIM>(a.bc_coef + (bf * NFP + p) * NC, v, v2);
-          } else {
-#pragma unroll
-            for (int p = 0; p < NFP; ++p) fh[p] = a.bc_dense[(bf * NFP + p) * a.n_v + j];
-          }
-        }
-#pragma unroll
-        for (int ia = 0; ia < NFP; ++ia) {
-          const int ra = E::T.fnode[k][ia];
-          double acc = 0.0;
-#pragma unroll
-          for (int p = 0; p < NFP; ++p) acc = fma(E::T.fmass[k][ra][E::T.fnode[k][p]], fh[p], acc);
-          r[ra] = fma(inflow, acc, r[ra]);
-        }
-      }
-      // FP64 residual r -= A f_prev; FP32 copy of A
-      float Af[NP][NP], rf[NP];
-#pragma unroll
-      for (int ia = 0; ia < NP; ++ia) {
-        double x = r[ia];
-#pragma unroll
-        for (int b = 0; b < NP; ++b) x = fma(-A[ia][b], fold[b], x);
-        rf[ia] = (float)x;
-#pragma unroll
-        for (int b = 0; b < NP; ++b) Af[ia][b] = (float)A[ia][b];
-      }
-      // inflow of the correction through non-lagged interior facets (FP32)
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        if (!(fl[k] < 0.0)) continue;
-        const FacetRec fr = a.facet[(size_t)K * NF + k];
-        if (fr.nb < 0 || ((lb >> k) & 1)) continue;
-        const float inflow = (float)(-fl[k]);
-        const size_t sl = (size_t)pos[fr.nb];
-        float dh[NFP];
-#pragma unroll
-        for (int p = 0; p < NFP; ++p) dh[p] = dl[sl * NP + ((fr.pack >> (4 * (p + 1))) & 15)];
-#pragma unroll
-        for (int ia = 0; ia < NFP; ++ia) {
-          const int ra = E::T.fnode[k][ia];
-          float acc = 0.0f;
-#pragma unroll
-          for (int p = 0; p < NFP; ++p)
-            acc = fmaf((float)E::T.fmass[k][ra][E::T.fnode[k][p]], dh[p], acc);
-          rf[ra] = fmaf(inflow, acc, rf[ra]);
-        }
-      }
-      lu_solve<NP, float>(Af, rf);
-#pragma unroll
-      for (int b = 0; b < NP; ++b) {
-        dl[(size_t)s * NP + b] = rf[b];
-        fo[(size_t)s * NP + b] = fold[b] + (double)rf[b];
-      }
+    const int ring_lo = s1 - RS;
+    // values older than the ring come from HBM: fence only when this
+    // generation reads one that may not be visible yet
+    if (gm[g] < ring_lo && ring_lo > synced) {
+      __syncthreads();
+      synced = s0;
     }
-    __syncthreads();
+    if (P.s >= 0) {
+      if constexpr (F32)
+        finish32c<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo);
+      else
+        finish64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo);
+    }
+    // cells of a generation wider than the workgroup: solved without look-ahead
+    for (int s = s0 + T + tid; s < s1; s += T) {
+      Prep<DIM, ORDER> Q;
+      Q.s = s;
+      load_rec<DIM>(a, base, s, Q.K, Q.code, Q.pack);
+      prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, Q);
+      if constexpr (F32)
+        finish32c<DIM, ORDER>(a, Q, base, j, v, v2, ring, ring_lo);
+      else
+        finish64<DIM, ORDER>(a, Q, base, j, v, v2, ring, ring_lo);
+    }
+    // look-ahead: prepare this thread's cell of generation g+1, fetch the
+    // record of generation g+2
+    P.s = ns;
+    if (ns >= 0) {
+      P.K = nK;
+      P.pack = npack;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) P.code[k] = ncode[k];
+      prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, P);
+    }
+    ns = -1;
+    if (g + 3 <= G && go[g + 2] + tid < go[g + 3]) {
+      ns = go[g + 2] + tid;
+      load_rec<DIM>(a, base, ns, nK, ncode, npack);
+    }
+    lds_barrier();
   }
+}
+
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+                 const double* mtab, float* d32, hipStream_t stream, int threads) {
+  SweepArgs a{d->d_geo,   d->d_facet, d->d_v,      d->d_rec,   d->d_recx,  d->d_perm,
+              d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, node_map, io->nu,
+              io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
+              io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
+              d->n_1d};
+  const bool fp32 = io->precision == TGS_FP32_CORRECTION;
+  if (threads <= 0) threads = d->sweep_threads;
+  if (threads <= 0) {
+    // keep four workgroups per CU resident at the kernels' register use:
+    // P1 triangles fit 256 threads; P2 triangles and tetrahedra need <= 168
+    // VGPRs (192 threads) in FP64 and 128 threads in the FP32 form
+    const bool small = d->dim == 2 && d->order == 1;
+    threads = small ? 256 : (fp32 ? 128 : 192);
+  }
+  const dim3 grid(d->n_v), block(threads);
+#define BGK_LAUNCH(D_, O_)                                                                \
+  if (fp32 && mtab)                                                                       \
+    hipLaunchKernelGGL((k_sweep<D_, O_, true, true>), grid, block, 0, stream, a);         \
+  else if (fp32)                                                                          \
+    hipLaunchKernelGGL((k_sweep<D_, O_, true, false>), grid, block, 0, stream, a);        \
+  else if (mtab)                                                                          \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, true>), grid, block, 0, stream, a);        \
+  else                                                                                    \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, false>), grid, block, 0, stream, a);
+  if (d->dim == 2 && d->order == 1) {
+    BGK_LAUNCH(2, 1)
+  } else if (d->dim == 2 && d->order == 2) {
+    BGK_LAUNCH(2, 2)
+  } else {
+    BGK_LAUNCH(3, 1)
+  }
+#undef BGK_LAUNCH
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
 }
 
 // canonical f[user cell][node][v] <-> sweep f[v][slot][node]
@@ -348,30 +587,6 @@ __global__ void k_eval_maxw(const double* __restrict__ coef, double* __restrict_
   }
 }
 
-int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, float* d32, hipStream_t stream) {
-  SweepArgs a{d->d_geo,  d->d_facet, d->d_uid, d->d_v,   d->d_perm,   d->d_pos,
-              d->d_goff, d->d_gbase, d->d_G,   d->d_lag, d->d_vorder, io->nu,
-              io->mcoef, io->q,      io->bc_coef, io->bc_dense, io->f_prev, io->f_out,
-              d32,       io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v};
-  const dim3 grid(d->n_v), block(d->sweep_threads);
-  const bool fp32 = io->precision == TGS_FP32_CORRECTION;
-#define BGK_LAUNCH(D_, O_)                                                                 \
-  if (fp32)                                                                                \
-    hipLaunchKernelGGL((k_sweep_fp32c<D_, O_>), grid, block, 0, stream, a);                \
-  else                                                                                     \
-    hipLaunchKernelGGL((k_sweep_fp64<D_, O_>), grid, block, 0, stream, a);
-  if (d->dim == 2 && d->order == 1) {
-    BGK_LAUNCH(2, 1)
-  } else if (d->dim == 2 && d->order == 2) {
-    BGK_LAUNCH(2, 2)
-  } else {
-    BGK_LAUNCH(3, 1)
-  }
-#undef BGK_LAUNCH
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
-}
-
 int grid_for(size_t total) {
   size_t g = (total + 255) / 256;
   return (int)std::min<size_t>(g, 65536);
@@ -397,7 +612,7 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
     if (hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), (hipStream_t)stream) != hipSuccess)
       return fail(BGK_E_NOMEM, "correction buffer allocation failed");
   }
-  int rc = launch_sweep(d, io, d32, (hipStream_t)stream);
+  int rc = launch_sweep(d, io, d->d_uid, nullptr, d32, (hipStream_t)stream, 0);
   if (d32) (void)hipFreeAsync(d32, (hipStream_t)stream);
   return rc;
 }
