@@ -269,6 +269,63 @@ int bgk_solver_destroy(bgk_solver* solver);
 int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out,
              bgk_step_stats* stats, bgk_stream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned Picard initial guess (an addition to the paper's method: the       */
+/* paper initialises Picard from the previous stage, Sec. 4)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Network: 11 inputs -> 64 -> 64 -> 64 (GELU, exact erf) -> 5 outputs, per
+ * DG node.  Inputs (raw): the primitive state (n, u1, u2, u3, theta) at
+ * step t-1, its change from t-2 to t-1 (state and difference rather than two
+ * states, so the small change survives BF16 rounding), and dt*nu at t-1
+ * (u3 = 0 in 2D).  Outputs: the change of (n, u1, u2, u3, theta)
+ * from t-1 to t.  Inputs and outputs are z-scored inside the library with the
+ * statistics given to bgk_mlp_set_normalization.  Matrix products run on
+ * BF16 MFMA with FP32 accumulation; the master weights and the optimiser
+ * state are FP32.  Gradients are reduced in a fixed order (reproducible).
+ * Logical parameter layout (host arrays, 9413 floats): W1[11][64], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[64][5], b4[5]; W_l[fan_in][fan_out]. */
+typedef struct bgk_mlp bgk_mlp;
+enum { BGK_MLP_PARAMS = 9413, BGK_MLP_IN = 11, BGK_MLP_OUT = 5 };
+
+int bgk_mlp_create(const float* params /* host [9413] or NULL = zeros */, bgk_mlp** out);
+int bgk_mlp_destroy(bgk_mlp* mlp);
+int bgk_mlp_set_params(bgk_mlp* mlp, const float* params /* host [9413] */);  /* resets Adam */
+int bgk_mlp_get_params(const bgk_mlp* mlp, float* params /* host [9413] */);
+/* stats (host): mean_in[11], std_in[11], mean_out[5], std_out[5] */
+int bgk_mlp_set_normalization(bgk_mlp* mlp, const float* stats);
+
+/* Y (device [n][5]) = network output, de-normalised, for raw features X
+ * (device [n][11]). */
+int bgk_mlp_forward(bgk_mlp* mlp, const float* X, int64_t n, float* Y, bgk_stream_t stream);
+
+/* Mean squared error between the normalised outputs and the normalised
+ * targets T (device [n][5], raw changes); writes grad (device [9413],
+ * logical layout, may be NULL) and loss (device float[1], may be NULL). */
+int bgk_mlp_loss_grad(bgk_mlp* mlp, const float* X, const float* T, int64_t n, float* grad,
+                      float* loss, bgk_stream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch (X, T). */
+int bgk_mlp_adam_step(bgk_mlp* mlp, const float* X, const float* T, int64_t n, float lr,
+                      float* loss, bgk_stream_t stream);
+
+/* Raw features (device float [n_nodes][11]) from nodal moments at t-1 and
+ * t-2 (device [n_nodes][dim+2], user order) and the collision model. */
+int bgk_mlp_features(const tgs_dag* dag, const double* U_tm1, const double* U_tm2,
+                     const tgs_nu_model* nu_model, double dt, float* X, bgk_stream_t stream);
+
+/* Raw targets (device float [n_nodes][5]): primitive state at t minus t-1. */
+int bgk_mlp_targets(const tgs_dag* dag, const double* U_t, const double* U_tm1, float* T,
+                    bgk_stream_t stream);
+
+/* Initial Picard moments for the next step: U_guess = U(prim(U_tm1) + net),
+ * per node; a node whose prediction has n <= 0, theta <= 0 or is not finite
+ * falls back to U_tm1 (the plain previous-step guess) and is counted in
+ * n_fallback (device int32, accumulated).  All nodal arrays in user order. */
+int bgk_mlp_guess(bgk_mlp* mlp, const tgs_dag* dag, const double* U_tm1, const double* U_tm2,
+                  const tgs_nu_model* nu_model, double dt, double* U_guess, int32_t* n_fallback,
+                  bgk_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,9 @@ EXPORTED = [
     "tgs_dag_generations", "tgs_dag_lagged", "tgs_dag_geometry", "tgs_pack", "tgs_unpack",
     "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
     "tgs_eval_maxwellian", "bgk_solver_create", "bgk_solver_destroy", "bgk_step",
+    "bgk_mlp_create", "bgk_mlp_destroy", "bgk_mlp_set_params", "bgk_mlp_get_params",
+    "bgk_mlp_set_normalization", "bgk_mlp_forward", "bgk_mlp_loss_grad", "bgk_mlp_adam_step",
+    "bgk_mlp_features", "bgk_mlp_targets", "bgk_mlp_guess",
 ]
 
 
@@ -177,10 +180,12 @@ class Dag:
                    n_1d=len(vg.nodes_1d) if tensor else 0, nodes_1d=vg.nodes_1d,
                    weights_1d=vg.weights_1d, L=vg.L, **kw)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.tgs_dag_destroy):
+        # the library function is bound at definition time: module globals
+        # may already be gone when this runs at interpreter exit
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            _lib.tgs_dag_destroy(h)
+            _destroy(h)
             self.h = None
 
     @property
@@ -294,10 +299,12 @@ class Solver:
         _check(_lib.bgk_solver_create(dag.h, C.byref(o), C.byref(h)))
         self.h = h
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.bgk_solver_destroy):
+        # the library function is bound at definition time: module globals
+        # may already be gone when this runs at interpreter exit
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            _lib.bgk_solver_destroy(h)
+            _destroy(h)
             self.h = None
 
     def step(self, f, U_guess=None, U_out=None, stream=None):
@@ -323,5 +330,122 @@ def problem_setup(pr, dag=None, **dag_kw):
     return dag, f0, bc, dag.explicit_dt(pr.cfl)
 
 
+# ---------------------------------------------------------------------------
+# learned Picard initial guess
+# ---------------------------------------------------------------------------
+MLP_ARCH = (11, 64, 64, 64, 5)
+MLP_PARAMS = 9413
+
+_vp = C.c_void_p
+_lib.bgk_mlp_create.argtypes = [_vp, C.POINTER(_vp)]
+_lib.bgk_mlp_destroy.argtypes = [_vp]
+_lib.bgk_mlp_set_params.argtypes = [_vp, _vp]
+_lib.bgk_mlp_get_params.argtypes = [_vp, _vp]
+_lib.bgk_mlp_set_normalization.argtypes = [_vp, _vp]
+_lib.bgk_mlp_forward.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
+_lib.bgk_mlp_loss_grad.argtypes = [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]
+_lib.bgk_mlp_adam_step.argtypes = [_vp, _vp, _vp, C.c_int64, C.c_float, _vp, _vp]
+_lib.bgk_mlp_features.argtypes = [_vp, _vp, _vp, C.POINTER(NuModel), C.c_double, _vp, _vp]
+_lib.bgk_mlp_targets.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.bgk_mlp_guess.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(NuModel), C.c_double, _vp, _vp, _vp]
+
+
+def mlp_flatten(params):
+    """{W1, b1, ..., W4, b4} (W_l [fan_in][fan_out]) -> float32 [9413] in the
+    library's logical order."""
+    parts = []
+    for l in range(1, len(MLP_ARCH)):
+        parts += [np.asarray(params[f"W{l}"], dtype=np.float32).ravel(),
+                  np.asarray(params[f"b{l}"], dtype=np.float32).ravel()]
+    flat = np.ascontiguousarray(np.concatenate(parts))
+    assert flat.size == MLP_PARAMS
+    return flat
+
+
+def mlp_unflatten(flat):
+    out, o = {}, 0
+    for l in range(1, len(MLP_ARCH)):
+        fi, fo = MLP_ARCH[l - 1], MLP_ARCH[l]
+        out[f"W{l}"] = np.asarray(flat[o:o + fi * fo]).reshape(fi, fo)
+        o += fi * fo
+        out[f"b{l}"] = np.asarray(flat[o:o + fo])
+        o += fo
+    return out
+
+
+class Mlp:
+    """bgk_mlp: per-node network on BF16 MFMA with FP32 master weights."""
+
+    def __init__(self, params=None):
+        flat = None if params is None else mlp_flatten(params)
+        h = C.c_void_p()
+        _check(_lib.bgk_mlp_create(_p(flat), C.byref(h)))
+        self.h = h
+
+    def __del__(self, _destroy=_lib.bgk_mlp_destroy):
+        # the library function is bound at definition time: module globals
+        # may already be gone when this runs at interpreter exit
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _destroy(h)
+            self.h = None
+
+    def set_params(self, params):
+        _check(_lib.bgk_mlp_set_params(self.h, _p(mlp_flatten(params))))
+
+    def get_params(self):
+        flat = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.bgk_mlp_get_params(self.h, _p(flat)))
+        return mlp_unflatten(flat)
+
+    def set_normalization(self, mean_in, std_in, mean_out, std_out):
+        st = np.ascontiguousarray(np.concatenate(
+            [np.asarray(a, dtype=np.float32).ravel() for a in (mean_in, std_in, mean_out, std_out)]))
+        assert st.size == 32
+        _check(_lib.bgk_mlp_set_normalization(self.h, _p(st)))
+
+    def forward(self, X, stream=None):
+        X = X.contiguous()
+        Y = torch.empty((X.shape[0], 5), dtype=torch.float32, device="cuda")
+        _check(_lib.bgk_mlp_forward(self.h, _p(X), int(X.shape[0]), _p(Y), _stream(stream)))
+        return Y
+
+    def loss_grad(self, X, T, stream=None):
+        """(loss tensor [1], gradient [9413] in logical order)."""
+        X, T = X.contiguous(), T.contiguous()
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(_lib.bgk_mlp_loss_grad(self.h, _p(X), _p(T), int(X.shape[0]), _p(g), _p(loss),
+                                      _stream(stream)))
+        return loss, g
+
+    def adam_step(self, X, T, lr, loss=None, stream=None):
+        _check(_lib.bgk_mlp_adam_step(self.h, _p(X), _p(T), int(X.shape[0]), float(lr), _p(loss),
+                                      _stream(stream)))
+
+    def guess(self, dag, U_tm1, U_tm2, dt, nu_model="const", nu_const=1.0, kn=1.0, n_fallback=None,
+              stream=None):
+        Ug = torch.empty_like(U_tm1)
+        nm = NuModel(NU[nu_model], float(nu_const), float(kn))
+        _check(_lib.bgk_mlp_guess(self.h, dag.h, _p(U_tm1), _p(U_tm2), C.byref(nm), float(dt),
+                                  _p(Ug), _p(n_fallback), _stream(stream)))
+        return Ug
+
+
+def mlp_features(dag, U_tm1, U_tm2, dt, nu_model="const", nu_const=1.0, kn=1.0, stream=None):
+    X = torch.empty((dag.n_nodes, 11), dtype=torch.float32, device="cuda")
+    nm = NuModel(NU[nu_model], float(nu_const), float(kn))
+    _check(_lib.bgk_mlp_features(dag.h, _p(U_tm1), _p(U_tm2), C.byref(nm), float(dt), _p(X),
+                                 _stream(stream)))
+    return X
+
+
+def mlp_targets(dag, U_t, U_tm1, stream=None):
+    T = torch.empty((dag.n_nodes, 5), dtype=torch.float32, device="cuda")
+    _check(_lib.bgk_mlp_targets(dag.h, _p(U_t), _p(U_tm1), _p(T), _stream(stream)))
+    return T
+
+
 __all__ = ["Dag", "Solver", "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
-           "state_coefficients", "problem_setup", "BGKError", "exported_symbols", "math"]
+           "state_coefficients", "problem_setup", "BGKError", "exported_symbols", "Mlp",
+           "mlp_features", "mlp_targets", "mlp_flatten", "mlp_unflatten", "math"]

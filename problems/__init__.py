@@ -267,6 +267,20 @@ def planar_riemann_state(dim: int, seed: int) -> State:
                            "left": SOD_LEFT, "right": SOD_RIGHT})
 
 
+def random_riemann_state(dim: int, seed: int) -> State:
+    """Sod-like planar Riemann problem with seeded states and normal: left
+    (n, theta) in [0.5, 1.5] x [0.7, 1.3], right n in [0.1, 0.5], theta in
+    [0.6, 1.0], both at rest; the plane passes through a seeded point of the
+    central half of the domain."""
+    rng = np.random.default_rng(seed)
+    nrm = rng.normal(size=dim)
+    nrm /= np.linalg.norm(nrm)
+    left = (float(rng.uniform(0.5, 1.5)), (0.0, 0.0, 0.0), float(rng.uniform(0.7, 1.3)))
+    right = (float(rng.uniform(0.1, 0.5)), (0.0, 0.0, 0.0), float(rng.uniform(0.6, 1.0)))
+    return State("plane", {"normal": nrm, "center": rng.uniform(0.25, 0.75, size=dim),
+                           "left": left, "right": right})
+
+
 def fourier_state(dim: int, seed: int, modes: int = 8, amplitude: float = 0.1) -> State:
     """Smooth seeded perturbation of (1, 0, 1): each field gets a sum of
     ``modes`` sines with integer wave vectors in [1,4]^dim, scaled so the
@@ -338,6 +352,23 @@ def config_c4_instances(count: int = 64, seed0: int = 4000, max_tri: int = 50000
     return out
 
 
+def learned_guess_problem(dim: int, seed: int, n_side: int, n_1d: int, L: float = 6.0,
+                          kn_range=(1e-2, 1.0)) -> Problem:
+    """A seeded backward-Euler Riemann run for the learned initial guess:
+    jittered mesh, P1, tensor velocity grid, random Sod-like states and
+    normal, Kn log-uniform in kn_range, CFL 10."""
+    rng = np.random.default_rng(seed)
+    kn = math.exp(rng.uniform(math.log(kn_range[0]), math.log(kn_range[1])))
+    if dim == 2:
+        mesh = jittered_square_mesh(n_side, 0.2, seed=seed + 100000)
+    else:
+        mesh = jittered_cube_mesh(n_side, 0.2, seed=seed + 100000)
+    return Problem(mesh, 1, tensor_velocity_grid(n_1d, L, dim),
+                   random_riemann_state(dim, seed + 200000), nu_model="kn", kn=kn,
+                   tableau="BE", cfl=10.0, n_steps=10, tau=1e-9,
+                   name=f"learned_{dim}d_{seed}_kn{kn:.3g}")
+
+
 def small_problem(dim=2, order=1, n_side=4, n_1d=6, L=6.0, seed=7, state="sod",
                   nu_model="const", nu_const=1.0, kn=1.0, tableau="BE", jitter=0.25) -> Problem:
     """A tiny instance for oracle pins and parity tests."""
@@ -350,3 +381,22 @@ def small_problem(dim=2, order=1, n_side=4, n_1d=6, L=6.0, seed=7, state="sod",
           "uniform": lambda: uniform_state(dim=dim)}[state]()
     return Problem(mesh, order, tensor_velocity_grid(n_1d, L, dim), st, nu_model=nu_model,
                    nu_const=nu_const, kn=kn, tableau=tableau, name="small")
+
+
+# ----------------------------------------------------------------------------
+# learned initial guess: seeded initial weights (random numbers only)
+# ----------------------------------------------------------------------------
+MLP_ARCH = (11, 64, 64, 64, 5)
+
+
+def mlp_init_params(seed: int, arch=MLP_ARCH):
+    """Glorot-uniform weights and zero biases for the fully connected network
+    ``arch``; W_l has shape [fan_in][fan_out]."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for l in range(len(arch) - 1):
+        fi, fo = arch[l], arch[l + 1]
+        lim = math.sqrt(6.0 / (fi + fo))
+        out[f"W{l + 1}"] = rng.uniform(-lim, lim, size=(fi, fo))
+        out[f"b{l + 1}"] = np.zeros(fo)
+    return out

@@ -296,3 +296,60 @@ def test_uniform_maxwellian_preserved_on_gpu():
         st = s.step(f)
         assert st["iters"] == [1]
     assert rel(d.unpack(f).cpu().numpy(), f_init) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# FP32 solve with FP64 refinement (defect correction): per sweep the result
+# must be within 1e-5 of the FP64 oracle sweep on identical inputs; converged
+# moments within 1e-9 of an FP64 oracle run converged to tau = 1e-13.
+# ---------------------------------------------------------------------------
+TOL32_SWEEP = 1e-5
+TOL32_MOMENTS = 1e-9
+
+
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+def test_sweep_fp32_correction_matches_oracle(dim, order, n_side, n1):
+    say("sweep fp32c", dim, order, n_side, n1)
+    pr = _problem(dim, order, n_side, n1, state="riemann")
+    d = B.Dag.from_problem(pr)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 13)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    rng = np.random.default_rng(14)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 37.0, 2.5, gens)
+    # previous iterate: the answer perturbed by 10% (a Picard iterate, not the solution)
+    f_prev = f_ref * (1.0 + 0.1 * rng.uniform(-1, 1, f_ref.shape))
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 37.0, 2.5, f_prev=f_prev, precision=B.TGS_FP32_CORRECTION)
+    err = rel(f_gpu, f_ref)
+    assert err <= TOL32_SWEEP, err
+    assert err > 1e-13          # the solve really ran in FP32
+
+
+def _moment_err(U, Uref, dim):
+    blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
+    n0 = np.linalg.norm(Uref[:, 0])
+    out = []
+    for m, sl in enumerate(blocks):
+        den = np.linalg.norm(Uref[:, sl])
+        if m == 1:
+            den = max(den, n0)
+        out.append(np.linalg.norm(U[:, sl] - Uref[:, sl]) / den)
+    return max(out)
+
+
+@pytest.mark.parametrize("prob", ["c1", "p2_kn"])
+def test_fp32_refined_steps_match_converged_fp64_moments(prob):
+    say("fp32 refined steps", prob)
+    if prob == "c1":
+        pr = P.config_c1()
+        nsteps = 2
+    else:
+        pr = P.small_problem(order=2, n_side=4, n_1d=10, state="fourier", nu_model="kn", kn=0.05,
+                             tableau="DIRK2")
+        nsteps = 2
+    d, f, st, dt = _run_steps(pr, nsteps, tau=1e-12, precision=B.TGS_FP32_CORRECTION)
+    geo, fref, _ = _oracle_steps(pr, nsteps, dt, tau=1e-13)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    U = kinetic.moments(f, V, w).reshape(-1, geo.dim + 2)
+    Uref = kinetic.moments(fref, V, w).reshape(-1, geo.dim + 2)
+    err = _moment_err(U, Uref, geo.dim)
+    assert err <= TOL32_MOMENTS, err

@@ -1,0 +1,91 @@
+"""Oracle pins for the learned-guess network (no paper reference: the
+network is an addition; pins are mathematical).
+
+* FP64 back-propagation equals central finite differences of the loss.
+* GELU: g(0) = 0, g(z) - g(-z) = z (erf is odd), derivative equals finite
+  differences, and the known value g(1) = Phi(1) = 0.8413447460685429.
+* bfloat16 rounding: exact values pass through, halfway cases round to even.
+* A network with zero weights outputs its last bias.
+"""
+import math
+
+import numpy as np
+
+import problems as P
+from oracle import mlp
+
+
+def test_bf16_rounding_rules():
+    one = np.float32(1.0)
+    assert mlp.bf16(one) == one
+    # 1 + 2^-8 is exactly halfway between 1 and 1 + 2^-7 -> ties to even (1.0)
+    assert mlp.bf16(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    # 1 + 3*2^-8 is halfway between 1+2^-7 and 1+2^-6 -> even is 1 + 2^-6
+    assert mlp.bf16(np.float32(1.0 + 3 * 2.0 ** -8)) == np.float32(1.0 + 2.0 ** -6)
+    x = np.random.default_rng(0).normal(size=1000).astype(np.float32)
+    assert np.max(np.abs(mlp.bf16(x) - x) / np.abs(x)) <= 2.0 ** -8
+
+
+def test_gelu_values_and_derivative():
+    assert mlp.gelu(0.0) == 0.0
+    assert abs(mlp.gelu(1.0) - 0.8413447460685429) < 1e-15
+    z = np.linspace(-4, 4, 17)
+    assert np.allclose(mlp.gelu(z) - mlp.gelu(-z), z, atol=1e-15)
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_grad(z), fd, atol=1e-9)
+
+
+def test_zero_weights_output_last_bias():
+    p = P.mlp_init_params(1)
+    for k in p:
+        p[k] = np.zeros_like(p[k])
+    p["b4"] = np.arange(5.0)
+    Y, _ = mlp.forward(p, np.random.default_rng(0).normal(size=(7, 11)))
+    assert np.array_equal(Y, np.tile(np.arange(5.0), (7, 1)))
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    p = P.mlp_init_params(5)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.normal(scale=0.1, size=p[k].shape)
+    X = rng.normal(size=(9, 11))
+    T = rng.normal(size=(9, 5))
+    loss, g = mlp.loss_and_grads(p, X, T)
+    h = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        idx = rng.choice(flat.size, size=min(6, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            lp, _ = mlp.loss_and_grads(p, X, T)
+            flat[i] = old - h
+            lm, _ = mlp.loss_and_grads(p, X, T)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].reshape(-1)[i]
+            assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (k, i, an, fd)
+
+
+def test_bf16_path_close_to_fp64():
+    rng = np.random.default_rng(4)
+    p = P.mlp_init_params(6)
+    X = rng.normal(size=(64, 11))
+    T = rng.normal(size=(64, 5))
+    Y64, _ = mlp.forward(p, X)
+    Y16, _ = mlp.forward(p, X, "bf16")
+    assert np.max(np.abs(Y16 - Y64)) <= 0.05 * np.max(np.abs(Y64))
+
+
+def test_primitive_roundtrip():
+    rng = np.random.default_rng(5)
+    for dim in (2, 3):
+        p = np.zeros((10, 5))
+        p[:, 0] = rng.uniform(0.1, 2, 10)
+        p[:, 1:1 + dim] = rng.normal(size=(10, dim))
+        p[:, 4] = rng.uniform(0.5, 2, 10)
+        U = mlp.moments_from_primitive(p, dim)
+        assert np.allclose(mlp.primitive_state(U, dim), p)
