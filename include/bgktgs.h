@@ -114,7 +114,8 @@ typedef struct tgs_dag tgs_dag;
 /* Builds cell geometry and facet connectivity on the host, then every
  * velocity's upwind DAG and its longest-path generations on the GPU
  * (Sec. 4.1).  An edge a->b exists when b's facet shared with a has
- * v.n < 0 from b's side; facets with v.n == 0 carry no edge.  When a
+ * v.n < 0 from b's side; tangential facets (|v.n| <= 1e-12 |v| |n|, with n
+ * the area-weighted normal stored once per facet) carry no edge.  When a
  * velocity's graph has a cycle (never the case on Delaunay meshes) the
  * builder releases the lowest-numbered unreleased cell into the next
  * generation and lags its unreleased in-edges (exported by
@@ -264,6 +265,9 @@ int bgk_solver_destroy(bgk_solver* solver);
  * on exit.  U_guess (device [n_nodes][dim+2] or NULL) replaces the moments
  * of f^k as the first stage's initial Picard iterate (learned guess); U_out
  * (device or NULL) receives the converged moments of f^{k+1}.
+ * With MATCHED Maxwellians a node whose Newton solve fails keeps the DIRECT
+ * coefficients for the rest of the stage (maxw_fallbacks counts such nodes
+ * in every iteration).
  * Synchronises `stream` once per Picard iteration to test convergence.
  * Errors: BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_HIP. */
 int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out,

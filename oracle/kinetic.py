@@ -81,12 +81,16 @@ def coefficients_to_primitive(coef: np.ndarray, dim: int):
     return n, u, theta
 
 
-def matched_coefficients(U: np.ndarray, V: np.ndarray, w: np.ndarray, tol=1e-14, maxit=30):
+def matched_coefficients(U: np.ndarray, V: np.ndarray, w: np.ndarray, tol=1e-14, maxit=30,
+                         force_direct=None, failed=None):
     """Newton solve of sum_j w_j e(v_j) exp(a + b.v_j + c|v_j|^2) = U per node.
 
     Starts from the DIRECT coefficients; stops when the residual is below
     tol*|U| (Euclidean) or after maxit iterations, in which case that node
-    falls back to DIRECT.  Returns (coef[N][d+2], n_fallback).
+    falls back to DIRECT.  Nodes flagged in ``force_direct`` (bool per node)
+    skip Newton and take DIRECT; ``failed`` (bool per node, written) marks
+    the nodes that took DIRECT.  Returns (coef[N][d+2], n_fallback), the
+    count including forced nodes.
     """
     V = np.asarray(V, dtype=np.float64)
     dim = V.shape[1]
@@ -97,7 +101,14 @@ def matched_coefficients(U: np.ndarray, V: np.ndarray, w: np.ndarray, tol=1e-14,
     P = np.concatenate([np.ones((V.shape[0], 1)), V, np.sum(V * V, axis=1)[:, None]], axis=1)
     out = coef0.copy()
     nfb = 0
+    fd = None if force_direct is None else np.asarray(force_direct).reshape(-1)
+    fl = None if failed is None else failed.reshape(-1)
     for i in range(Uf.shape[0]):
+        if fd is not None and fd[i]:
+            nfb += 1
+            if fl is not None:
+                fl[i] = True
+            continue
         x = coef0[i].copy()
         ok = False
         with np.errstate(all="ignore"):
@@ -118,6 +129,8 @@ def matched_coefficients(U: np.ndarray, V: np.ndarray, w: np.ndarray, tol=1e-14,
             out[i] = x
         else:
             nfb += 1
+            if fl is not None:
+                fl[i] = True
     return out.reshape(U.shape[:-1] + (dim + 2,)), nfb
 
 

@@ -87,13 +87,22 @@ def relative_changes(U_new: np.ndarray, U_old: np.ndarray, dim: int) -> np.ndarr
     return out
 
 
-def maxwellian_coefficients(U, V, w, mode: str, L: float):
+def maxwellian_coefficients(U, V, w, mode: str, L: float, sticky=None):
+    """Maxwellian coefficients per node.  MATCHED with ``sticky`` (bool per
+    node, updated in place): a node whose Newton solve has failed once keeps
+    the DIRECT coefficients for the rest of the stage (design reading A5:
+    an iterate alternating between the two would never converge)."""
     dim = V.shape[1]
     if mode == "DIRECT":
         n, u, th = kinetic.primitive(U, dim)
         return kinetic.direct_coefficients(n, u, th), 0
     if mode == "MATCHED":
-        return kinetic.matched_coefficients(U, V, w)
+        if sticky is None:
+            return kinetic.matched_coefficients(U, V, w)
+        failed = np.zeros(sticky.shape, dtype=bool)
+        coef, nfb = kinetic.matched_coefficients(U, V, w, force_direct=sticky, failed=failed)
+        sticky |= failed
+        return coef, nfb
     if mode == "LINEAR":
         return kinetic.linear_coefficients(U, L, dim), 0
     raise ValueError(mode)
@@ -108,6 +117,7 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
     U = kinetic.moments(f, V, w) if U_init is None else U_init
     hist = []
     nfb = 0
+    sticky = np.zeros(U.shape[:-1], dtype=bool)
     for ell in range(lmax):
         collisional = not (nu_model == "const" and nu_const == 0.0)
         needs_theta = not (mode == "LINEAR" and nu_model == "const")
@@ -119,7 +129,7 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
             raise NonPhysicalError("non-physical moments (n <= 0 or theta <= 0)")
         nu = kinetic.collision_frequency(U, dim, nu_model, nu_const, kn)
         if np.any(nu != 0.0):
-            coef, fb = maxwellian_coefficients(U, V, w, mode, L)
+            coef, fb = maxwellian_coefficients(U, V, w, mode, L, sticky)
             nfb += fb
             Mv = kinetic.coef_values(coef, V)
         else:                      # collision term vanishes: no Maxwellian needed

@@ -175,6 +175,9 @@ struct MaxwArgs {
   int mode;
   int nu_kind;
   double nu_const, kn, L;
+  // MATCHED: per node, set once its Newton solve has failed; such a node
+  // keeps the DIRECT coefficients while the flag stays set (nullable)
+  uint8_t* sticky;
 };
 
 template <int N>
@@ -408,7 +411,9 @@ __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) x[1 + d] = u[d] / th;
     x[1 + DIM] = -0.5 / th;
-    if (p.mode == BGK_MAXW_MATCHED && physical) {
+    if (p.mode == BGK_MAXW_MATCHED && physical && p.sticky && p.sticky[i]) {
+      if (p.status) atomicAdd(&p.status[0], 1);
+    } else if (p.mode == BGK_MAXW_MATCHED && physical) {
       double Unorm = 0.0;
 #pragma unroll
       for (int m = 0; m < NM; ++m) Unorm = fma(U[m], U[m], Unorm);
@@ -442,8 +447,9 @@ __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
       if (ok && y[1 + DIM] < 0.0) {
 #pragma unroll
         for (int m = 0; m < NM; ++m) x[m] = y[m];
-      } else if (p.status) {
-        atomicAdd(&p.status[0], 1);
+      } else {
+        if (p.status) atomicAdd(&p.status[0], 1);
+        if (p.sticky) p.sticky[i] = 1;
       }
     }
   }
@@ -584,7 +590,7 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
 
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
-                      unsigned long long* numax, hipStream_t stream) {
+                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream) {
   BGK_CHECK(mode == BGK_MAXW_DIRECT || mode == BGK_MAXW_MATCHED || mode == BGK_MAXW_LINEAR,
             BGK_E_INVALID, "unknown Maxwellian mode");
   BGK_CHECK(nm && (nm->kind == BGK_NU_CONST || (nm->kind == BGK_NU_KN && nm->kn > 0)),
@@ -593,7 +599,7 @@ int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_
             "LINEAR mode needs the velocity box half-width L");
   MaxwArgs p{U,      coef,     nu,          M_dense,       status, numax,
              d->d_v, d->d_w,   d->d_nodes1d, d->d_weights1d, d->n_1d, d->n_v,
-             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L};
+             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L, sticky};
   const dim3 grid((unsigned)((d->n_nodes + 127) / 128)), block(128);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxwellian<2>, grid, block, 0, stream, p);
@@ -635,7 +641,7 @@ extern "C" int maxwellian(const tgs_dag* d, int mode, const double* U, const tgs
                           double* coef, double* nu, double* M_dense, int32_t* status,
                           bgk_stream_t stream) {
   if (!d || !U || !coef || !nu) return fail(BGK_E_INVALID, "null argument");
-  return launch_maxwellian(d, mode, U, nm, coef, nu, M_dense, status, nullptr,
+  return launch_maxwellian(d, mode, U, nm, coef, nu, M_dense, status, nullptr, nullptr,
                            (hipStream_t)stream);
 }
 

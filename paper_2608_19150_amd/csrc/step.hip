@@ -25,7 +25,7 @@ int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_i
                       hipStream_t stream);
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
-                      unsigned long long* numax, hipStream_t stream);
+                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream);
 int moment_blocks(const tgs_dag* d);
 
 // out = sum_i c_i x_i (up to 5 inputs), grid-stride, vectorised by 2
@@ -54,6 +54,12 @@ __global__ void k_reset(int32_t* status, unsigned long long* numax) {
   }
 }
 
+__global__ void k_clear_u8(uint8_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 }  // namespace bgk
 
 using namespace bgk;
@@ -79,6 +85,7 @@ struct bgk_solver {
   double* ratio = nullptr;       // [4]
   int32_t* status = nullptr;     // [2]
   unsigned long long* numax = nullptr;
+  uint8_t* sticky = nullptr;     // MATCHED nodes held on DIRECT for the stage
   // pinned host mirror: ratio[4], numax bits, status[2]
   double* h_info = nullptr;
   hipEvent_t ev[4] = {};  // kernel timing: before maxw, before sweep, before moments, after
@@ -199,6 +206,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->ratio, 4);
   if (!rc) rc = dmalloc(&s->status, 2);
   if (!rc) rc = dmalloc(&s->numax, 1);
+  if (!rc) rc = dmalloc(&s->sticky, (size_t)d->n_nodes);
   if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
     rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
   if (!rc && o->timing)
@@ -216,7 +224,7 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
   if (!s) return BGK_OK;
   void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
                   s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
-                  s->nu,    s->partial, s->ratio, s->status, s->numax};
+                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_info) (void)hipHostFree(s->h_info);
@@ -274,11 +282,15 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     int it = 0;
     bool converged = false;
     double last = 0.0;
+    // a node whose MATCHED solve fails stays on DIRECT for the rest of the
+    // stage: an iterate switching between the two would not settle
+    hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)std::min<int64_t>((d->n_nodes + 255) / 256, 1024)),
+                       dim3(256), 0, stream, s->sticky, d->n_nodes);
     while (it < o.l_max) {
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], stream));
       if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
-                                  nullptr, s->status, s->numax, stream)))
+                                  nullptr, s->status, s->numax, s->sticky, stream)))
         return rc;
       if (s->mtab && (rc = launch_maxw_tables(d, s->mcoef, s->mtab, stream))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));

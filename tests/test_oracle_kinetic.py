@@ -122,3 +122,33 @@ def test_linear_maxwellian_and_collision_frequency():
     nu = kinetic.collision_frequency(U, 2, "kn", kn=0.01)
     # n = 2, theta = (2*3/2 - 0)/2 = 1.5 -> nu = 2/sqrt(1.5)/0.01
     assert np.isclose(nu[0], 2.0 / math.sqrt(1.5) / 0.01)
+
+
+def test_matched_fallback_is_sticky_within_a_stage():
+    """On an 8-point grid without v = 0 no non-negative discrete
+    distribution has mean 0 and variance below 0.857^2 per axis, so the
+    moments (1, 0, theta = 0.3) have no matched Maxwellian: Newton fails and
+    the node takes DIRECT.  With the stage's sticky flags the node then
+    stays on DIRECT even for realisable moments (A5 reading)."""
+    from oracle import solver
+    vg = P.tensor_velocity_grid(8, 6.0, 2)
+    assert np.min(np.abs(vg.v[:, 0])) > 0.8
+    U_bad = np.array([[1.0, 0.0, 0.0, 0.3], [1.0, 0.0, 0.0, 1.0]])     # theta 0.3 and 1.0
+    sticky = np.zeros(2, dtype=bool)
+    coef, nfb = solver.maxwellian_coefficients(U_bad, vg.v, vg.w, "MATCHED", 0.0, sticky)
+    assert nfb == 1 and sticky.tolist() == [True, False]
+    n, u, th = kinetic.primitive(U_bad, 2)
+    np.testing.assert_array_equal(coef[0], kinetic.direct_coefficients(n, u, th)[0])
+    # realisable moments at both nodes: node 0 stays on DIRECT, node 1 matches
+    U_ok = np.array([[1.0, 0.0, 0.0, 1.2], [1.0, 0.0, 0.0, 1.2]])
+    coef, nfb = solver.maxwellian_coefficients(U_ok, vg.v, vg.w, "MATCHED", 0.0, sticky)
+    assert nfb == 1 and sticky.tolist() == [True, False]
+    n, u, th = kinetic.primitive(U_ok, 2)
+    direct = kinetic.direct_coefficients(n, u, th)
+    np.testing.assert_array_equal(coef[0], direct[0])
+    assert np.abs(coef[1] - direct[1]).max() > 1e-8
+    U2 = kinetic.moments(kinetic.coef_values(coef[1:], vg.v), vg.v, vg.w)
+    assert np.abs(U2 - U_ok[1:]).max() <= 1e-14 * np.abs(U_ok).max() * 10
+    # without sticky flags the same call matches both nodes
+    coef, nfb = solver.maxwellian_coefficients(U_ok, vg.v, vg.w, "MATCHED", 0.0)
+    assert nfb == 0
