@@ -274,6 +274,66 @@ int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out
              bgk_step_stats* stats, bgk_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched instances (an addition to the paper's method: many independent    */
+/* problems stepped together, for uneven workloads that each fill only part  */
+/* of the GPU)                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* A batch steps n solvers together: every stage's Picard iteration (Sec. 4)
+ * is one launch each of the Maxwellian, the Maxwellian tables, the sweep
+ * (a persistent launch over all instances' velocities, longest generation
+ * counts first), the moments and the stopping test of eq.
+ * convergence-criteria, the last evaluated per instance on the device.  A
+ * converged or failed instance is skipped by the rest of its stage.  With
+ * `graph` set, each stage's chunk of `chunk_iters` iterations is captured
+ * once in a hipGraph and replayed until every instance has stopped; the
+ * host polls a small control block once per chunk.  Per instance the
+ * arithmetic is bgk_step's, so results equal single-instance steps bit for
+ * bit.  Requirements: all solvers share the dimension and the tableau, use
+ * the FP64 sweep and have acyclic sweep graphs (else BGK_E_UNSUPPORTED).
+ * The batch borrows the solvers (and their DAGs): destroy it first. */
+typedef struct bgk_batch bgk_batch;
+
+typedef struct {
+  int graph;          /* 1: replay captured hipGraphs; 0: launch the same kernels eagerly */
+  int chunk_iters;    /* Picard iterations between convergence polls (0: 4) */
+  int sweep_threads;  /* workgroup size of the batched sweep, a multiple of 64 up to 256
+                         (0: 192) */
+} bgk_batch_opts;
+
+typedef struct {
+  int status;             /* BGK_OK or this instance's error code */
+  int stages;
+  int iters[4];           /* Picard iterations per stage */
+  int total_iters;
+  double last_ratio[4];
+  int maxw_fallbacks;
+  double finish_ms;       /* host milliseconds from the step's start to the poll
+                             that saw this instance's last stage stop */
+} bgk_batch_stats;
+
+int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_batch_opts* opts,
+                     bgk_batch** out);
+int bgk_batch_destroy(bgk_batch* batch);
+
+/* One DIRK step of every instance.  f: host array of n device pointers
+ * (sweep layout), f^k on entry and f^{k+1} on exit; an instance that fails
+ * leaves its f unspecified and reports its code in stats[i].status (stats:
+ * host array of n, or NULL).  Returns BGK_OK when every instance succeeded,
+ * else the first failing instance's code.  Ordered after prior work on
+ * `stream` and before later work on it; runs on an internal stream of
+ * default priority and synchronises once per chunk. */
+int bgk_batch_step(bgk_batch* batch, double* const* f, bgk_batch_stats* stats,
+                   bgk_stream_t stream);
+
+/* Autotuning probe: from f's moments builds the Maxwellians, then times
+ * `reps` batched sweeps of the first stage with `threads` per workgroup
+ * (reading f, writing the solvers' f^k scratch); *ms = milliseconds per
+ * sweep (host float).  Leaves f unchanged. */
+int bgk_batch_time_sweep(bgk_batch* batch, double* const* f, int threads, int reps, float* ms,
+                         bgk_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Learned Picard initial guess (an addition to the paper's method: the       */
 /* paper initialises Picard from the previous stage, Sec. 4)                  */
 /* ------------------------------------------------------------------------ */

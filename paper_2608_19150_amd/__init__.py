@@ -37,6 +37,7 @@ EXPORTED = [
     "bgk_mlp_create", "bgk_mlp_destroy", "bgk_mlp_set_params", "bgk_mlp_get_params",
     "bgk_mlp_set_normalization", "bgk_mlp_forward", "bgk_mlp_loss_grad", "bgk_mlp_adam_step",
     "bgk_mlp_features", "bgk_mlp_targets", "bgk_mlp_guess",
+    "bgk_batch_create", "bgk_batch_destroy", "bgk_batch_step", "bgk_batch_time_sweep",
 ]
 
 
@@ -331,6 +332,67 @@ def problem_setup(pr, dag=None, **dag_kw):
 
 
 # ---------------------------------------------------------------------------
+# batched instances
+# ---------------------------------------------------------------------------
+class BatchOpts(C.Structure):
+    _fields_ = [("graph", C.c_int), ("chunk_iters", C.c_int), ("sweep_threads", C.c_int)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("stages", C.c_int), ("iters", C.c_int * 4),
+                ("total_iters", C.c_int), ("last_ratio", C.c_double * 4),
+                ("maxw_fallbacks", C.c_int), ("finish_ms", C.c_double)]
+
+
+_lib.bgk_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(BatchOpts),
+                                  C.POINTER(C.c_void_p)]
+_lib.bgk_batch_destroy.argtypes = [C.c_void_p]
+_lib.bgk_batch_step.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(BatchStats),
+                                C.c_void_p]
+_lib.bgk_batch_time_sweep.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int,
+                                      C.POINTER(C.c_float), C.c_void_p]
+
+
+class Batch:
+    """bgk_batch: many solvers stepped together (one launch per kernel per
+    Picard iteration, optional hipGraph replay of iteration chunks)."""
+
+    def __init__(self, solvers, *, graph=True, chunk_iters=4, sweep_threads=0):
+        self.solvers = list(solvers)          # keep them (and their DAGs) alive
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        o = BatchOpts(int(bool(graph)), int(chunk_iters), int(sweep_threads))
+        h = C.c_void_p()
+        _check(_lib.bgk_batch_create(arr, len(self.solvers), C.byref(o), C.byref(h)))
+        self.h = h
+
+    def __del__(self, _destroy=_lib.bgk_batch_destroy):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _destroy(h)
+            self.h = None
+
+    def _fptrs(self, fs):
+        assert len(fs) == len(self.solvers)
+        return (C.c_void_p * len(fs))(*[f.data_ptr() for f in fs])
+
+    def step(self, fs, stream=None, check=True):
+        """One DIRK step of every instance; returns per-instance stats."""
+        st = (BatchStats * len(fs))()
+        rc = _lib.bgk_batch_step(self.h, self._fptrs(fs), st, _stream(stream))
+        if check:
+            _check(rc)
+        return [{"status": s.status, "iters": list(s.iters[:s.stages]),
+                 "total_iters": s.total_iters, "last_ratio": list(s.last_ratio[:s.stages]),
+                 "fallbacks": s.maxw_fallbacks, "finish_ms": s.finish_ms} for s in st]
+
+    def time_sweep(self, fs, threads, reps=3, stream=None):
+        ms = C.c_float()
+        _check(_lib.bgk_batch_time_sweep(self.h, self._fptrs(fs), int(threads), int(reps),
+                                         C.byref(ms), _stream(stream)))
+        return ms.value
+
+
+# ---------------------------------------------------------------------------
 # learned Picard initial guess
 # ---------------------------------------------------------------------------
 MLP_ARCH = (11, 64, 64, 64, 5)
@@ -448,4 +510,4 @@ def mlp_targets(dag, U_t, U_tm1, stream=None):
 
 __all__ = ["Dag", "Solver", "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
            "state_coefficients", "problem_setup", "BGKError", "exported_symbols", "Mlp",
-           "mlp_features", "mlp_targets", "mlp_flatten", "mlp_unflatten", "math"]
+           "mlp_features", "mlp_targets", "mlp_flatten", "mlp_unflatten", "Batch", "math"]

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "device_common.h"
+#include "kinetic_args.h"
 
 namespace bgk {
 
@@ -17,28 +18,24 @@ namespace bgk {
 // reproducible.  Optionally the per-block pieces of the convergence norms
 // are written for a fixed-order final reduction.
 // ----------------------------------------------------------------------------
-constexpr int MOM_THREADS = 256;
 
-struct MomArgs {
-  const double* f;
-  const int32_t* pos;
-  const int32_t* uid;
-  const double* v;
-  const double* w;
-  double* U;
-  const double* U_prev;
-  double* partial;  // [gridDim][6]: |dU_m|^2 (m = 0,1,2), |U_prev_m|^2
-  int n_cells;
-  int n_v;
-};
 
 template <int DIM, int NP, int VL>
-__global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
+struct MomSmem {
+  static constexpr int CB = MOM_THREADS / VL, NM = DIM + 2;
+  static constexpr int RED = VL > 1 ? (VL - 1) * CB * NP * NM : 1;
+  static constexpr int TOTAL = RED + 6 * CB;
+};
+
+// One block of the moment kernel: block `blk` of the instance; `smem` holds
+// MomSmem<DIM, NP, VL>::TOTAL doubles of LDS.
+template <int DIM, int NP, int VL>
+__device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double* smem) {
   constexpr int CB = MOM_THREADS / VL, NM = DIM + 2;
-  __shared__ double s_red[MOM_THREADS / 64 > 0 ? (VL > 1 ? (VL - 1) * CB * NP * NM : 1) : 1];
-  __shared__ double s_norm[6][CB];
+  double* s_red = smem;
+  double* s_norm = smem + MomSmem<DIM, NP, VL>::RED;  // [6][CB]
   const int tid = threadIdx.x, c = tid % CB, lane = tid / CB;
-  const int K = blockIdx.x * CB + c;
+  const int K = blk * CB + c;
   const bool valid = K < a.n_cells;
   double acc[NP][NM];
 #pragma unroll
@@ -107,7 +104,7 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
     }
     if (a.U_prev)
 #pragma unroll
-      for (int i = 0; i < 6; ++i) s_norm[i][c] = nrm[i];
+      for (int i = 0; i < 6; ++i) s_norm[i * CB + c] = nrm[i];
   }
   if (a.U_prev) {
     __syncthreads();
@@ -115,18 +112,23 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
     for (int off = CB / 2; off > 0; off >>= 1) {
       if (tid < off)
 #pragma unroll
-        for (int i = 0; i < 6; ++i) s_norm[i][tid] += s_norm[i][tid + off];
+        for (int i = 0; i < 6; ++i) s_norm[i * CB + tid] += s_norm[i * CB + tid + off];
       __syncthreads();
     }
-    if (tid < 6) a.partial[(size_t)blockIdx.x * 6 + tid] = s_norm[tid][0];
+    if (tid < 6) a.partial[(size_t)blk * 6 + tid] = s_norm[tid * CB];
   }
+}
+
+template <int DIM, int NP, int VL>
+__global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
+  __shared__ double smem[MomSmem<DIM, NP, VL>::TOTAL];
+  moments_block<DIM, NP, VL>(a, blockIdx.x, smem);
 }
 
 // Final reduction of the block pieces in a fixed order; writes
 // out[0..2] = ratios, out[3] = max ratio.
-__global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partial, int nblk,
-                                               double* out) {
-  __shared__ double s[6][256];
+__device__ __forceinline__ void ratio_block(const double* __restrict__ partial, int nblk,
+                                            double* out, double (*s)[256]) {
   const int tid = threadIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int b = tid; b < nblk; b += 256)
@@ -155,30 +157,16 @@ __global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partia
   }
 }
 
+__global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partial, int nblk,
+                                               double* out) {
+  __shared__ double s[6][256];
+  ratio_block(partial, nblk, out, s);
+}
+
 // ----------------------------------------------------------------------------
 // Maxwellian coefficients and collision frequency, one thread per node.
 // ----------------------------------------------------------------------------
-struct MaxwArgs {
-  const double* U;
-  double* coef;
-  double* nu;
-  double* M_dense;          // canonical [n_nodes][n_v] or null
-  int32_t* status;          // [0] fallbacks, [1] non-physical, or null
-  unsigned long long* numax;  // bit pattern of max nu (nu >= 0), or null
-  const double* v;
-  const double* w;
-  const double* x1;         // tensor 1-D nodes or null
-  const double* w1;
-  int n1;
-  int n_v;
-  int64_t n_nodes;
-  int mode;
-  int nu_kind;
-  double nu_const, kn, L;
-  // MATCHED: per node, set once its Newton solve has failed; such a node
-  // keeps the DIRECT coefficients while the flag stays set (nullable)
-  uint8_t* sticky;
-};
+
 
 template <int N>
 __device__ bool small_solve(double (&A)[N][N], double (&b)[N]) {
@@ -364,13 +352,12 @@ __device__ void matched_system(const MaxwArgs& p, const double (&x)[DIM + 2],
 }
 
 template <int DIM>
-__global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
+__device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double* __restrict__ Uin,
+                                                int64_t i) {
   constexpr int NM = DIM + 2;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= p.n_nodes) return;
   double U[NM];
 #pragma unroll
-  for (int m = 0; m < NM; ++m) U[m] = p.U[i * NM + m];
+  for (int m = 0; m < NM; ++m) U[m] = Uin[i * NM + m];
   const double n = U[0];
   double u[DIM], uu = 0.0;
 #pragma unroll
@@ -469,6 +456,13 @@ __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
 }
 
 template <int DIM>
+__global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= p.n_nodes) return;
+  maxwellian_node<DIM>(p, p.U, i);
+}
+
+template <int DIM>
 __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __restrict__ coef,
                                  int64_t n) {
   constexpr int NM = DIM + 2;
@@ -489,21 +483,27 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
 // and M(v_j) is the product of d table entries (node fastest, coalesced).
 template <int DIM>
+__device__ __forceinline__ void table_entry(const double* __restrict__ coef,
+                                            const double* __restrict__ x1, double* __restrict__ tab,
+                                            int64_t n_nodes, int n1, int64_t idx) {
+  constexpr int NM = DIM + 2;
+  const int64_t node = idx % n_nodes;
+  const int64_t r = idx / n_nodes;
+  const int i = (int)(r % n1), al = (int)(r / n1);
+  const double x = x1[i];
+  const double* c = coef + node * NM;
+  double e = __fma_rn(c[1 + DIM], x * x, c[1 + al] * x);
+  if (al == 0) e += c[0];
+  tab[idx] = bgk_exp(e);
+}
+
+template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ x1,
                               double* __restrict__ tab, int64_t n_nodes, int n1) {
-  constexpr int NM = DIM + 2;
   const int64_t total = n_nodes * DIM * n1;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t node = idx % n_nodes;
-    const int64_t r = idx / n_nodes;
-    const int i = (int)(r % n1), al = (int)(r / n1);
-    const double x = x1[i];
-    const double* c = coef + node * NM;
-    double e = __fma_rn(c[1 + DIM], x * x, c[1 + al] * x);
-    if (al == 0) e += c[0];
-    tab[idx] = bgk_exp(e);
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    table_entry<DIM>(coef, x1, tab, n_nodes, n1, idx);
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, double* tab, hipStream_t stream) {
@@ -606,6 +606,141 @@ int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_
   else
     hipLaunchKernelGGL(k_maxwellian<3>, grid, block, 0, stream, p);
   BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Batched forms: one launch over many instances (per-instance arguments in
+// device memory; an instance whose done flag is set is skipped).
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int find_instance(const T* __restrict__ first, int n, T x) {
+  int lo = 0, hi = n;  // first[lo] <= x < first[lo + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __restrict__ kin,
+                                                          const int32_t* __restrict__ par,
+                                                          const int32_t* __restrict__ done,
+                                                          const int64_t* __restrict__ first,
+                                                          int n_inst, int64_t total) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int i = find_instance<int64_t>(first, n_inst, g);
+  if (done[i]) return;
+  const BatchKin& k = kin[i];
+  maxwellian_node<DIM>(k.maxw, k.U[par[i]], g - first[i]);
+}
+
+template <int DIM>
+__global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* __restrict__ done,
+                               const int64_t* __restrict__ first, int n_inst, int64_t total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_instance<int64_t>(first, n_inst, g);
+    if (done[i] || !kin[i].mtab) continue;
+    const BatchKin& k = kin[i];
+    table_entry<DIM>(k.maxw.coef, k.x1, k.mtab, k.n_nodes, k.n1, g - first[i]);
+  }
+}
+
+template <int DIM, int NP>
+__device__ __forceinline__ void moments_vl(const MomArgs& a, int vl, int blk, double* smem) {
+  if (vl == 1)
+    moments_block<DIM, NP, 1>(a, blk, smem);
+  else if (vl == 4)
+    moments_block<DIM, NP, 4>(a, blk, smem);
+  else
+    moments_block<DIM, NP, 16>(a, blk, smem);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(MOM_THREADS) void k_moments_batch(
+    const BatchKin* __restrict__ kin, const int32_t* __restrict__ par,
+    const int32_t* __restrict__ done, const int32_t* __restrict__ first, int n_inst,
+    int with_ratio) {
+  constexpr int SM = DIM == 2 ? MomSmem<2, 6, 16>::TOTAL : MomSmem<3, 4, 16>::TOTAL;
+  static_assert(DIM == 3 || (MomSmem<2, 3, 16>::TOTAL <= SM && MomSmem<2, 6, 4>::TOTAL <= SM),
+                "moment scratch");
+  __shared__ double smem[SM];
+  const int i = find_instance<int32_t>(first, n_inst, (int32_t)blockIdx.x);
+  if (done[i]) return;
+  const BatchKin& k = kin[i];
+  MomArgs a = k.mom;
+  const int p = par[i];
+  a.U = const_cast<double*>(k.U[p ^ 1]);
+  a.U_prev = with_ratio ? k.U[p] : nullptr;
+  const int blk = blockIdx.x - first[i];
+  if constexpr (DIM == 2) {
+    if (k.np == 3)
+      moments_vl<2, 3>(a, k.mom_vl, blk, smem);
+    else
+      moments_vl<2, 6>(a, k.mom_vl, blk, smem);
+  } else {
+    moments_vl<3, 4>(a, k.mom_vl, blk, smem);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ratio_batch(const BatchKin* __restrict__ kin,
+                                                     const int32_t* __restrict__ done) {
+  __shared__ double s[6][256];
+  const int i = blockIdx.x;
+  if (done[i]) return;
+  ratio_block(kin[i].mom.partial, kin[i].mom_blocks, kin[i].ratio, s);
+}
+
+int launch_maxwellian_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
+                            const int64_t* node_first, int n_inst, int64_t n_total,
+                            hipStream_t stream) {
+  if (n_total == 0) return BGK_OK;
+  const dim3 grid((unsigned)((n_total + 127) / 128)), block(128);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_maxwellian_batch<2>, grid, block, 0, stream, kin, par, done, node_first,
+                       n_inst, n_total);
+  else
+    hipLaunchKernelGGL(k_maxwellian_batch<3>, grid, block, 0, stream, kin, par, done, node_first,
+                       n_inst, n_total);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_tables_batch(int dim, const BatchKin* kin, const int32_t* done,
+                        const int64_t* entry_first, int n_inst, int64_t n_total,
+                        hipStream_t stream) {
+  if (n_total == 0) return BGK_OK;
+  const int grid = (int)std::min<int64_t>((n_total + 255) / 256, 65536);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_tables_batch<2>, dim3(grid), dim3(256), 0, stream, kin, done, entry_first,
+                       n_inst, n_total);
+  else
+    hipLaunchKernelGGL(k_tables_batch<3>, dim3(grid), dim3(256), 0, stream, kin, done, entry_first,
+                       n_inst, n_total);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
+                         const int32_t* blk_first, int n_inst, int n_blocks, bool with_ratio,
+                         hipStream_t stream) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_moments_batch<2>, dim3(n_blocks), dim3(MOM_THREADS), 0, stream, kin, par,
+                       done, blk_first, n_inst, (int)with_ratio);
+  else
+    hipLaunchKernelGGL(k_moments_batch<3>, dim3(n_blocks), dim3(MOM_THREADS), 0, stream, kin, par,
+                       done, blk_first, n_inst, (int)with_ratio);
+  BGK_HIP(hipGetLastError());
+  if (with_ratio) {
+    hipLaunchKernelGGL(k_ratio_batch, dim3(n_inst), dim3(256), 0, stream, kin, done);
+    BGK_HIP(hipGetLastError());
+  }
   return BGK_OK;
 }
 

@@ -1,0 +1,74 @@
+// Arguments of the moment and Maxwellian kernels, and the batched launchers.
+#pragma once
+#include "internal.h"
+
+namespace bgk {
+
+constexpr int MOM_THREADS = 256;
+
+struct MomArgs {
+  const double* f;
+  const int32_t* pos;
+  const int32_t* uid;
+  const double* v;
+  const double* w;
+  double* U;
+  const double* U_prev;
+  double* partial;  // [gridDim][6]: |dU_m|^2 (m = 0,1,2), |U_prev_m|^2
+  int n_cells;
+  int n_v;
+};
+
+struct MaxwArgs {
+  const double* U;
+  double* coef;
+  double* nu;
+  double* M_dense;          // canonical [n_nodes][n_v] or null
+  int32_t* status;          // [0] fallbacks, [1] non-physical, or null
+  unsigned long long* numax;  // bit pattern of max nu (nu >= 0), or null
+  const double* v;
+  const double* w;
+  const double* x1;         // tensor 1-D nodes or null
+  const double* w1;
+  int n1;
+  int n_v;
+  int64_t n_nodes;
+  int mode;
+  int nu_kind;
+  double nu_const, kn, L;
+  // MATCHED: per node, set once its Newton solve has failed; such a node
+  // keeps the DIRECT coefficients while the flag stays set (nullable)
+  uint8_t* sticky;
+};
+
+// Per-instance description for the batched kinetic kernels.  Nodal moments
+// ping-pong between U[0] and U[1]: the current iterate is U[par[i]].
+struct BatchKin {
+  MaxwArgs maxw;       // .U is replaced by U[par]
+  MomArgs mom;         // .U / .U_prev are replaced by U[par ^ 1] / U[par]
+  const double* U[2];
+  double* mtab;        // factorised tables or null
+  const double* x1;
+  int n1;
+  int mom_vl;          // velocity lanes of the moment kernel (1, 4, 16)
+  int mom_blocks;
+  int np;              // nodes per cell
+  int64_t n_nodes;
+  double* ratio;       // [4]
+};
+
+// Launchers over all instances; done[i] != 0 skips instance i.  blk_first
+// is the exclusive prefix of per-instance block counts (n + 1 entries).
+int launch_maxwellian_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
+                            const int64_t* node_first, int n_inst, int64_t n_total,
+                            hipStream_t stream);
+int launch_tables_batch(int dim, const BatchKin* kin, const int32_t* done,
+                        const int64_t* entry_first, int n_inst, int64_t n_total,
+                        hipStream_t stream);
+int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
+                         const int32_t* blk_first, int n_inst, int n_blocks, bool with_ratio,
+                         hipStream_t stream);
+int moment_vl(const tgs_dag* d);
+int moment_blocks(const tgs_dag* d);
+
+}  // namespace bgk

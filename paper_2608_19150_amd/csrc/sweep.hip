@@ -26,37 +26,11 @@
 #include <type_traits>
 
 #include "device_common.h"
+#include "sweep_args.h"
 
 namespace bgk {
 
-struct SweepArgs {
-  const double* geo;
-  const FacetRec* facet;
-  const double* v;
-  const int32_t* rec;
-  const int32_t* recx;
-  const int32_t* perm;
-  const int32_t* goff;
-  const int32_t* gmin;
-  const int64_t* gbase;
-  const int32_t* G;
-  const int32_t* vorder;
-  const int32_t* node_map;   // internal cell -> row of the nodal arrays (null: identity)
-  const double* nu;
-  const double* mcoef;
-  const double* mtab;        // factorised Maxwellian [dim][n1][n_nodes] (internal order) or null
-  const double* q;
-  const double* bc_coef;
-  const double* bc_dense;
-  const double* f_prev;
-  double* f_out;
-  float* d32;                // FP32 corrections (sweep layout), FP32 form only
-  double sigma_shift;
-  double q_scale;
-  int n_cells;
-  int n_v;
-  int n1;                    // points per axis of a tensor velocity grid (mtab)
-};
+
 
 // ---------------------------------------------------------------------------
 // Integer-scaled reference tables.  Every normalised element integral is a
@@ -418,14 +392,14 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// One workgroup's walk over velocity j's generations; `ring` is LDS of
+// RS * NP values of the sweep's precision.
 template <int DIM, int ORDER, bool F32, bool TAB>
-__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_velocity(
+    const SweepArgs& a, int j, typename std::conditional<F32, float, double>::type* ring) {
   constexpr int NF = DIM + 1;
   constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
-  using RT = typename std::conditional<F32, float, double>::type;
-  __shared__ RT ring[RS * NP];
   const int T = blockDim.x, tid = threadIdx.x;
-  const int j = a.vorder[blockIdx.x];
   double v[DIM], v2 = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -507,13 +481,66 @@ __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep
   }
 }
 
+template <int DIM, int ORDER, bool F32, bool TAB>
+__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep(SweepArgs a) {
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
+  using RT = typename std::conditional<F32, float, double>::type;
+  __shared__ RT ring[RS * NP];
+  sweep_velocity<DIM, ORDER, F32, TAB>(a, a.vorder[blockIdx.x], ring);
+}
+
+// Batched FP64 sweep over many instances in one launch: block b sweeps
+// velocity map[b].y (a position in its instance's velocity order) of
+// instance map[b].x; instances flagged done skip.  2D instances may mix P1
+// and P2 (both rings hold 3072 values).
+template <int DIM, bool TAB>
+__global__ __launch_bounds__(256, 3) void k_sweep_batch(const SweepArgs* __restrict__ args,
+                                                        const int2* __restrict__ map,
+                                                        const int32_t* __restrict__ done) {
+  constexpr int RING = SweepCfg<DIM, 1>::RS * SweepCfg<DIM, 1>::NP;
+  static_assert(DIM == 3 || SweepCfg<2, 2>::RS * SweepCfg<2, 2>::NP <= RING, "ring size");
+  __shared__ double ring[RING];
+  const int2 m = map[blockIdx.x];
+  if (done[m.x]) return;
+  const SweepArgs a = args[m.x];
+  const int j = a.vorder[m.y];
+  if constexpr (DIM == 2) {
+    if (a.order == 1)
+      sweep_velocity<2, 1, false, TAB>(a, j, ring);
+    else
+      sweep_velocity<2, 2, false, TAB>(a, j, ring);
+  } else {
+    sweep_velocity<3, 1, false, TAB>(a, j, ring);
+  }
+}
+
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nblocks,
+                       const int32_t* done, int threads, hipStream_t stream) {
+  const dim3 grid(nblocks), block(threads);
+  if (dim == 2 && tab)
+    hipLaunchKernelGGL((k_sweep_batch<2, true>), grid, block, 0, stream, args, map, done);
+  else if (dim == 2)
+    hipLaunchKernelGGL((k_sweep_batch<2, false>), grid, block, 0, stream, args, map, done);
+  else if (tab)
+    hipLaunchKernelGGL((k_sweep_batch<3, true>), grid, block, 0, stream, args, map, done);
+  else
+    hipLaunchKernelGGL((k_sweep_batch<3, false>), grid, block, 0, stream, args, map, done);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+                          const double* mtab, float* d32) {
+  return SweepArgs{d->d_geo,   d->d_facet, d->d_v,      d->d_rec,   d->d_recx,  d->d_perm,
+                   d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, node_map, io->nu,
+                   io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
+                   io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
+                   d->n_1d,    d->order};
+}
+
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
                  const double* mtab, float* d32, hipStream_t stream, int threads) {
-  SweepArgs a{d->d_geo,   d->d_facet, d->d_v,      d->d_rec,   d->d_recx,  d->d_perm,
-              d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, node_map, io->nu,
-              io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
-              io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
-              d->n_1d};
+  const SweepArgs a = make_sweep_args(d, io, node_map, mtab, d32);
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {

@@ -1,0 +1,44 @@
+// Arguments of the sweep kernels (one instance, one sweep).
+#pragma once
+#include "internal.h"
+
+namespace bgk {
+
+struct SweepArgs {
+  const double* geo;
+  const FacetRec* facet;
+  const double* v;
+  const int32_t* rec;
+  const int32_t* recx;
+  const int32_t* perm;
+  const int32_t* goff;
+  const int32_t* gmin;
+  const int64_t* gbase;
+  const int32_t* G;
+  const int32_t* vorder;
+  const int32_t* node_map;   // internal cell -> row of the nodal arrays (null: identity)
+  const double* nu;
+  const double* mcoef;
+  const double* mtab;        // factorised Maxwellian [dim][n1][n_nodes] (internal order) or null
+  const double* q;
+  const double* bc_coef;
+  const double* bc_dense;
+  const double* f_prev;
+  double* f_out;
+  float* d32;                // FP32 corrections (sweep layout), FP32 form only
+  double sigma_shift;
+  double q_scale;
+  int n_cells;
+  int n_v;
+  int n1;                    // points per axis of a tensor velocity grid (mtab)
+  int order;
+};
+
+// One launch of the batched FP64 sweep: block b sweeps velocity position
+// map[b].y of instance map[b].x with args[map[b].x], unless done[map[b].x].
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nblocks,
+                       const int32_t* done, int threads, hipStream_t stream);
+SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+                          const double* mtab, float* d32);
+
+}  // namespace bgk
