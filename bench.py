@@ -131,6 +131,121 @@ def run_gpu(pr, steps, warmup, precision, timing=True):
     return out
 
 
+def run_c4(steps, warmup, tune_cache):
+    """Batched uneven instances (64 seeded 2D problems, P1/P2, 8^2..32^2
+    velocities, Kn log-uniform in [1e-4, 1], DIRK2): one batched launch per
+    kernel per Picard iteration, hipGraph-replayed chunks, autotuned sweep
+    workgroup size.  Instances that go non-physical in the warm-up step are
+    dropped and counted.  Also times the same step with each instance stepped
+    alone, one after another."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    from paper_2608_19150_amd import autotune
+    t0 = time.perf_counter()
+    probs = P.config_c4_instances()
+    setups = []
+    for pr in probs:
+        d, f0, bc, dt = B.problem_setup(pr)
+        s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, mode="MATCHED",
+                     nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn)
+        setups.append((pr, s, f0))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    # warm-up: find instances that cannot be stepped (non-physical moments)
+    probe = B.Batch([x[1] for x in setups], graph=False)
+    fcopy = [x[2].clone() for x in setups]
+    st = probe.step(fcopy, check=False)
+    keep = [i for i, x in enumerate(st) if x["status"] == 0]
+    dropped = len(setups) - len(keep)
+    del probe, fcopy
+    setups = [setups[i] for i in keep]
+    solvers, fs = [x[1] for x in setups], [x[2] for x in setups]
+    best, tune_ms = autotune.tune_sweep_threads(solvers, fs, cache_path=tune_cache,
+                                                use_cache=False)
+    batch = B.Batch(solvers, graph=True, chunk_iters=4, sweep_threads=best)
+    for _ in range(warmup):
+        batch.step(fs, check=False)
+    torch.cuda.synchronize()
+    per_inst, sweeps, failed = [], 0, set()
+    nu = [s.dag.n_cells * s.dag.n_p * s.dag.n_v for s in solvers]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = batch.step(fs, check=False)
+        for i, x in enumerate(st):
+            if x["status"] != 0:
+                failed.add(i)
+            else:
+                per_inst.append(x["finish_ms"])
+                sweeps += nu[i] * x["total_iters"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the same step, each instance alone
+    t1 = time.perf_counter()
+    seq_sweeps = 0
+    for s, f in zip(solvers, fs):
+        g = f.clone()
+        r = s.step(g)
+        seq_sweeps += s.dag.n_cells * s.dag.n_p * s.dag.n_v * r["total_iters"]
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    pct = np.percentile(np.array(per_inst), [50, 99])
+    return {"instances": len(solvers), "dropped_nonphysical": dropped,
+            "failed_in_timed_steps": len(failed),
+            "unknowns_total": int(sum(nu)), "steps": steps, "ms_per_step": 1e3 * elapsed / steps,
+            "value": sweeps / elapsed, "unit": "unknowns/s",
+            "p50_instance_step_ms": float(pct[0]), "p99_instance_step_ms": float(pct[1]),
+            "sweep_threads": best, "autotune_ms_per_sweep": tune_ms,
+            "sequential_single_instance_value": seq_sweeps / seq,
+            "sequential_single_instance_ms_per_step": 1e3 * seq, "setup_s": setup_s}
+
+
+def run_c3(steps, warmup, kn):
+    """3D x 3D: ~55k tetrahedra, P1, 16^3 velocities, backward Euler."""
+    import problems as P
+    pr = P.config_c3(kn=kn)
+    r = run_gpu(pr, steps, warmup, 0)
+    sweep_s = r["sweep_ms_avg"] * 1e-3
+    achieved = SWEEP_BYTES_PER_UNKNOWN * r["n_unknown"] / sweep_s / 1e9
+    return {"workload": pr.name, "kn": kn, "unknowns": r["n_unknown"], "max_generations": r["max_G"],
+            "value": r["value"], "unit": "unknowns/s", "ms_per_step": r["ms_per_step"],
+            "picard_iters": r["iters"], "kernel_ms": {"sweep": r["sweep_ms_avg"],
+                                                     "moments": r["moments_ms_avg"],
+                                                     "maxwellian": r["maxwellian_ms_avg"]},
+            "sweep_roofline_frac": achieved / HBM_PEAK_GBS, "sweep_achieved_gbs": achieved}
+
+
+def run_c5(steps, n_train, kn):
+    """Learned initial guess: train on solver trajectories of small seeded 3D
+    Riemann problems (12^3 velocities), then step the 3D workload with the
+    plain previous-step guess, linear extrapolation, and the network; report
+    Picard iterations and seconds per step and the moment difference."""
+    import torch
+
+    import problems as P
+    from paper_2608_19150_amd import learned
+    train = [P.learned_guess_problem(3, 5000 + i, 5, 12, kn_range=(1e-3, 1.0))
+             for i in range(n_train)]
+    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=30, batch=4096, lr=2e-3, seed=0)
+    pr = P.config_c3(kn=kn)
+    res = learned.compare(pr, mlp, n_steps=steps, tau=1e-9)
+    out = {"workload": pr.name, "tau": 1e-9, "train_trajectories": info["trajectories"],
+           "train_skipped": len(info["skipped"]), "train_samples": info["samples"],
+           "train_loss_first_last": [info["loss"][0], info["loss"][-1]],
+           "generate_s": info["generate_s"], "train_s": info["train_s"]}
+    ref = res["plain"]["U"][-1]
+    for mode, r in res.items():
+        # step 0 has no history and uses the plain guess in every mode
+        out[mode] = {"iters": r["iters"], "iters_after_first": int(sum(r["iters"][1:])),
+                     "s_per_step_after_first": float(np.mean(r["seconds"][1:])),
+                     "fallbacks": r["fallbacks"],
+                     "moment_diff_vs_plain": learned.moment_difference(r["U"][-1], ref, 3)}
+    del res
+    torch.cuda.empty_cache()
+    return out
+
+
 def moment_error(U, Uref, dim):
     """Per component: |U_m - Uref_m| / max(|Uref_m|, s_m |Uref_0|), s = (0,1,0)."""
     blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
@@ -194,6 +309,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-velocities", type=int, default=32)
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--c5-train", type=int, default=24, help="training trajectories")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -222,6 +341,36 @@ def main():
                 "moment_err_vs_fp64": moment_error(r32["U"], r64["U"], 2)}
         print(f"[bench] fp32+refine {r32['value']:.3e} unknowns/s, {r32['ms_per_step']:.1f} ms/step",
               file=sys.stderr, flush=True)
+    import paper_2608_19150_amd as B
+
+    def section(name, fn, report):
+        print(f"[bench] {name}: start", file=sys.stderr, flush=True)
+        try:
+            out = fn()
+        except B.BGKError as e:       # a workload the method cannot step is reported, not fatal
+            print(f"[bench] {name}: {e}", file=sys.stderr, flush=True)
+            return {"error": str(e)}
+        print(f"[bench] {name}: " + report(out), file=sys.stderr, flush=True)
+        return out
+
+    c3 = c4 = c5 = None
+    if not args.no_c3:
+        c3 = section("c3", lambda: run_c3(2, 1, 1e-2),
+                     lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.1f} ms/step, "
+                               f"sweep {c['kernel_ms']['sweep']:.2f} ms, G {c['max_generations']}")
+    if not args.no_c4:
+        import tempfile
+        with tempfile.TemporaryDirectory() as tdir:
+            c4 = section("c4", lambda: run_c4(args.steps, 1, os.path.join(tdir, "tune.json")),
+                         lambda c: f"{c['value']:.3e} unknowns/s batched vs "
+                                   f"{c['sequential_single_instance_value']:.3e} one by one; "
+                                   f"p50/p99 {c['p50_instance_step_ms']:.1f}/"
+                                   f"{c['p99_instance_step_ms']:.1f} ms")
+    if not args.no_c5:
+        c5 = section("c5", lambda: run_c5(4, args.c5_train, 1e-2),
+                     lambda c: f"iters after step 1: plain {c['plain']['iters_after_first']} "
+                               f"linear {c['linear']['iters_after_first']} "
+                               f"learned {c['learned']['iters_after_first']}")
     sweep_s = r64["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r64["n_unknown"] / sweep_s / 1e9
     cpu = None
@@ -247,6 +396,9 @@ def main():
                      "kernel": "k_sweep<2, 2, false, true>",
                      "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},
         "cpu_baseline": cpu,
+        "c3_3d": c3,
+        "c4_batched": c4,
+        "c5_learned_guess": c5,
     }
     print(json.dumps(line), flush=True)
 

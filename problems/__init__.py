@@ -84,12 +84,21 @@ class State:
         if self.kind == "plane":
             nrm = np.asarray(self.data["normal"], dtype=np.float64)
             c = np.asarray(self.data["center"], dtype=np.float64)
-            left = (x - c) @ nrm < 0.0
             nl, ul, tl = self.data["left"]
             nr, ur, tr = self.data["right"]
+            ul = np.asarray(ul, dtype=np.float64)[:dim]
+            ur = np.asarray(ur, dtype=np.float64)[:dim]
+            width = float(self.data.get("width", 0.0))
+            if width > 0.0:
+                # jump spread over a tanh layer of the given width
+                s = 0.5 * (1.0 + np.tanh(((x - c) @ nrm) / width))
+                n = nl + (nr - nl) * s
+                u = ul[None, :] + (ur - ul)[None, :] * s[:, None]
+                th = tl + (tr - tl) * s
+                return n.astype(np.float64), u, th.astype(np.float64)
+            left = (x - c) @ nrm < 0.0
             n = np.where(left, nl, nr).astype(np.float64)
-            u = np.where(left[:, None], np.asarray(ul, dtype=np.float64)[None, :dim],
-                         np.asarray(ur, dtype=np.float64)[None, :dim])
+            u = np.where(left[:, None], ul[None, :], ur[None, :])
             th = np.where(left, tl, tr).astype(np.float64)
             return n, u, th
         if self.kind == "fourier":
@@ -258,16 +267,17 @@ def sod_state(dim: int) -> State:
                            "left": SOD_LEFT, "right": SOD_RIGHT})
 
 
-def planar_riemann_state(dim: int, seed: int) -> State:
-    """Sod states split by the plane through the domain centre with a seeded random normal."""
+def planar_riemann_state(dim: int, seed: int, width: float = 0.0) -> State:
+    """Sod states split by the plane through the domain centre with a seeded
+    random normal; width > 0 spreads the jump over a tanh layer."""
     rng = np.random.default_rng(seed)
     nrm = rng.normal(size=dim)
     nrm /= np.linalg.norm(nrm)
     return State("plane", {"normal": nrm, "center": np.full(dim, 0.5),
-                           "left": SOD_LEFT, "right": SOD_RIGHT})
+                           "left": SOD_LEFT, "right": SOD_RIGHT, "width": width})
 
 
-def random_riemann_state(dim: int, seed: int) -> State:
+def random_riemann_state(dim: int, seed: int, width: float = 0.0) -> State:
     """Sod-like planar Riemann problem with seeded states and normal: left
     (n, theta) in [0.5, 1.5] x [0.7, 1.3], right n in [0.1, 0.5], theta in
     [0.6, 1.0], both at rest; the plane passes through a seeded point of the
@@ -278,7 +288,7 @@ def random_riemann_state(dim: int, seed: int) -> State:
     left = (float(rng.uniform(0.5, 1.5)), (0.0, 0.0, 0.0), float(rng.uniform(0.7, 1.3)))
     right = (float(rng.uniform(0.1, 0.5)), (0.0, 0.0, 0.0), float(rng.uniform(0.6, 1.0)))
     return State("plane", {"normal": nrm, "center": rng.uniform(0.25, 0.75, size=dim),
-                           "left": left, "right": right})
+                           "left": left, "right": right, "width": width})
 
 
 def fourier_state(dim: int, seed: int, modes: int = 8, amplitude: float = 0.1) -> State:
@@ -324,11 +334,18 @@ def config_c2(n_side: int = 316) -> Problem:
                    tau=1e-10, name=f"c2_fourier_p2_{2 * n_side * n_side}tri_32x32")
 
 
+# Riemann-type workloads spread the jump over a tanh layer about this many
+# lattice cells wide: a sharp jump drives some P1 nodal moments non-physical
+# (the method has no limiter; both the oracle and the library reject it).
+RIEMANN_WIDTH_CELLS = 1.5
+
+
 def config_c3(kn: float = 1e-2, n_side: int = 20) -> Problem:
     """~5e4-tet jittered Delaunay cube, P1, 16^3 velocities on [-6,6]^3,
     planar Riemann problem with a seeded normal, backward Euler, CFL 10."""
     mesh = jittered_cube_mesh(n_side, 0.2, seed=3000)
-    return Problem(mesh, 1, tensor_velocity_grid(16, 6.0, 3), planar_riemann_state(3, seed=3001),
+    return Problem(mesh, 1, tensor_velocity_grid(16, 6.0, 3),
+                   planar_riemann_state(3, seed=3001, width=RIEMANN_WIDTH_CELLS / n_side),
                    nu_model="kn", kn=kn, tableau="BE", cfl=10.0, n_steps=10, tau=1e-10,
                    name=f"c3_riemann_p1_{mesh.n_cells}tet_16^3_kn{kn:g}")
 
@@ -346,7 +363,9 @@ def config_c4_instances(count: int = 64, seed0: int = 4000, max_tri: int = 50000
         kn = math.exp(rng.uniform(math.log(1e-4), 0.0))
         mesh = jittered_square_mesh(n_side, 0.2, seed=seed0 + 1000 + i)
         out.append(Problem(mesh, order, tensor_velocity_grid(n1, 8.0, 2),
-                           planar_riemann_state(2, seed=seed0 + 2000 + i), nu_model="kn", kn=kn,
+                           planar_riemann_state(2, seed=seed0 + 2000 + i,
+                                                width=RIEMANN_WIDTH_CELLS / n_side),
+                           nu_model="kn", kn=kn,
                            tableau="DIRK2", cfl=10.0, n_steps=5, tau=1e-10,
                            name=f"c4_{i}"))
     return out
@@ -364,7 +383,8 @@ def learned_guess_problem(dim: int, seed: int, n_side: int, n_1d: int, L: float 
     else:
         mesh = jittered_cube_mesh(n_side, 0.2, seed=seed + 100000)
     return Problem(mesh, 1, tensor_velocity_grid(n_1d, L, dim),
-                   random_riemann_state(dim, seed + 200000), nu_model="kn", kn=kn,
+                   random_riemann_state(dim, seed + 200000, width=RIEMANN_WIDTH_CELLS / n_side),
+                   nu_model="kn", kn=kn,
                    tableau="BE", cfl=10.0, n_steps=10, tau=1e-9,
                    name=f"learned_{dim}d_{seed}_kn{kn:.3g}")
 
