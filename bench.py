@@ -217,17 +217,18 @@ def run_c3(steps, warmup, kn):
 
 
 def run_c5(steps, n_train, kn):
-    """Learned initial guess: train on solver trajectories of small seeded 3D
-    Riemann problems (12^3 velocities), then step the 3D workload with the
+    """Learned initial guess: train on solver trajectories of seeded 3D
+    Riemann problems (jittered 4^3..8^3 lattices, 12^3..16^3 velocities, Kn
+    log-uniform in [1e-3, 1]), then step the 3D workload with the
     plain previous-step guess, linear extrapolation, and the network; report
     Picard iterations and seconds per step and the moment difference."""
     import torch
 
     import problems as P
     from paper_2608_19150_amd import learned
-    train = [P.learned_guess_problem(3, 5000 + i, 5, 12, kn_range=(1e-3, 1.0))
-             for i in range(n_train)]
-    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=30, batch=4096, lr=2e-3, seed=0)
+    train = [P.learned_guess_problem(3, 5000 + i, 4 + i % 5, 12 + 2 * (i % 3),
+                                     kn_range=(1e-3, 1.0)) for i in range(n_train)]
+    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=12, batch=4096, lr=2e-3, seed=0)
     pr = P.config_c3(kn=kn)
     res = learned.compare(pr, mlp, n_steps=steps, tau=1e-9)
     out = {"workload": pr.name, "tau": 1e-9, "train_trajectories": info["trajectories"],
@@ -312,7 +313,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
-    ap.add_argument("--c5-train", type=int, default=24, help="training trajectories")
+    ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()

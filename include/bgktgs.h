@@ -342,9 +342,10 @@ int bgk_batch_time_sweep(bgk_batch* batch, double* const* f, int threads, int re
  * DG node.  Inputs (raw): the primitive state (n, u1, u2, u3, theta) at
  * step t-1, its change from t-2 to t-1 (state and difference rather than two
  * states, so the small change survives BF16 rounding), and dt*nu at t-1
- * (u3 = 0 in 2D).  Outputs: the change of (n, u1, u2, u3, theta)
- * from t-1 to t.  Inputs and outputs are z-scored inside the library with the
- * statistics given to bgk_mlp_set_normalization.  Matrix products run on
+ * (u3 = 0 in 2D).  Outputs: the difference between (n, u1, u2, u3, theta)
+ * at t and its linear extrapolation from t-2 and t-1 (a zero output gives
+ * the extrapolated guess).  Inputs and outputs are z-scored inside the
+ * library with the statistics given to bgk_mlp_set_normalization.  Matrix products run on
  * BF16 MFMA with FP32 accumulation; the master weights and the optimiser
  * state are FP32.  Gradients are reduced in a fixed order (reproducible).
  * Logical parameter layout (host arrays, 9413 floats): W1[11][64], b1[64],
@@ -378,11 +379,13 @@ int bgk_mlp_adam_step(bgk_mlp* mlp, const float* X, const float* T, int64_t n, f
 int bgk_mlp_features(const tgs_dag* dag, const double* U_tm1, const double* U_tm2,
                      const tgs_nu_model* nu_model, double dt, float* X, bgk_stream_t stream);
 
-/* Raw targets (device float [n_nodes][5]): primitive state at t minus t-1. */
-int bgk_mlp_targets(const tgs_dag* dag, const double* U_t, const double* U_tm1, float* T,
-                    bgk_stream_t stream);
+/* Raw targets (device float [n_nodes][5]): the primitive state at t minus its
+ * linear extrapolation 2 p(t-1) - p(t-2). */
+int bgk_mlp_targets(const tgs_dag* dag, const double* U_t, const double* U_tm1,
+                    const double* U_tm2, float* T, bgk_stream_t stream);
 
-/* Initial Picard moments for the next step: U_guess = U(prim(U_tm1) + net),
+/* Initial Picard moments for the next step:
+ * U_guess = U(2 prim(U_tm1) - prim(U_tm2) + net),
  * per node; a node whose prediction has n <= 0, theta <= 0 or is not finite
  * falls back to U_tm1 (the plain previous-step guess) and is counted in
  * n_fallback (device int32, accumulated).  All nodal arrays in user order. */

@@ -4,7 +4,8 @@ The network maps per-DG-node features to a correction of the primitive
 state: inputs (n, u_1, u_2, u_3, theta) at step t-1, its change from t-2
 to t-1, and dt*nu at t-1 (11 features; 2D states have u_3 = 0), three hidden layers of 64 with
 the exact GELU g(z) = z Phi(z) = z (1 + erf(z/sqrt 2))/2, and 5 linear
-outputs (the normalised change of (n, u, theta) from t-1 to t).  Loss: mean
+outputs (the normalised difference between (n, u, theta) at t and its
+linear extrapolation from t-2 and t-1).  Loss: mean
 squared error over rows and outputs.
 
 Two paths:
@@ -134,6 +135,24 @@ def features(U_tm1, U_tm2, nu_dt, dim):
     out[:, 5:10] = p1 - p2
     out[:, 10] = nu_dt
     return out
+
+
+def targets(U_t, U_tm1, U_tm2, dim):
+    """Raw targets per node: the primitive state at t minus its linear
+    extrapolation 2 p(t-1) - p(t-2), so that a zero output reproduces the
+    extrapolated guess."""
+    p0 = primitive_state(U_t, dim)
+    p1 = primitive_state(U_tm1, dim)
+    p2 = primitive_state(U_tm2, dim)
+    return p0 - (p1 + (p1 - p2))
+
+
+def guess(delta, U_tm1, U_tm2, dim):
+    """Initial moments from a predicted correction: p = p(t-1) + (p(t-1) -
+    p(t-2)) + delta, back to conserved moments."""
+    p1 = primitive_state(U_tm1, dim)
+    p2 = primitive_state(U_tm2, dim)
+    return moments_from_primitive(p1 + (p1 - p2) + delta, dim)
 
 
 def primitive_state(U, dim):

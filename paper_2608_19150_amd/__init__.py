@@ -408,7 +408,7 @@ _lib.bgk_mlp_forward.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
 _lib.bgk_mlp_loss_grad.argtypes = [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]
 _lib.bgk_mlp_adam_step.argtypes = [_vp, _vp, _vp, C.c_int64, C.c_float, _vp, _vp]
 _lib.bgk_mlp_features.argtypes = [_vp, _vp, _vp, C.POINTER(NuModel), C.c_double, _vp, _vp]
-_lib.bgk_mlp_targets.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.bgk_mlp_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.bgk_mlp_guess.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(NuModel), C.c_double, _vp, _vp, _vp]
 
 
@@ -502,9 +502,9 @@ def mlp_features(dag, U_tm1, U_tm2, dt, nu_model="const", nu_const=1.0, kn=1.0, 
     return X
 
 
-def mlp_targets(dag, U_t, U_tm1, stream=None):
+def mlp_targets(dag, U_t, U_tm1, U_tm2, stream=None):
     T = torch.empty((dag.n_nodes, 5), dtype=torch.float32, device="cuda")
-    _check(_lib.bgk_mlp_targets(dag.h, _p(U_t), _p(U_tm1), _p(T), _stream(stream)))
+    _check(_lib.bgk_mlp_targets(dag.h, _p(U_t), _p(U_tm1), _p(U_tm2), _p(T), _stream(stream)))
     return T
 
 

@@ -385,14 +385,15 @@ __global__ void k_mlp_features(const double* __restrict__ U1, const double* __re
 
 template <int DIM>
 __global__ void k_mlp_targets(const double* __restrict__ Ut, const double* __restrict__ U1,
-                              int64_t n, float* __restrict__ T) {
+                              const double* __restrict__ U2, int64_t n, float* __restrict__ T) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double pt[5], p1[5];
+  double pt[5], p1[5], p2[5];
   prim5<DIM>(Ut + i * (DIM + 2), pt);
   prim5<DIM>(U1 + i * (DIM + 2), p1);
+  prim5<DIM>(U2 + i * (DIM + 2), p2);
 #pragma unroll
-  for (int c = 0; c < NO; ++c) T[i * NO + c] = (float)(pt[c] - p1[c]);
+  for (int c = 0; c < NO; ++c) T[i * NO + c] = (float)(pt[c] - (p1[c] + (p1[c] - p2[c])));
 }
 
 template <int DIM>
@@ -433,13 +434,14 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_guess(MlpArgs m, const doub
     if (lane < 16) {
       const int64_t node = row0 + lane;
       if (node < n) {
-        double p1[5], q[5];
+        double p1[5], p2[5], q[5];
         prim5<DIM>(U1 + node * NM, p1);
+        prim5<DIM>(U2 + node * NM, p2);
         bool ok = true;
 #pragma unroll
         for (int c = 0; c < NO; ++c) {
           const double dlt = (double)(ys[lane * 17 + c] * m.stats[2 * NI + NO + c] + m.stats[2 * NI + c]);
-          q[c] = p1[c] + dlt;
+          q[c] = p1[c] + (p1[c] - p2[c]) + dlt;
           ok = ok && isfinite(q[c]);
         }
         ok = ok && q[0] > 0.0 && q[4] > 0.0;
@@ -683,15 +685,15 @@ extern "C" int bgk_mlp_features(const tgs_dag* d, const double* U1, const double
   return BGK_OK;
 }
 
-extern "C" int bgk_mlp_targets(const tgs_dag* d, const double* Ut, const double* U1, float* T,
-                               bgk_stream_t stream) {
-  if (!d || !Ut || !U1 || !T) return fail(BGK_E_INVALID, "null argument");
+extern "C" int bgk_mlp_targets(const tgs_dag* d, const double* Ut, const double* U1,
+                               const double* U2, float* T, bgk_stream_t stream) {
+  if (!d || !Ut || !U1 || !U2 || !T) return fail(BGK_E_INVALID, "null argument");
   const int64_t n = d->n_nodes;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (d->dim == 2)
-    hipLaunchKernelGGL(k_mlp_targets<2>, grid, block, 0, (hipStream_t)stream, Ut, U1, n, T);
+    hipLaunchKernelGGL(k_mlp_targets<2>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
   else
-    hipLaunchKernelGGL(k_mlp_targets<3>, grid, block, 0, (hipStream_t)stream, Ut, U1, n, T);
+    hipLaunchKernelGGL(k_mlp_targets<3>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

@@ -2,9 +2,11 @@
 
 The solver produces its own training data: backward-Euler runs of seeded
 problems record the converged nodal moments U^k after every step.  A sample
-pairs the features of (U^k, U^{k-1}, dt nu(U^k)) with the change of the
-primitive state (n, u, theta) from U^k to U^{k+1}; the network (BF16 MFMA
-kernels of the library) is fitted to it with minibatch Adam on the GPU.  At
+pairs the features of (U^k, U^{k-1}, dt nu(U^k)) with the difference between
+the primitive state (n, u, theta) at k+1 and its linear extrapolation from
+k-1 and k; the network (BF16 MFMA kernels of the library) is fitted to it
+with minibatch Adam on the GPU, so an uninformed network falls back to the
+extrapolated guess.  At
 run time the prediction replaces the plain initial iterate U^k of the first
 Picard iteration of step k -> k+1 (Sec. 4 starts Picard from the previous
 stage); the converged iteration, with its tolerance unchanged, remains the
@@ -73,22 +75,24 @@ def samples(traj, U):
     Xs, Ts = [], []
     for k in range(1, len(U) - 1):
         Xs.append(mlp_features(traj.dag, U[k], U[k - 1], traj.dt, **traj.nu_kw()))
-        Ts.append(mlp_targets(traj.dag, U[k + 1], U[k]))
+        Ts.append(mlp_targets(traj.dag, U[k + 1], U[k], U[k - 1]))
     return torch.cat(Xs), torch.cat(Ts)
 
 
 def normalization(X, T):
-    """Per-column mean and standard deviation (a column with no spread gets
-    std 1, so it is only centred)."""
-    def stats(A):
-        A64 = A.double()
-        mu = A64.mean(0)
-        sd = A64.std(0, unbiased=False)
-        sd = torch.where(sd > 1e-6 * torch.clamp(mu.abs(), min=1.0), sd, torch.ones_like(sd))
-        return mu.float().cpu().numpy(), sd.float().cpu().numpy()
-    mi, si = stats(X)
-    mo, so = stats(T)
-    return mi, si, mo, so
+    """Inputs: per-column mean and standard deviation (a column with no
+    spread gets std 1, so it is only centred).  Outputs: scaled by their
+    root mean square but not centred, so that a zero network output is the
+    extrapolated guess exactly (most nodes of a run barely change, and a
+    centred output would shift all of them by the targets' mean)."""
+    X64 = X.double()
+    mu = X64.mean(0)
+    sd = X64.std(0, unbiased=False)
+    sd = torch.where(sd > 1e-6 * torch.clamp(mu.abs(), min=1.0), sd, torch.ones_like(sd))
+    rms = T.double().pow(2).mean(0).sqrt()
+    rms = torch.where(rms > 0, rms, torch.ones_like(rms))
+    return (mu.float().cpu().numpy(), sd.float().cpu().numpy(),
+            np.zeros(T.shape[1], dtype=np.float32), rms.float().cpu().numpy())
 
 
 def train(mlp, X, T, *, epochs=20, batch=4096, lr=1e-3, seed=0, log_every=0):

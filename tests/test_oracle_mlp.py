@@ -89,3 +89,26 @@ def test_primitive_roundtrip():
         p[:, 4] = rng.uniform(0.5, 2, 10)
         U = mlp.moments_from_primitive(p, dim)
         assert np.allclose(mlp.primitive_state(U, dim), p)
+
+
+def test_targets_measure_the_departure_from_linear_extrapolation():
+    """A primitive state moving linearly in time has zero targets, and
+    guess(targets) returns the state at t (inverse pair)."""
+    rng = np.random.default_rng(6)
+    for dim in (2, 3):
+        p2 = np.zeros((12, 5))
+        p2[:, 0] = rng.uniform(0.5, 1.5, 12)
+        p2[:, 1:1 + dim] = rng.normal(scale=0.3, size=(12, dim))
+        p2[:, 4] = rng.uniform(0.7, 1.3, 12)
+        step = np.zeros_like(p2)
+        step[:, 0] = rng.uniform(-0.01, 0.01, 12)
+        step[:, 1:1 + dim] = rng.uniform(-0.01, 0.01, (12, dim))
+        step[:, 4] = rng.uniform(-0.01, 0.01, 12)
+        U2 = mlp.moments_from_primitive(p2, dim)
+        U1 = mlp.moments_from_primitive(p2 + step, dim)
+        Ut = mlp.moments_from_primitive(p2 + 2 * step, dim)
+        assert np.abs(mlp.targets(Ut, U1, U2, dim)).max() < 1e-13
+        Uo = mlp.moments_from_primitive(p2 + 2 * step + 0.01 * rng.normal(size=p2.shape) *
+                                        np.r_[1, np.ones(dim), np.zeros(3 - dim), 1], dim)
+        np.testing.assert_allclose(mlp.guess(mlp.targets(Uo, U1, U2, dim), U1, U2, dim), Uo,
+                                   rtol=1e-13, atol=1e-13)
