@@ -16,7 +16,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbgktgs.so")
+# BGK_LIBRARY may name another build of the same library (e.g. a variant
+# built for comparison); the default is the in-tree build
+LIB_PATH = os.environ.get("BGK_LIBRARY") or os.path.join(_HERE, "libbgktgs.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_19150_amd.build`")
