@@ -636,8 +636,10 @@ __global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __rest
   if (g >= total) return;
   const int i = find_instance<int64_t>(first, n_inst, g);
   if (done[i]) return;
-  const BatchKin& k = kin[i];
-  maxwellian_node<DIM>(k.maxw, k.U[par[i]], g - first[i]);
+  // arguments into registers: the Newton loop reads them repeatedly
+  const MaxwArgs p = kin[i].maxw;
+  const double* U = kin[i].U[par[i]];
+  maxwellian_node<DIM>(p, U, g - first[i]);
 }
 
 template <int DIM>

@@ -128,6 +128,22 @@ def test_sweep_fp64_c1_size_matches_oracle():
     assert rel(f_gpu, f_ref) <= TOL64
 
 
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 1)])
+def test_sweep_bitwise_reproducible_across_runs_and_workgroup_sizes(dim, order):
+    """The workgroup size changes which thread solves which cell of a
+    generation (and which generations overflow); results are bitwise equal,
+    and so are repeated runs."""
+    say("sweep reproducibility", dim, order)
+    pr = _problem(dim, order, 5 if dim == 2 else 3, 6)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 12)
+    outs = []
+    for T in (64, 128, 192, 256, 192):
+        d = B.Dag.from_problem(pr, sweep_threads=T)
+        outs.append(_gpu_sweep(d, pr, q, nu, prim, 7.0, 3.0))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_sweep_dense_boundary_matches_oracle():
     pr = _problem(2, 2, 3, 4)
     d = B.Dag.from_problem(pr)

@@ -97,3 +97,27 @@ def test_geometry_closure(dim):
             if geo.nbr[c, k] < 0:
                 n = geo.normal[c, k]
                 assert np.isclose(np.abs(n).max(), 1.0)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 1)])
+def test_local_matrix_symmetric_part_is_the_energy_form(dim, order):
+    """For a cell-constant sigma the local DG matrix has symmetric part
+    sigma|K| M + (1/2) sum_k |v.n_k| |e_k| M_k (integration by parts turns the
+    transport term into half the facet fluxes; eq. l2-estimate), which is
+    positive definite."""
+    from oracle import transport
+    pr = P.small_problem(dim=dim, order=order, n_side=3, n_1d=4)
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, order)
+    rng = np.random.default_rng(3)
+    cells = rng.integers(0, geo.n_cells, 40)
+    V = rng.normal(size=(40, dim)) * 3.0
+    sig = rng.uniform(0.1, 5.0, 40)
+    A, s = transport.cell_matrices(geo, cells, V, np.repeat(sig[:, None], geo.n_p, axis=1))
+    ref = geo.ref
+    for i in range(40):
+        sym = 0.5 * (A[i] + A[i].T)
+        expect = sig[i] * geo.vol[cells[i]] * ref["mass"]
+        for k in range(dim + 1):
+            expect = expect + 0.5 * abs(s[i, k]) * geo.area[cells[i], k] * ref["face_mass"][k]
+        assert np.abs(sym - expect).max() <= 1e-13 * np.abs(expect).max()
+        assert np.linalg.eigvalsh(sym).min() > 0.0

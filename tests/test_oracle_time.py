@@ -183,3 +183,29 @@ def test_explicit_dt_formula():
     dt = solver.explicit_dt(geo, pr.vgrid.v, 10.0)
     hmin = math.sqrt(geo.vol.min())
     assert np.isclose(dt, 10.0 * 0.5 * (1 / 3) * hmin / (6 * math.sqrt(2)))
+
+
+def test_converged_step_does_not_depend_on_lagged_facets():
+    """Lagging inflow facets (Sec. 4: the lagged part of the inflow boundary
+    takes the previous iterate) changes every sweep but not the fixed point:
+    a converged step with a random lagged set equals the unlagged one to the
+    stopping tolerance."""
+    pr = P.small_problem(dim=2, order=1, n_side=4, n_1d=6, state="sod")
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    rng = np.random.default_rng(11)
+    lags = np.zeros((V.shape[0], geo.n_cells, geo.dim + 1), dtype=bool)
+    for j in range(V.shape[0]):
+        s = dag.facet_speeds(geo, V[j])
+        cand = (s < 0) & (geo.nbr >= 0)
+        lags[j] = cand & (rng.uniform(size=cand.shape) < 0.3)
+    assert lags.sum() > 10
+    f0 = solver.initial_condition(geo, V, pr.state)
+    g = solver.boundary_values(geo, V, pr.state)
+    dt = solver.explicit_dt(geo, V, pr.cfl)
+    gens0, lag0 = dag.build_all(geo, V)
+    gens1, lag1 = dag.build_all(geo, V, lagged=lags)
+    f_a, st_a = solver.bgk_step(geo, V, w, f0, g, dt, gens0, lag0, tau=1e-13)
+    f_b, st_b = solver.bgk_step(geo, V, w, f0, g, dt, gens1, lag1, tau=1e-13)
+    assert st_b["iters"][0] > st_a["iters"][0]          # lagging slows the iteration
+    assert np.abs(f_b - f_a).max() <= 1e-10 * np.abs(f_a).max()
