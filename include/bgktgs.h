@@ -104,8 +104,8 @@ typedef struct {
      (the lagged part of the inflow boundary, Sec. 4).  NULL = lag only what
      cycle breaking requires. */
   const uint8_t* lagged;
-  /* Threads per workgroup of the sweep kernel (64..1024, multiple of 64);
-     0 = the library's choice. */
+  /* Threads per workgroup of the sweep kernel (64..256, multiple of 64);
+     0 = the library's choice (256 for P1 triangles, else 128). */
   int sweep_threads;
 } tgs_dag_opts;
 
@@ -298,7 +298,7 @@ typedef struct {
   int graph;          /* 1: replay captured hipGraphs; 0: launch the same kernels eagerly */
   int chunk_iters;    /* Picard iterations between convergence polls (0: 4) */
   int sweep_threads;  /* workgroup size of the batched sweep, a multiple of 64 up to 256
-                         (0: 192) */
+                         (0: 128) */
 } bgk_batch_opts;
 
 typedef struct {

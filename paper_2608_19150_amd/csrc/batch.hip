@@ -395,7 +395,7 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
   bgk_batch_opts o{};
   if (opts) o = *opts;
   if (o.chunk_iters <= 0) o.chunk_iters = 4;
-  if (o.sweep_threads <= 0) o.sweep_threads = 192;
+  if (o.sweep_threads <= 0) o.sweep_threads = 128;
   if (o.sweep_threads % 64 || o.sweep_threads > 256)
     return fail(BGK_E_INVALID, "sweep_threads must be a multiple of 64 up to 256");
   const bgk_solver* s0 = solvers[0];

@@ -551,9 +551,9 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   D->v_host.assign(vg->v, vg->v + (size_t)vg->n_v * dim);
   D->w_host.assign(vg->w, vg->w + vg->n_v);
   if (opts && opts->sweep_threads) {
-    BGK_CHECK(opts->sweep_threads >= 64 && opts->sweep_threads <= 1024 &&
+    BGK_CHECK(opts->sweep_threads >= 64 && opts->sweep_threads <= 256 &&
                   opts->sweep_threads % 64 == 0,
-              BGK_E_INVALID, "sweep_threads must be a multiple of 64 in [64, 1024]");
+              BGK_E_INVALID, "sweep_threads must be a multiple of 64 in [64, 256]");
     D->sweep_threads = opts->sweep_threads;
   }
   // tensor grid declaration

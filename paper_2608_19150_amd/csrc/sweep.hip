@@ -544,11 +544,13 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_m
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {
-    // keep four workgroups per CU resident at the kernels' register use:
-    // P1 triangles fit 256 threads; P2 triangles and tetrahedra need <= 168
-    // VGPRs (192 threads) in FP64 and 128 threads in the FP32 form
+    // P1 triangles: 256 threads.  P2 triangles and tetrahedra (168 VGPRs):
+    // 128 threads, measured fastest on 200k P2 triangles x 1024 velocities
+    // (20.8 ms against 25.6 ms at 192 and 25.3 ms at 256) and on par on 55k
+    // tetrahedra x 4096 velocities; smaller workgroups keep more velocities
+    // per CU resident, and wider generations take a second pass
     const bool small = d->dim == 2 && d->order == 1;
-    threads = small ? 256 : (fp32 ? 128 : 192);
+    threads = small ? 256 : 128;
   }
   const dim3 grid(d->n_v), block(threads);
 #define BGK_LAUNCH(D_, O_)                                                                \
