@@ -482,8 +482,12 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // prod_alpha exp([alpha == 0] a + b_alpha x + c x^2) with x the node of axis
 // alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
 // and M(v_j) is the product of d table entries (node fastest, coalesced).
+// Entry idx = (al * n1 + i) * n_nodes + node of the factorised tables.  Axis
+// 0 is stored as (E_0, nu) pairs, [n1][n_nodes][2] (the sweep then gathers
+// both with one access); axes 1..d-1 follow as [n1][n_nodes].
 template <int DIM>
 __device__ __forceinline__ void table_entry(const double* __restrict__ coef,
+                                            const double* __restrict__ nu,
                                             const double* __restrict__ x1, double* __restrict__ tab,
                                             int64_t n_nodes, int n1, int64_t idx) {
   constexpr int NM = DIM + 2;
@@ -493,28 +497,36 @@ __device__ __forceinline__ void table_entry(const double* __restrict__ coef,
   const double x = x1[i];
   const double* c = coef + node * NM;
   double e = __fma_rn(c[1 + DIM], x * x, c[1 + al] * x);
-  if (al == 0) e += c[0];
-  tab[idx] = bgk_exp(e);
+  if (al == 0) {
+    e += c[0];
+    double* t = tab + ((int64_t)i * n_nodes + node) * 2;
+    t[0] = bgk_exp(e);
+    t[1] = nu[node];
+  } else {
+    tab[((int64_t)(al + 1) * n1 + i) * n_nodes + node] = bgk_exp(e);
+  }
 }
 
 template <int DIM>
-__global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ x1,
-                              double* __restrict__ tab, int64_t n_nodes, int n1) {
+__global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
+                              const double* __restrict__ x1, double* __restrict__ tab,
+                              int64_t n_nodes, int n1) {
   const int64_t total = n_nodes * DIM * n1;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x)
-    table_entry<DIM>(coef, x1, tab, n_nodes, n1, idx);
+    table_entry<DIM>(coef, nu, x1, tab, n_nodes, n1, idx);
 }
 
-int launch_maxw_tables(const tgs_dag* d, const double* coef, double* tab, hipStream_t stream) {
+int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
+                       hipStream_t stream) {
   const int64_t total = d->n_nodes * d->dim * d->n_1d;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
-    hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, d->d_nodes1d, tab,
-                       d->n_nodes, d->n_1d);
+    hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
+                       tab, d->n_nodes, d->n_1d);
   else
-    hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, d->d_nodes1d, tab,
-                       d->n_nodes, d->n_1d);
+    hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
+                       tab, d->n_nodes, d->n_1d);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -650,7 +662,7 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
     const int i = find_instance<int64_t>(first, n_inst, g);
     if (done[i] || !kin[i].mtab) continue;
     const BatchKin& k = kin[i];
-    table_entry<DIM>(k.maxw.coef, k.x1, k.mtab, k.n_nodes, k.n1, g - first[i]);
+    table_entry<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes, k.n1, g - first[i]);
   }
 }
 

@@ -19,7 +19,12 @@
 namespace bgk {
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
                  const double* mtab, float* d32, hipStream_t stream, int threads);
-int launch_maxw_tables(const tgs_dag* d, const double* coef, double* tab, hipStream_t stream);
+int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
+                       hipStream_t stream);
+// doubles of the factorised tables: axis 0 as (E_0, nu) pairs, then d-1 axes
+inline size_t maxw_table_size(const tgs_dag* d) {
+  return (size_t)(d->dim + 1) * d->n_1d * d->n_nodes;
+}
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                    double* partial, double* ratio_out, hipStream_t stream, bool user_order);
 int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,
@@ -179,7 +184,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->U[0], nn);
   if (!rc) rc = dmalloc(&s->U[1], nn);
   if (!rc) rc = dmalloc(&s->mcoef, nn);
-  if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, (size_t)d->dim * d->n_1d * d->n_nodes);
+  if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
   if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
   if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
   if (!rc) rc = dmalloc(&s->ratio, 4);
@@ -271,7 +276,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
                                   nullptr, s->status, s->numax, s->sticky, stream)))
         return rc;
-      if (s->mtab && (rc = launch_maxw_tables(d, s->mcoef, s->mtab, stream))) return rc;
+      if (s->mtab && (rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
       if (need_prev) cur_out = (prev == out) ? s->fping : out;
       tgs_sweep_io io{};

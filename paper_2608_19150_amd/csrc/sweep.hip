@@ -168,18 +168,24 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
 #pragma unroll
   for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
   const size_t u = a.node_map ? (size_t)a.node_map[P.K] : (size_t)P.K;
-  const double* __restrict__ nu = a.nu + u * NP;
   const double* __restrict__ q = a.q + (base + P.s) * NP;
-  double M[NP];
+  double M[NP], nu[NP];
   if constexpr (TAB) {
-    // tensor grid: M = prod_alpha E_alpha[i_alpha][node]
+    // tensor grid: M = prod_alpha E_alpha[i_alpha][node]; the first factor
+    // is stored interleaved with nu, so one gather brings both
+    const double* __restrict__ e0 = mrow[0] + u * NP * 2;
 #pragma unroll
-    for (int b = 0; b < NP; ++b) M[b] = mrow[0][u * NP + b];
+    for (int b = 0; b < NP; ++b) {
+      M[b] = e0[2 * b];
+      nu[b] = e0[2 * b + 1];
+    }
 #pragma unroll
     for (int al = 1; al < DIM; ++al)
 #pragma unroll
       for (int b = 0; b < NP; ++b) M[b] *= mrow[al][u * NP + b];
   } else {
+#pragma unroll
+    for (int b = 0; b < NP; ++b) nu[b] = a.nu[u * NP + b];
     const double* __restrict__ mc = a.mcoef + u * NP * NC;
 #pragma unroll
     for (int b = 0; b < NP; ++b) M[b] = maxw_eval<DIM>(mc + b * NC, v, v2);
@@ -415,11 +421,15 @@ __device__ __forceinline__ void sweep_velocity(
   {
     int rem = j;
     const size_t nn = (size_t)a.n_cells * NP;
+    // table layout: axis 0 as (E_0, nu) pairs [n1][n_nodes][2], then axes
+    // 1..d-1 as [n1][n_nodes]
 #pragma unroll
     for (int al = DIM - 1; al >= 0; --al) {
       const int i = a.mtab ? rem % a.n1 : 0;
       rem = a.mtab ? rem / a.n1 : rem;
-      mrow[al] = a.mtab ? a.mtab + ((size_t)al * a.n1 + i) * nn : nullptr;
+      mrow[al] = !a.mtab ? nullptr
+                 : al == 0 ? a.mtab + (size_t)i * nn * 2
+                           : a.mtab + ((size_t)(al + 1) * a.n1 + i) * nn;
     }
   }
 
