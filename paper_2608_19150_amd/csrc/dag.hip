@@ -610,12 +610,13 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
     D->iid_host[mk[i].second] = (int32_t)i;
   }
   // internal-order device records
-  const int gs = 1 + (dim + 1) * dim;
-  std::vector<double> geo_i(nc * gs);
+  const int gs = 1 + (dim + 1) * dim;  // host record
+  const int gstride = dim == 2 ? GeoLayout<2>::STRIDE : GeoLayout<3>::STRIDE;  // padded device record
+  std::vector<double> geo_i(nc * gstride, 0.0);
   std::vector<FacetRec> fac_i(nc * nf);
   for (int64_t i = 0; i < nc; ++i) {
     const int64_t u = D->uid_host[i];
-    std::copy(&H.geo[u * gs], &H.geo[u * gs] + gs, &geo_i[i * gs]);
+    std::copy(&H.geo[u * gs], &H.geo[u * gs] + gs, &geo_i[i * gstride]);
     for (int k = 0; k < nf; ++k) {
       const int32_t nb = H.nb[u * nf + k];
       FacetRec r;

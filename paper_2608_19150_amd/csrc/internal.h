@@ -204,9 +204,37 @@ struct Elem {
 // w_{k-1} = -(d-1)! v.N_k and J^{-1} need not be stored.
 // internal cells are numbered in Morton order of their centroids
 // ---------------------------------------------------------------------------
+// A record is padded to a power of two of doubles, so that it never
+// straddles a 128-byte cache line (the sweep gathers it per cell).
 template <int DIM>
 struct GeoLayout {
-  static constexpr int STRIDE = 1 + (DIM + 1) * DIM;  // doubles
+  static constexpr int USED = 1 + (DIM + 1) * DIM;  // doubles
+  static constexpr int STRIDE = DIM == 2 ? 8 : 16;   // padded record
+  static_assert(STRIDE >= USED, "record size");
+};
+
+// Factorised Maxwellian tables of a tensor velocity grid with n1 points per
+// axis, per cell and padded like the geometry: axis 0 as the cell's nodes'
+// (E_0, nu) pairs, [n1][n_cells][s0], then axes 1..d-1 as the nodes' E_alpha,
+// [d-1][n1][n_cells][s1] (s0, s1 = 2 n_p and n_p rounded up to a power of 2).
+struct TabLayout {
+  int64_t nc;
+  int n1, np, s0, s1;
+  __host__ __device__ static constexpr int pow2(int x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
+  }
+  __host__ __device__ TabLayout(int64_t n_cells, int n1_, int np_)
+      : nc(n_cells), n1(n1_), np(np_), s0(pow2(2 * np_)), s1(pow2(np_)) {}
+  // first double of cell c's record on row i of axis al
+  __host__ __device__ int64_t at(int al, int i, int64_t c) const {
+    return al == 0 ? ((int64_t)i * nc + c) * s0
+                   : (int64_t)n1 * nc * s0 + (((int64_t)(al - 1) * n1 + i) * nc + c) * s1;
+  }
+  __host__ __device__ int64_t size(int dim) const {
+    return (int64_t)n1 * nc * (s0 + (int64_t)(dim - 1) * s1);
+  }
 };
 
 // facet record: x = neighbour internal cell id, or -(1 + boundary facet id);

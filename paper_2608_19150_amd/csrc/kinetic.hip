@@ -42,27 +42,52 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
   for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+  // the weights w_j e_m(v_j) of velocity j applied to one cell's nodal values
+  auto accumulate = [&](int j, const double* fv) {
+    const double wj = a.w[j];
+    double e[NM];
+    double v2 = 0.0;
+    e[0] = wj;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double vd = a.v[(size_t)j * DIM + d];
+      e[1 + d] = wj * vd;
+      v2 = fma(vd, vd, v2);
+    }
+    e[NM - 1] = 0.5 * wj * v2;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[p][m] = fma(e[m], fv[p], acc[p][m]);
+  };
   if (valid) {
-    for (int j = lane; j < a.n_v; j += VL) {
+    // UNR velocities' gathers (pos, then the cell's NP values at that slot)
+    // are issued before any is summed, so each lane has UNR independent
+    // load chains in flight; the summation order is unchanged
+    constexpr int UNR = 8;
+    int j = lane;
+    for (; j + (UNR - 1) * VL < a.n_v; j += UNR * VL) {
+      double fv[UNR][NP];
+      size_t slot[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        slot[u] = (size_t)a.pos[(size_t)(j + u * VL) * a.n_cells + K];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const double* fp = a.f + ((size_t)(j + u * VL) * a.n_cells + slot[u]) * NP;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) fv[u][p] = fp[p];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) accumulate(j + u * VL, fv[u]);
+    }
+    for (; j < a.n_v; j += VL) {
       const size_t slot = (size_t)a.pos[(size_t)j * a.n_cells + K];
       const double* fp = a.f + ((size_t)j * a.n_cells + slot) * NP;
-      const double wj = a.w[j];
-      double e[NM];
-      double v2 = 0.0;
-      e[0] = wj;
+      double fv[NP];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double vd = a.v[(size_t)j * DIM + d];
-        e[1 + d] = wj * vd;
-        v2 = fma(vd, vd, v2);
-      }
-      e[NM - 1] = 0.5 * wj * v2;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const double fv = fp[p];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) acc[p][m] = fma(e[m], fv, acc[p][m]);
-      }
+      for (int p = 0; p < NP; ++p) fv[p] = fp[p];
+      accumulate(j, fv);
     }
   }
   if (VL > 1) {
@@ -74,6 +99,7 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
     }
     __syncthreads();
     if (lane == 0) {
+#pragma unroll 1
       for (int l = 1; l < VL; ++l)
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -481,52 +507,56 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // Factorised Maxwellian for tensor velocity grids: exp(a + b.v + c|v|^2) =
 // prod_alpha exp([alpha == 0] a + b_alpha x + c x^2) with x the node of axis
 // alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
-// and M(v_j) is the product of d table entries (node fastest, coalesced).
-// Entry idx = (al * n1 + i) * n_nodes + node of the factorised tables.  Axis
-// 0 is stored as (E_0, nu) pairs, [n1][n_nodes][2] (the sweep then gathers
-// both with one access); axes 1..d-1 follow as [n1][n_nodes].
+// and M(v_j) is the product of d table entries.  Entry idx = (al * n1 + i) *
+// n_nodes + node; it is stored at its place in the per-cell padded layout
+// (TabLayout): axis 0 with nu as (E_0, nu) pairs, so the sweep gathers both
+// with one access.
 template <int DIM>
 __device__ __forceinline__ void table_entry(const double* __restrict__ coef,
                                             const double* __restrict__ nu,
                                             const double* __restrict__ x1, double* __restrict__ tab,
-                                            int64_t n_nodes, int n1, int64_t idx) {
+                                            int64_t n_nodes, int n1, int np, int64_t idx) {
   constexpr int NM = DIM + 2;
   const int64_t node = idx % n_nodes;
   const int64_t r = idx / n_nodes;
   const int i = (int)(r % n1), al = (int)(r / n1);
+  const TabLayout L(n_nodes / np, n1, np);
+  const int64_t c = node / np;
+  const int b = (int)(node - c * np);
   const double x = x1[i];
-  const double* c = coef + node * NM;
-  double e = __fma_rn(c[1 + DIM], x * x, c[1 + al] * x);
+  const double* cf = coef + node * NM;
+  double e = __fma_rn(cf[1 + DIM], x * x, cf[1 + al] * x);
   if (al == 0) {
-    e += c[0];
-    double* t = tab + ((int64_t)i * n_nodes + node) * 2;
+    e += cf[0];
+    double* t = tab + L.at(0, i, c) + 2 * b;
     t[0] = bgk_exp(e);
     t[1] = nu[node];
   } else {
-    tab[((int64_t)(al + 1) * n1 + i) * n_nodes + node] = bgk_exp(e);
+    tab[L.at(al, i, c) + b] = bgk_exp(e);
   }
 }
 
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
                               const double* __restrict__ x1, double* __restrict__ tab,
-                              int64_t n_nodes, int n1) {
+                              int64_t n_nodes, int n1, int np) {
   const int64_t total = n_nodes * DIM * n1;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x)
-    table_entry<DIM>(coef, nu, x1, tab, n_nodes, n1, idx);
+    table_entry<DIM>(coef, nu, x1, tab, n_nodes, n1, np, idx);
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream) {
   const int64_t total = d->n_nodes * d->dim * d->n_1d;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  const int np = (int)(d->n_nodes / d->n_cells);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_nodes, d->n_1d);
+                       tab, d->n_nodes, d->n_1d, np);
   else
     hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_nodes, d->n_1d);
+                       tab, d->n_nodes, d->n_1d, np);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -578,9 +608,10 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
   MomArgs a{f,      d->d_pos, user_order ? d->d_uid : nullptr, d->d_v, d->d_w, U, U_prev, partial,
             (int)d->n_cells, d->n_v};
   const int vl = moment_vl(d);
-  const dim3 grid(moment_blocks(d)), block(MOM_THREADS);
-#define BGK_MOM(D_, P_)                                                                   \
-  do {                                                                                    \
+  const int nblk = moment_blocks(d);
+  const dim3 grid((unsigned)nblk), block(MOM_THREADS);
+#define BGK_MOM(D_, P_)                                                                         \
+  do {                                                                                          \
     if (vl == 1) hipLaunchKernelGGL((k_moments<D_, P_, 1>), grid, block, 0, stream, a);   \
     else if (vl == 4) hipLaunchKernelGGL((k_moments<D_, P_, 4>), grid, block, 0, stream, a); \
     else hipLaunchKernelGGL((k_moments<D_, P_, 16>), grid, block, 0, stream, a);          \
@@ -594,7 +625,7 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
 #undef BGK_MOM
   BGK_HIP(hipGetLastError());
   if (U_prev && ratio_out) {
-    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, (int)grid.x, ratio_out);
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, nblk, ratio_out);
     BGK_HIP(hipGetLastError());
   }
   return BGK_OK;
@@ -662,7 +693,7 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
     const int i = find_instance<int64_t>(first, n_inst, g);
     if (done[i] || !kin[i].mtab) continue;
     const BatchKin& k = kin[i];
-    table_entry<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes, k.n1, g - first[i]);
+    table_entry<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes, k.n1, k.np, g - first[i]);
   }
 }
 

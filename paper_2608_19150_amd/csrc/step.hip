@@ -21,9 +21,9 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_m
                  const double* mtab, float* d32, hipStream_t stream, int threads);
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream);
-// doubles of the factorised tables: axis 0 as (E_0, nu) pairs, then d-1 axes
+// doubles of the factorised tables (per-cell padded layout)
 inline size_t maxw_table_size(const tgs_dag* d) {
-  return (size_t)(d->dim + 1) * d->n_1d * d->n_nodes;
+  return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells)).size(d->dim);
 }
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                    double* partial, double* ratio_out, hipStream_t stream, bool user_order);
@@ -34,19 +34,55 @@ int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_
                       unsigned long long* numax, uint8_t* sticky, hipStream_t stream);
 int moment_blocks(const tgs_dag* d);
 
-// out = sum_i c_i x_i (up to 5 inputs), grid-stride, vectorised by 2
-__global__ void k_combine(double* __restrict__ out, const double* __restrict__ x0,
-                          const double* __restrict__ x1, const double* __restrict__ x2,
-                          const double* __restrict__ x3, const double* __restrict__ x4, double c0,
-                          double c1, double c2, double c3, double c4, int nin, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    double s = c0 * x0[i];
-    if (nin > 1) s = fma(c1, x1[i], s);
-    if (nin > 2) s = fma(c2, x2[i], s);
-    if (nin > 3) s = fma(c3, x3[i], s);
-    if (nin > 4) s = fma(c4, x4[i], s);
-    out[i] = s;
+// out = sum_i c_i x_i (up to 5 inputs), grid-stride; out may be x0 (each
+// element is read before it is written by the same thread).  V = 2: pairs of
+// doubles in 16-byte loads and stores (every pointer 16-byte aligned), the
+// odd last element by the grid's first thread.
+template <int V>
+__global__ __launch_bounds__(256) void k_combine(double* out, const double* x0, const double* x1,
+                                                 const double* x2, const double* x3,
+                                                 const double* x4, double c0, double c1,
+                                                 double c2, double c3, double c4, int nin,
+                                                 size_t n) {
+  using VT = typename std::conditional<V == 2, double2, double>::type;
+  const auto lin = [&](size_t i, auto get) {
+    VT s = get(x0, i);
+    VT r;
+    if constexpr (V == 2) {
+      r.x = c0 * s.x;
+      r.y = c0 * s.y;
+    } else {
+      r = c0 * s;
+    }
+    const double* xs[4] = {x1, x2, x3, x4};
+    const double cs[4] = {c1, c2, c3, c4};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (nin > k + 1) {
+        const VT t = get(xs[k], i);
+        if constexpr (V == 2) {
+          r.x = fma(cs[k], t.x, r.x);
+          r.y = fma(cs[k], t.y, r.y);
+        } else {
+          r = fma(cs[k], t, r);
+        }
+      }
+    }
+    return r;
+  };
+  const auto ld = [](const double* p, size_t i) { return reinterpret_cast<const VT*>(p)[i]; };
+  const size_t nv = n / V;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * blockDim.x)
+    reinterpret_cast<VT*>(out)[i] = lin(i, ld);
+  if (V == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t t = n - 1;
+    double r = c0 * x0[t];
+    const double* xs[4] = {x1, x2, x3, x4};
+    const double cs[4] = {c1, c2, c3, c4};
+    for (int k = 0; k < 4; ++k)
+      if (nin > k + 1) r = fma(cs[k], xs[k][t], r);
+    out[t] = r;
   }
 }
 
@@ -151,9 +187,16 @@ int combine(double* out, const double* const* xs, const double* cs, int nin, siz
                         nin > 3 ? xs[3] : xs[0], nin > 4 ? xs[4] : xs[0]};
   double c[5] = {cs[0], nin > 1 ? cs[1] : 0, nin > 2 ? cs[2] : 0, nin > 3 ? cs[3] : 0,
                  nin > 4 ? cs[4] : 0};
-  const int grid = (int)std::min<size_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), 0, stream, out, x[0], x[1], x[2], x[3],
-                     x[4], c[0], c[1], c[2], c[3], c[4], nin, n);
+  bool aligned = ((uintptr_t)out & 15) == 0;
+  for (int i = 0; i < nin; ++i) aligned = aligned && ((uintptr_t)xs[i] & 15) == 0;
+  const int V = aligned ? 2 : 1;
+  const int grid = (int)std::min<size_t>((n / V + 255) / 256, 8192);
+  if (V == 2)
+    hipLaunchKernelGGL(k_combine<2>, dim3(std::max(grid, 1)), dim3(256), 0, stream, out, x[0],
+                       x[1], x[2], x[3], x[4], c[0], c[1], c[2], c[3], c[4], nin, n);
+  else
+    hipLaunchKernelGGL(k_combine<1>, dim3(std::max(grid, 1)), dim3(256), 0, stream, out, x[0],
+                       x[1], x[2], x[3], x[4], c[0], c[1], c[2], c[3], c[4], nin, n);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -231,18 +274,25 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
   bgk_step_stats st{};
   st.stages = s->S;
   int rc;
-  // keep f^k; the last stage of a stiffly accurate tableau writes into f
-  BGK_HIP(hipMemcpyAsync(s->fk, f, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  // f^k is read by every stage's source and by the final combination.  The
+  // last stage of a stiffly accurate tableau writes its iterates into f; with
+  // two or more stages f^k is no longer needed by then (that stage's source
+  // was formed before its first sweep), so only a one-stage tableau copies it
+  const double* fk = f;
+  if (s->stiffly_accurate && s->S == 1) {
+    BGK_HIP(hipMemcpyAsync(s->fk, f, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    fk = s->fk;
+  }
   double* fst[4] = {s->fst[0], s->fst[1], s->fst[2], s->fst[3]};
   if (s->stiffly_accurate) fst[s->S - 1] = f;
-  const double* stage_init = s->fk;   // initial Picard iterate of the stage
+  const double* stage_init = fk;   // initial Picard iterate of the stage
   int ucur = 0;
   // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
   // order during the step; U_guess / U_out are in user order
   if (U_guess) {
     if ((rc = launch_nodal_perm(d, U_guess, s->U[0], 1, stream))) return rc;
   } else {
-    if ((rc = launch_moments(d, s->fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
+    if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
       return rc;
   }
   for (int stg = 0; stg < s->S; ++stg) {
@@ -250,10 +300,10 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     const double* qsrc;
     double qscale;
     if (stg == 0) {
-      qsrc = s->fk;
+      qsrc = fk;
       qscale = s->qcoef[0][0];
     } else {
-      const double* xs[5] = {s->fk, fst[0], fst[1], fst[2], fst[3]};
+      const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
       if ((rc = combine(s->q, xs, s->qcoef[stg], stg + 1, nf, stream))) return rc;
       qsrc = s->q;
       qscale = 1.0;
@@ -354,7 +404,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     stage_init = out;
   }
   if (!s->stiffly_accurate) {
-    const double* xs[5] = {s->fk, fst[0], fst[1], fst[2], fst[3]};
+    const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
     if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
     if (U_out &&
         (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false)))

@@ -155,6 +155,83 @@ __device__ __forceinline__ void load_rec(const SweepArgs& a, size_t base, int s,
   }
 }
 
+// Raw inputs of one cell-velocity item, loaded a step before they are
+// turned into a Prep (the pipelined walk): geometry, q, and either the
+// Maxwellian factors of a tensor grid (TAB) or the node coefficients and nu.
+template <int DIM, int ORDER, bool TAB>
+struct Raw {
+  static constexpr int NP = Elem<DIM, ORDER>::NP, NG = 1 + (DIM + 1) * DIM, NC = DIM + 2;
+  static constexpr int NM = TAB ? 2 * NP : NP;                // (E_0, nu) pairs | nu
+  static constexpr int NX = TAB ? (DIM - 1) * NP : NP * NC;   // E_1 .. E_{d-1} | coefficients
+  double g[NG];
+  double q[NP];
+  double m[NM];
+  double x[NX];
+};
+
+// Plain loads of the raw inputs of slot s (cell K); nodal arrays in the
+// internal cell order (no node map)
+template <int DIM, int ORDER, bool TAB>
+__device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s, int K,
+                                         const double* const (&mrow)[DIM],
+                                         Raw<DIM, ORDER, TAB>& R) {
+  using RW = Raw<DIM, ORDER, TAB>;
+  constexpr int NP = Elem<DIM, ORDER>::NP;
+  const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
+#pragma unroll
+  for (int i = 0; i < RW::NG; ++i) R.g[i] = gk[i];
+  const double* __restrict__ q = a.q + (base + s) * NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) R.q[b] = q[b];
+  const size_t u = (size_t)K;
+  if constexpr (TAB) {
+    constexpr int S0 = TabLayout::pow2(2 * NP), S1 = TabLayout::pow2(NP);
+    const double* __restrict__ e0 = mrow[0] + u * S0;
+#pragma unroll
+    for (int b = 0; b < RW::NM; ++b) R.m[b] = e0[b];
+#pragma unroll
+    for (int al = 1; al < DIM; ++al)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) R.x[(al - 1) * NP + b] = mrow[al][u * S1 + b];
+  } else {
+#pragma unroll
+    for (int b = 0; b < NP; ++b) R.m[b] = a.nu[u * NP + b];
+    const double* __restrict__ mc = a.mcoef + u * NP * RW::NC;
+#pragma unroll
+    for (int i = 0; i < RW::NX; ++i) R.x[i] = mc[i];
+  }
+}
+
+// the arithmetic of prepare<..., TAB>, in the same order, on loaded data
+template <int DIM, int ORDER, bool TAB>
+__device__ __forceinline__ void compute_prep(const SweepArgs& a, const double* v, double v2,
+                                             const Raw<DIM, ORDER, TAB>& R,
+                                             Prep<DIM, ORDER>& P) {
+  using RW = Raw<DIM, ORDER, TAB>;
+  constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1;
+  P.vol = R.g[0];
+  double raw[NF];
+  facet_flux_raw<DIM>(R.g, v, v2, P.fl, raw);
+  constexpr double wf = (DIM == 2) ? -1.0 : -2.0;
+#pragma unroll
+  for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    double M, nub;
+    if constexpr (TAB) {
+      M = R.m[2 * b];
+#pragma unroll
+      for (int al = 1; al < DIM; ++al) M *= R.x[(al - 1) * NP + b];
+      nub = R.m[2 * b + 1];
+    } else {
+      M = maxw_eval<DIM>(R.x + b * RW::NC, v, v2);
+      nub = R.m[b];
+    }
+    P.sig[b] = nub + a.sigma_shift;
+    P.src[b] = fma(nub, M, a.q_scale * R.q[b]);
+  }
+}
+
 template <int DIM, int ORDER, bool TAB>
 __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, double v2,
                                         size_t base, const double* const (&mrow)[DIM],
@@ -173,7 +250,8 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
   if constexpr (TAB) {
     // tensor grid: M = prod_alpha E_alpha[i_alpha][node]; the first factor
     // is stored interleaved with nu, so one gather brings both
-    const double* __restrict__ e0 = mrow[0] + u * NP * 2;
+    constexpr int S0 = TabLayout::pow2(2 * NP), S1 = TabLayout::pow2(NP);
+    const double* __restrict__ e0 = mrow[0] + u * S0;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       M[b] = e0[2 * b];
@@ -182,7 +260,7 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
 #pragma unroll
     for (int al = 1; al < DIM; ++al)
 #pragma unroll
-      for (int b = 0; b < NP; ++b) M[b] *= mrow[al][u * NP + b];
+      for (int b = 0; b < NP; ++b) M[b] *= mrow[al][u * S1 + b];
   } else {
 #pragma unroll
     for (int b = 0; b < NP; ++b) nu[b] = a.nu[u * NP + b];
@@ -234,6 +312,14 @@ __device__ __forceinline__ void assemble(const Prep<DIM, ORDER>& P,
   }
 }
 
+// Completes the load that produced x at this point: the empty asm reads x
+// (so the compiler waits for that load here) and redefines it.  Used inside
+// the rare branches that read global memory, so that code after the branch
+// merge does not wait for outstanding loads: the vector-memory counter
+// retires in order, and such a wait would also drain the loads prefetched
+// for the following generations.
+__device__ __forceinline__ void settle(double& x) { asm volatile("" : "+v"(x)); }
+
 // upwind trace values of facet k at its nodes (in facet-node order)
 template <int DIM, int ORDER, typename RT>
 __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM, ORDER>& P,
@@ -251,6 +337,8 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
       const double* src = a.f_prev + (base + sl) * NP;
 #pragma unroll
       for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) settle(fh[p]);
     } else if (sl >= ring_lo) {
       const RT* src = ring + (sl & (RS - 1)) * NP;
 #pragma unroll
@@ -259,6 +347,8 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
       const double* src = a.f_out + (base + sl) * NP;
 #pragma unroll
       for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) settle(fh[p]);
     }
   } else {
     const size_t bf = (size_t)(-2 - c);
@@ -268,19 +358,21 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
     } else {
 #pragma unroll
       for (int p = 0; p < NFP; ++p) fh[p] = a.bc_dense[(bf * NFP + p) * a.n_v + j];
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) settle(fh[p]);
     }
   }
 }
 
-// FP64 solve of a prepared cell; the result goes to HBM and the LDS ring
+// FP64 solve of a prepared cell into rhs, which also goes to the LDS ring
 template <int DIM, int ORDER>
-__device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORDER>& P,
-                                         size_t base, int j, const double* v, double v2,
-                                         double* ring, int ring_lo) {
+__device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDER>& P, size_t base,
+                                        int j, const double* v, double v2, double* ring,
+                                        int ring_lo, double (&rhs)[Elem<DIM, ORDER>::NP]) {
   using S = Scaled<DIM, ORDER>;
   constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
   constexpr int RS = SweepCfg<DIM, ORDER>::RS;
-  double A[NP][NP], rhs[NP];
+  double A[NP][NP];
   assemble<DIM, ORDER>(P, A, rhs);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
@@ -299,13 +391,22 @@ __device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORD
     }
   }
   lu_solve<NP, double>(A, rhs);
-  double* fo = a.f_out + (base + P.s) * NP;
   double* rg = ring + (P.s & (RS - 1)) * NP;
 #pragma unroll
-  for (int b = 0; b < NP; ++b) {
-    fo[b] = rhs[b];
-    rg[b] = rhs[b];
-  }
+  for (int b = 0; b < NP; ++b) rg[b] = rhs[b];
+}
+
+// FP64 solve of a prepared cell; the result goes to HBM and the LDS ring
+template <int DIM, int ORDER>
+__device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORDER>& P,
+                                         size_t base, int j, const double* v, double v2,
+                                         double* ring, int ring_lo) {
+  constexpr int NP = Elem<DIM, ORDER>::NP;
+  double rhs[NP];
+  solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo, rhs);
+  double* fo = a.f_out + (base + P.s) * NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) fo[b] = rhs[b];
 }
 
 // FP32 defect correction of a prepared cell: FP64 residual of f_prev,
@@ -399,8 +500,10 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // One workgroup's walk over velocity j's generations; `ring` is LDS of
-// RS * NP values of the sweep's precision.
-template <int DIM, int ORDER, bool F32, bool TAB>
+// RS * NP values of the sweep's precision.  PIPE takes the pipelined walk
+// (FP64, nodal arrays in the internal order), which holds one cell's raw
+// inputs in registers across a solve.
+template <int DIM, int ORDER, bool F32, bool TAB, bool PIPE = false>
 __device__ __forceinline__ void sweep_velocity(
     const SweepArgs& a, int j, typename std::conditional<F32, float, double>::type* ring) {
   constexpr int NF = DIM + 1;
@@ -413,24 +516,117 @@ __device__ __forceinline__ void sweep_velocity(
     v2 = __fma_rn(v[d], v[d], v2);
   }
   const size_t base = (size_t)j * a.n_cells;
-  const int32_t* __restrict__ go = a.goff + a.gbase[j];
-  const int32_t* __restrict__ gm = a.gmin + a.gbase[j];
+  // generation offsets and minimum upwind slots, read through the scalar
+  // unit (constant address space: nothing writes them during the sweep):
+  // their loads are then counted apart from the vector loads in flight, and
+  // waiting for them does not drain the prefetched cell data
+  using cint32 = __attribute__((address_space(4))) const int32_t;
+  cint32* go = (cint32*)(a.goff + a.gbase[j]);
+  cint32* gm = (cint32*)(a.gmin + a.gbase[j]);
   const int G = a.G[j];
-  // rows of the factorised Maxwellian tables for this velocity (tensor grids)
+  // rows of the factorised Maxwellian tables for this velocity (tensor
+  // grids): cell c's record of axis al is mrow[al] + c * (s0 or s1)
   const double* mrow[DIM];
   {
     int rem = j;
-    const size_t nn = (size_t)a.n_cells * NP;
-    // table layout: axis 0 as (E_0, nu) pairs [n1][n_nodes][2], then axes
-    // 1..d-1 as [n1][n_nodes]
+    const TabLayout L(a.n_cells, a.n1, NP);
 #pragma unroll
     for (int al = DIM - 1; al >= 0; --al) {
       const int i = a.mtab ? rem % a.n1 : 0;
       rem = a.mtab ? rem / a.n1 : rem;
-      mrow[al] = !a.mtab ? nullptr
-                 : al == 0 ? a.mtab + (size_t)i * nn * 2
-                           : a.mtab + ((size_t)(al + 1) * a.n1 + i) * nn;
+      mrow[al] = a.mtab ? a.mtab + L.at(al, i, 0) : nullptr;
     }
+  }
+
+  if constexpr (PIPE) {
+    // Pipelined (FP64, no node map).  The walk is a sequence of steps, one per
+    // T-cell chunk of a generation (a generation wider than the workgroup
+    // takes several), with an LDS barrier after a generation's last chunk.
+    // Step i: issue the record load of this thread's cell of step i+2, solve
+    // step i, turn the raw inputs of step i+1 (loaded during step i-1) into
+    // its Prep, issue the raw-input loads of step i+2, store step i's result.
+    // Each load has a solve to complete under.  The vector-memory counter
+    // retires in order, so a wait for one load waits for all issued before
+    // it; the prefetch loads are therefore issued by every lane, whether or
+    // not it has a cell in that step (an idle lane loads slot 0 and ignores
+    // it), and a record is only copied between registers once it has arrived.
+    static_assert(!F32, "the pipelined walk is FP64");
+    using RawT = Raw<DIM, ORDER, TAB>;
+    const auto next = [&](int& g, int& k) {
+      if (g >= G) return;
+      if (go[g] + (k + 1) * T < go[g + 1]) {
+        ++k;
+      } else {
+        ++g;
+        k = 0;
+      }
+    };
+    const auto slot_of = [&](int g, int k) {
+      if (g >= G) return -1;
+      const int s = go[g] + k * T + tid;
+      return s < go[g + 1] ? s : -1;
+    };
+    Prep<DIM, ORDER> P;
+    RawT R;
+    int g0 = 0, k0 = 0;
+    int g1 = 0, k1 = 0;
+    next(g1, k1);
+    P.s = slot_of(g0, k0);
+    if (P.s >= 0) {
+      load_rec<DIM>(a, base, P.s, P.K, P.code, P.pack);
+      prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, P);
+    }
+    // record of this thread's cell of step i+1 (its raw inputs are in R); a
+    // slot of -1 marks an idle lane
+    int n1s = slot_of(g1, k1), n1K = 0, n1code[NF], n1pack = 0;
+    load_rec<DIM>(a, base, n1s >= 0 ? n1s : 0, n1K, n1code, n1pack);
+    load_raw<DIM, ORDER, TAB>(a, base, n1s >= 0 ? n1s : 0, n1K, mrow, R);
+    int synced = 0;
+    while (g0 < G) {
+      // step i+2: its record
+      int g2 = g1, k2 = k1;
+      next(g2, k2);
+      const int n2s = slot_of(g2, k2);
+      int n2K, n2code[NF], n2pack;
+      load_rec<DIM>(a, base, n2s >= 0 ? n2s : 0, n2K, n2code, n2pack);
+      // step i
+      const int s1 = go[g0 + 1];
+      const int ring_lo = s1 - RS;
+      if (k0 == 0 && gm[g0] < ring_lo && ring_lo > synced) {
+        __syncthreads();
+        synced = go[g0];
+      }
+      double out[NP];
+      const int out_s = P.s;
+      if (P.s >= 0) solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo, out);
+      const bool last_chunk = go[g0] + (k0 + 1) * T >= s1;
+      // step i+1: Prep from the raw inputs loaded one step ago
+      P.s = n1s;
+      P.K = n1K;
+      P.pack = n1pack;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) P.code[k] = n1code[k];
+      compute_prep<DIM, ORDER, TAB>(a, v, v2, R, P);
+      // step i+2: its raw-input loads
+      load_raw<DIM, ORDER, TAB>(a, base, n2s >= 0 ? n2s : 0, n2K, mrow, R);
+      n1s = n2s;
+      n1K = n2K;
+      n1pack = n2pack;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) n1code[k] = n2code[k];
+      // step i's result
+      if (out_s >= 0) {
+        double* fo = a.f_out + (base + out_s) * NP;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) fo[b] = out[b];
+      }
+      g0 = g1;
+      k0 = k1;
+      g1 = g2;
+      k1 = k2;
+      if (last_chunk) lds_barrier();
+    }
+    return;
   }
 
   Prep<DIM, ORDER> P;
@@ -491,16 +687,16 @@ __device__ __forceinline__ void sweep_velocity(
   }
 }
 
-template <int DIM, int ORDER, bool F32, bool TAB>
 // Register budget: P1 triangles fit 4 waves per SIMD; P2 triangles and
 // tetrahedra get 2 (up to 256 VGPRs, no spills): a sweep has at most a few
 // velocities per CU resident anyway, and the spill-free kernel is faster
 // (200k P2 triangles x 1024 velocities: 17.6 ms against 20.1 ms at 3).
+template <int DIM, int ORDER, bool F32, bool TAB, bool PIPE>
 __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep(SweepArgs a) {
   constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
   using RT = typename std::conditional<F32, float, double>::type;
   __shared__ RT ring[RS * NP];
-  sweep_velocity<DIM, ORDER, F32, TAB>(a, a.vorder[blockIdx.x], ring);
+  sweep_velocity<DIM, ORDER, F32, TAB, PIPE>(a, a.vorder[blockIdx.x], ring);
 }
 
 // Batched FP64 sweep over many instances in one launch: block b sweeps
@@ -554,6 +750,7 @@ SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io, const int32_
 
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
                  const double* mtab, float* d32, hipStream_t stream, int threads) {
+  if (mtab && node_map) return fail(BGK_E_INVALID, "Maxwellian tables need the internal node order");
   const SweepArgs a = make_sweep_args(d, io, node_map, mtab, d32);
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
@@ -567,15 +764,25 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_m
     threads = small ? 256 : 128;
   }
   const dim3 grid(d->n_v), block(threads);
-#define BGK_LAUNCH(D_, O_)                                                                \
-  if (fp32 && mtab)                                                                       \
-    hipLaunchKernelGGL((k_sweep<D_, O_, true, true>), grid, block, 0, stream, a);         \
-  else if (fp32)                                                                          \
-    hipLaunchKernelGGL((k_sweep<D_, O_, true, false>), grid, block, 0, stream, a);        \
-  else if (mtab)                                                                          \
-    hipLaunchKernelGGL((k_sweep<D_, O_, false, true>), grid, block, 0, stream, a);        \
-  else                                                                                    \
-    hipLaunchKernelGGL((k_sweep<D_, O_, false, false>), grid, block, 0, stream, a);
+  // FP64 sweeps in the internal node order take the pipelined walk (P1
+  // triangles keep the plain walk: their 4-waves-per-SIMD register budget
+  // has no room for a second cell's inputs)
+  const bool pipe = !fp32 && !node_map && !(d->dim == 2 && d->order == 1);
+#define BGK_LAUNCH(D_, O_)                                                                 \
+  if (fp32 && mtab)                                                                        \
+    hipLaunchKernelGGL((k_sweep<D_, O_, true, true, false>), grid, block, 0, stream, a);   \
+  else if (fp32)                                                                           \
+    hipLaunchKernelGGL((k_sweep<D_, O_, true, false, false>), grid, block, 0, stream, a);  \
+  else if (mtab && pipe)                                                                   \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, true, (D_ != 2 || O_ != 1)>), grid, block, 0, \
+                       stream, a);                                                         \
+  else if (mtab)                                                                           \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, true, false>), grid, block, 0, stream, a);  \
+  else if (pipe)                                                                           \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, false, (D_ != 2 || O_ != 1)>), grid, block, 0, \
+                       stream, a);                                                         \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, false, false>), grid, block, 0, stream, a);
   if (d->dim == 2 && d->order == 1) {
     BGK_LAUNCH(2, 1)
   } else if (d->dim == 2 && d->order == 2) {

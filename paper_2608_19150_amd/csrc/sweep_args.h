@@ -19,7 +19,7 @@ struct SweepArgs {
   const int32_t* node_map;   // internal cell -> row of the nodal arrays (null: identity)
   const double* nu;
   const double* mcoef;
-  const double* mtab;        // factorised Maxwellian [dim][n1][n_nodes] (internal order) or null
+  const double* mtab;        // factorised Maxwellian tables (TabLayout, internal order) or null
   const double* q;
   const double* bc_coef;
   const double* bc_dense;
