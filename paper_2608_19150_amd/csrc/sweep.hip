@@ -714,13 +714,14 @@ __global__ __launch_bounds__(256, 2) void k_sweep_batch(const SweepArgs* __restr
   if (done[m.x]) return;
   const SweepArgs a = args[m.x];
   const int j = a.vorder[m.y];
+  // batched instances are FP64 in the internal node order: pipelined walk
   if constexpr (DIM == 2) {
     if (a.order == 1)
-      sweep_velocity<2, 1, false, TAB>(a, j, ring);
+      sweep_velocity<2, 1, false, TAB, true>(a, j, ring);
     else
-      sweep_velocity<2, 2, false, TAB>(a, j, ring);
+      sweep_velocity<2, 2, false, TAB, true>(a, j, ring);
   } else {
-    sweep_velocity<3, 1, false, TAB>(a, j, ring);
+    sweep_velocity<3, 1, false, TAB, true>(a, j, ring);
   }
 }
 
