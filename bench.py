@@ -275,13 +275,24 @@ def calibrate_copy(mib):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_p2_c2_traffic.txt")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2608_19150_amd", "csrc", "sweep.hip")
+# the sweep kernel and the layouts it reads (geometry, tables, records)
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2608_19150_amd", "csrc", name)
+                 for name in ("sweep.hip", "sweep_args.h", "internal.h", "device_common.h")]
+SWEEP_KERNEL = "k_sweep<2, 2, false, true, true>"
+
+
+def sweep_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for path in SWEEP_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per sweep launch from the committed counter summary, or
     None when the sweep source has changed since the counters were taken."""
-    import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -290,9 +301,9 @@ def measured_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    with open(SWEEP_SOURCE, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    if fields.get("sweep_source_sha256") != digest:
+    if fields.get("sweep_source_sha256") != sweep_source_digest():
+        return None
+    if fields.get("kernel") != SWEEP_KERNEL:
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -394,7 +405,7 @@ def main():
         "fp32_refine": fp32,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_sweep<2, 2, false, true>",
+                     "kernel": SWEEP_KERNEL,
                      "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},
         "cpu_baseline": cpu,
         "c3_3d": c3,

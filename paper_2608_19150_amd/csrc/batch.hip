@@ -442,7 +442,8 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
   for (int i = 0; i < n; ++i) {
     const tgs_dag* d = solvers[i]->dag;
     nfirst[i + 1] = nfirst[i] + d->n_nodes;
-    tfirst[i + 1] = tfirst[i] + (tab ? d->n_nodes * d->dim * d->n_1d : 0);
+    tfirst[i + 1] =
+        tfirst[i] + (tab ? table_chunks(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table chunks
     mfirst[i + 1] = mfirst[i] + moment_blocks(d);
     npart += (int64_t)moment_blocks(d) * 6;
   }

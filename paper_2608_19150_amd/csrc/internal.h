@@ -237,6 +237,11 @@ struct TabLayout {
   }
 };
 
+// 16-byte chunks of the tables (the unit the table kernels write)
+__host__ __device__ inline int64_t table_chunks(int dim, int64_t n_cells, int n1, int np) {
+  return TabLayout(n_cells, n1, np).size(dim) / 2;
+}
+
 // facet record: x = neighbour internal cell id, or -(1 + boundary facet id);
 // y = bits 0..1 neighbour's facet index, bits 4*(p+1).. neighbour local node
 // of facet node p (4 bits each)

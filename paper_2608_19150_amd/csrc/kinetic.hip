@@ -507,56 +507,73 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // Factorised Maxwellian for tensor velocity grids: exp(a + b.v + c|v|^2) =
 // prod_alpha exp([alpha == 0] a + b_alpha x + c x^2) with x the node of axis
 // alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
-// and M(v_j) is the product of d table entries.  Entry idx = (al * n1 + i) *
-// n_nodes + node; it is stored at its place in the per-cell padded layout
-// (TabLayout): axis 0 with nu as (E_0, nu) pairs, so the sweep gathers both
-// with one access.
+// and M(v_j) is the product of d table entries.  The padded per-cell records
+// (TabLayout) are written as 16-byte chunks, pad included, consecutive
+// chunks by consecutive threads: chunk t of axis 0 is node b of a record as
+// (E_0, nu) (the sweep gathers both with one access), a chunk of another
+// axis holds two nodes' entries.  Chunks are numbered through axis 0's
+// records first, then through those of axes 1..d-1.
 template <int DIM>
-__device__ __forceinline__ void table_entry(const double* __restrict__ coef,
+__device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
                                             const double* __restrict__ nu,
-                                            const double* __restrict__ x1, double* __restrict__ tab,
-                                            int64_t n_nodes, int n1, int np, int64_t idx) {
+                                            const double* __restrict__ x1,
+                                            double* __restrict__ tab, int64_t n_cells, int n1,
+                                            int np, int64_t t) {
   constexpr int NM = DIM + 2;
-  const int64_t node = idx % n_nodes;
-  const int64_t r = idx / n_nodes;
-  const int i = (int)(r % n1), al = (int)(r / n1);
-  const TabLayout L(n_nodes / np, n1, np);
-  const int64_t c = node / np;
-  const int b = (int)(node - c * np);
-  const double x = x1[i];
-  const double* cf = coef + node * NM;
-  double e = __fma_rn(cf[1 + DIM], x * x, cf[1 + al] * x);
-  if (al == 0) {
-    e += cf[0];
-    double* t = tab + L.at(0, i, c) + 2 * b;
-    t[0] = bgk_exp(e);
-    t[1] = nu[node];
+  const TabLayout L(n_cells, n1, np);
+  const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
+  int al, h;
+  int64_t r;
+  if (t < a0) {
+    al = 0;
+    r = t / (L.s0 / 2);
+    h = (int)(t - r * (L.s0 / 2));
   } else {
-    tab[L.at(al, i, c) + b] = bgk_exp(e);
+    const int64_t u = t - a0;
+    const int64_t q = u / (L.s1 / 2);
+    h = (int)(u - q * (L.s1 / 2));
+    al = 1 + (int)(q / ((int64_t)n1 * n_cells));
+    r = q - (int64_t)(al - 1) * n1 * n_cells;
   }
+  const int64_t c = r % n_cells;
+  const int i = (int)(r / n_cells);
+  const double x = x1[i];
+  const auto entry = [&](int b) {
+    const double* cf = coef + (c * np + b) * NM;
+    double e = __fma_rn(cf[1 + DIM], x * x, cf[1 + al] * x);
+    if (al == 0) e += cf[0];
+    return bgk_exp(e);
+  };
+  double2 v;
+  if (al == 0) {
+    v = h < np ? make_double2(entry(h), nu[c * np + h]) : make_double2(0.0, 0.0);
+  } else {
+    v = make_double2(2 * h < np ? entry(2 * h) : 0.0, 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
+  }
+  reinterpret_cast<double2*>(tab + L.at(al, i, c))[h] = v;
 }
 
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
                               const double* __restrict__ x1, double* __restrict__ tab,
-                              int64_t n_nodes, int n1, int np) {
-  const int64_t total = n_nodes * DIM * n1;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    table_entry<DIM>(coef, nu, x1, tab, n_nodes, n1, np, idx);
+                              int64_t n_cells, int n1, int np) {
+  const int64_t total = table_chunks(DIM, n_cells, n1, np);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    table_chunk<DIM>(coef, nu, x1, tab, n_cells, n1, np, t);
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream) {
-  const int64_t total = d->n_nodes * d->dim * d->n_1d;
-  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   const int np = (int)(d->n_nodes / d->n_cells);
+  const int64_t total = table_chunks(d->dim, d->n_cells, d->n_1d, np);
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_nodes, d->n_1d, np);
+                       tab, d->n_cells, d->n_1d, np);
   else
     hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_nodes, d->n_1d, np);
+                       tab, d->n_cells, d->n_1d, np);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -693,7 +710,8 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
     const int i = find_instance<int64_t>(first, n_inst, g);
     if (done[i] || !kin[i].mtab) continue;
     const BatchKin& k = kin[i];
-    table_entry<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes, k.n1, k.np, g - first[i]);
+    table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes / k.np, k.n1, k.np,
+                     g - first[i]);
   }
 }
 

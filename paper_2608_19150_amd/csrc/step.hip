@@ -44,42 +44,31 @@ __global__ __launch_bounds__(256) void k_combine(double* out, const double* x0, 
                                                  const double* x4, double c0, double c1,
                                                  double c2, double c3, double c4, int nin,
                                                  size_t n) {
-  using VT = typename std::conditional<V == 2, double2, double>::type;
-  const auto lin = [&](size_t i, auto get) {
-    VT s = get(x0, i);
+  // V doubles per access; the arrays are streamed once, with non-temporal
+  // loads and stores
+  typedef double VT __attribute__((ext_vector_type(V)));
+  const double* xs[4] = {x1, x2, x3, x4};
+  const double cs[4] = {c1, c2, c3, c4};
+  const size_t nv = n / V;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const VT s0 = __builtin_nontemporal_load(reinterpret_cast<const VT*>(x0) + i);
     VT r;
-    if constexpr (V == 2) {
-      r.x = c0 * s.x;
-      r.y = c0 * s.y;
-    } else {
-      r = c0 * s;
-    }
-    const double* xs[4] = {x1, x2, x3, x4};
-    const double cs[4] = {c1, c2, c3, c4};
+#pragma unroll
+    for (int e = 0; e < V; ++e) r[e] = c0 * s0[e];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (nin > k + 1) {
-        const VT t = get(xs[k], i);
-        if constexpr (V == 2) {
-          r.x = fma(cs[k], t.x, r.x);
-          r.y = fma(cs[k], t.y, r.y);
-        } else {
-          r = fma(cs[k], t, r);
-        }
+        const VT t = __builtin_nontemporal_load(reinterpret_cast<const VT*>(xs[k]) + i);
+#pragma unroll
+        for (int e = 0; e < V; ++e) r[e] = fma(cs[k], t[e], r[e]);
       }
     }
-    return r;
-  };
-  const auto ld = [](const double* p, size_t i) { return reinterpret_cast<const VT*>(p)[i]; };
-  const size_t nv = n / V;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * blockDim.x)
-    reinterpret_cast<VT*>(out)[i] = lin(i, ld);
+    __builtin_nontemporal_store(r, reinterpret_cast<VT*>(out) + i);
+  }
   if (V == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     const size_t t = n - 1;
     double r = c0 * x0[t];
-    const double* xs[4] = {x1, x2, x3, x4};
-    const double cs[4] = {c1, c2, c3, c4};
     for (int k = 0; k < 4; ++k)
       if (nin > k + 1) r = fma(cs[k], xs[k][t], r);
     out[t] = r;
