@@ -176,7 +176,11 @@ typedef struct {
  *   b = M_K (nu*M_j + q_scale*q) + sum_{v.n<0} |v.n| M_e fhat
  * with fhat the upwind neighbour's new value, the lagged f_prev, or the
  * boundary value (exactly one of bc_coef / bc_dense non-NULL).  Exactly one
- * sweep; no convergence logic.  Asynchronous on `stream`. */
+ * sweep; no convergence logic.  Asynchronous on `stream`; allocates stream-
+ * ordered scratch (nu and the coefficients in the library's internal cell
+ * order, n_nodes*(dim+3) doubles, plus the FP32 corrections in that form)
+ * and frees it on the same stream.
+ * Errors: BGK_E_INVALID (missing or aliased buffers), BGK_E_NOMEM, BGK_E_HIP. */
 int tgs_sweep(const tgs_dag* dag, const tgs_sweep_io* io, bgk_stream_t stream);
 
 /* ------------------------------------------------------------------------ */

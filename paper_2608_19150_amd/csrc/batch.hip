@@ -231,7 +231,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       io.q = st == 0 ? s->fk : s->q;
       io.bc_coef = o.bc_coef;
       io.f_out = out[st];
-      sargs[(size_t)st * n + i] = make_sweep_args(d, &io, nullptr, mtab, nullptr);
+      sargs[(size_t)st * n + i] = make_sweep_args(d, &io, mtab, nullptr);
     }
     {
       // autotuning probe: read the caller's f as the source, write f^k
@@ -244,7 +244,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       io.q = f[i];
       io.bc_coef = o.bc_coef;
       io.f_out = s->fk;
-      tune[i] = make_sweep_args(d, &io, nullptr, mtab, nullptr);
+      tune[i] = make_sweep_args(d, &io, mtab, nullptr);
     }
     for (int k = 0; k < S + 2; ++k) {
       BatchKin& b = kin[(size_t)k * n + i];

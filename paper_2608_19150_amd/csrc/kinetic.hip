@@ -5,6 +5,7 @@
 
 #include "device_common.h"
 #include "kinetic_args.h"
+#include "sweep_args.h"
 
 namespace bgk {
 
@@ -597,7 +598,11 @@ __global__ void k_nodal_perm(const double* __restrict__ src, double* __restrict_
 
 int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,
                       hipStream_t stream) {
-  const int row = d->n_p * (d->dim + 2);
+  return launch_nodal_rows(d, src, dst, d->n_p * (d->dim + 2), to_internal, stream);
+}
+
+int launch_nodal_rows(const tgs_dag* d, const double* src, double* dst, int row, int to_internal,
+                      hipStream_t stream) {
   const int64_t total = d->n_cells * row;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(k_nodal_perm, dim3(grid), dim3(256), 0, stream, src, dst, d->d_uid,

@@ -17,8 +17,8 @@
 #include "solver.h"
 
 namespace bgk {
-int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
-                 const double* mtab, float* d32, hipStream_t stream, int threads);
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
+                 hipStream_t stream, int threads);
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream);
 // doubles of the factorised tables (per-cell padded layout)
@@ -328,7 +328,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       io.bc_coef = o.bc_coef;
       io.f_prev = need_prev ? prev : nullptr;
       io.f_out = cur_out;
-      if ((rc = launch_sweep(d, &io, nullptr, s->mtab, s->d32, stream, 0))) return rc;
+      if ((rc = launch_sweep(d, &io, s->mtab, s->d32, stream, 0))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
       if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
                                stream, false)))

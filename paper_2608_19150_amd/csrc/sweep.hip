@@ -244,7 +244,7 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
   constexpr double wf = (DIM == 2) ? -1.0 : -2.0;
 #pragma unroll
   for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
-  const size_t u = a.node_map ? (size_t)a.node_map[P.K] : (size_t)P.K;
+  const size_t u = (size_t)P.K;  // nodal arrays in the internal cell order
   const double* __restrict__ q = a.q + (base + P.s) * NP;
   double M[NP], nu[NP];
   if constexpr (TAB) {
@@ -740,19 +740,18 @@ int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map
   return BGK_OK;
 }
 
-SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32) {
   return SweepArgs{d->d_geo,   d->d_facet, d->d_v,      d->d_rec,   d->d_recx,  d->d_perm,
-                   d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, node_map, io->nu,
+                   d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, io->nu,
                    io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
                    io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
                    d->n_1d,    d->order};
 }
 
-int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
-                 const double* mtab, float* d32, hipStream_t stream, int threads) {
-  if (mtab && node_map) return fail(BGK_E_INVALID, "Maxwellian tables need the internal node order");
-  const SweepArgs a = make_sweep_args(d, io, node_map, mtab, d32);
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
+                 hipStream_t stream, int threads) {
+  const SweepArgs a = make_sweep_args(d, io, mtab, d32);
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {
@@ -765,10 +764,10 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_m
     threads = small ? 256 : 128;
   }
   const dim3 grid(d->n_v), block(threads);
-  // FP64 sweeps in the internal node order take the pipelined walk (P1
-  // triangles keep the plain walk: their 4-waves-per-SIMD register budget
-  // has no room for a second cell's inputs)
-  const bool pipe = !fp32 && !node_map && !(d->dim == 2 && d->order == 1);
+  // FP64 sweeps take the pipelined walk (P1 triangles keep the plain walk:
+  // their 4-waves-per-SIMD register budget has no room for a second cell's
+  // inputs)
+  const bool pipe = !fp32 && !(d->dim == 2 && d->order == 1);
 #define BGK_LAUNCH(D_, O_)                                                                 \
   if (fp32 && mtab)                                                                        \
     hipLaunchKernelGGL((k_sweep<D_, O_, true, true, false>), grid, block, 0, stream, a);   \
@@ -858,13 +857,28 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
   if ((d->d_lag || io->precision == TGS_FP32_CORRECTION) && !io->f_prev)
     return fail(BGK_E_INVALID, "f_prev is required with lagged facets or the FP32 form");
   if (io->f_prev && io->f_prev == io->f_out) return fail(BGK_E_INVALID, "f_out aliases f_prev");
+  // the kernels read nodal arrays in the internal cell order: nu and the
+  // coefficients are permuted into scratch first
+  hipStream_t st = (hipStream_t)stream;
+  const int np = d->n_p, nm = d->dim + 2;
   float* d32 = nullptr;
-  if (io->precision == TGS_FP32_CORRECTION) {
-    if (hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), (hipStream_t)stream) != hipSuccess)
-      return fail(BGK_E_NOMEM, "correction buffer allocation failed");
+  double* nodal = nullptr;  // [n_nodes] nu, then [n_nodes][dim+2] coefficients
+  if (hipMallocAsync((void**)&nodal, (size_t)d->n_nodes * (1 + nm) * sizeof(double), st) !=
+      hipSuccess)
+    return fail(BGK_E_NOMEM, "scratch allocation failed");
+  if (io->precision == TGS_FP32_CORRECTION &&
+      hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), st) != hipSuccess) {
+    (void)hipFreeAsync(nodal, st);
+    return fail(BGK_E_NOMEM, "correction buffer allocation failed");
   }
-  int rc = launch_sweep(d, io, d->d_uid, nullptr, d32, (hipStream_t)stream, 0);
-  if (d32) (void)hipFreeAsync(d32, (hipStream_t)stream);
+  tgs_sweep_io io_i = *io;
+  io_i.nu = nodal;
+  io_i.mcoef = nodal + d->n_nodes;
+  int rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
+  if (!rc) rc = launch_nodal_rows(d, io->mcoef, nodal + d->n_nodes, np * nm, 1, st);
+  if (!rc) rc = launch_sweep(d, &io_i, nullptr, d32, st, 0);
+  if (d32) (void)hipFreeAsync(d32, st);
+  (void)hipFreeAsync(nodal, st);
   return rc;
 }
 

@@ -16,7 +16,6 @@ struct SweepArgs {
   const int64_t* gbase;
   const int32_t* G;
   const int32_t* vorder;
-  const int32_t* node_map;   // internal cell -> row of the nodal arrays (null: identity)
   const double* nu;
   const double* mcoef;
   const double* mtab;        // factorised Maxwellian tables (TabLayout, internal order) or null
@@ -38,7 +37,11 @@ struct SweepArgs {
 // map[b].y of instance map[b].x with args[map[b].x], unless done[map[b].x].
 int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nblocks,
                        const int32_t* done, int threads, hipStream_t stream);
-SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io, const int32_t* node_map,
+SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32);
+// copies per-cell rows of `row` doubles between the user and the internal
+// cell order (kinetic.hip)
+int launch_nodal_rows(const tgs_dag* d, const double* src, double* dst, int row, int to_internal,
+                      hipStream_t stream);
 
 }  // namespace bgk

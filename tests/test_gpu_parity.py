@@ -144,6 +144,48 @@ def test_sweep_bitwise_reproducible_across_runs_and_workgroup_sizes(dim, order):
         assert np.array_equal(o, outs[0])
 
 
+WIDE = [(3, 1, 10, 2), (2, 2, 80, 2), (2, 1, 80, 2)]
+
+
+@pytest.mark.parametrize("dim,order,n_side,n1", WIDE)
+def test_sweep_wide_generations_match_oracle(dim, order, n_side, n1):
+    """Generations of 60-110 cells: with 64-thread workgroups a generation
+    takes two chunks (the pipelined walk's steps, or the plain walk's second
+    pass for P1 triangles); the result matches the oracle and equals the
+    256-thread (one chunk per generation) sweep bit for bit."""
+    say("sweep wide generations", dim, order, n_side, n1)
+    pr = _problem(dim, order, n_side, n1, state="riemann")
+    geo, q, nu, prim = _random_sweep_inputs(pr, 21)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    widest = max(int(np.bincount(g).max()) for g in gens)
+    assert 64 < widest <= 256
+    outs = []
+    for T in (64, 256):
+        d = B.Dag.from_problem(pr, sweep_threads=T)
+        outs.append(_gpu_sweep(d, pr, q, nu, prim, 37.0, 2.5))
+    assert np.array_equal(outs[0], outs[1])
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 37.0, 2.5, gens)
+    assert rel(outs[0], f_ref) <= TOL64
+
+
+@pytest.mark.parametrize("dim,order,n_side", [(2, 2, 80), (3, 1, 10)])
+def test_step_wide_generations_bitwise_across_workgroup_sizes(dim, order, n_side):
+    """Whole steps through the solver (factorised tables, pipelined walk) on
+    meshes whose generations are wider than 64 cells: 64-, 128- and
+    256-thread workgroups give the same f bit for bit."""
+    say("step wide generations", dim, order, n_side)
+    pr = _problem(dim, order, n_side, 4, state="fourier")
+    outs = []
+    for T in (64, 128, 256):
+        d, f0, bc, dt = B.problem_setup(pr, sweep_threads=T)
+        s = B.Solver(d, dt=dt, bc_coef=bc, tableau="DIRK2", fixed_iters=2, mode="MATCHED",
+                     nu_model="kn", kn=0.1)
+        s.step(f0)
+        outs.append(d.unpack(f0).cpu().numpy())
+        del s, d, f0
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_sweep_dense_boundary_matches_oracle():
     pr = _problem(2, 2, 3, 4)
     d = B.Dag.from_problem(pr)
