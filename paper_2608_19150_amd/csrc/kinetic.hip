@@ -707,13 +707,20 @@ __global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __rest
   maxwellian_node<DIM>(p, U, g - first[i]);
 }
 
+// Grid-stride over every instance's table chunks; a thread that meets a
+// finished instance (or one without tables) jumps to its first position past
+// that instance's range, so finished instances cost O(instances) per thread.
 template <int DIM>
 __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* __restrict__ done,
                                const int64_t* __restrict__ first, int n_inst, int64_t total) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += stride) {
     const int i = find_instance<int64_t>(first, n_inst, g);
-    if (done[i] || !kin[i].mtab) continue;
+    if (done[i] || !kin[i].mtab) {
+      const int64_t end = first[i + 1];
+      if (end > g + stride) g += (end - g - 1) / stride * stride;
+      continue;
+    }
     const BatchKin& k = kin[i];
     table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes / k.np, k.n1, k.np,
                      g - first[i]);
