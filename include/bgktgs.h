@@ -107,6 +107,12 @@ typedef struct {
   /* Threads per workgroup of the sweep kernel (64..256, multiple of 64);
      0 = the library's choice (256 for P1 triangles, else 128). */
   int sweep_threads;
+  /* Slots of the sweep's LDS ring of recent cell outputs (a power of two in
+     16..1024, capped at what the element type's ring holds: 1024, or 512 for
+     P2 triangles); 0 = that maximum.  Upwind values older than the ring are
+     read from HBM after a workgroup fence: a small ring exercises that path
+     on small meshes (tests); it never changes results. */
+  int ring_slots;
 } tgs_dag_opts;
 
 typedef struct tgs_dag tgs_dag;

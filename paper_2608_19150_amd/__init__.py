@@ -68,7 +68,7 @@ class VGridDesc(C.Structure):
 
 
 class DagOpts(C.Structure):
-    _fields_ = [("lagged", C.c_void_p), ("sweep_threads", C.c_int)]
+    _fields_ = [("lagged", C.c_void_p), ("sweep_threads", C.c_int), ("ring_slots", C.c_int)]
 
 
 class SweepIO(C.Structure):
@@ -143,7 +143,7 @@ class Dag:
     """Handle returned by build_mesh_dag (mesh geometry + per-velocity DAGs)."""
 
     def __init__(self, vert, cells, order, v, w, *, n_1d=0, nodes_1d=None, weights_1d=None,
-                 L=0.0, lagged=None, sweep_threads=0, stream=None):
+                 L=0.0, lagged=None, sweep_threads=0, ring_slots=0, stream=None):
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         v = np.ascontiguousarray(v, dtype=np.float64)
@@ -161,7 +161,8 @@ class Dag:
         if lagged is not None:
             lag = np.ascontiguousarray(lagged, dtype=np.uint8)
             self._keep.append(lag)
-        opts = DagOpts(lag.ctypes.data if lag is not None else None, int(sweep_threads))
+        opts = DagOpts(lag.ctypes.data if lag is not None else None, int(sweep_threads),
+                       int(ring_slots))
         h = C.c_void_p()
         _check(_lib.build_mesh_dag(C.byref(md), C.byref(vd), C.byref(opts), _stream(stream),
                                    C.byref(h)))

@@ -556,6 +556,12 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
               BGK_E_INVALID, "sweep_threads must be a multiple of 64 in [64, 256]");
     D->sweep_threads = opts->sweep_threads;
   }
+  if (opts && opts->ring_slots) {
+    const int r = opts->ring_slots;
+    BGK_CHECK(r >= 16 && r <= 1024 && (r & (r - 1)) == 0, BGK_E_INVALID,
+              "ring_slots must be a power of two in [16, 1024]");
+    D->ring_slots = r;
+  }
   // tensor grid declaration
   D->n_1d = vg->n_1d;
   if (vg->n_1d > 0) {

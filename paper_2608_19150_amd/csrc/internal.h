@@ -263,6 +263,7 @@ struct tgs_dag {
   int max_G = 0;
   int64_t n_lagged = 0;
   int sweep_threads = 0;   // 0: chosen per element type and precision
+  int ring_slots = 0;      // 0: the element type's full LDS ring
   // host copies
   std::vector<double> v_host, w_host;       // [n_v][dim], [n_v]
   int n_1d = 0;

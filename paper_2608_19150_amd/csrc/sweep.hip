@@ -18,7 +18,8 @@
 // Latency.  Everything a cell needs except its upwind neighbours' new values
 // (record, geometry, Maxwellian, sigma, source) is loaded and evaluated one
 // generation ahead, before the barrier.  New values are also kept in an LDS
-// ring of the last RS slots; upwind reads are served from it when their slot
+// ring of the last ring_slots slots (at most RS, a power of two; fewer only
+// to test the HBM path); upwind reads are served from it when their slot
 // is recent enough, so the per-generation barrier only orders LDS
 // (s_waitcnt lgkmcnt + s_barrier) and global loads stay in flight across it.
 // Older upwind values are read from HBM after a full workgroup fence, which
@@ -324,10 +325,9 @@ __device__ __forceinline__ void settle(double& x) { asm volatile("" : "+v"(x)); 
 template <int DIM, int ORDER, typename RT>
 __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM, ORDER>& P,
                                               int k, size_t base, int j, const double* v,
-                                              double v2, const RT* ring, int ring_lo,
+                                              double v2, const RT* ring, int rmask, int ring_lo,
                                               bool use_prev, double (&fh)[Elem<DIM, ORDER>::NFP]) {
   constexpr int NP = Elem<DIM, ORDER>::NP, NFP = Elem<DIM, ORDER>::NFP, NC = DIM + 2;
-  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
   constexpr int NB = NP <= 4 ? 2 : 3, NM = (1 << NB) - 1;
   const int c = P.code[k];
   if (c >= 0) {
@@ -340,7 +340,7 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
 #pragma unroll
       for (int p = 0; p < NFP; ++p) settle(fh[p]);
     } else if (sl >= ring_lo) {
-      const RT* src = ring + (sl & (RS - 1)) * NP;
+      const RT* src = ring + (sl & rmask) * NP;
 #pragma unroll
       for (int p = 0; p < NFP; ++p) fh[p] = (double)src[(pk >> (NB * p)) & NM];
     } else {
@@ -368,17 +368,17 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
 template <int DIM, int ORDER>
 __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDER>& P, size_t base,
                                         int j, const double* v, double v2, double* ring,
-                                        int ring_lo, double (&rhs)[Elem<DIM, ORDER>::NP]) {
+                                        int rmask, int ring_lo,
+                                        double (&rhs)[Elem<DIM, ORDER>::NP]) {
   using S = Scaled<DIM, ORDER>;
   constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
-  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
   double A[NP][NP];
   assemble<DIM, ORDER>(P, A, rhs);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
     if (P.code[k] == -1) continue;
     double fh[NFP];
-    upwind_values<DIM, ORDER, double>(a, P, k, base, j, v, v2, ring, ring_lo, false, fh);
+    upwind_values<DIM, ORDER, double>(a, P, k, base, j, v, v2, ring, rmask, ring_lo, false, fh);
     const double inflow = -P.fl[k] * (1.0 / S::FS);
 #pragma unroll
     for (int ia = 0; ia < NFP; ++ia) {
@@ -391,7 +391,7 @@ __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDE
     }
   }
   lu_solve<NP, double>(A, rhs);
-  double* rg = ring + (P.s & (RS - 1)) * NP;
+  double* rg = ring + (P.s & rmask) * NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) rg[b] = rhs[b];
 }
@@ -400,10 +400,10 @@ __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDE
 template <int DIM, int ORDER>
 __device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORDER>& P,
                                          size_t base, int j, const double* v, double v2,
-                                         double* ring, int ring_lo) {
+                                         double* ring, int rmask, int ring_lo) {
   constexpr int NP = Elem<DIM, ORDER>::NP;
   double rhs[NP];
-  solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo, rhs);
+  solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo, rhs);
   double* fo = a.f_out + (base + P.s) * NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) fo[b] = rhs[b];
@@ -414,10 +414,9 @@ __device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORD
 template <int DIM, int ORDER>
 __device__ __forceinline__ void finish32c(const SweepArgs& a, const Prep<DIM, ORDER>& P,
                                           size_t base, int j, const double* v, double v2,
-                                          float* ring, int ring_lo) {
+                                          float* ring, int rmask, int ring_lo) {
   using S = Scaled<DIM, ORDER>;
   constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
-  constexpr int RS = SweepCfg<DIM, ORDER>::RS;
   double A[NP][NP], r[NP], fold[NP];
   assemble<DIM, ORDER>(P, A, r);
   const double* fp = a.f_prev + (base + P.s) * NP;
@@ -428,7 +427,7 @@ __device__ __forceinline__ void finish32c(const SweepArgs& a, const Prep<DIM, OR
   for (int k = 0; k < NF; ++k) {
     if (P.code[k] == -1) continue;
     double fh[NFP];
-    upwind_values<DIM, ORDER, float>(a, P, k, base, j, v, v2, ring, ring_lo, true, fh);
+    upwind_values<DIM, ORDER, float>(a, P, k, base, j, v, v2, ring, rmask, ring_lo, true, fh);
     const double inflow = -P.fl[k] * (1.0 / S::FS);
 #pragma unroll
     for (int ia = 0; ia < NFP; ++ia) {
@@ -460,7 +459,7 @@ __device__ __forceinline__ void finish32c(const SweepArgs& a, const Prep<DIM, OR
     const int pk = P.pack >> (NB * k * NFP);
     float dh[NFP];
     if (sl >= ring_lo) {
-      const float* src = ring + (sl & (RS - 1)) * NP;
+      const float* src = ring + (sl & rmask) * NP;
 #pragma unroll
       for (int p = 0; p < NFP; ++p) dh[p] = src[(pk >> (NB * p)) & NM];
     } else {
@@ -482,7 +481,7 @@ __device__ __forceinline__ void finish32c(const SweepArgs& a, const Prep<DIM, OR
   lu_solve<NP, float>(Af, rf);
   double* fo = a.f_out + (base + P.s) * NP;
   float* dg = a.d32 + (base + P.s) * NP;
-  float* rg = ring + (P.s & (RS - 1)) * NP;
+  float* rg = ring + (P.s & rmask) * NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
     fo[b] = fold[b] + (double)rf[b];
@@ -500,15 +499,21 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // One workgroup's walk over velocity j's generations; `ring` is LDS of
-// RS * NP values of the sweep's precision.  PIPE takes the pipelined walk
+// SweepCfg::RS * NP values of the sweep's precision (rs * NP used).  PIPE takes the pipelined walk
 // (FP64, nodal arrays in the internal order), which holds one cell's raw
 // inputs in registers across a solve.
 template <int DIM, int ORDER, bool F32, bool TAB, bool PIPE = false>
 __device__ __forceinline__ void sweep_velocity(
     const SweepArgs& a, int j, typename std::conditional<F32, float, double>::type* ring) {
   constexpr int NF = DIM + 1;
-  constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
+  constexpr int NP = SweepCfg<DIM, ORDER>::NP;
   const int T = blockDim.x, tid = threadIdx.x;
+  // ring slots: at least the workgroup size, so that two cells of one chunk
+  // never share a ring slot (cells rs slots apart in a generation wider
+  // than the ring are then separated by a barrier, below)
+  int rs = a.ring_slots;
+  while (rs < T) rs *= 2;
+  const int rmask = rs - 1;
   double v[DIM], v2 = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -591,15 +596,16 @@ __device__ __forceinline__ void sweep_velocity(
       load_rec<DIM>(a, base, n2s >= 0 ? n2s : 0, n2K, n2code, n2pack);
       // step i
       const int s1 = go[g0 + 1];
-      const int ring_lo = s1 - RS;
+      const int ring_lo = s1 - rs;
       if (k0 == 0 && gm[g0] < ring_lo && ring_lo > synced) {
         __syncthreads();
         synced = go[g0];
       }
       double out[NP];
       const int out_s = P.s;
-      if (P.s >= 0) solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo, out);
+      if (P.s >= 0) solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo, out);
       const bool last_chunk = go[g0] + (k0 + 1) * T >= s1;
+      const bool wide = s1 - go[g0] > rs;
       // step i+1: Prep from the raw inputs loaded one step ago
       P.s = n1s;
       P.K = n1K;
@@ -624,7 +630,10 @@ __device__ __forceinline__ void sweep_velocity(
       k0 = k1;
       g1 = g2;
       k1 = k2;
-      if (last_chunk) lds_barrier();
+      // after a generation's last chunk; and between the chunks of a
+      // generation wider than the ring, whose cells rs slots apart share a
+      // ring slot and must write it in slot order
+      if (last_chunk || wide) lds_barrier();
     }
     return;
   }
@@ -644,7 +653,7 @@ __device__ __forceinline__ void sweep_velocity(
   int synced = 0;  // global stores of slots < synced are complete and visible
   for (int g = 0; g < G; ++g) {
     const int s0 = go[g], s1 = go[g + 1];
-    const int ring_lo = s1 - RS;
+    const int ring_lo = s1 - rs;
     // values older than the ring come from HBM: fence only when this
     // generation reads one that may not be visible yet
     if (gm[g] < ring_lo && ring_lo > synced) {
@@ -653,20 +662,27 @@ __device__ __forceinline__ void sweep_velocity(
     }
     if (P.s >= 0) {
       if constexpr (F32)
-        finish32c<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo);
+        finish32c<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo);
       else
-        finish64<DIM, ORDER>(a, P, base, j, v, v2, ring, ring_lo);
+        finish64<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo);
     }
-    // cells of a generation wider than the workgroup: solved without look-ahead
-    for (int s = s0 + T + tid; s < s1; s += T) {
+    // cells of a generation wider than the workgroup: further passes without
+    // look-ahead, separated by a barrier when the generation is wider than
+    // the ring (cells rs slots apart share a ring slot and must write it in
+    // slot order)
+    const bool wide = s1 - s0 > rs;
+    for (int pass = s0 + T; pass < s1; pass += T) {
+      if (wide) lds_barrier();
+      const int s = pass + tid;
+      if (s >= s1) continue;
       Prep<DIM, ORDER> Q;
       Q.s = s;
       load_rec<DIM>(a, base, s, Q.K, Q.code, Q.pack);
       prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, Q);
       if constexpr (F32)
-        finish32c<DIM, ORDER>(a, Q, base, j, v, v2, ring, ring_lo);
+        finish32c<DIM, ORDER>(a, Q, base, j, v, v2, ring, rmask, ring_lo);
       else
-        finish64<DIM, ORDER>(a, Q, base, j, v, v2, ring, ring_lo);
+        finish64<DIM, ORDER>(a, Q, base, j, v, v2, ring, rmask, ring_lo);
     }
     // look-ahead: prepare this thread's cell of generation g+1, fetch the
     // record of generation g+2
@@ -740,13 +756,20 @@ int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map
   return BGK_OK;
 }
 
+// ring slots: the DAG's choice, else the most the element type's LDS ring holds
+int ring_slots(const tgs_dag* d) {
+  const int max = d->dim == 3 ? SweepCfg<3, 1>::RS : d->order == 1 ? SweepCfg<2, 1>::RS
+                                                                   : SweepCfg<2, 2>::RS;
+  return d->ring_slots > 0 ? std::min(d->ring_slots, max) : max;
+}
+
 SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32) {
   return SweepArgs{d->d_geo,   d->d_facet, d->d_v,      d->d_rec,   d->d_recx,  d->d_perm,
                    d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, io->nu,
                    io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
                    io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
-                   d->n_1d,    d->order};
+                   d->n_1d,    ring_slots(d), d->order};
 }
 
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,

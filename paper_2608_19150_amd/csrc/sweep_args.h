@@ -30,6 +30,7 @@ struct SweepArgs {
   int n_cells;
   int n_v;
   int n1;                    // points per axis of a tensor velocity grid (mtab)
+  int ring_slots;            // LDS ring of recent outputs, slots (power of two)
   int order;
 };
 

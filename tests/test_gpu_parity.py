@@ -186,6 +186,55 @@ def test_step_wide_generations_bitwise_across_workgroup_sizes(dim, order, n_side
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("dim,order,n_side,n1", WIDE)
+def test_sweep_small_ring_matches_oracle(dim, order, n_side, n1):
+    """A 64-slot LDS ring with 64-thread workgroups on generations of 60-110
+    cells: upwind values older than the ring come from HBM after a workgroup
+    fence, and the chunks of a generation wider than the ring are separated
+    by barriers.  The FP64 sweep matches the oracle and equals the full-ring
+    sweep bit for bit; so does the FP32 correction sweep, whose corrections
+    are then read back from HBM."""
+    say("sweep small ring", dim, order, n_side, n1)
+    pr = _problem(dim, order, n_side, n1, state="riemann")
+    geo, q, nu, prim = _random_sweep_inputs(pr, 31)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    assert max(int(np.bincount(g).max()) for g in gens) > 64
+    small = B.Dag.from_problem(pr, sweep_threads=64, ring_slots=64)
+    full = B.Dag.from_problem(pr, sweep_threads=64)
+    f_small = _gpu_sweep(small, pr, q, nu, prim, 11.0, 2.0)
+    assert np.array_equal(f_small, _gpu_sweep(full, pr, q, nu, prim, 11.0, 2.0))
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 11.0, 2.0, gens)
+    assert rel(f_small, f_ref) <= TOL64
+    fp = f_ref * (1.0 + 1e-3 * np.random.default_rng(32).standard_normal(f_ref.shape))
+    g_small = _gpu_sweep(small, pr, q, nu, prim, 11.0, 2.0, f_prev=fp, precision=1)
+    g_full = _gpu_sweep(full, pr, q, nu, prim, 11.0, 2.0, f_prev=fp, precision=1)
+    assert np.array_equal(g_small, g_full)
+
+
+def test_step_small_ring_bitwise_equal_to_full_ring():
+    """Whole DIRK2 steps through the solver (tables, pipelined walk) with a
+    64-slot ring on generations wider than it equal full-ring steps bit for
+    bit."""
+    pr = _problem(2, 2, 80, 4, state="fourier")
+    outs = []
+    for rs in (64, 0):
+        d, f0, bc, dt = B.problem_setup(pr, sweep_threads=64, ring_slots=rs)
+        s = B.Solver(d, dt=dt, bc_coef=bc, tableau="DIRK2", fixed_iters=2, mode="MATCHED",
+                     nu_model="kn", kn=0.1)
+        s.step(f0)
+        outs.append(d.unpack(f0).cpu().numpy())
+        del s, d, f0
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_dag_rejects_bad_ring_slots():
+    pr = _problem(2, 1, 3, 4)
+    for bad in (8, 24, 2048):
+        with pytest.raises(B.BGKError) as e:
+            B.Dag.from_problem(pr, ring_slots=bad)
+        assert e.value.code == B.BGK_E_INVALID
+
+
 def test_sweep_dense_boundary_matches_oracle():
     pr = _problem(2, 2, 3, 4)
     d = B.Dag.from_problem(pr)
