@@ -16,14 +16,17 @@
 // sigma > 0 plus the upwind facet terms).
 //
 // Latency.  Everything a cell needs except its upwind neighbours' new values
-// (record, geometry, Maxwellian, sigma, source) is loaded and evaluated one
-// generation ahead, before the barrier.  New values are also kept in an LDS
-// ring of the last ring_slots slots (at most RS, a power of two; fewer only
-// to test the HBM path); upwind reads are served from it when their slot
-// is recent enough, so the per-generation barrier only orders LDS
-// (s_waitcnt lgkmcnt + s_barrier) and global loads stay in flight across it.
-// Older upwind values are read from HBM after a full workgroup fence, which
-// runs only when the ring no longer covers the generation's reach.
+// (record, geometry, Maxwellian, sigma, source) is loaded ahead: in the
+// pipelined walk (FP64) a whole solve ahead, over workgroup-sized chunks of
+// the generations; in the plain walk (FP32 correction form, P1 triangles)
+// the first chunk of the next generation before the barrier.  New values
+// are also kept in an LDS ring of the last rs slots (a power of two, at
+// least the workgroup size, at most RS); upwind reads are served from it
+// when their slot is recent enough, so the per-generation barrier only
+// orders LDS (s_waitcnt lgkmcnt + s_barrier) and global loads stay in
+// flight across it.  Older upwind values are read from HBM after a full
+// workgroup fence, which runs only when the ring no longer covers the
+// generation's reach.
 #include <type_traits>
 
 #include "device_common.h"
