@@ -184,8 +184,10 @@ typedef struct {
  * boundary value (exactly one of bc_coef / bc_dense non-NULL).  Exactly one
  * sweep; no convergence logic.  Asynchronous on `stream`; allocates stream-
  * ordered scratch (nu and the coefficients in the library's internal cell
- * order, n_nodes*(dim+3) doubles, plus the FP32 corrections in that form)
- * and frees it on the same stream.
+ * order, n_nodes*(dim+3) doubles; on a tensor velocity grid the factorised
+ * Maxwellian tables, (dim+1)*n_1d*n_nodes doubles before padding; the FP32
+ * corrections in that form) and frees it on the same stream.  The sweep
+ * runs the same kernels as bgk_step's.
  * Errors: BGK_E_INVALID (missing or aliased buffers), BGK_E_NOMEM, BGK_E_HIP. */
 int tgs_sweep(const tgs_dag* dag, const tgs_sweep_io* io, bgk_stream_t stream);
 

@@ -15,16 +15,11 @@
 
 #include "device_common.h"
 #include "solver.h"
+#include "sweep_args.h"
 
 namespace bgk {
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
                  hipStream_t stream, int threads);
-int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
-                       hipStream_t stream);
-// doubles of the factorised tables (per-cell padded layout)
-inline size_t maxw_table_size(const tgs_dag* d) {
-  return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells)).size(d->dim);
-}
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                    double* partial, double* ratio_out, hipStream_t stream, bool user_order);
 int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,

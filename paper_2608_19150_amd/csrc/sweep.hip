@@ -884,13 +884,16 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
     return fail(BGK_E_INVALID, "f_prev is required with lagged facets or the FP32 form");
   if (io->f_prev && io->f_prev == io->f_out) return fail(BGK_E_INVALID, "f_out aliases f_prev");
   // the kernels read nodal arrays in the internal cell order: nu and the
-  // coefficients are permuted into scratch first
+  // coefficients are permuted into scratch first; on a tensor velocity grid
+  // the factorised Maxwellian tables are built from them, as in bgk_step, so
+  // this is the solver's sweep kernel
   hipStream_t st = (hipStream_t)stream;
   const int np = d->n_p, nm = d->dim + 2;
+  const size_t ntab = d->n_1d > 0 ? maxw_table_size(d) : 0;
   float* d32 = nullptr;
-  double* nodal = nullptr;  // [n_nodes] nu, then [n_nodes][dim+2] coefficients
-  if (hipMallocAsync((void**)&nodal, (size_t)d->n_nodes * (1 + nm) * sizeof(double), st) !=
-      hipSuccess)
+  double* nodal = nullptr;  // [n_nodes] nu, [n_nodes][dim+2] coefficients, tables
+  if (hipMallocAsync((void**)&nodal, ((size_t)d->n_nodes * (1 + nm) + ntab) * sizeof(double),
+                     st) != hipSuccess)
     return fail(BGK_E_NOMEM, "scratch allocation failed");
   if (io->precision == TGS_FP32_CORRECTION &&
       hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), st) != hipSuccess) {
@@ -900,9 +903,11 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
   tgs_sweep_io io_i = *io;
   io_i.nu = nodal;
   io_i.mcoef = nodal + d->n_nodes;
+  double* tab = ntab ? nodal + (size_t)d->n_nodes * (1 + nm) : nullptr;
   int rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
   if (!rc) rc = launch_nodal_rows(d, io->mcoef, nodal + d->n_nodes, np * nm, 1, st);
-  if (!rc) rc = launch_sweep(d, &io_i, nullptr, d32, st, 0);
+  if (!rc && tab) rc = launch_maxw_tables(d, io_i.mcoef, io_i.nu, tab, st);
+  if (!rc) rc = launch_sweep(d, &io_i, tab, d32, st, 0);
   if (d32) (void)hipFreeAsync(d32, st);
   (void)hipFreeAsync(nodal, st);
   return rc;

@@ -40,6 +40,13 @@ int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map
                        const int32_t* done, int threads, hipStream_t stream);
 SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32);
+// factorised Maxwellian tables of a tensor velocity grid from nodal
+// coefficients and nu (kinetic.hip), and their size in doubles
+int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
+                       hipStream_t stream);
+inline size_t maxw_table_size(const tgs_dag* d) {
+  return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells)).size(d->dim);
+}
 // copies per-cell rows of `row` doubles between the user and the internal
 // cell order (kinetic.hip)
 int launch_nodal_rows(const tgs_dag* d, const double* src, double* dst, int row, int to_internal,

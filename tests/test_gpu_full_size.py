@@ -1,0 +1,112 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(library-chosen workgroup size and ring, factorised Maxwellian tables, the
+pipelined walk): every velocity and node is computed on the GPU, and the
+oracle recomputes a sample one by one - whole velocities of the sweep over
+the full mesh, single nodes of the moment reduction and the Maxwellian.
+
+Workloads: ~200k graded P2 triangles x 32^2 velocities (the 2D workload)
+and ~55k P1 tetrahedra x 16^3 velocities (the 3D workload)."""
+import gc
+
+import numpy as np
+import pytest
+
+import problems as P
+from oracle import dag as odag
+from oracle import geometry, kinetic, solver, transport
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2608_19150_amd as B
+
+TOL64 = 1e-12
+
+
+def rel(x, ref):
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def _release():
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _nodal_inputs(n_nodes, dim, seed):
+    """Seeded per-node nu and primitive (n, u, theta)."""
+    rng = np.random.default_rng(seed)
+    nu = rng.uniform(0.1, 2.0, n_nodes)
+    prim = np.concatenate([rng.uniform(0.2, 1.5, (n_nodes, 1)),
+                           rng.uniform(-0.5, 0.5, (n_nodes, dim)),
+                           rng.uniform(0.6, 1.4, (n_nodes, 1))], axis=1)
+    return nu, prim
+
+
+@pytest.mark.parametrize("workload,sample", [("2d", (0, 311, 528, 777, 1023)),
+                                             ("3d", (0, 1365, 2050, 4095))])
+def test_full_size_sweep_matches_oracle_on_sampled_velocities(workload, sample):
+    pr = P.config_c2(316) if workload == "2d" else P.config_c3(kn=1e-2)
+    d = B.Dag.from_problem(pr)
+    assert d.n_cells > 5e4 and d.n_v >= 1024
+    nu, prim = _nodal_inputs(d.n_nodes, d.dim, 9100)
+    gen = torch.Generator(device="cuda").manual_seed(9101)
+    q = torch.rand(d.f_shape, dtype=torch.float64, device="cuda", generator=gen)
+    js = np.array(sample)
+    jt = torch.as_tensor(js, device="cuda")
+    q_s = q[..., jt].cpu().numpy()
+    qg = d.pack(q)
+    del q
+    mcoef = B.maxwellian_coef_from_primitive(B._dev(prim), d.dim)
+    bc = B.state_coefficients(d, pr.state, "boundary")
+    fo = torch.empty_like(qg)
+    B.tgs_sweep(d, q=qg, nu=B._dev(nu), mcoef=mcoef, f_out=fo, sigma_shift=41.0, q_scale=3.0,
+                bc_coef=bc)
+    del qg
+    f_s = d.unpack(fo)[..., jt].cpu().numpy()
+    del fo, mcoef, bc, d
+    _release()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    V = pr.vgrid.v[js]
+    gens, lags = odag.build_all(geo, V)
+    assert not lags.any()
+    nn = nu.reshape(geo.n_cells, geo.n_p)
+    pp = prim.reshape(geo.n_cells, geo.n_p, -1)
+    coef = kinetic.direct_coefficients(pp[..., 0], pp[..., 1:-1], pp[..., -1])
+    Mv = kinetic.coef_values(coef, V)
+    g = solver.boundary_values(geo, V, pr.state)
+    f_ref = transport.sweep(geo, V, nn + 41.0, nn, Mv, 3.0 * q_s, g, gens)
+    assert rel(f_s, f_ref) <= TOL64
+
+
+def test_full_size_moments_and_maxwellian_match_oracle_on_sampled_nodes():
+    pr = P.config_c2(316)
+    d = B.Dag.from_problem(pr)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    rng = np.random.default_rng(9200)
+    cells = np.sort(rng.choice(d.n_cells, 400, replace=False))
+    gen = torch.Generator(device="cuda").manual_seed(9201)
+    f = torch.rand(d.f_shape, dtype=torch.float64, device="cuda", generator=gen)
+    f_s = f[torch.as_tensor(cells, device="cuda")].cpu().numpy()
+    fg = d.pack(f)
+    del f
+    U = B.moments(d, fg).cpu().numpy().reshape(d.n_cells, d.n_p, -1)
+    del fg
+    assert rel(U[cells], kinetic.moments(f_s, V, w)) <= TOL64
+    # Maxwellian of seeded realizable moments at every node (n, n u,
+    # n (d theta + |u|^2) / 2 from a seeded (n, u, theta))
+    _, prim = _nodal_inputs(d.n_nodes, d.dim, 9202)
+    n, u, th = prim[:, 0], prim[:, 1:-1], prim[:, -1]
+    Um = np.concatenate([n[:, None], n[:, None] * u,
+                         (0.5 * n * (d.dim * th + np.sum(u * u, axis=1)))[:, None]], axis=1)
+    coef, nu, _, status = B.maxwellian(d, B._dev(Um), mode="MATCHED", nu_model="kn", kn=1e-2)
+    assert int(status[1]) == 0
+    nodes = np.sort(rng.choice(d.n_nodes, 2000, replace=False))
+    ref, nfb = kinetic.matched_coefficients(Um[nodes], V, w)
+    assert nfb == 0 and int(status[0]) == 0
+    assert rel(coef.cpu().numpy()[nodes], ref) <= TOL64
+    nu_ref = kinetic.collision_frequency(Um[nodes], d.dim, "kn", kn=1e-2)
+    assert rel(nu.cpu().numpy()[nodes], nu_ref) <= 1e-14
+    del coef, nu, d
+    _release()

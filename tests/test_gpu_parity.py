@@ -118,6 +118,19 @@ def test_sweep_fp64_matches_oracle(dim, order, n_side, n1):
     assert rel(f_gpu, f_ref) <= TOL64
 
 
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+def test_sweep_fp64_coefficient_path_matches_oracle(dim, order, n_side, n1):
+    """A velocity set given without its tensor structure: the sweep evaluates
+    the Maxwellian from the node coefficients (no factorised tables)."""
+    pr = _problem(dim, order, n_side, n1, state="riemann")
+    d = B.Dag(pr.mesh.vert, pr.mesh.cells, pr.order, pr.vgrid.v, pr.vgrid.w)
+    geo, q, nu, prim = _random_sweep_inputs(pr, 13)
+    gens, _ = odag.build_all(geo, pr.vgrid.v)
+    f_gpu = _gpu_sweep(d, pr, q, nu, prim, 37.0, 2.5)
+    f_ref = _oracle_sweep(geo, pr, q, nu, prim, 37.0, 2.5, gens)
+    assert rel(f_gpu, f_ref) <= TOL64
+
+
 def test_sweep_fp64_c1_size_matches_oracle():
     pr = P.config_c1()
     d = B.Dag.from_problem(pr)
