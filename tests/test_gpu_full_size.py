@@ -110,3 +110,39 @@ def test_full_size_moments_and_maxwellian_match_oracle_on_sampled_nodes():
     assert rel(nu.cpu().numpy()[nodes], nu_ref) <= 1e-14
     del coef, nu, d
     _release()
+
+
+def test_batched_workload_instances_at_full_size_equal_single_instance_steps():
+    """Instances of the batched workload at their own sizes (the two largest
+    meshes, the largest velocity grid and the stiffest Kn among the 64),
+    stepped together in the benchmark's batch configuration (hipGraph chunks
+    of 4 iterations, 64-thread sweeps) and one by one through bgk_step: the
+    same f bit for bit, with the same iteration counts."""
+    probs = P.config_c4_instances()
+    size = [p.mesh.n_cells * (3 if p.order == 1 else 6) * p.vgrid.n_v for p in probs]
+    pick = set(np.argsort(size)[-2:].tolist())
+    pick.add(int(np.argmax([p.vgrid.n_v for p in probs])))
+    pick.add(int(np.argmin([p.kn for p in probs])))
+    picked = [probs[i] for i in sorted(pick)]
+
+    def setup(pr):
+        d, f0, bc, dt = B.problem_setup(pr)
+        s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, mode="MATCHED",
+                     nu_model=pr.nu_model, kn=pr.kn)
+        return s, f0
+
+    ref, ref_iters = [], []
+    for pr in picked:
+        s, f = setup(pr)
+        ref_iters.append(s.step(f)["iters"])
+        ref.append(f.cpu())
+        del s, f
+        _release()
+    pairs = [setup(pr) for pr in picked]
+    batch = B.Batch([p[0] for p in pairs], graph=True, chunk_iters=4, sweep_threads=64)
+    st = batch.step([p[1] for p in pairs])
+    for i, x in enumerate(st):
+        assert x["status"] == 0 and x["iters"] == ref_iters[i], (i, x, ref_iters[i])
+        assert torch.equal(pairs[i][1].cpu(), ref[i]), i
+    del batch, pairs
+    _release()
