@@ -214,32 +214,36 @@ struct GeoLayout {
 };
 
 // Factorised Maxwellian tables of a tensor velocity grid with n1 points per
-// axis, per cell and padded like the geometry: axis 0 as the cell's nodes'
-// (E_0, nu) pairs, [n1][n_cells][s0], then axes 1..d-1 as the nodes' E_alpha,
-// [d-1][n1][n_cells][s1] (s0, s1 = 2 n_p and n_p rounded up to a power of 2).
+// axis, per cell and padded like the geometry, in two parts: axis 0 as the
+// cell's nodes' (E_0, nu) pairs, [n1][n_cells][s0]; then the product of the
+// other axes' factors as one table, [n1^(d-1)][n_cells][s1], row r = the
+// velocity's row-major index over axes 1..d-1 (s0, s1 = 2 n_p and n_p
+// rounded up to a power of 2).  A velocity's Maxwellian is then one
+// multiply of two gathered factors in 2D and 3D alike.
 struct TabLayout {
   int64_t nc;
-  int n1, np, s0, s1;
+  int n1, np, s0, s1, nr;
   __host__ __device__ static constexpr int pow2(int x) {
     int p = 1;
     while (p < x) p *= 2;
     return p;
   }
-  __host__ __device__ TabLayout(int64_t n_cells, int n1_, int np_)
-      : nc(n_cells), n1(n1_), np(np_), s0(pow2(2 * np_)), s1(pow2(np_)) {}
-  // first double of cell c's record on row i of axis al
+  __host__ __device__ TabLayout(int64_t n_cells, int n1_, int np_, int dim)
+      : nc(n_cells), n1(n1_), np(np_), s0(pow2(2 * np_)), s1(pow2(np_)),
+        nr(dim == 3 ? n1_ * n1_ : n1_) {}
+  // first double of cell c's record on row i of part al (0: axis 0, 1: the rest)
   __host__ __device__ int64_t at(int al, int i, int64_t c) const {
     return al == 0 ? ((int64_t)i * nc + c) * s0
-                   : (int64_t)n1 * nc * s0 + (((int64_t)(al - 1) * n1 + i) * nc + c) * s1;
+                   : (int64_t)n1 * nc * s0 + ((int64_t)i * nc + c) * s1;
   }
-  __host__ __device__ int64_t size(int dim) const {
-    return (int64_t)n1 * nc * (s0 + (int64_t)(dim - 1) * s1);
+  __host__ __device__ int64_t size() const {
+    return (int64_t)n1 * nc * s0 + (int64_t)nr * nc * s1;
   }
 };
 
 // 16-byte chunks of the tables (the unit the table kernels write)
 __host__ __device__ inline int64_t table_chunks(int dim, int64_t n_cells, int n1, int np) {
-  return TabLayout(n_cells, n1, np).size(dim) / 2;
+  return TabLayout(n_cells, n1, np, dim).size() / 2;
 }
 
 // facet record: x = neighbour internal cell id, or -(1 + boundary facet id);

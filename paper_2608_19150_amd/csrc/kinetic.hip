@@ -506,14 +506,13 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 }
 
 // Factorised Maxwellian for tensor velocity grids: exp(a + b.v + c|v|^2) =
-// prod_alpha exp([alpha == 0] a + b_alpha x + c x^2) with x the node of axis
-// alpha, so tab[alpha][i][node] = exp([alpha == 0] a + b_alpha x_i + c x_i^2)
-// and M(v_j) is the product of d table entries.  The padded per-cell records
-// (TabLayout) are written as 16-byte chunks, pad included, consecutive
-// chunks by consecutive threads: chunk t of axis 0 is node b of a record as
-// (E_0, nu) (the sweep gathers both with one access), a chunk of another
-// axis holds two nodes' entries.  Chunks are numbered through axis 0's
-// records first, then through those of axes 1..d-1.
+// E_0 E_rest with E_0 = exp(a + b_0 x_0 + c x_0^2) on axis 0 and E_rest =
+// exp(sum over the other axes of b_al x_al + c x_al^2), both per node.  The
+// padded per-cell records (TabLayout) are written as 16-byte chunks, pad
+// included, consecutive chunks by consecutive threads: a chunk of axis 0 is
+// node b of a record as (E_0, nu) (the sweep gathers both with one access),
+// a chunk of the rest holds two nodes' entries.  Chunks are numbered
+// through axis 0's records first, then through the rest's.
 template <int DIM>
 __device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
                                             const double* __restrict__ nu,
@@ -521,37 +520,37 @@ __device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
                                             double* __restrict__ tab, int64_t n_cells, int n1,
                                             int np, int64_t t) {
   constexpr int NM = DIM + 2;
-  const TabLayout L(n_cells, n1, np);
+  const TabLayout L(n_cells, n1, np, DIM);
   const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
-  int al, h;
-  int64_t r;
-  if (t < a0) {
-    al = 0;
-    r = t / (L.s0 / 2);
-    h = (int)(t - r * (L.s0 / 2));
-  } else {
-    const int64_t u = t - a0;
-    const int64_t q = u / (L.s1 / 2);
-    h = (int)(u - q * (L.s1 / 2));
-    al = 1 + (int)(q / ((int64_t)n1 * n_cells));
-    r = q - (int64_t)(al - 1) * n1 * n_cells;
-  }
-  const int64_t c = r % n_cells;
-  const int i = (int)(r / n_cells);
-  const double x = x1[i];
+  const bool first = t < a0;
+  const int64_t u = first ? t : t - a0;
+  const int half = (first ? L.s0 : L.s1) / 2;
+  const int64_t q = u / half;
+  const int h = (int)(u - q * half);
+  const int64_t c = q % n_cells;
+  const int row = (int)(q / n_cells);
   const auto entry = [&](int b) {
     const double* cf = coef + (c * np + b) * NM;
-    double e = __fma_rn(cf[1 + DIM], x * x, cf[1 + al] * x);
-    if (al == 0) e += cf[0];
+    double e;
+    if (first) {
+      const double x = x1[row];
+      e = __fma_rn(cf[1 + DIM], x * x, cf[1] * x) + cf[0];
+    } else if (DIM == 2) {
+      const double x = x1[row];
+      e = __fma_rn(cf[1 + DIM], x * x, cf[2] * x);
+    } else {
+      const double y = x1[row / n1], z = x1[row % n1];
+      e = __fma_rn(cf[1 + DIM], y * y, cf[2] * y) + __fma_rn(cf[1 + DIM], z * z, cf[3] * z);
+    }
     return bgk_exp(e);
   };
   double2 v;
-  if (al == 0) {
+  if (first) {
     v = h < np ? make_double2(entry(h), nu[c * np + h]) : make_double2(0.0, 0.0);
   } else {
     v = make_double2(2 * h < np ? entry(2 * h) : 0.0, 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
   }
-  reinterpret_cast<double2*>(tab + L.at(al, i, c))[h] = v;
+  reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] = v;
 }
 
 template <int DIM>

@@ -166,7 +166,7 @@ template <int DIM, int ORDER, bool TAB>
 struct Raw {
   static constexpr int NP = Elem<DIM, ORDER>::NP, NG = 1 + (DIM + 1) * DIM, NC = DIM + 2;
   static constexpr int NM = TAB ? 2 * NP : NP;                // (E_0, nu) pairs | nu
-  static constexpr int NX = TAB ? (DIM - 1) * NP : NP * NC;   // E_1 .. E_{d-1} | coefficients
+  static constexpr int NX = TAB ? NP : NP * NC;   // E_rest | coefficients
   double g[NG];
   double q[NP];
   double m[NM];
@@ -177,7 +177,7 @@ struct Raw {
 // internal cell order (no node map)
 template <int DIM, int ORDER, bool TAB>
 __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s, int K,
-                                         const double* const (&mrow)[DIM],
+                                         const double* const (&mrow)[2],
                                          Raw<DIM, ORDER, TAB>& R) {
   using RW = Raw<DIM, ORDER, TAB>;
   constexpr int NP = Elem<DIM, ORDER>::NP;
@@ -194,9 +194,7 @@ __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s,
 #pragma unroll
     for (int b = 0; b < RW::NM; ++b) R.m[b] = e0[b];
 #pragma unroll
-    for (int al = 1; al < DIM; ++al)
-#pragma unroll
-      for (int b = 0; b < NP; ++b) R.x[(al - 1) * NP + b] = mrow[al][u * S1 + b];
+    for (int b = 0; b < NP; ++b) R.x[b] = mrow[1][u * S1 + b];
   } else {
 #pragma unroll
     for (int b = 0; b < NP; ++b) R.m[b] = a.nu[u * NP + b];
@@ -223,9 +221,7 @@ __device__ __forceinline__ void compute_prep(const SweepArgs& a, const double* v
   for (int b = 0; b < NP; ++b) {
     double M, nub;
     if constexpr (TAB) {
-      M = R.m[2 * b];
-#pragma unroll
-      for (int al = 1; al < DIM; ++al) M *= R.x[(al - 1) * NP + b];
+      M = R.m[2 * b] * R.x[b];
       nub = R.m[2 * b + 1];
     } else {
       M = maxw_eval<DIM>(R.x + b * RW::NC, v, v2);
@@ -238,7 +234,7 @@ __device__ __forceinline__ void compute_prep(const SweepArgs& a, const double* v
 
 template <int DIM, int ORDER, bool TAB>
 __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, double v2,
-                                        size_t base, const double* const (&mrow)[DIM],
+                                        size_t base, const double* const (&mrow)[2],
                                         Prep<DIM, ORDER>& P) {
   constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1, NC = DIM + 2;
   const double* __restrict__ gk = a.geo + (size_t)P.K * GeoLayout<DIM>::STRIDE;
@@ -252,19 +248,15 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
   const double* __restrict__ q = a.q + (base + P.s) * NP;
   double M[NP], nu[NP];
   if constexpr (TAB) {
-    // tensor grid: M = prod_alpha E_alpha[i_alpha][node]; the first factor
-    // is stored interleaved with nu, so one gather brings both
+    // tensor grid: M = E_0[i_0][node] * E_rest[i_1..i_{d-1}][node]; the
+    // first factor is stored interleaved with nu, so one gather brings both
     constexpr int S0 = TabLayout::pow2(2 * NP), S1 = TabLayout::pow2(NP);
     const double* __restrict__ e0 = mrow[0] + u * S0;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      M[b] = e0[2 * b];
+      M[b] = e0[2 * b] * mrow[1][u * S1 + b];
       nu[b] = e0[2 * b + 1];
     }
-#pragma unroll
-    for (int al = 1; al < DIM; ++al)
-#pragma unroll
-      for (int b = 0; b < NP; ++b) M[b] *= mrow[al][u * S1 + b];
   } else {
 #pragma unroll
     for (int b = 0; b < NP; ++b) nu[b] = a.nu[u * NP + b];
@@ -533,17 +525,13 @@ __device__ __forceinline__ void sweep_velocity(
   cint32* gm = (cint32*)(a.gmin + a.gbase[j]);
   const int G = a.G[j];
   // rows of the factorised Maxwellian tables for this velocity (tensor
-  // grids): cell c's record of axis al is mrow[al] + c * (s0 or s1)
-  const double* mrow[DIM];
-  {
-    int rem = j;
-    const TabLayout L(a.n_cells, a.n1, NP);
-#pragma unroll
-    for (int al = DIM - 1; al >= 0; --al) {
-      const int i = a.mtab ? rem % a.n1 : 0;
-      rem = a.mtab ? rem / a.n1 : rem;
-      mrow[al] = a.mtab ? a.mtab + L.at(al, i, 0) : nullptr;
-    }
+  // grids): axis 0's row and the rest's row; cell c's records are at
+  // mrow[0] + c * s0 and mrow[1] + c * s1
+  const double* mrow[2] = {nullptr, nullptr};
+  if (a.mtab) {
+    const TabLayout L(a.n_cells, a.n1, NP, DIM);
+    mrow[0] = a.mtab + L.at(0, j / L.nr, 0);
+    mrow[1] = a.mtab + L.at(1, j % L.nr, 0);
   }
 
   if constexpr (PIPE) {

@@ -45,7 +45,7 @@ SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream);
 inline size_t maxw_table_size(const tgs_dag* d) {
-  return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells)).size(d->dim);
+  return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells), d->dim).size();
 }
 // copies per-cell rows of `row` doubles between the user and the internal
 // cell order (kinetic.hip)
