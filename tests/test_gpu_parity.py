@@ -359,6 +359,29 @@ def _oracle_steps(pr, nsteps, dt, *, mode="MATCHED", fixed_iters=None, tau=1e-10
     return geo, f, stats
 
 
+@pytest.mark.parametrize("tableau", ["BE", "DIRK2", "DIRK3"])
+def test_steps_chained_through_their_moments_equal_plain_steps(tableau):
+    """A step's converged moments (U_out) handed to the next step as its
+    initial moments (U_guess) are the moments of f^k that step would compute:
+    the chained steps equal plain steps bit for bit."""
+    pr = _problem(2, 2, 4, 6, state="fourier")
+    outs = []
+    for chained in (False, True):
+        d, f, bc, dt = B.problem_setup(pr)
+        s = B.Solver(d, dt=dt, bc_coef=bc, tableau=tableau, tau=1e-10, mode="MATCHED",
+                     nu_model="kn", kn=0.05)
+        U = torch.empty((d.n_nodes, d.dim + 2), dtype=torch.float64, device="cuda")
+        iters = []
+        for k in range(3):
+            if chained:
+                iters.append(s.step(f, U_guess=U if k else None, U_out=U)["iters"])
+            else:
+                iters.append(s.step(f)["iters"])
+        outs.append((d.unpack(f).cpu().numpy(), iters))
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
 def test_bgk_step_c1_fixed_iterations_matches_oracle():
     say("bgk_step c1 fixed")
     pr = P.config_c1()
