@@ -281,7 +281,10 @@ int bgk_solver_destroy(bgk_solver* solver);
  * coefficients for the rest of the stage (maxw_fallbacks counts such nodes
  * in every iteration).
  * Synchronises `stream` once per Picard iteration to test convergence.
- * Errors: BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_HIP. */
+ * Errors: BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_HIP.  After an error
+ * f still holds f^k unless the failure came where f is written: in the last
+ * stage of a stiffly accurate tableau (backward Euler's only stage), which
+ * iterates in f, or in the final combination of the other tableaux. */
 int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out,
              bgk_step_stats* stats, bgk_stream_t stream);
 
