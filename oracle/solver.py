@@ -10,6 +10,8 @@
   iterate l, the sweep gives f^{l+1}, the moments of f^{l+1} give the next
   Maxwellian.  Stage 1 starts from f^k and stage s > 1 from the converged
   f^(s-1) (design note A3; the printed "s = 0" case is read as s = 1).
+  On the Q2 velocity space of Sec. 3.2 the Maxwellian can instead be the
+  conservative projection of App. B (mode PROJECTED, velocity.py).
 * Stopping rule (eq. convergence-criteria, design note A13):
   max_m |U^{l+1,m} - U^{l,m}| / max(|U^{l,m}|, |U^{l,0}| s_m)
       < tau / max(1, max_i nu_i dt),
@@ -31,7 +33,7 @@ import math
 
 import numpy as np
 
-from . import kinetic, transport
+from . import kinetic, transport, velocity
 from .geometry import Geometry
 
 
@@ -110,8 +112,12 @@ def maxwellian_coefficients(U, V, w, mode: str, L: float, sticky=None):
 
 def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged, *, dt,
                  mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10,
-                 lmax=2000, fixed_iters=None, U_init=None, L=0.0):
-    """Picard iteration for one DIRK stage.  Returns (f, U, iterations, history)."""
+                 lmax=2000, fixed_iters=None, U_init=None, L=0.0, vcells=0):
+    """Picard iteration for one DIRK stage.  Returns (f, U, iterations, history).
+
+    mode PROJECTED (the Q2 velocity space of Sec. 3.2 with ``vcells`` cells
+    per axis on [-L, L]): the Maxwellian is the conservative projection of
+    App. B of M_{n,u,theta} with (n, u, theta) from U."""
     dim = geo.dim
     f = f_init
     U = kinetic.moments(f, V, w) if U_init is None else U_init
@@ -128,7 +134,9 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
         if collisional and not ok:
             raise NonPhysicalError("non-physical moments (n <= 0 or theta <= 0)")
         nu = kinetic.collision_frequency(U, dim, nu_model, nu_const, kn)
-        if np.any(nu != 0.0):
+        if np.any(nu != 0.0) and mode == "PROJECTED":
+            Mv = velocity.projected_maxwellian(n_, kinetic.primitive(U, dim)[1], th_, vcells, L)
+        elif np.any(nu != 0.0):
             coef, fb = maxwellian_coefficients(U, V, w, mode, L, sticky)
             nfb += fb
             Mv = kinetic.coef_values(coef, V)
@@ -150,7 +158,7 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
 
 def bgk_step(geo: Geometry, V, w, f, gbc, dt, gens, lagged=None, *, scheme="BE",
              mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10, lmax=2000,
-             fixed_iters=None, U_guess=None, L=0.0):
+             fixed_iters=None, U_guess=None, L=0.0, vcells=0):
     """One DIRK time step of the discretised BGK equation.
 
     ``gbc`` is either the boundary data [n_bf][n_fp][N_v] or a callable
@@ -172,7 +180,7 @@ def bgk_step(geo: Geometry, V, w, f, gbc, dt, gens, lagged=None, *, scheme="BE",
         f_s, U_s, it, hist, nfb = picard_stage(
             geo, V, w, q, g, 1.0 / (dt * A[s, s]), stage_f, gens, lagged, dt=dt, mode=mode,
             nu_model=nu_model, nu_const=nu_const, kn=kn, tau=tau, lmax=lmax,
-            fixed_iters=fixed_iters, U_init=U_guess if s == 0 else None, L=L)
+            fixed_iters=fixed_iters, U_init=U_guess if s == 0 else None, L=L, vcells=vcells)
         Fs.append((f_s - acc) / (dt * A[s, s]))
         stage_f = f_s
         iters.append(it)

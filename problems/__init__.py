@@ -57,6 +57,7 @@ class VelocityGrid:
     nodes_1d: np.ndarray | None = None
     weights_1d: np.ndarray | None = None
     L: float = 0.0
+    dg_cells: int = 0      # > 0: Q2 DG velocity space, this many uniform cells per axis
 
     @property
     def n_v(self) -> int:
@@ -245,6 +246,25 @@ def tensor_velocity_grid(n_1d: int, L: float, dim: int) -> VelocityGrid:
     for gg in wg:
         w = w * gg.ravel()
     return VelocityGrid(np.ascontiguousarray(v), w, x, w1, L)
+
+
+def gl_velocity_grid(n_cells: int, L: float, dim: int) -> VelocityGrid:
+    """The velocity space of the paper's Sec. 3.2: n_cells uniform cells per
+    axis on [-L, L], in each the 3 Gauss-Legendre nodes and weights of Q2
+    (k_v = 2); tensor product with the first axis slowest."""
+    h = 2.0 * L / n_cells
+    ref = np.array([-math.sqrt(0.6), 0.0, math.sqrt(0.6)])
+    wref = np.array([5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0])
+    centres = -L + h * (np.arange(n_cells) + 0.5)
+    x = (centres[:, None] + 0.5 * h * ref[None, :]).ravel()
+    w1 = np.tile(0.5 * h * wref, n_cells)
+    grids = np.meshgrid(*([x] * dim), indexing="ij")
+    v = np.stack([gg.ravel() for gg in grids], axis=1)
+    wg = np.meshgrid(*([w1] * dim), indexing="ij")
+    w = np.ones(v.shape[0])
+    for gg in wg:
+        w = w * gg.ravel()
+    return VelocityGrid(np.ascontiguousarray(v), w, x, w1, L, n_cells)
 
 
 # ----------------------------------------------------------------------------
