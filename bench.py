@@ -91,7 +91,7 @@ def cpu_baseline(pr, n_vel, dt):
                       f"{sum(times):.1f} s of CPU work"}
 
 
-def run_gpu(pr, steps, warmup, precision, timing=True):
+def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED"):
     import torch
 
     import paper_2608_19150_amd as B
@@ -100,7 +100,7 @@ def run_gpu(pr, steps, warmup, precision, timing=True):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, precision=precision,
-                 mode="MATCHED", nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn,
+                 mode=mode, nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn,
                  timing=timing)
     # each step hands its converged moments (those of the f it leaves) to the
     # next as the first stage's initial moments, which are exactly the
@@ -254,6 +254,28 @@ def run_c5(steps, n_train, kn):
     return out
 
 
+def run_q2(n_side, steps, warmup):
+    """The 2D workload on the Q2 velocity space (30^2 Gauss-Legendre nodes):
+    steps with the conservative projected Maxwellian against steps with the
+    moment-matched nodal Gaussian, same chained-moment stepping."""
+    import problems as P
+    pr = P.config_c2_q2(n_side)
+    out = {"workload": pr.name}
+    res = {}
+    for mode in ("PROJECTED", "MATCHED"):
+        r = run_gpu(pr, steps, warmup, 0, mode=mode)
+        res[mode] = r
+        out[mode.lower()] = {
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "iters": r["iters"],
+            "kernel_ms": {"sweep": r["sweep_ms_avg"], "moments": r["moments_ms_avg"],
+                          "maxwellian": r["maxwellian_ms_avg"]},
+            "fallbacks": r["fallbacks"]}
+    out["velocities"] = res["PROJECTED"]["n_v"]
+    out["moment_diff_projected_vs_matched"] = moment_error(res["PROJECTED"]["U"],
+                                                           res["MATCHED"]["U"], 2)
+    return out
+
+
 def moment_error(U, Uref, dim):
     """Per component: |U_m - Uref_m| / max(|Uref_m|, s_m |Uref_0|), s = (0,1,0)."""
     blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
@@ -331,6 +353,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--no-q2", action="store_true",
+                    help="skip the Q2 velocity space (projected vs matched Maxwellian)")
     ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
@@ -372,7 +396,12 @@ def main():
         print(f"[bench] {name}: " + report(out), file=sys.stderr, flush=True)
         return out
 
-    c3 = c4 = c5 = None
+    c3 = c4 = c5 = q2 = None
+    if not args.no_q2:
+        q2 = section("q2", lambda: run_q2(args.n_side, args.steps, args.warmup),
+                     lambda c: f"PROJECTED {c['projected']['value']:.3e} unknowns/s "
+                               f"{c['projected']['ms_per_step']:.1f} ms/step vs MATCHED "
+                               f"{c['matched']['value']:.3e} {c['matched']['ms_per_step']:.1f}")
     if not args.no_c3:
         c3 = section("c3", lambda: run_c3(2, 1, 1e-2),
                      lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.1f} ms/step, "
@@ -418,6 +447,7 @@ def main():
         "c3_3d": c3,
         "c4_batched": c4,
         "c5_learned_guess": c5,
+        "q2_projected": q2,
     }
     print(json.dumps(line), flush=True)
 

@@ -95,7 +95,15 @@ typedef struct {
                              product of nodes_1d / weights_1d (checked) */
   const double* nodes_1d; /* host [n_1d] or NULL */
   const double* weights_1d;
-  double L;               /* half-width of the velocity box (LINEAR mode) */
+  double L;               /* half-width of the velocity box (LINEAR and
+                             PROJECTED modes) */
+  int dg_cells;           /* > 0: the Q2 discontinuous-Galerkin velocity space
+                             of Sec. 3.2: [-L, L] cut into dg_cells uniform
+                             cells per axis (at most 32), nodes_1d the 3
+                             Gauss-Legendre points of each cell in order and
+                             weights_1d their weights (n_1d = 3*dg_cells;
+                             checked).  Enables BGK_MAXW_PROJECTED.  0 = a
+                             point set. */
 } tgs_vgrid_desc;
 
 typedef struct {
@@ -203,7 +211,12 @@ int tgs_sweep(const tgs_dag* dag, const tgs_sweep_io* io, bgk_stream_t stream);
 int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
             double* rel3, bgk_stream_t stream);
 
-enum { BGK_MAXW_DIRECT = 0, BGK_MAXW_MATCHED = 1, BGK_MAXW_LINEAR = 2 };
+/* DIRECT: the Maxwellian of (n, u, theta) at the nodes; MATCHED: the nodal
+ * Gaussian whose discrete moments equal U (Newton from DIRECT); LINEAR:
+ * n/|V|; PROJECTED (Q2 velocity space only, App. B): the projection of
+ * M_{n,u,theta} onto the velocity space with the first and last cells
+ * extended to infinity, whose discrete moments equal U exactly. */
+enum { BGK_MAXW_DIRECT = 0, BGK_MAXW_MATCHED = 1, BGK_MAXW_LINEAR = 2, BGK_MAXW_PROJECTED = 3 };
 enum { BGK_NU_CONST = 0, BGK_NU_KN = 1 };
 
 typedef struct {
@@ -217,7 +230,11 @@ typedef struct {
  * DIRECT = the Maxwellian of (n, u, theta); MATCHED = the nodal Gaussian
  * whose discrete moments equal U (Newton from DIRECT, residual <= 1e-14|U|,
  * at most 30 steps, else that node falls back to DIRECT and is counted);
- * LINEAR = n/|V| (the simplified linear Maxwellian).  Optional outputs:
+ * LINEAR = n/|V| (the simplified linear Maxwellian); PROJECTED (needs
+ * dg_cells > 0) = the conservative projection of App. B, for which mcoef
+ * holds the primitive (n, u_1..u_d, theta) instead of log-coefficients and
+ * the values are n (2 pi theta)^(-d/2) times the product over the axes of
+ * the projected 1-D Gaussians (erf/erfc closed forms).  Optional outputs:
  * M_dense (device canonical [n_nodes][n_v]) and status (device int32[2]:
  * fallback count, non-physical count; accumulated, caller zeroes). */
 int maxwellian(const tgs_dag* dag, int mode, const double* U, const tgs_nu_model* nu_model,

@@ -27,7 +27,7 @@ _lib = C.CDLL(LIB_PATH)
 BGK_OK, BGK_E_INVALID, BGK_E_HIP, BGK_E_NOMEM = 0, -1, -2, -3
 BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_UNSUPPORTED = -4, -5, -6
 TGS_FP64, TGS_FP32_CORRECTION = 0, 1
-MAXW = {"DIRECT": 0, "MATCHED": 1, "LINEAR": 2}
+MAXW = {"DIRECT": 0, "MATCHED": 1, "LINEAR": 2, "PROJECTED": 3}
 NU = {"const": 0, "kn": 1}
 TABLEAU = {"BE": 0, "DIRK2": 1, "DIRK3": 2, "BDIRK2": 3}
 
@@ -64,7 +64,8 @@ class MeshDesc(C.Structure):
 
 class VGridDesc(C.Structure):
     _fields_ = [("n_v", C.c_int), ("v", C.c_void_p), ("w", C.c_void_p), ("n_1d", C.c_int),
-                ("nodes_1d", C.c_void_p), ("weights_1d", C.c_void_p), ("L", C.c_double)]
+                ("nodes_1d", C.c_void_p), ("weights_1d", C.c_void_p), ("L", C.c_double),
+                ("dg_cells", C.c_int)]
 
 
 class DagOpts(C.Structure):
@@ -143,7 +144,7 @@ class Dag:
     """Handle returned by build_mesh_dag (mesh geometry + per-velocity DAGs)."""
 
     def __init__(self, vert, cells, order, v, w, *, n_1d=0, nodes_1d=None, weights_1d=None,
-                 L=0.0, lagged=None, sweep_threads=0, ring_slots=0, stream=None):
+                 L=0.0, dg_cells=0, lagged=None, sweep_threads=0, ring_slots=0, stream=None):
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         v = np.ascontiguousarray(v, dtype=np.float64)
@@ -156,7 +157,7 @@ class Dag:
         self._keep += [n1, w1]
         vd = VGridDesc(v.shape[0], v.ctypes.data, w.ctypes.data, int(n_1d),
                        n1.ctypes.data if n_1d else None, w1.ctypes.data if n_1d else None,
-                       float(L))
+                       float(L), int(dg_cells))
         lag = None
         if lagged is not None:
             lag = np.ascontiguousarray(lagged, dtype=np.uint8)
@@ -175,6 +176,7 @@ class Dag:
         self.v = torch.as_tensor(v)
         self.w = torch.as_tensor(w)
         self.L = float(L)
+        self.dg_cells = int(dg_cells)
 
     @classmethod
     def from_problem(cls, pr, **kw):
@@ -182,7 +184,7 @@ class Dag:
         tensor = vg.nodes_1d is not None
         return cls(pr.mesh.vert, pr.mesh.cells, pr.order, vg.v, vg.w,
                    n_1d=len(vg.nodes_1d) if tensor else 0, nodes_1d=vg.nodes_1d,
-                   weights_1d=vg.weights_1d, L=vg.L, **kw)
+                   weights_1d=vg.weights_1d, L=vg.L, dg_cells=vg.dg_cells, **kw)
 
     def __del__(self, _destroy=_lib.tgs_dag_destroy):
         # the library function is bound at definition time: module globals

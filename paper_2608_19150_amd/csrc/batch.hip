@@ -266,6 +266,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       b.maxw.nu_const = o.nu_model.nu_const;
       b.maxw.kn = o.nu_model.kn;
       b.maxw.L = d->L;
+      b.maxw.dg_cells = d->dg_cells;
       b.maxw.sticky = B->sticky + nfirst[i];
       const double* mf = k == 0 ? s->fk : (k <= S ? out[k - 1] : f[i]);
       b.mom = MomArgs{mf,      d->d_pos, nullptr, d->d_v, d->d_w, nullptr, nullptr,
@@ -413,6 +414,8 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
       return fail(BGK_E_UNSUPPORTED, "batched stepping runs the FP64 sweep");
     if (d->d_lag) return fail(BGK_E_UNSUPPORTED, "batched stepping needs acyclic sweep graphs");
     if (d->dim == 3 && d->order != 1) return fail(BGK_E_UNSUPPORTED, "3D instances must be P1");
+    if (s->opts.maxw_mode == BGK_MAXW_PROJECTED)
+      return fail(BGK_E_UNSUPPORTED, "batched stepping has no projected Maxwellian");
     tab = tab && s->mtab != nullptr;
     n_nodes += d->n_nodes;
   }

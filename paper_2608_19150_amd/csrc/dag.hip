@@ -588,6 +588,27 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
                 "weights are not the declared tensor product");
     }
   }
+  // Q2 discontinuous-Galerkin velocity space (Sec. 3.2): on each of the
+  // dg_cells uniform cells of [-L, L] the 3-point Gauss-Legendre nodes
+  // centre + (h/2) xi with weights (h/2) (5/9, 8/9, 5/9)
+  if (vg->dg_cells) {
+    const int nc1 = vg->dg_cells;
+    BGK_CHECK(nc1 > 0 && nc1 <= 32, BGK_E_INVALID, "dg_cells must be in [1, 32]");
+    BGK_CHECK(vg->n_1d == 3 * nc1, BGK_E_INVALID, "a Q2 velocity space needs n_1d = 3*dg_cells");
+    BGK_CHECK(vg->L > 0, BGK_E_INVALID, "a Q2 velocity space needs L > 0");
+    const double h = 2.0 * vg->L / nc1;
+    const double xi[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+    const double wr[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    for (int c = 0; c < nc1; ++c)
+      for (int k = 0; k < 3; ++k) {
+        const double x = -vg->L + h * (c + 0.5) + 0.5 * h * xi[k];
+        const double w = 0.5 * h * wr[k];
+        BGK_CHECK(std::fabs(vg->nodes_1d[3 * c + k] - x) <= 1e-12 * vg->L &&
+                      std::fabs(vg->weights_1d[3 * c + k] - w) <= 1e-12 * w,
+                  BGK_E_INVALID, "nodes_1d / weights_1d are not the Q2 Gauss-Legendre grid");
+      }
+    D->dg_cells = nc1;
+  }
   const int64_t nc = H.n_cells;
   const int nf = dim + 1;
   // Morton order of centroids -> internal numbering

@@ -273,6 +273,7 @@ struct tgs_dag {
   int n_1d = 0;
   std::vector<double> nodes_1d, weights_1d;
   double L = 0.0;
+  int dg_cells = 0;                         // Q2 velocity cells per axis, or 0
   std::vector<int32_t> uid_host;            // internal -> user cell
   std::vector<int32_t> iid_host;            // user -> internal cell
   std::vector<double> node_x, bnode_x, vol_user;  // exports (user order)

@@ -378,6 +378,45 @@ __device__ void matched_system(const MaxwArgs& p, const double (&x)[DIM + 2],
   }
 }
 
+// Projection onto the Q2 velocity space (App. B).  The Lagrange basis sits
+// at the Gauss-Legendre nodes, so each cell's mass matrix is the diagonal of
+// the quadrature weights and node k of cell c takes the value
+//   (1/w_k) * integral over I_c of g(x) l_k(x) dx,   g = exp(-(x-u)^2/(2 theta)),
+// where I_c is the cell except that the first cell extends to -infinity and
+// the last to +infinity (the extension E of the projection's definition).
+// Substituting x = u + sigma t (sigma^2 = theta) and writing the cell's
+// reference coordinate as y = alpha + beta t, the integrals of g y^m are
+// sigma times combinations of G_m = integral of t^m exp(-t^2/2) over
+// [t_a, t_b], m = 0, 1, 2: G_0 from erfc, G_1 = e_a - e_b, G_2 = G_0 +
+// t_a e_a - t_b e_b with e = exp(-t^2/2).  The reference nodes are xi = -s, 0, s with
+// s^2 = 3/5 and weights (h/2)(5/9, 8/9, 5/9); in monomials of y the basis
+// is l_0 = (y^2 - s y)/(2 s^2), l_1 = 1 - y^2/s^2, l_2 = (y^2 + s y)/(2 s^2).
+__device__ __forceinline__ double proj_node(double u, double sig, int i, int nc1, double L) {
+  constexpr double RT2 = 0.70710678118654752440;   // 1/sqrt(2)
+  constexpr double SPI2 = 1.2533141373155002512;   // sqrt(pi/2)
+  constexpr double S = 0.77459666924148337704;     // sqrt(3/5)
+  const int c = i / 3, k = i - 3 * c;
+  const double hh = L / nc1;                       // half the cell width
+  const double lo = -L + 2.0 * hh * c;
+  const bool a_inf = c == 0, b_inf = c == nc1 - 1;
+  const double ta = (lo - u) / sig, tb = (lo + 2.0 * hh - u) / sig;
+  // with A = erfc(|t_a|/sqrt2), B = erfc(|t_b|/sqrt2) (0 at an infinite
+  // limit): G_0 / sqrt(pi/2) = A - B if 0 <= t_a, B - A if t_b <= 0, else
+  // 2 - A - B; no difference of nearly equal terms in any case
+  const double A = a_inf ? 0.0 : erfc(fabs(ta) * RT2);
+  const double B = b_inf ? 0.0 : erfc(fabs(tb) * RT2);
+  const double g0 = SPI2 * (!a_inf && ta >= 0.0 ? A - B : (!b_inf && tb <= 0.0 ? B - A : 2.0 - A - B));
+  const double ea = a_inf ? 0.0 : bgk_exp(-0.5 * ta * ta);
+  const double eb = b_inf ? 0.0 : bgk_exp(-0.5 * tb * tb);
+  const double g1 = ea - eb;
+  const double g2 = g0 + (a_inf ? 0.0 : ta * ea) - (b_inf ? 0.0 : tb * eb);
+  const double al = (u - (lo + hh)) / hh, be = sig / hh;
+  const double m1 = sig * fma(al, g0, be * g1);
+  const double m2 = sig * fma(al * al, g0, fma(2.0 * al * be, g1, be * be * g2));
+  if (k == 1) return (sig * g0 - m2 * (5.0 / 3.0)) / (hh * (8.0 / 9.0));
+  return (m2 + (k == 0 ? -S : S) * m1) * (5.0 / 6.0) / (hh * (5.0 / 9.0));
+}
+
 template <int DIM>
 __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double* __restrict__ Uin,
                                                 int64_t i) {
@@ -400,8 +439,11 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
   const bool collisional = !(p.nu_kind == BGK_NU_CONST && p.nu_const == 0.0);
   if (!collisional) {
     if (p.nu) p.nu[i] = 0.0;
+    // PROJECTED keeps (n, u, theta): n = 0 makes its tables vanish
 #pragma unroll
-    for (int m = 0; m < NM; ++m) p.coef[i * NM + m] = m == 0 ? -INFINITY : 0.0;
+    for (int m = 0; m < NM; ++m)
+      p.coef[i * NM + m] = p.mode == BGK_MAXW_PROJECTED ? (m == NM - 1 ? 1.0 : 0.0)
+                                                         : (m == 0 ? -INFINITY : 0.0);
     if (p.M_dense)
       for (int j = 0; j < p.n_v; ++j) p.M_dense[i * p.n_v + j] = 0.0;
     return;
@@ -410,6 +452,29 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
   double nu = p.nu_kind == BGK_NU_CONST ? p.nu_const : n / sqrt(th) / p.kn;
   if (p.nu) p.nu[i] = nu;
   if (p.numax && physical) atomicMax(p.numax, (unsigned long long)__double_as_longlong(nu));
+  if (p.mode == BGK_MAXW_PROJECTED) {
+    // coefficients are the primitive variables; the values are products of
+    // per-axis projections times n (2 pi theta)^(-d/2)
+    p.coef[i * NM] = n;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) p.coef[i * NM + 1 + d] = u[d];
+    p.coef[i * NM + 1 + DIM] = th;
+    if (p.M_dense) {
+      const double sig = sqrt(th);
+      const double pref = n / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th));
+      for (int j = 0; j < p.n_v; ++j) {
+        int rem = j;
+        double val = pref;
+        for (int d = DIM - 1; d >= 0; --d) {
+          const int ia = rem % p.n1;
+          rem /= p.n1;
+          val *= proj_node(u[d], sig, ia, p.dg_cells, p.L);
+        }
+        p.M_dense[i * p.n_v + j] = val;
+      }
+    }
+    return;
+  }
   double x[NM];
   if (p.mode == BGK_MAXW_LINEAR) {
     double vol = 1.0;
@@ -578,6 +643,87 @@ int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, d
   return BGK_OK;
 }
 
+// Projected-Maxwellian tables.  Pass 1: the per-axis projections of every
+// node, pr[(a n1 + i) n_nodes + node] (axis 0 carrying n (2 pi theta)^(-d/2)),
+// one thread per (node, axis, 1-D velocity node), consecutive nodes on
+// consecutive threads.  Pass 2: the tables of the factorised layout from
+// them, as 16-byte chunks like the exponential tables: axis 0's entry of 1-D
+// node i0 paired with nu, the rest's entry pr_1[i1] (2D) or pr_1[i1] pr_2[i2]
+// (3D, row i1 n1 + i2).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_proj_axes(const double* __restrict__ prim, double* __restrict__ pr,
+                            int64_t n_nodes, int n1, int nc1, double L) {
+  constexpr int NM = DIM + 2;
+  const int64_t total = (int64_t)DIM * n1 * n_nodes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = t % n_nodes;
+    const int ai = (int)(t / n_nodes);
+    const int a = ai / n1, i = ai - a * n1;
+    const double* P = prim + node * NM;
+    const double th = P[1 + DIM];
+    double v = proj_node(P[1 + a], sqrt(th), i, nc1, L);
+    if (a == 0)
+      v *= P[0] / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th));
+    pr[t] = v;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ pr, const double* __restrict__ nu,
+                              double* __restrict__ tab, int64_t n_cells, int n1, int np) {
+  const TabLayout L(n_cells, n1, np, DIM);
+  const int64_t nn = n_cells * np;
+  const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
+  const int64_t total = table_chunks(DIM, n_cells, n1, np);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const bool first = t < a0;
+    const int64_t u = first ? t : t - a0;
+    const int half = (first ? L.s0 : L.s1) / 2;
+    const int64_t q = u / half;
+    const int h = (int)(u - q * half);
+    const int64_t c = q % n_cells;
+    const int row = (int)(q / n_cells);
+    const auto rest = [&](int b) {
+      const int64_t node = c * np + b;
+      if (DIM == 2) return pr[((int64_t)n1 + row) * nn + node];
+      return pr[((int64_t)n1 + row / n1) * nn + node] *
+             pr[((int64_t)2 * n1 + row % n1) * nn + node];
+    };
+    double2 v;
+    if (first)
+      v = h < np ? make_double2(pr[(int64_t)row * nn + c * np + h], nu[c * np + h])
+                 : make_double2(0.0, 0.0);
+    else
+      v = make_double2(2 * h < np ? rest(2 * h) : 0.0, 2 * h + 1 < np ? rest(2 * h + 1) : 0.0);
+    reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] = v;
+  }
+}
+
+int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, double* pr,
+                       double* tab, hipStream_t stream) {
+  BGK_CHECK(d->dg_cells > 0, BGK_E_INVALID, "projected tables need a Q2 velocity space");
+  const int np = (int)(d->n_nodes / d->n_cells);
+  const int64_t n_pr = (int64_t)d->dim * d->n_1d * d->n_nodes;
+  const int64_t total = table_chunks(d->dim, d->n_cells, d->n_1d, np);
+  const int g1 = (int)std::min<int64_t>((n_pr + 255) / 256, 65536);
+  const int g2 = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  if (d->dim == 2) {
+    hipLaunchKernelGGL(k_proj_axes<2>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
+                       d->n_1d, d->dg_cells, d->L);
+    hipLaunchKernelGGL(k_proj_tables<2>, dim3(g2), dim3(256), 0, stream, pr, nu, tab, d->n_cells,
+                       d->n_1d, np);
+  } else {
+    hipLaunchKernelGGL(k_proj_axes<3>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
+                       d->n_1d, d->dg_cells, d->L);
+    hipLaunchKernelGGL(k_proj_tables<3>, dim3(g2), dim3(256), 0, stream, pr, nu, tab, d->n_cells,
+                       d->n_1d, np);
+  }
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
 // nodal rows between user order and internal order: to_internal:
 // dst[K] = src[uid[K]], else dst[uid[K]] = src[K]; rows of `width` doubles
 __global__ void k_nodal_perm(const double* __restrict__ src, double* __restrict__ dst,
@@ -655,15 +801,18 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
                       unsigned long long* numax, uint8_t* sticky, hipStream_t stream) {
-  BGK_CHECK(mode == BGK_MAXW_DIRECT || mode == BGK_MAXW_MATCHED || mode == BGK_MAXW_LINEAR,
+  BGK_CHECK(mode == BGK_MAXW_DIRECT || mode == BGK_MAXW_MATCHED || mode == BGK_MAXW_LINEAR ||
+                mode == BGK_MAXW_PROJECTED,
             BGK_E_INVALID, "unknown Maxwellian mode");
+  BGK_CHECK(mode != BGK_MAXW_PROJECTED || d->dg_cells > 0, BGK_E_INVALID,
+            "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
   BGK_CHECK(nm && (nm->kind == BGK_NU_CONST || (nm->kind == BGK_NU_KN && nm->kn > 0)),
             BGK_E_INVALID, "bad collision-frequency model");
   BGK_CHECK(mode != BGK_MAXW_LINEAR || d->L > 0, BGK_E_INVALID,
             "LINEAR mode needs the velocity box half-width L");
   MaxwArgs p{U,      coef,     nu,          M_dense,       status, numax,
              d->d_v, d->d_w,   d->d_nodes1d, d->d_weights1d, d->n_1d, d->n_v,
-             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L, sticky};
+             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L, d->dg_cells, sticky};
   const dim3 grid((unsigned)((d->n_nodes + 127) / 128)), block(128);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxwellian<2>, grid, block, 0, stream, p);

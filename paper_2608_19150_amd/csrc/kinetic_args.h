@@ -36,6 +36,7 @@ struct MaxwArgs {
   int mode;
   int nu_kind;
   double nu_const, kn, L;
+  int dg_cells;             // Q2 velocity cells per axis (PROJECTED), or 0
   // MATCHED: per node, set once its Newton solve has failed; such a node
   // keeps the DIRECT coefficients while the flag stays set (nullable)
   uint8_t* sticky;

@@ -19,6 +19,7 @@ struct bgk_solver {
   double* U[2] = {};             // moments ping-pong
   double* mcoef = nullptr;
   double* mtab = nullptr;        // factorised Maxwellian tables (tensor grids)
+  double* pr = nullptr;          // per-axis projections (PROJECTED mode)
   double* nu = nullptr;
   double* partial = nullptr;
   double* ratio = nullptr;       // [4]

@@ -195,6 +195,8 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!o->bc_coef) return fail(BGK_E_INVALID, "bc_coef is required");
   if (o->precision != TGS_FP64 && o->precision != TGS_FP32_CORRECTION)
     return fail(BGK_E_INVALID, "unknown precision");
+  if (o->maxw_mode == BGK_MAXW_PROJECTED && d->dg_cells <= 0)
+    return fail(BGK_E_INVALID, "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
   bgk_solver* s = new (std::nothrow) bgk_solver();
   if (!s) return fail(BGK_E_NOMEM, "host allocation failed");
   s->dag = d;
@@ -212,6 +214,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->U[1], nn);
   if (!rc) rc = dmalloc(&s->mcoef, nn);
   if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
+  if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
   if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
   if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
   if (!rc) rc = dmalloc(&s->ratio, 4);
@@ -235,7 +238,7 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
   if (!s) return BGK_OK;
   void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
                   s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
-                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky};
+                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_info) (void)hipHostFree(s->h_info);
@@ -310,7 +313,11 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
                                   nullptr, s->status, s->numax, s->sticky, stream)))
         return rc;
-      if (s->mtab && (rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream))) return rc;
+      if (s->pr)
+        rc = launch_proj_tables(d, s->mcoef, s->nu, s->pr, s->mtab, stream);
+      else if (s->mtab)
+        rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream);
+      if (rc) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
       if (need_prev) cur_out = (prev == out) ? s->fping : out;
       tgs_sweep_io io{};

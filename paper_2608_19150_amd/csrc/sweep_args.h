@@ -44,6 +44,13 @@ SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
 // coefficients and nu (kinetic.hip), and their size in doubles
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream);
+// the same tables for the projected Maxwellian from primitive (n, u, theta)
+// coefficients; pr is scratch of proj_scratch_size(d) doubles
+int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, double* pr,
+                       double* tab, hipStream_t stream);
+inline size_t proj_scratch_size(const tgs_dag* d) {
+  return (size_t)d->dim * d->n_1d * d->n_nodes;
+}
 inline size_t maxw_table_size(const tgs_dag* d) {
   return (size_t)TabLayout(d->n_cells, d->n_1d, (int)(d->n_nodes / d->n_cells), d->dim).size();
 }

@@ -354,6 +354,17 @@ def config_c2(n_side: int = 316) -> Problem:
                    tau=1e-10, name=f"c2_fourier_p2_{2 * n_side * n_side}tri_32x32")
 
 
+def config_c2_q2(n_side: int = 316, vcells: int = 10) -> Problem:
+    """The 2D workload's mesh, state and physics on the Q2 velocity space of
+    Sec. 3.2: vcells uniform cells per axis on [-8, 8] with 3 Gauss-Legendre
+    nodes each (10 cells: 30^2 = 900 velocities)."""
+    base = config_c2(n_side)
+    return Problem(base.mesh, 2, gl_velocity_grid(vcells, 8.0, 2), base.state,
+                   nu_model=base.nu_model, kn=base.kn, tableau=base.tableau, cfl=base.cfl,
+                   n_steps=base.n_steps, tau=base.tau,
+                   name=f"c2_fourier_p2_{2 * n_side * n_side}tri_q2_{3 * vcells}x{3 * vcells}")
+
+
 # Riemann-type workloads spread the jump over a tanh layer about this many
 # lattice cells wide: a sharp jump drives some P1 nodal moments non-physical
 # (the method has no limiter; both the oracle and the library reject it).

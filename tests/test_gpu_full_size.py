@@ -4,8 +4,9 @@ pipelined walk): every velocity and node is computed on the GPU, and the
 oracle recomputes a sample one by one - whole velocities of the sweep over
 the full mesh, single nodes of the moment reduction and the Maxwellian.
 
-Workloads: ~200k graded P2 triangles x 32^2 velocities (the 2D workload)
-and ~55k P1 tetrahedra x 16^3 velocities (the 3D workload)."""
+Workloads: ~200k graded P2 triangles x 32^2 velocities (the 2D workload),
+the same mesh on 30^2- and 33^2-node Q2 velocity spaces with the projected
+Maxwellian, and ~55k P1 tetrahedra x 16^3 velocities (the 3D workload)."""
 import gc
 
 import numpy as np
@@ -13,7 +14,7 @@ import pytest
 
 import problems as P
 from oracle import dag as odag
-from oracle import geometry, kinetic, solver, transport
+from oracle import geometry, kinetic, solver, transport, velocity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -146,3 +147,45 @@ def test_batched_workload_instances_at_full_size_equal_single_instance_steps():
         assert torch.equal(pairs[i][1].cpu(), ref[i]), i
     del batch, pairs
     _release()
+
+
+@pytest.mark.parametrize("vcells", [10, 11])
+def test_full_size_projected_step_matches_oracle_on_sampled_velocities(vcells):
+    """One Picard iteration of a backward-Euler step on the 2D workload's mesh
+    with the Q2 velocity space in PROJECTED mode (10 cells per axis: the
+    benchmarked 30^2 nodes; 11: 33^2 nodes, more sweep workgroups than stay
+    resident at once), from seeded moments: projected-Maxwellian tables at
+    full size feed the pipelined sweep; the oracle recomputes whole sampled
+    velocities from the same moments, its 1-D erf projections and its sweep."""
+    base = P.config_c2_q2(316, vcells)
+    pr = P.Problem(base.mesh, 2, base.vgrid, base.state, nu_model="kn", kn=1e-2, tableau="BE",
+                   cfl=base.cfl)
+    d, f, bc, dt = B.problem_setup(pr)
+    n1 = 3 * vcells
+    assert d.n_cells > 5e4 and d.n_v == n1 * n1 and d.dg_cells == vcells
+    _, prim = _nodal_inputs(d.n_nodes, 2, 9300)
+    n, u, th = prim[:, 0], prim[:, 1:-1], prim[:, -1]
+    Um = np.concatenate([n[:, None], n[:, None] * u,
+                         (0.5 * n * (2 * th + np.sum(u * u, axis=1)))[:, None]], axis=1)
+    s = B.Solver(d, dt=dt, bc_coef=bc, tableau="BE", fixed_iters=1, mode="PROJECTED",
+                 nu_model="kn", kn=1e-2)
+    assert s.step(f, U_guess=B._dev(Um))["iters"] == [1]
+    js = np.array([0, 7 * n1 + 3, (n1 // 2) * n1 + n1 // 2, 21 * n1 + 8, n1 * n1 - 1])
+    f_s = d.unpack(f)[..., torch.as_tensor(js, device="cuda")].cpu().numpy()
+    del s, f, bc, d
+    _release()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    V = pr.vgrid.v[js]
+    gens, lags = odag.build_all(geo, V)
+    assert not lags.any()
+    # projected Maxwellian at the sampled velocities: n (2 pi theta)^-1 times
+    # the two axes' 1-D projections at the sample's tensor indices
+    p0 = velocity.project_gaussian_1d(u[:, 0], th, vcells, 8.0)
+    p1 = velocity.project_gaussian_1d(u[:, 1], th, vcells, 8.0)
+    Mv = (n / (2.0 * np.pi * th))[:, None] * p0[:, js // n1] * p1[:, js % n1]
+    Mv = Mv.reshape(geo.n_cells, geo.n_p, -1)
+    nu = kinetic.collision_frequency(Um, 2, "kn", kn=1e-2).reshape(geo.n_cells, geo.n_p)
+    f0 = solver.initial_condition(geo, V, pr.state)
+    g = solver.boundary_values(geo, V, pr.state)
+    f_ref = transport.sweep(geo, V, nu + 1.0 / dt, nu, Mv, f0 / dt, g, gens)
+    assert rel(f_s, f_ref) <= TOL64
