@@ -251,6 +251,40 @@ int tgs_eval_maxwellian(const tgs_dag* dag, const double* coef, double* f_sweep,
                         bgk_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Wall boundaries (Sec. "Boundary conditions")                             */
+/* ------------------------------------------------------------------------ */
+
+/* Kind of a boundary facet: given inflow data; bounce-back,
+ * f_bc(x, v) = f(x, -v); specular reflection, f_bc(x, v) = f(x, R_n v) with
+ * R_n v = v - 2 (v.n) n.  The velocity set must be closed under the map of
+ * every wall facet (as the paper assumes: walls normal to a coordinate axis
+ * and a grid symmetric about 0). */
+enum { BGK_BC_INFLOW = 0, BGK_BC_BOUNCE_BACK = 1, BGK_BC_REFLECT = 2 };
+
+typedef struct tgs_walls tgs_walls;
+
+/* Prepares the wall facets of a DAG.  bface_kind: host int8 [n_bfaces]
+ * (BGK_BC_*), boundary facets in ascending (user cell, local facet) order,
+ * the order of tgs_dag_geometry's bnode_x and of bc_coef / bc_dense.  For
+ * every distinct (kind, normal) the velocity map is found by matching the
+ * mapped velocity against the set (tolerance 1e-9 max(1, max|v|));
+ * BGK_E_INVALID if a kind is unknown or an image is not a velocity of the
+ * set.  The DAG must outlive the handle.  Synchronises the device. */
+int tgs_walls_create(const tgs_dag* dag, const int8_t* bface_kind, tgs_walls** out);
+int tgs_walls_destroy(tgs_walls* walls);
+/* number of wall (non-inflow) facets */
+int64_t tgs_walls_count(const tgs_walls* walls);
+
+/* For every wall facet bf, facet node p and velocity j:
+ *   bc_dense[bf][p][j] = f(cell of bf, its local node at p, T_bf(j)),
+ * f device in the sweep layout, bc_dense device [n_bfaces][n_fp][n_v]
+ * (rows of inflow facets are left untouched).  This is the boundary update
+ * of a Picard iteration: the solver calls it with the previous iterate
+ * before each sweep. */
+int tgs_wall_values(const tgs_walls* walls, const double* f, double* bc_dense,
+                    bgk_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Implicit time step: DIRK stages with Picard iteration (Sec. 3.5, Sec. 4)  */
 /* ------------------------------------------------------------------------ */
 
@@ -269,6 +303,11 @@ typedef struct {
   const double* bc_coef;  /* device [n_bfaces][n_fp][dim+2] time-independent inflow */
   int timing;             /* 1: time every kernel with HIP events on the step's
                              stream (bgk_step_stats.*_ms); 0: no events */
+  const tgs_walls* walls; /* NULL, or wall facets of the same DAG: before each
+                             sweep their boundary data are taken from the
+                             previous Picard iterate (the first iteration of a
+                             stage: the stage's initial iterate); bc_coef
+                             gives the data of the inflow facets */
 } bgk_solver_opts;
 
 typedef struct {

@@ -11,7 +11,9 @@
   Maxwellian.  Stage 1 starts from f^k and stage s > 1 from the converged
   f^(s-1) (design note A3; the printed "s = 0" case is read as s = 1).
   On the Q2 velocity space of Sec. 3.2 the Maxwellian can instead be the
-  conservative projection of App. B (mode PROJECTED, velocity.py).
+  conservative projection of App. B (mode PROJECTED, velocity.py).  Wall
+  facets (bounce-back, reflection) take their data from the iterate before
+  each sweep (walls.py).
 * Stopping rule (eq. convergence-criteria, design note A13):
   max_m |U^{l+1,m} - U^{l,m}| / max(|U^{l,m}|, |U^{l,0}| s_m)
       < tau / max(1, max_i nu_i dt),
@@ -33,7 +35,7 @@ import math
 
 import numpy as np
 
-from . import kinetic, transport, velocity
+from . import kinetic, transport, velocity, walls as wallbc
 from .geometry import Geometry
 
 
@@ -112,12 +114,15 @@ def maxwellian_coefficients(U, V, w, mode: str, L: float, sticky=None):
 
 def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged, *, dt,
                  mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10,
-                 lmax=2000, fixed_iters=None, U_init=None, L=0.0, vcells=0):
+                 lmax=2000, fixed_iters=None, U_init=None, L=0.0, vcells=0, walls=None):
     """Picard iteration for one DIRK stage.  Returns (f, U, iterations, history).
 
     mode PROJECTED (the Q2 velocity space of Sec. 3.2 with ``vcells`` cells
     per axis on [-L, L]): the Maxwellian is the conservative projection of
-    App. B of M_{n,u,theta} with (n, u, theta) from U."""
+    App. B of M_{n,u,theta} with (n, u, theta) from U.
+    ``walls`` (optional, [n_bfaces] of walls.INFLOW / BOUNCE_BACK / REFLECT):
+    before each sweep the wall facets' data are taken from the current
+    iterate (walls.py)."""
     dim = geo.dim
     f = f_init
     U = kinetic.moments(f, V, w) if U_init is None else U_init
@@ -142,7 +147,8 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
             Mv = kinetic.coef_values(coef, V)
         else:                      # collision term vanishes: no Maxwellian needed
             Mv = np.zeros_like(q)
-        f_new = transport.sweep(geo, V, nu + sigma_shift, nu, Mv, q, gbc, gens, lagged, f)
+        g_it = gbc if walls is None else wallbc.wall_values(geo, V, f, walls, gbc)
+        f_new = transport.sweep(geo, V, nu + sigma_shift, nu, Mv, q, g_it, gens, lagged, f)
         U_new = kinetic.moments(f_new, V, w)
         ratio = relative_changes(U_new, U, dim)
         hist.append(float(ratio.max()))
@@ -158,12 +164,13 @@ def picard_stage(geo: Geometry, V, w, q, gbc, sigma_shift, f_init, gens, lagged,
 
 def bgk_step(geo: Geometry, V, w, f, gbc, dt, gens, lagged=None, *, scheme="BE",
              mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, tau=1e-10, lmax=2000,
-             fixed_iters=None, U_guess=None, L=0.0, vcells=0):
+             fixed_iters=None, U_guess=None, L=0.0, vcells=0, walls=None):
     """One DIRK time step of the discretised BGK equation.
 
     ``gbc`` is either the boundary data [n_bf][n_fp][N_v] or a callable
     gbc(stage_index) returning it.  ``U_guess`` (optional) replaces the
-    moments of f^k as the first stage's initial Picard iterate.
+    moments of f^k as the first stage's initial Picard iterate.  ``walls``
+    marks bounce-back and reflecting boundary facets (picard_stage).
     Returns (f^{k+1}, stats dict).
     """
     A, b, _ = tableau(scheme)
@@ -180,7 +187,8 @@ def bgk_step(geo: Geometry, V, w, f, gbc, dt, gens, lagged=None, *, scheme="BE",
         f_s, U_s, it, hist, nfb = picard_stage(
             geo, V, w, q, g, 1.0 / (dt * A[s, s]), stage_f, gens, lagged, dt=dt, mode=mode,
             nu_model=nu_model, nu_const=nu_const, kn=kn, tau=tau, lmax=lmax,
-            fixed_iters=fixed_iters, U_init=U_guess if s == 0 else None, L=L, vcells=vcells)
+            fixed_iters=fixed_iters, U_init=U_guess if s == 0 else None, L=L, vcells=vcells,
+            walls=walls)
         Fs.append((f_s - acc) / (dt * A[s, s]))
         stage_f = f_s
         iters.append(it)

@@ -40,6 +40,7 @@ EXPORTED = [
     "bgk_mlp_set_normalization", "bgk_mlp_forward", "bgk_mlp_loss_grad", "bgk_mlp_adam_step",
     "bgk_mlp_features", "bgk_mlp_targets", "bgk_mlp_guess",
     "bgk_batch_create", "bgk_batch_destroy", "bgk_batch_step", "bgk_batch_time_sweep",
+    "tgs_walls_create", "tgs_walls_destroy", "tgs_walls_count", "tgs_wall_values",
 ]
 
 
@@ -87,7 +88,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("tableau", C.c_int), ("dt", C.c_double), ("tau", C.c_double),
                 ("l_max", C.c_int), ("fixed_iters", C.c_int), ("precision", C.c_int),
                 ("maxw_mode", C.c_int), ("nu_model", NuModel), ("bc_coef", C.c_void_p),
-                ("timing", C.c_int)]
+                ("timing", C.c_int), ("walls", C.c_void_p)]
 
 
 class StepStats(C.Structure):
@@ -295,12 +296,13 @@ class Solver:
 
     def __init__(self, dag, *, dt, bc_coef, tableau="BE", tau=1e-10, l_max=2000, fixed_iters=0,
                  precision=TGS_FP64, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0,
-                 timing=False):
+                 timing=False, walls=None):
         self.dag = dag
         self.bc_coef = bc_coef
+        self.walls = walls            # keep the wall handle alive with the solver
         o = SolverOpts(TABLEAU[tableau], float(dt), float(tau), int(l_max), int(fixed_iters),
                        int(precision), MAXW[mode], NuModel(NU[nu_model], float(nu_const), float(kn)),
-                       _p(bc_coef), int(bool(timing)))
+                       _p(bc_coef), int(bool(timing)), walls.h if walls is not None else None)
         h = C.c_void_p()
         _check(_lib.bgk_solver_create(dag.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -320,6 +322,53 @@ class Solver:
                 "last_ratio": list(st.last_ratio[:st.stages]), "fallbacks": st.maxw_fallbacks,
                 "seconds": st.seconds, "sweep_ms": st.sweep_ms, "moments_ms": st.moments_ms,
                 "maxwellian_ms": st.maxwellian_ms, "sweeps": st.sweeps}
+
+
+BC = {"INFLOW": 0, "BOUNCE_BACK": 1, "REFLECT": 2}
+
+_lib.tgs_walls_create.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.tgs_walls_destroy.argtypes = [C.c_void_p]
+_lib.tgs_walls_count.argtypes = [C.c_void_p]
+_lib.tgs_walls_count.restype = C.c_int64
+_lib.tgs_wall_values.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+
+
+class Walls:
+    """tgs_walls: the bounce-back and reflecting facets of a DAG's boundary.
+
+    ``kinds`` int8 [n_bfaces] of BC values (or their names), boundary facets
+    in the order of Dag.geometry()'s boundary nodes."""
+
+    def __init__(self, dag, kinds):
+        k = np.asarray([BC[x] if isinstance(x, str) else int(x) for x in kinds], dtype=np.int8)
+        if k.shape != (dag.n_bfaces,):
+            raise ValueError(f"need {dag.n_bfaces} boundary kinds, got {k.shape}")
+        self.dag = dag
+        self.kinds = k
+        h = C.c_void_p()
+        _check(_lib.tgs_walls_create(dag.h, k.ctypes.data, C.byref(h)))
+        self.h = h
+
+    @property
+    def n_walls(self):
+        return int(_lib.tgs_walls_count(self.h))
+
+    def __del__(self, _destroy=_lib.tgs_walls_destroy):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _destroy(h)
+            self.h = None
+
+
+def wall_values(walls, f, bc_dense, stream=None):
+    """Fills the wall rows of bc_dense [n_bfaces][n_fp][n_v] from f (sweep layout)."""
+    _check(_lib.tgs_wall_values(walls.h, _p(f), _p(bc_dense), _stream(stream)))
+
+
+def boundary_facet_midpoints(dag):
+    """Mean of each boundary facet's nodes, [n_bfaces][dim] (host)."""
+    _, bx, _ = dag.geometry()
+    return bx.reshape(dag.n_bfaces, -1, dag.dim).mean(axis=1)
 
 
 def exported_symbols():

@@ -416,6 +416,7 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     if (d->dim == 3 && d->order != 1) return fail(BGK_E_UNSUPPORTED, "3D instances must be P1");
     if (s->opts.maxw_mode == BGK_MAXW_PROJECTED)
       return fail(BGK_E_UNSUPPORTED, "batched stepping has no projected Maxwellian");
+    if (s->opts.walls) return fail(BGK_E_UNSUPPORTED, "batched stepping has no wall boundaries");
     tab = tab && s->mtab != nullptr;
     n_nodes += d->n_nodes;
   }

@@ -26,6 +26,9 @@ struct HostMesh {
   std::vector<int32_t> nb_node;     // [c][dim+1][n_fp]
   std::vector<double> node_x;       // [c][n_p][dim]
   std::vector<double> bnode_x;      // [bf][n_fp][dim]
+  std::vector<int32_t> bcell;       // [bf] user cell of the boundary facet
+  std::vector<int32_t> bpack;       // [bf] its facet's local nodes, 4 bits each
+  std::vector<double> bnormal;      // [bf][dim] outward unit normal
   std::vector<double> vol;          // [c]
   std::vector<double> centroid;     // [c][dim]
   int64_t n_bfaces = 0;
@@ -225,9 +228,19 @@ int build_host_mesh(const tgs_mesh_desc* m, HostMesh& H) {
       if (H.nb[idx] == INT32_MIN) {
         H.nb[idx] = -(int32_t)(1 + nbf);
         ++nbf;
-        for (int p = 0; p < H.n_fp; ++p)
+        int32_t pack = 0;
+        for (int p = 0; p < H.n_fp; ++p) {
+          pack |= fn[p] << (4 * p);
           for (int d = 0; d < dim; ++d)
             H.bnode_x.push_back(H.node_x[(c * H.n_p + fn[p]) * dim + d]);
+        }
+        H.bcell.push_back((int32_t)c);
+        H.bpack.push_back(pack);
+        const double* nr = &H.geo[c * gs + 1 + k * dim];
+        double len = 0.0;
+        for (int d = 0; d < dim; ++d) len += nr[d] * nr[d];
+        len = std::sqrt(len);
+        for (int d = 0; d < dim; ++d) H.bnormal.push_back(nr[d] / len);
         continue;
       }
       const int32_t c2 = H.nb[idx];
@@ -657,6 +670,9 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   }
   D->node_x = std::move(H.node_x);
   D->bnode_x = std::move(H.bnode_x);
+  D->bface_cell = std::move(H.bcell);
+  D->bface_pack = std::move(H.bpack);
+  D->bface_normal = std::move(H.bnormal);
   D->vol_user = std::move(H.vol);
   const int nv = vg->n_v;
   if ((rc = dalloc(&D->d_geo, geo_i.size()))) return rc;

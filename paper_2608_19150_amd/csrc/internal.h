@@ -277,6 +277,10 @@ struct tgs_dag {
   std::vector<int32_t> uid_host;            // internal -> user cell
   std::vector<int32_t> iid_host;            // user -> internal cell
   std::vector<double> node_x, bnode_x, vol_user;  // exports (user order)
+  // boundary facets in ascending (user cell, local facet) order: cell, the
+  // facet's local nodes (4 bits each), outward unit normal [dim]
+  std::vector<int32_t> bface_cell, bface_pack;
+  std::vector<double> bface_normal;
   std::vector<int32_t> G_host;              // [n_v]
   std::vector<int64_t> gbase_host;          // [n_v]
   // device arrays

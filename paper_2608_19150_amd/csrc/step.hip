@@ -16,6 +16,7 @@
 #include "device_common.h"
 #include "solver.h"
 #include "sweep_args.h"
+#include "walls.h"
 
 namespace bgk {
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
@@ -195,6 +196,8 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!o->bc_coef) return fail(BGK_E_INVALID, "bc_coef is required");
   if (o->precision != TGS_FP64 && o->precision != TGS_FP32_CORRECTION)
     return fail(BGK_E_INVALID, "unknown precision");
+  if (o->walls && walls_dag(o->walls) != d)
+    return fail(BGK_E_INVALID, "walls belong to another DAG");
   if (o->maxw_mode == BGK_MAXW_PROJECTED && d->dg_cells <= 0)
     return fail(BGK_E_INVALID, "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
   bgk_solver* s = new (std::nothrow) bgk_solver();
@@ -215,6 +218,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
   if (!rc) rc = dmalloc(&s->mcoef, nn);
   if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
   if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
+  if (!rc && o->walls) rc = dmalloc(&s->bcd, (size_t)d->n_bfaces * d->n_fp * d->n_v);
   if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
   if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
   if (!rc) rc = dmalloc(&s->ratio, 4);
@@ -238,7 +242,8 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
   if (!s) return BGK_OK;
   void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
                   s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
-                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr};
+                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr,
+                  s->bcd};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_info) (void)hipHostFree(s->h_info);
@@ -274,6 +279,9 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
   if (s->stiffly_accurate) fst[s->S - 1] = f;
   const double* stage_init = fk;   // initial Picard iterate of the stage
   int ucur = 0;
+  // with walls the sweep reads dense boundary data: the inflow facets'
+  // Maxwellians once per step, the wall facets' rows before every sweep
+  if (o.walls && (rc = launch_bc_dense(d, o.bc_coef, s->bcd, stream))) return rc;
   // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
   // order during the step; U_guess / U_out are in user order
   if (U_guess) {
@@ -327,8 +335,10 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       io.nu = s->nu;
       io.mcoef = s->mcoef;
       io.q = qsrc;
-      io.bc_coef = o.bc_coef;
+      io.bc_coef = o.walls ? nullptr : o.bc_coef;
+      io.bc_dense = o.walls ? s->bcd : nullptr;
       io.f_prev = need_prev ? prev : nullptr;
+      if (o.walls && (rc = launch_wall_values(o.walls, prev, s->bcd, stream))) return rc;
       io.f_out = cur_out;
       if ((rc = launch_sweep(d, &io, s->mtab, s->d32, stream, 0))) return rc;
       if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));

@@ -189,6 +189,23 @@ def structured_square_mesh(n_side: int) -> Mesh:
     return Mesh(pts, np.asarray(cells, dtype=np.int32))
 
 
+def rectangle_mesh(nx: int, ny: int, x0: float, x1: float, y0: float, y1: float) -> Mesh:
+    """Right-triangle mesh of [x0,x1] x [y0,y1]: an nx x ny lattice of
+    rectangles, each split along its lower-left to upper-right diagonal."""
+    gx = np.linspace(x0, x1, nx + 1)
+    gy = np.linspace(y0, y1, ny + 1)
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    idx = lambda i, j: i * (ny + 1) + j  # noqa: E731
+    cells = []
+    for i in range(nx):
+        for j in range(ny):
+            a, b, c, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+            cells.append((a, b, c))
+            cells.append((a, c, d))
+    return Mesh(pts, np.asarray(cells, dtype=np.int32))
+
+
 def graded_square_mesh(n_side: int, jitter: float, seed: int, ratio: float = 4.0) -> Mesh:
     """Jittered lattice warped per axis by g(s) = s + a sin(2 pi s)/(2 pi).
 
