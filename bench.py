@@ -276,6 +276,78 @@ def run_q2(n_side, steps, warmup):
     return out
 
 
+def run_x3(cells, ref_cells, nus, tableaux, steps, tau, threads):
+    """Projection against interpolation of the Maxwellian on the 1D Sod
+    problem embedded in 2D (reflecting top and bottom walls, Q2 velocity
+    space on [-7, 7]^2): L2 errors over the mesh of the density, velocity
+    and temperature after `steps` steps of dt = 1.76e-3, against a reference
+    run with `ref_cells` velocity cells per axis (projected Maxwellian), for
+    each nu, tableau, velocity resolution and Maxwellian."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+
+    def solve(vc, nu, tab, mode):
+        pr = P.sod_strip_problem(vc, nu, tab)
+        d, f, bc, _ = B.problem_setup(pr, sweep_threads=threads)
+        walls = B.Walls(d, P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d)))
+        s = B.Solver(d, dt=P.SOD_STRIP_DT, bc_coef=bc, tableau=tab, tau=tau, mode=mode,
+                     nu_const=nu, walls=walls)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = [s.step(f)["total_iters"] for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        U = B.moments(d, f).cpu().numpy()
+        vol = d.geometry()[2]
+        del s, f, walls, d
+        torch.cuda.empty_cache()
+        n = U[:, 0]
+        u = U[:, 1:3] / n[:, None]
+        th = (2.0 * U[:, 3] / n - np.sum(u * u, axis=1)) / 2.0
+        print(f"[x3] nu={nu} {tab} cells={vc} {mode}: {sum(iters)} iterations, {el:.1f} s",
+              file=sys.stderr, flush=True)
+        return {"n": n, "u": u[:, 0], "theta": th, "vol": vol, "iters": iters, "seconds": el}
+
+    def l2(a, b, vol):
+        # P1 mass matrix per triangle: (|K|/12) (sum e_p^2 + (sum e_p)^2)
+        e = (a - b).reshape(-1, 3)
+        return float(np.sqrt(np.sum(vol / 12.0 * (np.sum(e * e, 1) + np.sum(e, 1) ** 2))))
+
+    out = {"setup": {"mesh": "256x6 lattice of [-1,1]x[-3/128,3/128], 3072 P1 triangles",
+                     "velocity_box": 7.0, "dt": P.SOD_STRIP_DT, "steps": steps, "tau": tau,
+                     "reference_cells": ref_cells, "sweep_threads": threads,
+                     "walls": "reflection top/bottom, inflow ends"}, "runs": []}
+    for tab in tableaux:
+        for nu in nus:
+            try:
+                ref = solve(ref_cells, nu, tab, "PROJECTED")
+            except B.BGKError as e:
+                print(f"[x3] nu={nu} {tab} reference: {e}", file=sys.stderr, flush=True)
+                out["runs"].append({"tableau": tab, "nu": nu, "reference_error": str(e)})
+                torch.cuda.empty_cache()
+                continue
+            rec = {"tableau": tab, "nu": nu, "reference_iters": int(sum(ref["iters"])),
+                   "errors": {}}
+            for vc in cells:
+                for mode in ("PROJECTED", "DIRECT"):
+                    try:
+                        r = solve(vc, nu, tab, mode)
+                    except B.BGKError as e:     # e.g. non-physical moments on coarse grids
+                        print(f"[x3] nu={nu} {tab} cells={vc} {mode}: {e}", file=sys.stderr,
+                              flush=True)
+                        rec["errors"][f"{vc}_{mode.lower()}"] = {"error": str(e)}
+                        torch.cuda.empty_cache()
+                        continue
+                    rec["errors"][f"{vc}_{mode.lower()}"] = {
+                        q: l2(r[q], ref[q], ref["vol"]) for q in ("n", "u", "theta")}
+                    rec["errors"][f"{vc}_{mode.lower()}"]["iters"] = int(sum(r["iters"]))
+                    rec["errors"][f"{vc}_{mode.lower()}"]["seconds"] = r["seconds"]
+            out["runs"].append(rec)
+    return out
+
+
 def moment_error(U, Uref, dim):
     """Per component: |U_m - Uref_m| / max(|Uref_m|, s_m |Uref_0|), s = (0,1,0)."""
     blocks = [slice(0, 1), slice(1, 1 + dim), slice(1 + dim, 2 + dim)]
@@ -356,6 +428,15 @@ def main():
     ap.add_argument("--no-q2", action="store_true",
                     help="skip the Q2 velocity space (projected vs matched Maxwellian)")
     ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
+    ap.add_argument("--x3", action="store_true",
+                    help="only run the projection-vs-interpolation study on the 1D Sod strip")
+    ap.add_argument("--x3-cells", default="4,8,16,32")
+    ap.add_argument("--x3-ref", type=int, default=64)
+    ap.add_argument("--x3-nu", default="1,1000")
+    ap.add_argument("--x3-tableaux", default="BE,DIRK2")
+    ap.add_argument("--x3-steps", type=int, default=85)
+    ap.add_argument("--x3-tau", type=float, default=1e-6)
+    ap.add_argument("--x3-threads", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -364,6 +445,12 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.x3:
+        res = run_x3([int(x) for x in args.x3_cells.split(",")], args.x3_ref,
+                     [float(x) for x in args.x3_nu.split(",")], args.x3_tableaux.split(","),
+                     args.x3_steps, args.x3_tau, args.x3_threads)
+        print(json.dumps({"study": "projection_vs_interpolation_sod_strip", **res}), flush=True)
         return
 
     import torch

@@ -99,7 +99,7 @@ typedef struct {
                              PROJECTED modes) */
   int dg_cells;           /* > 0: the Q2 discontinuous-Galerkin velocity space
                              of Sec. 3.2: [-L, L] cut into dg_cells uniform
-                             cells per axis (at most 32), nodes_1d the 3
+                             cells per axis, nodes_1d the 3
                              Gauss-Legendre points of each cell in order and
                              weights_1d their weights (n_1d = 3*dg_cells;
                              checked).  Enables BGK_MAXW_PROJECTED.  0 = a

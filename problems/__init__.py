@@ -382,6 +382,35 @@ def config_c2_q2(n_side: int = 316, vcells: int = 10) -> Problem:
                    name=f"c2_fourier_p2_{2 * n_side * n_side}tri_q2_{3 * vcells}x{3 * vcells}")
 
 
+SOD_STRIP_HALF_HEIGHT = 3.0 / 128.0
+
+
+def sod_strip_problem(vcells: int, nu: float, tableau: str = "BE") -> Problem:
+    """The 1D Sod problem embedded in 2D (the paper's Sec. 5.1.1): [-1, 1] x
+    [-3/128, 3/128], left (x_1 < 0) = (1, 0, 1), right = (0.125, 0, 0.8),
+    velocity space [-7, 7]^2 with vcells Q2 cells per axis, constant nu, the
+    paper's dt = 1.76e-3 for 85 steps.  Here the 256 x 6 lattice is split
+    into 3072 right triangles (P1) instead of quadrilaterals, and the jump
+    is spread over a tanh layer 1.5 lattice cells wide (with a sharp jump the
+    two-stage DIRK drives a nodal density non-positive at nu = 1000 on these
+    elements); the top and bottom walls reflect (sod_strip_wall_kinds) and
+    the ends take the initial state as inflow."""
+    mesh = rectangle_mesh(256, 6, -1.0, 1.0, -SOD_STRIP_HALF_HEIGHT, SOD_STRIP_HALF_HEIGHT)
+    st = State("plane", {"normal": np.array([1.0, 0.0]), "center": np.zeros(2),
+                         "left": SOD_LEFT, "right": SOD_RIGHT, "width": 1.5 * 2.0 / 256})
+    return Problem(mesh, 1, gl_velocity_grid(vcells, 7.0, 2), st, nu_model="const",
+                   nu_const=nu, tableau=tableau, n_steps=85, name=f"sod_strip_q2_{vcells}")
+
+
+SOD_STRIP_DT = 1.76e-3
+
+
+def sod_strip_wall_kinds(facet_midpoints: np.ndarray) -> np.ndarray:
+    """2 (reflection) on the top and bottom walls, 0 (inflow) at the ends."""
+    top = np.abs(np.abs(facet_midpoints[:, 1]) - SOD_STRIP_HALF_HEIGHT) < 1e-12
+    return np.where(top, 2, 0).astype(np.int8)
+
+
 # Riemann-type workloads spread the jump over a tanh layer about this many
 # lattice cells wide: a sharp jump drives some P1 nodal moments non-physical
 # (the method has no limiter; both the oracle and the library reject it).

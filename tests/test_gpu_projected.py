@@ -147,7 +147,7 @@ def test_projected_mode_and_q2_grid_validation():
 
     assert dag().dg_cells == 4
     assert code(lambda: dag(dg_cells=5)) == B.BGK_E_INVALID         # n_1d != 3 dg_cells
-    assert code(lambda: dag(dg_cells=33)) == B.BGK_E_INVALID        # beyond the cap
+    assert code(lambda: dag(dg_cells=-2)) == B.BGK_E_INVALID        # not positive
     assert code(lambda: dag(L=6.5)) == B.BGK_E_INVALID              # nodes of another box
     # equispaced nodes declared as a Q2 grid
     eq = P.tensor_velocity_grid(12, vg.L, 2)
