@@ -276,6 +276,40 @@ def run_q2(n_side, steps, warmup):
     return out
 
 
+def run_strip(steps, warmup):
+    """The 1D Sod strip (3072 P1 triangles, reflecting walls) with 192^2 Q2
+    velocities, nu = 1000, projected Maxwellian: whole backward-Euler steps
+    on the library's choice of sweep walk (the packed walk here) and on the
+    workgroup walk (64-thread workgroups, its best width on this mesh)."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    pr = P.sod_strip_problem(64, 1000.0)
+    out = {"workload": pr.name, "velocities": (3 * 64) ** 2, "cells": pr.mesh.n_cells}
+    for name, kw in (("auto", {}), ("workgroup_walk", {"sweep_threads": 64})):
+        d, f, bc, _ = B.problem_setup(pr, **kw)
+        walls = B.Walls(d, P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d)))
+        s = B.Solver(d, dt=P.SOD_STRIP_DT, bc_coef=bc, tau=1e-9, mode="PROJECTED",
+                     nu_const=1000.0, walls=walls, timing=True)
+        for _ in range(warmup):
+            s.step(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = [s.step(f) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sweeps = sum(x["sweeps"] for x in st)
+        n_unk = d.n_cells * d.n_p * d.n_v
+        out[name] = {"sweep_lanes": d.sweep_lanes, "ms_per_step": 1e3 * el / steps,
+                     "iters": [x["iters"] for x in st],
+                     "sweep_ms_avg": sum(x["sweep_ms"] for x in st) / sweeps,
+                     "value": n_unk * sweeps / el}
+        del s, f, walls, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_x3(cells, ref_cells, nus, tableaux, steps, tau, threads):
     """Projection against interpolation of the Maxwellian on the 1D Sod
     problem embedded in 2D (reflecting top and bottom walls, Q2 velocity
@@ -290,7 +324,7 @@ def run_x3(cells, ref_cells, nus, tableaux, steps, tau, threads):
 
     def solve(vc, nu, tab, mode):
         pr = P.sod_strip_problem(vc, nu, tab)
-        d, f, bc, _ = B.problem_setup(pr, sweep_threads=threads)
+        d, f, bc, _ = B.problem_setup(pr, **({"sweep_threads": threads} if threads else {}))
         walls = B.Walls(d, P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d)))
         s = B.Solver(d, dt=P.SOD_STRIP_DT, bc_coef=bc, tableau=tab, tau=tau, mode=mode,
                      nu_const=nu, walls=walls)
@@ -425,6 +459,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--no-strip", action="store_true",
+                    help="skip the narrow-generation strip (packed vs workgroup sweep walk)")
     ap.add_argument("--no-q2", action="store_true",
                     help="skip the Q2 velocity space (projected vs matched Maxwellian)")
     ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
@@ -436,7 +472,8 @@ def main():
     ap.add_argument("--x3-tableaux", default="BE,DIRK2")
     ap.add_argument("--x3-steps", type=int, default=85)
     ap.add_argument("--x3-tau", type=float, default=1e-6)
-    ap.add_argument("--x3-threads", type=int, default=64)
+    ap.add_argument("--x3-threads", type=int, default=0,
+                    help="workgroup walk of this width (0: the library's choice of walk)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -483,7 +520,12 @@ def main():
         print(f"[bench] {name}: " + report(out), file=sys.stderr, flush=True)
         return out
 
-    c3 = c4 = c5 = q2 = None
+    c3 = c4 = c5 = q2 = strip = None
+    if not args.no_strip:
+        strip = section("strip", lambda: run_strip(2, 1),
+                        lambda c: f"packed L={c['auto']['sweep_lanes']} "
+                                  f"{c['auto']['sweep_ms_avg']:.2f} ms/sweep vs workgroup walk "
+                                  f"{c['workgroup_walk']['sweep_ms_avg']:.2f} ms/sweep")
     if not args.no_q2:
         q2 = section("q2", lambda: run_q2(args.n_side, args.steps, args.warmup),
                      lambda c: f"PROJECTED {c['projected']['value']:.3e} unknowns/s "
@@ -535,6 +577,7 @@ def main():
         "c4_batched": c4,
         "c5_learned_guess": c5,
         "q2_projected": q2,
+        "strip_walks": strip,
     }
     print(json.dumps(line), flush=True)
 

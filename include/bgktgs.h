@@ -121,6 +121,17 @@ typedef struct {
      read from HBM after a workgroup fence: a small ring exercises that path
      on small meshes (tests); it never changes results. */
   int ring_slots;
+  /* Walk of the FP64 single-instance sweep (Sec. 4.1 names two: a thread per
+     velocity walking its whole graph, TS, and generation-parallel TGS).
+     1, 2, 4, 8, 16 or 32: the packed walk, a wavefront serving 64/L
+     velocities with L lanes each, every lane group stepping through its
+     velocity's generations L cells at a time (L = 1 is TS); 64: the
+     workgroup walk (a workgroup per velocity, sweep_threads wide); 0 = chosen
+     from the DAG: the packed walk with L the power of two nearest the mean
+     generation width when that is below 32, else the workgroup walk.  The
+     cell arithmetic is the same in both walks: results are bitwise equal.
+     The FP32 form and batched sweeps use the workgroup walk. */
+  int sweep_lanes;
 } tgs_dag_opts;
 
 typedef struct tgs_dag tgs_dag;
@@ -151,6 +162,9 @@ int tgs_dag_generations(const tgs_dag* dag, int32_t* gen, int32_t* G);
 
 /* Host output [n_v][n_cells] (user order) lagged-facet bitmasks. */
 int tgs_dag_lagged(const tgs_dag* dag, uint8_t* lagged);
+/* Lanes per velocity of the FP64 single-instance sweep (sweep_lanes as
+ * chosen at build: 1..32 = the packed walk, 64 = the workgroup walk). */
+int tgs_dag_sweep_lanes(const tgs_dag* dag);
 
 /* Host outputs (any may be NULL): node_x [n_cells][n_p][dim] node
  * coordinates, bnode_x [n_bfaces][n_fp][dim] boundary facet node

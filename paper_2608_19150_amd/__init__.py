@@ -41,6 +41,7 @@ EXPORTED = [
     "bgk_mlp_features", "bgk_mlp_targets", "bgk_mlp_guess",
     "bgk_batch_create", "bgk_batch_destroy", "bgk_batch_step", "bgk_batch_time_sweep",
     "tgs_walls_create", "tgs_walls_destroy", "tgs_walls_count", "tgs_wall_values",
+    "tgs_dag_sweep_lanes",
 ]
 
 
@@ -70,7 +71,8 @@ class VGridDesc(C.Structure):
 
 
 class DagOpts(C.Structure):
-    _fields_ = [("lagged", C.c_void_p), ("sweep_threads", C.c_int), ("ring_slots", C.c_int)]
+    _fields_ = [("lagged", C.c_void_p), ("sweep_threads", C.c_int), ("ring_slots", C.c_int),
+                ("sweep_lanes", C.c_int)]
 
 
 class SweepIO(C.Structure):
@@ -123,6 +125,7 @@ _lib.build_mesh_dag.argtypes = [C.POINTER(MeshDesc), C.POINTER(VGridDesc), C.POI
                                 C.c_void_p, C.POINTER(C.c_void_p)]
 _lib.tgs_dag_destroy.argtypes = [C.c_void_p]
 _lib.tgs_dag_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+_lib.tgs_dag_sweep_lanes.argtypes = [C.c_void_p]
 _lib.tgs_dag_generations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_dag_lagged.argtypes = [C.c_void_p, C.c_void_p]
 _lib.tgs_dag_geometry.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -145,7 +148,8 @@ class Dag:
     """Handle returned by build_mesh_dag (mesh geometry + per-velocity DAGs)."""
 
     def __init__(self, vert, cells, order, v, w, *, n_1d=0, nodes_1d=None, weights_1d=None,
-                 L=0.0, dg_cells=0, lagged=None, sweep_threads=0, ring_slots=0, stream=None):
+                 L=0.0, dg_cells=0, lagged=None, sweep_threads=0, ring_slots=0, sweep_lanes=0,
+                 stream=None):
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         v = np.ascontiguousarray(v, dtype=np.float64)
@@ -164,7 +168,7 @@ class Dag:
             lag = np.ascontiguousarray(lagged, dtype=np.uint8)
             self._keep.append(lag)
         opts = DagOpts(lag.ctypes.data if lag is not None else None, int(sweep_threads),
-                       int(ring_slots))
+                       int(ring_slots), int(sweep_lanes))
         h = C.c_void_p()
         _check(_lib.build_mesh_dag(C.byref(md), C.byref(vd), C.byref(opts), _stream(stream),
                                    C.byref(h)))
@@ -178,6 +182,7 @@ class Dag:
         self.w = torch.as_tensor(w)
         self.L = float(L)
         self.dg_cells = int(dg_cells)
+        self.sweep_lanes = int(_lib.tgs_dag_sweep_lanes(h))
 
     @classmethod
     def from_problem(cls, pr, **kw):

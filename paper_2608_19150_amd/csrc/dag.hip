@@ -537,10 +537,40 @@ void free_dag(tgs_dag* d) {
   if (!d) return;
   void* ptrs[] = {d->d_geo,  d->d_uid, d->d_facet, d->d_v,    d->d_w,    d->d_nodes1d,
                   d->d_weights1d, d->d_perm, d->d_pos, d->d_goff, d->d_gbase, d->d_G,
-                  d->d_lag, d->d_vorder, d->d_rec, d->d_recx, d->d_gmin};
+                  d->d_lag, d->d_vorder, d->d_rec, d->d_recx, d->d_gmin, d->d_vpack};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
+}
+
+// direction key of a velocity: the angle (2D), or the octant then two
+// angles (3D); sorting by it makes angular neighbours adjacent
+double velocity_key(const double* vj, int dim) {
+  if (dim == 2) return std::atan2(vj[1], vj[0]);
+  const int oct = (vj[0] < 0) * 4 + (vj[1] < 0) * 2 + (vj[2] < 0);
+  return oct * 10.0 + std::atan2(std::fabs(vj[1]), std::fabs(vj[0])) +
+         std::atan2(std::fabs(vj[2]), std::hypot(vj[0], vj[1]));
+}
+
+// Sorted positions 0..n-1 dealt to blocks: block b runs on XCD b % 8, and
+// sector x (positions [x n/8, (x+1) n/8)) goes to XCD x, so block b takes
+// the (b/8)-th position of sector b % 8 (sectors differ in size by at most
+// one: a full sector falls through to the next with room)
+std::vector<int32_t> deal_sectors(int n) {
+  constexpr int NX = 8;
+  std::vector<int32_t> out(n);
+  std::vector<int> used(NX, 0);
+  for (int b = 0; b < n; ++b) {
+    int x = b % NX;
+    int lo = (int)((int64_t)x * n / NX), hi = (int)((int64_t)(x + 1) * n / NX);
+    for (int t = 0; t < NX && lo + used[x] >= hi; ++t) {
+      x = (x + 1) % NX;
+      lo = (int)((int64_t)x * n / NX);
+      hi = (int)((int64_t)(x + 1) * n / NX);
+    }
+    out[b] = lo + used[x]++;
+  }
+  return out;
 }
 
 int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tgs_dag_opts* opts,
@@ -569,6 +599,11 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
               BGK_E_INVALID, "sweep_threads must be a multiple of 64 in [64, 256]");
     D->sweep_threads = opts->sweep_threads;
   }
+  const int lanes_opt = opts ? opts->sweep_lanes : 0;
+  BGK_CHECK(lanes_opt == 0 || (lanes_opt >= 1 && lanes_opt <= 64 && (lanes_opt & (lanes_opt - 1)) == 0),
+            BGK_E_INVALID, "sweep_lanes must be 0 or a power of two up to 64");
+  BGK_CHECK(!(opts && opts->sweep_threads && lanes_opt && lanes_opt < 64), BGK_E_INVALID,
+            "sweep_threads sets the workgroup walk; it cannot be combined with packed lanes");
   if (opts && opts->ring_slots) {
     const int r = opts->ring_slots;
     BGK_CHECK(r >= 16 && r <= 1024 && (r & (r - 1)) == 0, BGK_E_INVALID,
@@ -803,37 +838,48 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   std::vector<int32_t> vorder(nv);
   {
     std::vector<std::pair<double, int32_t>> key(nv);
-    for (int j = 0; j < nv; ++j) {
-      const double* vj = &D->v_host[(size_t)j * dim];
-      double k;
-      if (dim == 2) {
-        k = std::atan2(vj[1], vj[0]);
-      } else {
-        const int oct = (vj[0] < 0) * 4 + (vj[1] < 0) * 2 + (vj[2] < 0);
-        k = oct * 10.0 + std::atan2(std::fabs(vj[1]), std::fabs(vj[0])) +
-            std::atan2(std::fabs(vj[2]), std::hypot(vj[0], vj[1]));
-      }
-      key[j] = {k, j};
-    }
+    for (int j = 0; j < nv; ++j) key[j] = {velocity_key(&D->v_host[(size_t)j * dim], dim), j};
     std::stable_sort(key.begin(), key.end());
-    constexpr int NX = 8;
-    // sector x gets sorted positions [x*nv/NX, (x+1)*nv/NX); block b takes
-    // the (b/NX)-th velocity of sector b%NX
-    std::vector<int> used(NX, 0);
-    for (int b = 0; b < nv; ++b) {
-      int x = b % NX;
-      int lo = (int)((int64_t)x * nv / NX), hi = (int)((int64_t)(x + 1) * nv / NX);
-      // sectors can differ in size by one: fall through to the next with room
-      for (int t = 0; t < NX && lo + used[x] >= hi; ++t) {
-        x = (x + 1) % NX;
-        lo = (int)((int64_t)x * nv / NX);
-        hi = (int)((int64_t)(x + 1) * nv / NX);
-      }
-      vorder[b] = key[lo + used[x]++].second;
-    }
+    const std::vector<int32_t> pos = deal_sectors(nv);
+    for (int b = 0; b < nv; ++b) vorder[b] = key[pos[b]].second;
   }
   BGK_HIP(hipMemcpyAsync(D->d_vorder, vorder.data(), nv * sizeof(int32_t), hipMemcpyHostToDevice,
                          stream));
+  // packed walk: lanes per velocity from the mean generation width (or the
+  // caller's choice); a wavefront takes 64/L velocities that are angular
+  // neighbours (similar graphs, so its lane groups finish together), and the
+  // groups are dealt to the XCDs by sector like the workgroup walk's blocks
+  {
+    int lanes = lanes_opt;
+    if (lanes == 0 && !(opts && opts->sweep_threads)) {
+      double sumG = 0.0;
+      for (int j = 0; j < nv; ++j) sumG += D->G_host[j];
+      const double width = (double)nc * nv / std::max(sumG, 1.0);
+      lanes = 1;
+      while (lanes < 64 && lanes * 1.5 < width) lanes *= 2;
+      if (lanes >= 32) lanes = 64;
+    }
+    if (lanes == 0) lanes = 64;
+    D->sweep_lanes = lanes;
+    if (lanes < 64) {
+      const int vpb = 64 / lanes;
+      std::vector<std::pair<double, int32_t>> key(nv);
+      for (int j = 0; j < nv; ++j) key[j] = {velocity_key(&D->v_host[(size_t)j * dim], dim), j};
+      std::stable_sort(key.begin(), key.end());
+      const int ng = (nv + vpb - 1) / vpb;
+      const std::vector<int32_t> gorder = deal_sectors(ng);
+      D->vpack_blocks = ng;
+      std::vector<int32_t> vpack((size_t)ng * vpb, -1);
+      for (int b = 0; b < ng; ++b)
+        for (int t = 0; t < vpb; ++t) {
+          const int pos = gorder[b] * vpb + t;
+          if (pos < nv) vpack[(size_t)b * vpb + t] = key[pos].second;
+        }
+      if ((rc = dalloc(&D->d_vpack, vpack.size()))) return rc;
+      BGK_HIP(hipMemcpyAsync(D->d_vpack, vpack.data(), vpack.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, stream));
+    }
+  }
   BGK_HIP(hipStreamSynchronize(stream));
   return BGK_OK;
 }
@@ -916,6 +962,8 @@ extern "C" int tgs_dag_lagged(const tgs_dag* d, uint8_t* lagged) {
     for (int64_t i = 0; i < nc; ++i) lagged[(size_t)j * nc + d->uid_host[i]] = tmp[(size_t)j * nc + i];
   return BGK_OK;
 }
+
+extern "C" int tgs_dag_sweep_lanes(const tgs_dag* d) { return d ? d->sweep_lanes : 0; }
 
 extern "C" int tgs_dag_geometry(const tgs_dag* d, double* node_x, double* bnode_x, double* vol) {
   if (!d) return fail(BGK_E_INVALID, "null dag");

@@ -268,6 +268,7 @@ struct tgs_dag {
   int64_t n_lagged = 0;
   int sweep_threads = 0;   // 0: chosen per element type and precision
   int ring_slots = 0;      // 0: the element type's full LDS ring
+  int sweep_lanes = 64;    // lanes per velocity of the FP64 sweep; 64: workgroup walk
   // host copies
   std::vector<double> v_host, w_host;       // [n_v][dim], [n_v]
   int n_1d = 0;
@@ -298,6 +299,8 @@ struct tgs_dag {
   int32_t* d_G = nullptr;         // [n_v]
   uint8_t* d_lag = nullptr;       // [n_v][n_cells] lagged facet bits (internal), or null
   int32_t* d_vorder = nullptr;    // [n_v] velocity processed by sweep block b
+  int32_t* d_vpack = nullptr;     // packed walk: [blocks][64 / sweep_lanes] velocity or -1
+  int vpack_blocks = 0;
   // sweep item records, [n_v][n_cells][4] int32 per slot: 2D {K, c_0, c_1, c_2},
   // 3D {c_0, c_1, c_2, c_3} (K from d_perm); facet code c_k: -1 not an inflow
   // facet; >= 0 upwind neighbour's slot (bit 30 set when lagged); <= -2

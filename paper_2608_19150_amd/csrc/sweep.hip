@@ -27,6 +27,7 @@
 // flight across it.  Older upwind values are read from HBM after a full
 // workgroup fence, which runs only when the ring no longer covers the
 // generation's reach.
+#include <climits>
 #include <type_traits>
 
 #include "device_common.h"
@@ -360,7 +361,8 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
 }
 
 // FP64 solve of a prepared cell into rhs, which also goes to the LDS ring
-template <int DIM, int ORDER>
+// (RING; without it every upwind value is read from HBM)
+template <int DIM, int ORDER, bool RING = true>
 __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDER>& P, size_t base,
                                         int j, const double* v, double v2, double* ring,
                                         int rmask, int ring_lo,
@@ -386,19 +388,21 @@ __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDE
     }
   }
   lu_solve<NP, double>(A, rhs);
-  double* rg = ring + (P.s & rmask) * NP;
+  if constexpr (RING) {
+    double* rg = ring + (P.s & rmask) * NP;
 #pragma unroll
-  for (int b = 0; b < NP; ++b) rg[b] = rhs[b];
+    for (int b = 0; b < NP; ++b) rg[b] = rhs[b];
+  }
 }
 
 // FP64 solve of a prepared cell; the result goes to HBM and the LDS ring
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, bool RING = true>
 __device__ __forceinline__ void finish64(const SweepArgs& a, const Prep<DIM, ORDER>& P,
                                          size_t base, int j, const double* v, double v2,
                                          double* ring, int rmask, int ring_lo) {
   constexpr int NP = Elem<DIM, ORDER>::NP;
   double rhs[NP];
-  solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo, rhs);
+  solve64<DIM, ORDER, RING>(a, P, base, j, v, v2, ring, rmask, ring_lo, rhs);
   double* fo = a.f_out + (base + P.s) * NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) fo[b] = rhs[b];
@@ -706,6 +710,57 @@ __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep
   sweep_velocity<DIM, ORDER, F32, TAB, PIPE>(a, a.vorder[blockIdx.x], ring);
 }
 
+// Packed walk (FP64): a 64-lane workgroup serves 64/L velocities, lane
+// group t (lanes t L .. t L + L - 1) sweeping velocity vpack[block][t]
+// through its generations L cells per step.  Every group advances one
+// chunk per step; the stores of a step are made visible to the whole
+// workgroup before the next step, so a cell reads its upwind values (from
+// earlier generations, possibly written by other lanes of its group) from
+// memory.  L = 1 is a thread walking its velocity's whole graph in order.
+// Each cell is prepared and solved by the same code as in the workgroup
+// walk, so the results are bitwise equal.
+template <int DIM, int ORDER, bool TAB, int L>
+__global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
+  constexpr int NP = SweepCfg<DIM, ORDER>::NP, VPB = 64 / L;
+  const int lane = threadIdx.x, t = lane / L, r = lane - t * L;
+  const int jj = a.vorder[blockIdx.x * VPB + t];   // the packed order, -1: none
+  const int j = jj < 0 ? 0 : jj;
+  double v[DIM], v2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    v[d] = a.v[(size_t)j * DIM + d];
+    v2 = __fma_rn(v[d], v[d], v2);
+  }
+  const size_t base = (size_t)j * a.n_cells;
+  const int32_t* go = a.goff + a.gbase[j];
+  const int G = jj < 0 ? 0 : a.G[j];
+  const double* mrow[2] = {nullptr, nullptr};
+  if (a.mtab) {
+    const TabLayout TL(a.n_cells, a.n1, NP, DIM);
+    mrow[0] = a.mtab + TL.at(0, j / TL.nr, 0);
+    mrow[1] = a.mtab + TL.at(1, j % TL.nr, 0);
+  }
+  int g = 0, s = 0, e = G > 0 ? go[1] : 0;
+  while (__ballot(g < G)) {
+    if (g < G) {
+      if (s + r < e) {
+        Prep<DIM, ORDER> P;
+        P.s = s + r;
+        load_rec<DIM>(a, base, P.s, P.K, P.code, P.pack);
+        prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, P);
+        finish64<DIM, ORDER, false>(a, P, base, j, v, v2, nullptr, 0, INT_MAX);
+      }
+      s += L;
+      if (s >= e) {
+        ++g;
+        s = e;
+        if (g < G) e = go[g + 1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Batched FP64 sweep over many instances in one launch: block b sweeps
 // velocity map[b].y (a position in its instance's velocity order) of
 // instance map[b].x; instances flagged done skip.  2D instances may mix P1
@@ -776,6 +831,36 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
     // per CU resident, and wider generations take a second pass
     const bool small = d->dim == 2 && d->order == 1;
     threads = small ? 256 : 128;
+  }
+  if (!fp32 && d->sweep_lanes < 64) {
+    SweepArgs ap = a;
+    ap.vorder = d->d_vpack;
+    const dim3 pgrid(d->vpack_blocks), pblock(64);
+#define BGK_LANES(D_, O_, L_)                                                                \
+  if (mtab)                                                                                \
+    hipLaunchKernelGGL((k_sweep_lanes<D_, O_, true, L_>), pgrid, pblock, 0, stream, ap);   \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_sweep_lanes<D_, O_, false, L_>), pgrid, pblock, 0, stream, ap);
+#define BGK_LANES_L(D_, O_)   \
+  switch (d->sweep_lanes) {   \
+    case 1: BGK_LANES(D_, O_, 1) break;   \
+    case 2: BGK_LANES(D_, O_, 2) break;   \
+    case 4: BGK_LANES(D_, O_, 4) break;   \
+    case 8: BGK_LANES(D_, O_, 8) break;   \
+    case 16: BGK_LANES(D_, O_, 16) break; \
+    default: BGK_LANES(D_, O_, 32) break; \
+  }
+    if (d->dim == 2 && d->order == 1) {
+      BGK_LANES_L(2, 1)
+    } else if (d->dim == 2 && d->order == 2) {
+      BGK_LANES_L(2, 2)
+    } else {
+      BGK_LANES_L(3, 1)
+    }
+#undef BGK_LANES_L
+#undef BGK_LANES
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
   }
   const dim3 grid(d->n_v), block(threads);
   // FP64 sweeps take the pipelined walk (P1 triangles keep the plain walk:
