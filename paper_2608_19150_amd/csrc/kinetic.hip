@@ -757,11 +757,15 @@ int launch_nodal_rows(const tgs_dag* d, const double* src, double* dst, int row,
 }
 
 // velocity lanes per cell for the moment kernel: enough blocks to fill the chip
+// velocity lanes per cell: enough threads to cover the GPU's latency on
+// small meshes (a few thousand cells with tens of thousands of velocities
+// take 64 lanes per cell)
 int moment_vl(const tgs_dag* d) {
   const int64_t nc = d->n_cells;
   if (nc >= 65536) return 1;
   if (nc >= 16384) return 4;
-  return 16;
+  if (nc >= 4096 || d->n_v < 2048) return 16;
+  return 64;
 }
 
 int moment_blocks(const tgs_dag* d) {
@@ -781,7 +785,8 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
   do {                                                                                          \
     if (vl == 1) hipLaunchKernelGGL((k_moments<D_, P_, 1>), grid, block, 0, stream, a);   \
     else if (vl == 4) hipLaunchKernelGGL((k_moments<D_, P_, 4>), grid, block, 0, stream, a); \
-    else hipLaunchKernelGGL((k_moments<D_, P_, 16>), grid, block, 0, stream, a);          \
+    else if (vl == 16) hipLaunchKernelGGL((k_moments<D_, P_, 16>), grid, block, 0, stream, a); \
+    else hipLaunchKernelGGL((k_moments<D_, P_, 64>), grid, block, 0, stream, a);          \
   } while (0)
   if (d->dim == 2 && d->order == 1)
     BGK_MOM(2, 3);
@@ -881,8 +886,10 @@ __device__ __forceinline__ void moments_vl(const MomArgs& a, int vl, int blk, do
     moments_block<DIM, NP, 1>(a, blk, smem);
   else if (vl == 4)
     moments_block<DIM, NP, 4>(a, blk, smem);
-  else
+  else if (vl == 16)
     moments_block<DIM, NP, 16>(a, blk, smem);
+  else
+    moments_block<DIM, NP, 64>(a, blk, smem);
 }
 
 template <int DIM>
@@ -890,9 +897,11 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments_batch(
     const BatchKin* __restrict__ kin, const int32_t* __restrict__ par,
     const int32_t* __restrict__ done, const int32_t* __restrict__ first, int n_inst,
     int with_ratio) {
-  constexpr int SM = DIM == 2 ? MomSmem<2, 6, 16>::TOTAL : MomSmem<3, 4, 16>::TOTAL;
-  static_assert(DIM == 3 || (MomSmem<2, 3, 16>::TOTAL <= SM && MomSmem<2, 6, 4>::TOTAL <= SM),
+  constexpr int SM = DIM == 2 ? MomSmem<2, 6, 64>::TOTAL : MomSmem<3, 4, 64>::TOTAL;
+  static_assert(DIM == 3 || (MomSmem<2, 3, 64>::TOTAL <= SM && MomSmem<2, 6, 16>::TOTAL <= SM &&
+                             MomSmem<2, 6, 4>::TOTAL <= SM),
                 "moment scratch");
+  static_assert(DIM == 2 || MomSmem<3, 4, 16>::TOTAL <= SM, "moment scratch");
   __shared__ double smem[SM];
   const int i = find_instance<int32_t>(first, n_inst, (int32_t)blockIdx.x);
   if (done[i]) return;

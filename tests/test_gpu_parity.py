@@ -285,7 +285,9 @@ def test_sweep_with_lagged_facets_matches_oracle(dim, order):
     assert rel(f_gpu, f_ref) <= TOL64
 
 
-@pytest.mark.parametrize("dim,order,n_side,n1", CASES)
+# the last two: a few cells with thousands of velocities (64 velocity lanes
+# per cell in the moment kernel)
+@pytest.mark.parametrize("dim,order,n_side,n1", CASES + [(2, 2, 3, 48), (3, 1, 2, 14)])
 def test_moments_and_ratios_match_oracle(dim, order, n_side, n1):
     pr = _problem(dim, order, n_side, n1)
     d = B.Dag.from_problem(pr)
