@@ -384,37 +384,91 @@ __device__ void matched_system(const MaxwArgs& p, const double (&x)[DIM + 2],
 //   (1/w_k) * integral over I_c of g(x) l_k(x) dx,   g = exp(-(x-u)^2/(2 theta)),
 // where I_c is the cell except that the first cell extends to -infinity and
 // the last to +infinity (the extension E of the projection's definition).
-// Substituting x = u + sigma t (sigma^2 = theta) and writing the cell's
-// reference coordinate as y = alpha + beta t, the integrals of g y^m are
-// sigma times combinations of G_m = integral of t^m exp(-t^2/2) over
-// [t_a, t_b], m = 0, 1, 2: G_0 from erfc, G_1 = e_a - e_b, G_2 = G_0 +
-// t_a e_a - t_b e_b with e = exp(-t^2/2).  The reference nodes are xi = -s, 0, s with
-// s^2 = 3/5 and weights (h/2)(5/9, 8/9, 5/9); in monomials of y the basis
-// is l_0 = (y^2 - s y)/(2 s^2), l_1 = 1 - y^2/s^2, l_2 = (y^2 + s y)/(2 s^2).
-__device__ __forceinline__ double proj_node(double u, double sig, int i, int nc1, double L) {
+// With the cell's reference coordinate y (x = centre + (h/2) y) and the
+// basis in monomials of y (reference nodes -s, 0, s with s^2 = 3/5, weights
+// (h/2)(5/9, 8/9, 5/9)): l_0 = (y^2 - s y)/(2 s^2), l_1 = 1 - y^2/s^2,
+// l_2 = (y^2 + s y)/(2 s^2), so the three values follow from the cell
+// integrals m_k = integral of g y^k dx, k = 0, 1, 2.  Two evaluations of
+// m_k, both exact up to rounding:
+// * closed form: x = u + sigma t (sigma^2 = theta), y = alpha + beta t, and
+//   G_m = integral of t^m exp(-t^2/2) over [t_a, t_b] from erfc:
+//   G_0 = sqrt(pi/2) (A - B | B - A | 2 - A - B) with A = erfc(|t_a|/sqrt2),
+//   B = erfc(|t_b|/sqrt2) as both limits are >= 0, <= 0 or straddle 0;
+//   G_1 = e_a - e_b, G_2 = G_0 + t_a e_a - t_b e_b, e = exp(-t^2/2);
+// * quadrature: t = t_c + r (t_c the cell centre, r in [-d, d] with
+//   d = (h/2)/sigma): m_k = sigma beta^k exp(-t_c^2/2) K_k with
+//   K_k = integral over [-d, d] of r^k exp(-t_c r - r^2/2) dr by 20-point
+//   Gauss-Legendre, whose error for d <= 1 and |t_c| d <= 3 (an entire
+//   integrand) is far below rounding.
+// The closed form's expansion of (alpha + beta t)^2 cancels about
+// 12 alpha^2 ulp when the cell lies many half-widths from u on a fine grid;
+// the quadrature is used wherever it is exact (interior cells with d <= 1
+// and |t_c| d <= 3), the closed form elsewhere (the extended end cells,
+// cells wide against sigma).
+__device__ __forceinline__ void proj_cell(double u, double sig, int c, int nc1, double L,
+                                          double (&out)[3]) {
   constexpr double RT2 = 0.70710678118654752440;   // 1/sqrt(2)
   constexpr double SPI2 = 1.2533141373155002512;   // sqrt(pi/2)
   constexpr double S = 0.77459666924148337704;     // sqrt(3/5)
-  const int c = i / 3, k = i - 3 * c;
+  // the 10 positive nodes of 20-point Gauss-Legendre on [-1, 1] and weights
+  constexpr double GL[10][2] = {
+      {7.65265211334973383e-02, 1.52753387130725782e-01},
+      {2.27785851141645096e-01, 1.49172986472603658e-01},
+      {3.73706088715419549e-01, 1.42096109318381875e-01},
+      {5.10867001950827126e-01, 1.31688638449176526e-01},
+      {6.36053680726515025e-01, 1.18194531961518245e-01},
+      {7.46331906460150796e-01, 1.01930119817240261e-01},
+      {8.39116971822218782e-01, 8.32767415767046715e-02},
+      {9.12234428251325835e-01, 6.26720483341094425e-02},
+      {9.63971927277913809e-01, 4.06014298003862170e-02},
+      {9.93128599185094885e-01, 1.76140071391532732e-02}};
   const double hh = L / nc1;                       // half the cell width
   const double lo = -L + 2.0 * hh * c;
   const bool a_inf = c == 0, b_inf = c == nc1 - 1;
-  const double ta = (lo - u) / sig, tb = (lo + 2.0 * hh - u) / sig;
-  // with A = erfc(|t_a|/sqrt2), B = erfc(|t_b|/sqrt2) (0 at an infinite
-  // limit): G_0 / sqrt(pi/2) = A - B if 0 <= t_a, B - A if t_b <= 0, else
-  // 2 - A - B; no difference of nearly equal terms in any case
-  const double A = a_inf ? 0.0 : erfc(fabs(ta) * RT2);
-  const double B = b_inf ? 0.0 : erfc(fabs(tb) * RT2);
-  const double g0 = SPI2 * (!a_inf && ta >= 0.0 ? A - B : (!b_inf && tb <= 0.0 ? B - A : 2.0 - A - B));
-  const double ea = a_inf ? 0.0 : bgk_exp(-0.5 * ta * ta);
-  const double eb = b_inf ? 0.0 : bgk_exp(-0.5 * tb * tb);
-  const double g1 = ea - eb;
-  const double g2 = g0 + (a_inf ? 0.0 : ta * ea) - (b_inf ? 0.0 : tb * eb);
-  const double al = (u - (lo + hh)) / hh, be = sig / hh;
-  const double m1 = sig * fma(al, g0, be * g1);
-  const double m2 = sig * fma(al * al, g0, fma(2.0 * al * be, g1, be * be * g2));
-  if (k == 1) return (sig * g0 - m2 * (5.0 / 3.0)) / (hh * (8.0 / 9.0));
-  return (m2 + (k == 0 ? -S : S) * m1) * (5.0 / 6.0) / (hh * (5.0 / 9.0));
+  const double be = sig / hh, d = hh / sig;
+  const double tc = (lo + hh - u) / sig;
+  double m0, m1, m2;
+  if (!a_inf && !b_inf && d <= 1.0 && fabs(tc) * d <= 3.0) {
+    double k0 = 0.0, k1 = 0.0, k2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const double r = d * GL[q][0], w = d * GL[q][1];
+      const double ep = w * bgk_exp(-tc * r - 0.5 * r * r);    // at +r
+      const double em = w * bgk_exp(tc * r - 0.5 * r * r);     // at -r
+      k0 += ep + em;
+      k1 = fma(r, ep - em, k1);
+      k2 = fma(r * r, ep + em, k2);
+    }
+    const double sc = sig * bgk_exp(-0.5 * tc * tc);
+    m0 = sc * k0;
+    m1 = sc * be * k1;
+    m2 = sc * be * be * k2;
+  } else {
+    const double ta = (lo - u) / sig, tb = (lo + 2.0 * hh - u) / sig;
+    const double A = a_inf ? 0.0 : erfc(fabs(ta) * RT2);
+    const double B = b_inf ? 0.0 : erfc(fabs(tb) * RT2);
+    const double g0 =
+        SPI2 * (!a_inf && ta >= 0.0 ? A - B : (!b_inf && tb <= 0.0 ? B - A : 2.0 - A - B));
+    const double ea = a_inf ? 0.0 : bgk_exp(-0.5 * ta * ta);
+    const double eb = b_inf ? 0.0 : bgk_exp(-0.5 * tb * tb);
+    const double g1 = ea - eb;
+    const double g2 = g0 + (a_inf ? 0.0 : ta * ea) - (b_inf ? 0.0 : tb * eb);
+    const double al = (u - (lo + hh)) / hh;
+    m0 = sig * g0;
+    m1 = sig * fma(al, g0, be * g1);
+    m2 = sig * fma(al * al, g0, fma(2.0 * al * be, g1, be * be * g2));
+  }
+  out[0] = (m2 - S * m1) * (5.0 / 6.0) / (hh * (5.0 / 9.0));
+  out[1] = (m0 - m2 * (5.0 / 3.0)) / (hh * (8.0 / 9.0));
+  out[2] = (m2 + S * m1) * (5.0 / 6.0) / (hh * (5.0 / 9.0));
+}
+
+// value at 1-D node i = 3 c + k
+__device__ __forceinline__ double proj_node(double u, double sig, int i, int nc1, double L) {
+  const int c = i / 3, k = i - 3 * c;
+  double p[3];
+  proj_cell(u, sig, c, nc1, L, p);
+  return k == 0 ? p[0] : (k == 1 ? p[1] : p[2]);
 }
 
 template <int DIM>
@@ -453,26 +507,12 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
   if (p.nu) p.nu[i] = nu;
   if (p.numax && physical) atomicMax(p.numax, (unsigned long long)__double_as_longlong(nu));
   if (p.mode == BGK_MAXW_PROJECTED) {
-    // coefficients are the primitive variables; the values are products of
-    // per-axis projections times n (2 pi theta)^(-d/2)
+    // coefficients are the primitive variables (the values, if asked for,
+    // come from k_proj_dense)
     p.coef[i * NM] = n;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) p.coef[i * NM + 1 + d] = u[d];
     p.coef[i * NM + 1 + DIM] = th;
-    if (p.M_dense) {
-      const double sig = sqrt(th);
-      const double pref = n / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th));
-      for (int j = 0; j < p.n_v; ++j) {
-        int rem = j;
-        double val = pref;
-        for (int d = DIM - 1; d >= 0; --d) {
-          const int ia = rem % p.n1;
-          rem /= p.n1;
-          val *= proj_node(u[d], sig, ia, p.dg_cells, p.L);
-        }
-        p.M_dense[i * p.n_v + j] = val;
-      }
-    }
     return;
   }
   double x[NM];
@@ -544,6 +584,32 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
       }
       p.M_dense[i * p.n_v + j] = maxw_eval<DIM>(x, vv, v2);
     }
+  }
+}
+
+// Projected Maxwellian values at every (node, velocity) from the primitive
+// coefficients: n (2 pi theta)^(-d/2) times the product of the per-axis
+// projections at the velocity's tensor indices (first axis slowest)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_proj_dense(const double* __restrict__ prim,
+                                                    double* __restrict__ M, int64_t n_nodes,
+                                                    int n_v, int n1, int nc1, double L) {
+  constexpr int NM = DIM + 2;
+  const int64_t total = n_nodes * n_v;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = t / n_v;
+    const int j = (int)(t - node * n_v);
+    const double* P = prim + node * NM;
+    const double th = P[1 + DIM], sig = sqrt(th);
+    double val = P[0] / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th));
+    int rem = j;
+    for (int d = DIM - 1; d >= 0; --d) {
+      const int ia = rem % n1;
+      rem /= n1;
+      val *= proj_node(P[1 + d], sig, ia, nc1, L);
+    }
+    M[t] = val;
   }
 }
 
@@ -645,27 +711,31 @@ int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, d
 
 // Projected-Maxwellian tables.  Pass 1: the per-axis projections of every
 // node, pr[(a n1 + i) n_nodes + node] (axis 0 carrying n (2 pi theta)^(-d/2)),
-// one thread per (node, axis, 1-D velocity node), consecutive nodes on
-// consecutive threads.  Pass 2: the tables of the factorised layout from
-// them, as 16-byte chunks like the exponential tables: axis 0's entry of 1-D
-// node i0 paired with nu, the rest's entry pr_1[i1] (2D) or pr_1[i1] pr_2[i2]
-// (3D, row i1 n1 + i2).
+// one thread per (node, axis, velocity cell) writing the cell's 3 values,
+// consecutive nodes on consecutive threads.  Pass 2: the tables of the
+// factorised layout from them, as 16-byte chunks like the exponential
+// tables: axis 0's entry of 1-D node i0 paired with nu, the rest's entry
+// pr_1[i1] (2D) or pr_1[i1] pr_2[i2] (3D, row i1 n1 + i2).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_proj_axes(const double* __restrict__ prim, double* __restrict__ pr,
-                            int64_t n_nodes, int n1, int nc1, double L) {
+__global__ __launch_bounds__(256) void k_proj_axes(const double* __restrict__ prim,
+                                                   double* __restrict__ pr, int64_t n_nodes,
+                                                   int n1, int nc1, double L) {
   constexpr int NM = DIM + 2;
-  const int64_t total = (int64_t)DIM * n1 * n_nodes;
+  const int64_t total = (int64_t)DIM * nc1 * n_nodes;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t node = t % n_nodes;
-    const int ai = (int)(t / n_nodes);
-    const int a = ai / n1, i = ai - a * n1;
+    const int ac = (int)(t / n_nodes);
+    const int a = ac / nc1, c = ac - a * nc1;
     const double* P = prim + node * NM;
     const double th = P[1 + DIM];
-    double v = proj_node(P[1 + a], sqrt(th), i, nc1, L);
-    if (a == 0)
-      v *= P[0] / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th));
-    pr[t] = v;
+    double p[3];
+    proj_cell(P[1 + a], sqrt(th), c, nc1, L, p);
+    const double f =
+        a == 0 ? P[0] / (DIM == 2 ? 2.0 * M_PI * th : 2.0 * M_PI * th * sqrt(2.0 * M_PI * th))
+               : 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pr[((int64_t)a * n1 + 3 * c + k) * n_nodes + node] = p[k] * f;
   }
 }
 
@@ -705,7 +775,7 @@ int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, d
                        double* tab, hipStream_t stream) {
   BGK_CHECK(d->dg_cells > 0, BGK_E_INVALID, "projected tables need a Q2 velocity space");
   const int np = (int)(d->n_nodes / d->n_cells);
-  const int64_t n_pr = (int64_t)d->dim * d->n_1d * d->n_nodes;
+  const int64_t n_pr = (int64_t)d->dim * d->dg_cells * d->n_nodes;
   const int64_t total = table_chunks(d->dim, d->n_cells, d->n_1d, np);
   const int g1 = (int)std::min<int64_t>((n_pr + 255) / 256, 65536);
   const int g2 = (int)std::min<int64_t>((total + 255) / 256, 65536);
@@ -824,6 +894,17 @@ int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_
   else
     hipLaunchKernelGGL(k_maxwellian<3>, grid, block, 0, stream, p);
   BGK_HIP(hipGetLastError());
+  if (mode == BGK_MAXW_PROJECTED && M_dense) {
+    const int64_t total = d->n_nodes * d->n_v;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    if (d->dim == 2)
+      hipLaunchKernelGGL(k_proj_dense<2>, dim3(g), dim3(256), 0, stream, coef, M_dense,
+                         d->n_nodes, d->n_v, d->n_1d, d->dg_cells, d->L);
+    else
+      hipLaunchKernelGGL(k_proj_dense<3>, dim3(g), dim3(256), 0, stream, coef, M_dense,
+                         d->n_nodes, d->n_v, d->n_1d, d->dg_cells, d->L);
+    BGK_HIP(hipGetLastError());
+  }
   return BGK_OK;
 }
 

@@ -189,3 +189,48 @@ def test_full_size_projected_step_matches_oracle_on_sampled_velocities(vcells):
     g = solver.boundary_values(geo, V, pr.state)
     f_ref = transport.sweep(geo, V, nu + 1.0 / dt, nu, Mv, f0 / dt, g, gens)
     assert rel(f_s, f_ref) <= TOL64
+
+
+def test_strip_full_size_packed_walk_step_matches_oracle_on_sampled_velocities():
+    """The narrow-generation strip as benchmarked: 3072 P1 triangles, 192^2
+    Q2 velocities (the packed walk the library chooses), reflecting walls,
+    projected Maxwellian, nu = 1000: one Picard iteration of a backward-Euler
+    step from seeded moments.  The oracle recomputes sampled velocities: the
+    walls' data come from the initial state at the mirrored velocities (the
+    sample is closed under the mirror, so the oracle's wall update runs on
+    it directly)."""
+    from oracle import walls as owalls
+    pr = P.sod_strip_problem(64, 1000.0)
+    d, f, bc, _ = B.problem_setup(pr)
+    assert d.sweep_lanes < 64 and d.n_v == 192 * 192
+    kinds = P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d))
+    _, prim = _nodal_inputs(d.n_nodes, 2, 9400)
+    n, u, th = prim[:, 0], prim[:, 1:-1], prim[:, -1]
+    Um = np.concatenate([n[:, None], n[:, None] * u,
+                         (0.5 * n * (2 * th + np.sum(u * u, axis=1)))[:, None]], axis=1)
+    dt = P.SOD_STRIP_DT
+    s = B.Solver(d, dt=dt, bc_coef=bc, walls=B.Walls(d, kinds), fixed_iters=1, mode="PROJECTED",
+                 nu_const=1000.0)
+    assert s.step(f, U_guess=B._dev(Um))["iters"] == [1]
+    n1 = 192
+    base = np.array([0, 5 * n1 + 17, 96 * n1 + 40, 130 * n1 + 150, n1 * n1 - 1])
+    mirror = (base // n1) * n1 + (n1 - 1 - base % n1)        # v_2 -> -v_2
+    js = np.unique(np.concatenate([base, mirror]))
+    f_s = d.unpack(f)[..., torch.as_tensor(js, device="cuda")].cpu().numpy()
+    del s, f, bc, d
+    _release()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, 1)
+    V = pr.vgrid.v[js]
+    okinds = owalls.boundary_kinds(geo, lambda x, nrm: owalls.REFLECT if abs(nrm[1]) > 0.5 else
+                                   owalls.INFLOW)
+    np.testing.assert_array_equal(okinds, kinds)
+    gens, lags = odag.build_all(geo, V)
+    f0 = solver.initial_condition(geo, V, pr.state)
+    g = owalls.wall_values(geo, V, f0, okinds, solver.boundary_values(geo, V, pr.state))
+    p0 = velocity.project_gaussian_1d(u[:, 0], th, 64, 7.0)
+    p1 = velocity.project_gaussian_1d(u[:, 1], th, 64, 7.0)
+    Mv = ((n / (2.0 * np.pi * th))[:, None] * p0[:, js // n1] * p1[:, js % n1])
+    Mv = Mv.reshape(geo.n_cells, geo.n_p, -1)
+    nu = np.full((geo.n_cells, geo.n_p), 1000.0)
+    f_ref = transport.sweep(geo, V, nu + 1.0 / dt, nu, Mv, f0 / dt, g, gens, lags)
+    assert rel(f_s, f_ref) <= TOL64

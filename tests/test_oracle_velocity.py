@@ -92,3 +92,35 @@ def test_projected_maxwellian_moments_are_exact(dim):
 def test_centred_projection_is_symmetric():
     p = velocity.project_gaussian_1d(0.0, 1.1, 8, 6.0)
     np.testing.assert_allclose(p, p[::-1], rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("u,theta", [(0.3, 0.7), (-1.1, 1.4)])
+def test_projection_1d_relative_accuracy_on_a_fine_grid(u, theta):
+    """64 cells on [-7, 7] (the Sod strip's reference grid): every value, also
+    many half-cells from u where the closed form's expansion cancels, equals
+    adaptive quadrature of its defining integral to 1e-13 of itself."""
+    n_cells, L = 64, 7.0
+    p = velocity.project_gaussian_1d(u, theta, n_cells, L)
+    x, w = velocity.grid_1d(n_cells, L)
+    h = 2 * L / n_cells
+    xi, _ = velocity.gl_reference()
+    g = lambda t: math.exp(-(t - u) ** 2 / (2 * theta))  # noqa: E731
+    checked = 0
+    for c in range(1, n_cells - 1):
+        lo, hi, centre = -L + c * h, -L + (c + 1) * h, -L + (c + 0.5) * h
+        if abs(centre - u) > 5.0 * math.sqrt(theta):
+            continue
+        for i in range(3):
+            others = [m for m in range(3) if m != i]
+
+            def ell(t, i=i, others=others):
+                y = (t - centre) / (0.5 * h)
+                r = 1.0
+                for m in others:
+                    r *= (y - xi[m]) / (xi[i] - xi[m])
+                return r
+            val = integrate.quad(lambda t: g(t) * ell(t), lo, hi, epsabs=0.0, epsrel=1.2e-14,
+                                 limit=200)[0] / w[3 * c + i]
+            assert abs(p[3 * c + i] - val) <= 1e-13 * abs(val), (c, i, p[3 * c + i], val)
+            checked += 1
+    assert checked > 100
