@@ -128,7 +128,8 @@ typedef struct {
      velocity's generations L cells at a time (L = 1 is TS); 64: the
      workgroup walk (a workgroup per velocity, sweep_threads wide); 0 = chosen
      from the DAG: the packed walk with L the power of two nearest the mean
-     generation width when that is below 32, else the workgroup walk.  The
+     generation width when that is below 32, raised (up to 32) until the
+     launch has 1024 wavefronts, else the workgroup walk.  The
      cell arithmetic is the same in both walks: results are bitwise equal.
      The FP32 form and batched sweeps use the workgroup walk. */
   int sweep_lanes;

@@ -855,9 +855,13 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
       double sumG = 0.0;
       for (int j = 0; j < nv; ++j) sumG += D->G_host[j];
       const double width = (double)nc * nv / std::max(sumG, 1.0);
-      lanes = 1;
-      while (lanes < 64 && lanes * 1.5 < width) lanes *= 2;
-      if (lanes >= 32) lanes = 64;
+      int l0 = 1;
+      while (l0 < 64 && l0 * 1.5 < width) l0 *= 2;
+      // enough wavefronts to fill the GPU (4 per CU): fewer velocities per
+      // wavefront when there are few velocities
+      lanes = l0;
+      while (lanes < 32 && (double)nv * lanes / 64 < 1024) lanes *= 2;
+      if (l0 >= 32 || (double)nv * lanes / 64 < 1024) lanes = 64;
     }
     if (lanes == 0) lanes = 64;
     D->sweep_lanes = lanes;

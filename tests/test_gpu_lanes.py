@@ -86,10 +86,12 @@ def test_packed_walk_equals_workgroup_walk_and_oracle(dim, order, n_side, n1, te
 
 
 def test_automatic_walk_choice():
-    # narrow generations (a 256 x 6 strip): packed; the 2D workload's mesh
-    # (hundreds of cells per generation): the workgroup walk
-    strip = P.sod_strip_problem(2, 1.0)
-    assert B.Dag.from_problem(strip).sweep_lanes < 32
+    # narrow generations (a 256 x 6 strip) with many velocities: packed; the
+    # same strip with too few velocities to fill the GPU that way, and a
+    # mesh with wide generations: the workgroup walk
+    strip = P.sod_strip_problem(32, 1.0)
+    assert B.Dag.from_problem(strip).sweep_lanes == 8
+    assert B.Dag.from_problem(P.sod_strip_problem(4, 1.0)).sweep_lanes == 64
     wide = P.Problem(P.jittered_square_mesh(60, 0.25, 3), 1, P.tensor_velocity_grid(4, 3.0, 2),
                      P.sod_state(2))
     assert B.Dag.from_problem(wide).sweep_lanes == 64
