@@ -310,6 +310,56 @@ def run_strip(steps, warmup):
     return out
 
 
+def run_x7(steps):
+    """Linear stability study (the paper's 2D Sod test of the stability
+    proposition): a Sod state in a closed reflecting box, where the boundary
+    terms of the L2 estimate cancel exactly, stepped by every tableau for
+    streaming (nu = 0), the linear Maxwellian (nu = 1000) and nonlinear BGK
+    (MATCHED, nu = 1000).  Reports the change of the L2(X x V) norm per step
+    (P1 mass matrix, quadrature weights)."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    mesh = P.jittered_square_mesh(32, 0.25, 7700)
+    pr = P.Problem(mesh, 1, P.tensor_velocity_grid(24, 7.0, 2),
+                   P.planar_riemann_state(2, 7701, width=1.5 / 32))
+    d, f0, bc, dt = B.problem_setup(pr)
+    walls = B.Walls(d, np.full(d.n_bfaces, 2, dtype=np.int8))
+    vol = d.geometry()[2]
+    w = pr.vgrid.w
+
+    def norm2(f):
+        fc = d.unpack(f).cpu().numpy()                         # [cell][3][v]
+        s1 = np.einsum("cpj,j->cp", fc * fc, w).sum(1)
+        s2 = np.einsum("cj,j->c", fc.sum(1) ** 2, w)
+        return float(np.sum(vol / 12.0 * (s1 + s2)))
+
+    out = {"setup": {"cells": d.n_cells, "velocities": d.n_v, "steps": steps, "dt": dt,
+                     "walls": "reflection on every side"}, "runs": []}
+    for model, mode, nu in (("streaming", "MATCHED", 0.0), ("linear", "LINEAR", 1000.0),
+                            ("nonlinear", "MATCHED", 1000.0)):
+        for tab in ("BE", "DIRK2", "DIRK3", "BDIRK2"):
+            f = f0.clone()
+            s = B.Solver(d, dt=dt, bc_coef=bc, tableau=tab, tau=1e-12, mode=mode,
+                         nu_const=nu, walls=walls)
+            n = [norm2(f)]
+            for _ in range(steps):
+                s.step(f)
+                n.append(norm2(f))
+            dn = np.diff(n)
+            out["runs"].append({"model": model, "tableau": tab, "norm0": n[0],
+                                "max_increase_rel": float(max(dn.max(), 0.0) / n[0]),
+                                "monotone": bool((dn <= 1e-13 * n[0]).all()),
+                                "dnorm": [float(x) for x in dn]})
+            print(f"[x7] {model} {tab}: monotone {out['runs'][-1]['monotone']}, "
+                  f"total change {(n[-1] - n[0]) / n[0]:.3e}", file=sys.stderr, flush=True)
+            del s, f
+    del d, f0, walls
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_x3(cells, ref_cells, nus, tableaux, steps, tau, threads):
     """Projection against interpolation of the Maxwellian on the 1D Sod
     problem embedded in 2D (reflecting top and bottom walls, Q2 velocity
@@ -464,6 +514,9 @@ def main():
     ap.add_argument("--no-q2", action="store_true",
                     help="skip the Q2 velocity space (projected vs matched Maxwellian)")
     ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
+    ap.add_argument("--x7", action="store_true",
+                    help="only run the L2-stability study in a reflecting box")
+    ap.add_argument("--x7-steps", type=int, default=40)
     ap.add_argument("--x3", action="store_true",
                     help="only run the projection-vs-interpolation study on the 1D Sod strip")
     ap.add_argument("--x3-cells", default="4,8,16,32")
@@ -482,6 +535,10 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.x7:
+        res = run_x7(args.x7_steps)
+        print(json.dumps({"study": "l2_stability_reflecting_box", **res}), flush=True)
         return
     if args.x3:
         res = run_x3([int(x) for x in args.x3_cells.split(",")], args.x3_ref,

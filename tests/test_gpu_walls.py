@@ -167,3 +167,30 @@ def test_walls_validation():
     assert code(lambda: B.Solver(d2, dt=dt, bc_coef=bc, walls=other)) == B.BGK_E_INVALID
     s = B.Solver(d2, dt=dt, bc_coef=bc, walls=B.Walls(d2, good))
     assert code(lambda: B.Batch([s])) == B.BGK_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode,nu,tableau", [("MATCHED", 0.0, "BE"), ("LINEAR", 50.0, "BE"),
+                                             ("LINEAR", 50.0, "BDIRK2"),
+                                             ("MATCHED", 0.0, "BDIRK2")])
+def test_l2_norm_does_not_grow_in_a_reflecting_box_on_gpu(mode, nu, tableau):
+    """Prop. linear stability: in a closed reflecting box the boundary terms
+    cancel, so B-stable steps of streaming or the linear Maxwellian do not
+    increase the phase-space L2 norm."""
+    pr = P.Problem(P.jittered_square_mesh(8, 0.25, 9), 1, P.tensor_velocity_grid(10, 5.0, 2),
+                   P.planar_riemann_state(2, 13, width=0.2))
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, 1)
+    d, f, bc, dt = B.problem_setup(pr)
+    s = B.Solver(d, dt=dt, bc_coef=bc, tableau=tableau, tau=1e-13, mode=mode, nu_const=nu,
+                 walls=B.Walls(d, np.full(d.n_bfaces, owalls.REFLECT, dtype=np.int8)))
+    w = pr.vgrid.w
+
+    def norm():
+        fc = d.unpack(f).cpu().numpy()
+        return np.einsum("c,cpj,pq,cqj,j->", geo.vol, fc, geo.ref["mass"], fc, w)
+
+    prev = norm()
+    for _ in range(4):
+        s.step(f)
+        cur = norm()
+        assert cur <= prev * (1 + 1e-12)
+        prev = cur

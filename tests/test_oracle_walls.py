@@ -10,6 +10,8 @@
   steady state (its reflection is itself); one drifting across them is not.
 * A closed box (walls only) conserves total mass and energy over converged
   steps, for reflection, bounce-back and a mix, in 2D and 3D.
+* In a reflecting box the phase-space L2 norm does not grow under B-stable
+  schemes for streaming and the linear Maxwellian (Prop. linear stability).
 """
 import numpy as np
 import pytest
@@ -127,3 +129,30 @@ def test_closed_box_conserves_mass_and_energy(dim, scheme, rule):
     assert abs(t1[-1] - t0[-1]) <= 1e-10 * t0[-1]              # energy
     # momentum is not conserved: the walls push back
     assert np.abs(t1[1:-1] - t0[1:-1]).max() > 1e-6 * t0[0]
+
+
+@pytest.mark.parametrize("mode,nu,scheme", [("MATCHED", 0.0, "BE"), ("LINEAR", 5.0, "BE"),
+                                            ("LINEAR", 5.0, "BDIRK2"), ("MATCHED", 0.0, "BDIRK2")])
+def test_l2_norm_does_not_grow_in_a_reflecting_box(mode, nu, scheme):
+    """Prop. linear stability with walls: specular reflection returns through
+    the boundary exactly the |v.n| f^2 that leaves (the velocity set is
+    closed under the map, with equal weights), so for streaming (nu = 0) or
+    the linear Maxwellian a B-stable scheme cannot increase the phase-space
+    L2 norm."""
+    geo, _ = _box(2, 1, 3)
+    vg = P.tensor_velocity_grid(8, 4.0, 2)
+    V, w = vg.v, vg.w
+    st = P.planar_riemann_state(2, 12, width=0.3)
+    kinds = np.full(geo.bnode_x.shape[0], walls.REFLECT, dtype=np.int8)
+    gens, lags = dag.build_all(geo, V)
+    f = solver.initial_condition(geo, V, st)
+    g = solver.boundary_values(geo, V, st)
+    dt = solver.explicit_dt(geo, V, 10.0)
+    norm = lambda f: np.einsum("c,cpj,pq,cqj,j->", geo.vol, f, geo.ref["mass"], f, w)  # noqa: E731
+    prev = norm(f)
+    for _ in range(3):
+        f, _ = solver.bgk_step(geo, V, w, f, g, dt, gens, lags, scheme=scheme, mode=mode,
+                               nu_const=nu, L=vg.L, tau=1e-13, walls=kinds)
+        cur = norm(f)
+        assert cur <= prev * (1 + 1e-12)
+        prev = cur
