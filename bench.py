@@ -310,6 +310,57 @@ def run_strip(steps, warmup):
     return out
 
 
+def duct_setup(pr):
+    """DAG, walls, boundary coefficients and initial f of the duct."""
+    import paper_2608_19150_amd as B
+    import problems as P
+    d = B.Dag.from_problem(pr)
+    kinds, prim = P.duct_boundary(B.boundary_facet_midpoints(d))
+    walls = B.Walls(d, kinds)
+    bc = B.maxwellian_coef_from_primitive(B._dev(np.repeat(prim, d.n_fp, axis=0)), 3)
+    f = d.eval_maxwellian(B.state_coefficients(d, pr.state, "nodes"))
+    return d, walls, bc, f
+
+
+def run_duct(steps, warmup):
+    """The duct at one GPU's scale: 10,523 P1 tetrahedra x 48^3 = 110,592 Q2
+    velocities (4.7e9 unknowns), bounce-back and reflecting walls,
+    Maxwellian and zero inflow, projected Maxwellian, nu = 1, backward Euler
+    with dt = 5e-3."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    pr = P.duct_problem()
+    t0 = time.perf_counter()
+    d, walls, bc, f = duct_setup(pr)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    s = B.Solver(d, dt=P.DUCT_DT, bc_coef=bc, tau=1e-8, mode="PROJECTED", nu_const=pr.nu_const,
+                 walls=walls, timing=True)
+    free, total = torch.cuda.mem_get_info()
+    for _ in range(warmup):
+        s.step(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = [s.step(f) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sweeps = sum(x["sweeps"] for x in st)
+    n_unk = d.n_cells * d.n_p * d.n_v
+    out = {"workload": pr.name, "cells": d.n_cells, "velocities": d.n_v, "unknowns": n_unk,
+           "max_generations": d.max_G, "sweep_lanes": d.sweep_lanes, "setup_s": setup_s,
+           "ms_per_step": 1e3 * el / steps, "iters": [x["iters"] for x in st],
+           "value": n_unk * sweeps / el,
+           "kernel_ms": {"sweep": sum(x["sweep_ms"] for x in st) / sweeps,
+                         "moments": sum(x["moments_ms"] for x in st) / sweeps,
+                         "maxwellian": sum(x["maxwellian_ms"] for x in st) / sweeps},
+           "device_memory_in_use_gb": (total - free) / 1e9}
+    del s, f, walls, bc, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_x7(steps):
     """Linear stability study (the paper's 2D Sod test of the stability
     proposition): a Sod state in a closed reflecting box, where the boundary
@@ -509,6 +560,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--no-duct", action="store_true",
+                    help="skip the duct (3D walls, 110,592 Q2 velocities)")
     ap.add_argument("--no-strip", action="store_true",
                     help="skip the narrow-generation strip (packed vs workgroup sweep walk)")
     ap.add_argument("--no-q2", action="store_true",
@@ -577,7 +630,11 @@ def main():
         print(f"[bench] {name}: " + report(out), file=sys.stderr, flush=True)
         return out
 
-    c3 = c4 = c5 = q2 = strip = None
+    c3 = c4 = c5 = q2 = strip = duct = None
+    if not args.no_duct:
+        duct = section("duct", lambda: run_duct(1, 1),
+                       lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.0f} ms/step, "
+                                 f"iters {c['iters']}, sweep {c['kernel_ms']['sweep']:.1f} ms")
     if not args.no_strip:
         strip = section("strip", lambda: run_strip(2, 1),
                         lambda c: f"packed L={c['auto']['sweep_lanes']} "
@@ -635,6 +692,7 @@ def main():
         "c5_learned_guess": c5,
         "q2_projected": q2,
         "strip_walks": strip,
+        "duct": duct,
     }
     print(json.dumps(line), flush=True)
 

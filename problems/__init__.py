@@ -243,6 +243,25 @@ def jittered_cube_mesh(n_side: int, jitter: float, seed: int) -> Mesh:
     return Mesh(pts, cells)
 
 
+def jittered_box_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float,
+                      jitter: float, seed: int) -> Mesh:
+    """(nx+1) x (ny+1) x (nz+1) lattice on [0,lx] x [0,ly] x [0,lz] with
+    spacings lx/nx, ly/ny, lz/nz; interior points jittered in all directions,
+    boundary points only tangentially (the faces stay exact), then
+    Delaunay."""
+    rng = np.random.default_rng(seed)
+    L = np.array([lx, ly, lz])
+    n = np.array([nx, ny, nz])
+    h = L / n
+    axes = [np.linspace(0.0, L[a], n[a] + 1) for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    free = (pts > 0) & (pts < L[None, :])
+    pts = pts + np.where(free, rng.uniform(-1.0, 1.0, size=pts.shape) * jitter * h[None, :], 0.0)
+    cells = _drop_degenerate(pts, _delaunay(pts))
+    return Mesh(pts, cells)
+
+
 # ----------------------------------------------------------------------------
 # velocity grids
 # ----------------------------------------------------------------------------
@@ -380,6 +399,55 @@ def config_c2_q2(n_side: int = 316, vcells: int = 10) -> Problem:
                    nu_model=base.nu_model, kn=base.kn, tableau=base.tableau, cfl=base.cfl,
                    n_steps=base.n_steps, tau=base.tau,
                    name=f"c2_fourier_p2_{2 * n_side * n_side}tri_q2_{3 * vcells}x{3 * vcells}")
+
+
+DUCT = (0.3, 0.1, 0.1)
+
+
+def duct_problem(vcells: int = 16, nu: float = 1.0, lattice=(24, 8, 8)) -> Problem:
+    """The paper's duct (Sec. 5.3) at one GPU's scale: [0, 0.3] x [0, 0.1] x
+    [0, 0.1] as a jittered lattice (24 x 8 x 8 cells of 0.0125, Delaunay
+    tetrahedra, P1; the paper's meshes are graded, clustered at the walls
+    and far larger), initial Maxwellian (1, 0, 1) except near the inlet
+    (below), Q2 velocity space on [-12, 12]^3 with vcells cells per axis
+    (16: 110,592 velocities, the paper's count for its collisional case),
+    constant nu = 1 (its transition regime), backward Euler with DUCT_DT.
+    On this mesh the layers at the inlet and the walls have the width
+    |v| / (1/dt + nu), far below a cell at the paper's dt = 1e-3 or
+    nu = 1000, and the method (no limiter) then produces non-physical nodal
+    moments; dt = 5e-3 with nu = 1 stays physical.  Boundary data:
+    duct_boundary."""
+    mesh = jittered_box_mesh(*lattice, *DUCT, 0.2, 8000)
+    # the inflow (1, (2, 0, 0), 1) ramps down to the gas at rest over a tanh
+    # layer 1.5 lattice cells wide centred 3 such widths from the inlet, so
+    # the data at the inlet agree with the inflow: a jump there is a boundary
+    # layer far thinner than a cell (|v|/(1/dt + nu) << h), which P1 cannot
+    # resolve without non-physical nodal moments
+    w = 1.5 * DUCT[0] / lattice[0]
+    st = State("plane", {"normal": np.array([1.0, 0.0, 0.0]), "center": np.array([3 * w, 0, 0]),
+                         "left": (1.0, (2.0, 0.0, 0.0), 1.0), "right": (1.0, (0.0, 0.0, 0.0), 1.0),
+                         "width": w})
+    return Problem(mesh, 1, gl_velocity_grid(vcells, 12.0, 3), st, nu_model="const",
+                   nu_const=nu, tableau="BE", name=f"duct_q2_{vcells}")
+
+
+DUCT_DT = 5e-3
+
+
+def duct_boundary(facet_midpoints: np.ndarray):
+    """Per boundary facet: kind (0 inflow, 1 bounce-back on the x_2 walls,
+    2 reflection on the x_3 walls) and the inflow state's (n, u, theta) with
+    n = 0 meaning zero inflow: Maxwellian (1, (2, 0, 0), 1) at x_1 = 0, zero
+    at x_1 = 0.3."""
+    x = facet_midpoints
+    tol = 1e-12
+    kinds = np.zeros(x.shape[0], dtype=np.int8)
+    kinds[(np.abs(x[:, 1]) < tol) | (np.abs(x[:, 1] - DUCT[1]) < tol)] = 1
+    kinds[(np.abs(x[:, 2]) < tol) | (np.abs(x[:, 2] - DUCT[2]) < tol)] = 2
+    left = np.abs(x[:, 0]) < tol
+    prim = np.tile(np.array([0.0, 0.0, 0.0, 0.0, 1.0]), (x.shape[0], 1))
+    prim[left] = [1.0, 2.0, 0.0, 0.0, 1.0]
+    return kinds, prim
 
 
 SOD_STRIP_HALF_HEIGHT = 3.0 / 128.0

@@ -231,6 +231,60 @@ def test_strip_full_size_packed_walk_step_matches_oracle_on_sampled_velocities()
     p1 = velocity.project_gaussian_1d(u[:, 1], th, 64, 7.0)
     Mv = ((n / (2.0 * np.pi * th))[:, None] * p0[:, js // n1] * p1[:, js % n1])
     Mv = Mv.reshape(geo.n_cells, geo.n_p, -1)
-    nu = np.full((geo.n_cells, geo.n_p), 1000.0)
+    nu = np.full((geo.n_cells, geo.n_p), pr.nu_const)
+    f_ref = transport.sweep(geo, V, nu + 1.0 / dt, nu, Mv, f0 / dt, g, gens, lags)
+    assert rel(f_s, f_ref) <= TOL64
+
+
+def test_duct_full_size_step_matches_oracle_on_sampled_velocities():
+    """The duct as benchmarked: 10,523 P1 tetrahedra x 48^3 = 110,592 Q2
+    velocities, bounce-back (x_2) and reflecting (x_3) walls, Maxwellian and
+    zero inflow, projected Maxwellian, nu = 1: one Picard iteration of a
+    backward-Euler step from seeded moments.  The sample is closed under
+    both wall maps (v -> -v and v_3 -> -v_3), so the oracle's wall update
+    runs on it directly."""
+    from oracle import walls as owalls
+
+    import bench
+    pr = P.duct_problem()
+    d, walls, bc, f = bench.duct_setup(pr)
+    assert d.n_v == 110592
+    _, prim = _nodal_inputs(d.n_nodes, 3, 9500)
+    n, u, th = prim[:, 0], prim[:, 1:-1], prim[:, -1]
+    Um = np.concatenate([n[:, None], n[:, None] * u,
+                         (0.5 * n * (3 * th + np.sum(u * u, axis=1)))[:, None]], axis=1)
+    dt = P.DUCT_DT
+    s = B.Solver(d, dt=dt, bc_coef=bc, walls=walls, fixed_iters=1, mode="PROJECTED",
+                 nu_const=pr.nu_const)
+    assert s.step(f, U_guess=B._dev(Um))["iters"] == [1]
+    del s
+    _release()
+    n1 = 48
+    base = np.array([[0, 0, 0], [24, 23, 24], [30, 10, 40], [5, 33, 17], [47, 20, 26]])
+    imgs = [base, n1 - 1 - base, np.stack([base[:, 0], base[:, 1], n1 - 1 - base[:, 2]], 1),
+            np.stack([n1 - 1 - base[:, 0], n1 - 1 - base[:, 1], base[:, 2]], 1)]
+    idx = np.unique(np.concatenate(imgs), axis=0)
+    js = np.ravel_multi_index(idx.T, (n1, n1, n1))
+    f_s = d.unpack(f)[..., torch.as_tensor(js, device="cuda")].cpu().numpy()
+    kinds, bprim = P.duct_boundary(B.boundary_facet_midpoints(d))
+    del f, bc, walls, d
+    _release()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, 1)
+    V = pr.vgrid.v[js]
+    gens, lags = odag.build_all(geo, V)
+    f0 = solver.initial_condition(geo, V, pr.state)
+    # inflow data: Maxwellian of each boundary facet's state (n = 0: none)
+    bx = geo.bnode_x.reshape(-1, 3)
+    bp = np.repeat(bprim, geo.n_fp, axis=0)
+    g_in = np.where(bp[:, :1] > 0,
+                    kinetic.maxwellian_values(np.maximum(bp[:, 0], 1e-300), bp[:, 1:4], bp[:, 4],
+                                              V), 0.0).reshape(bx.shape[0] // geo.n_fp,
+                                                               geo.n_fp, -1)
+    g = owalls.wall_values(geo, V, f0, kinds, g_in)
+    p = [velocity.project_gaussian_1d(u[:, a], th, 16, 12.0) for a in range(3)]
+    i0, i1, i2 = idx[:, 0], idx[:, 1], idx[:, 2]
+    Mv = (n / (2.0 * np.pi * th) ** 1.5)[:, None] * p[0][:, i0] * p[1][:, i1] * p[2][:, i2]
+    Mv = Mv.reshape(geo.n_cells, geo.n_p, -1)
+    nu = np.full((geo.n_cells, geo.n_p), pr.nu_const)
     f_ref = transport.sweep(geo, V, nu + 1.0 / dt, nu, Mv, f0 / dt, g, gens, lags)
     assert rel(f_s, f_ref) <= TOL64
