@@ -157,3 +157,33 @@ def test_steps_with_walls_on_packed_walk_match_oracle(L):
         fr, _ = solver.bgk_step(geo, V, w, fr, g, P.SOD_STRIP_DT, gens, lags, mode="PROJECTED",
                                 nu_const=1000.0, fixed_iters=3, L=7.0, vcells=3, walls=okinds)
     assert rel(d.unpack(f).cpu().numpy(), fr) <= TOL64
+
+
+def test_fp32_and_batched_sweeps_on_packed_walk_dags():
+    """A DAG whose FP64 sweeps take the packed walk: its FP32-correction
+    sweeps and its batched steps use the workgroup walk, with the same
+    results as on a workgroup-walk DAG (bit for bit)."""
+    pr = P.small_problem(dim=2, order=1, n_side=4, n_1d=6, state="fourier")
+    geo, q, nu, prim = _inputs(pr, 91)
+    outs = {}
+    for L in (64, 4):
+        d = B.Dag.from_problem(pr, sweep_lanes=L)
+        qg = d.pack(B._dev(q))
+        fprev = d.pack(B._dev(np.random.default_rng(92).uniform(0, 1, q.shape)))
+        mcoef = B.maxwellian_coef_from_primitive(B._dev(prim.reshape(-1, 4)), 2)
+        fo = torch.empty_like(qg)
+        B.tgs_sweep(d, q=qg, nu=B._dev(nu.reshape(-1)), mcoef=mcoef, f_out=fo, sigma_shift=5.0,
+                    q_scale=1.0, bc_coef=B.state_coefficients(d, pr.state, "boundary"),
+                    f_prev=fprev, precision=1)
+        outs[("fp32", L)] = d.unpack(fo).cpu().numpy()
+        # one DIRK2 step single and batched
+        d2, f, bc, dt = B.problem_setup(pr, sweep_lanes=L)
+        s = B.Solver(d2, dt=dt, bc_coef=bc, tableau="DIRK2", fixed_iters=2, mode="MATCHED")
+        f_b = f.clone()
+        s.step(f)
+        s2 = B.Solver(d2, dt=dt, bc_coef=bc, tableau="DIRK2", fixed_iters=2, mode="MATCHED")
+        B.Batch([s2], graph=False).step([f_b])
+        assert torch.equal(f, f_b), L
+        outs[("step", L)] = d2.unpack(f).cpu().numpy()
+    assert np.array_equal(outs[("fp32", 64)], outs[("fp32", 4)])
+    assert np.array_equal(outs[("step", 64)], outs[("step", 4)])
