@@ -290,12 +290,14 @@ int tgs_walls_destroy(tgs_walls* walls);
 /* number of wall (non-inflow) facets */
 int64_t tgs_walls_count(const tgs_walls* walls);
 
-/* For every wall facet bf, facet node p and velocity j:
+/* For every wall facet bf, facet node p and every velocity j that can enter
+ * through it (v_j.n <= 1e-9 |v_j| for the facet's outward unit normal n, a
+ * superset of the velocities whose boundary data a sweep reads):
  *   bc_dense[bf][p][j] = f(cell of bf, its local node at p, T_bf(j)),
  * f device in the sweep layout, bc_dense device [n_bfaces][n_fp][n_v]
- * (rows of inflow facets are left untouched).  This is the boundary update
- * of a Picard iteration: the solver calls it with the previous iterate
- * before each sweep. */
+ * (rows of inflow facets and entries of outgoing velocities are left
+ * untouched).  This is the boundary update of a Picard iteration: the
+ * solver calls it with the previous iterate before each sweep. */
 int tgs_wall_values(const tgs_walls* walls, const double* f, double* bc_dense,
                     bgk_stream_t stream);
 

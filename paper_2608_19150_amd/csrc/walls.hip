@@ -16,28 +16,40 @@ struct tgs_walls {
   const tgs_dag* dag = nullptr;
   int64_t n_walls = 0;
   int n_maps = 0;
+  int max_in = 0;             // longest incoming list
   int4* d_wall = nullptr;     // [n_walls]: boundary facet, internal cell, map, facet nodes
   int32_t* d_map = nullptr;   // [n_maps][n_v]: T(j)
+  // per map: the velocities that can enter through such a wall (v.n <= 0 up
+  // to the tangential tolerance), the only ones whose boundary data a sweep
+  // reads; d_in_off[m] .. d_in_off[m + 1] index d_in
+  int32_t* d_in = nullptr;
+  int32_t* d_in_off = nullptr;
 };
 
 namespace bgk {
 
 namespace {
 
-// one thread per (wall facet, velocity), velocities fastest: the writes of a
-// wavefront to one boundary row are contiguous
+// one thread per (wall facet, incoming velocity), velocities fastest: the
+// writes of a wavefront to one boundary row are nearly contiguous
 __global__ __launch_bounds__(256) void k_wall_values(const int4* __restrict__ wall,
                                                      const int32_t* __restrict__ map,
+                                                     const int32_t* __restrict__ in,
+                                                     const int32_t* __restrict__ in_off,
                                                      const int32_t* __restrict__ pos,
                                                      const double* __restrict__ f,
                                                      double* __restrict__ bc, int64_t n_walls,
-                                                     int n_v, int64_t n_cells, int np, int nfp) {
-  const int64_t total = n_walls * n_v;
+                                                     int max_in, int n_v, int64_t n_cells,
+                                                     int np, int nfp) {
+  const int64_t total = n_walls * max_in;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = t / n_v;
-    const int j = (int)(t - w * n_v);
+    const int64_t w = t / max_in;
+    const int k = (int)(t - w * max_in);
     const int4 W = wall[w];
+    const int i0 = in_off[W.z];
+    if (k >= in_off[W.z + 1] - i0) continue;
+    const int j = in[i0 + k];
     const int jj = map[(int64_t)W.z * n_v + j];
     const int64_t slot = pos[(int64_t)jj * n_cells + W.y];
     const double* src = f + ((int64_t)jj * n_cells + slot) * np;
@@ -125,10 +137,10 @@ const tgs_dag* walls_dag(const tgs_walls* w) { return w->dag; }
 
 int launch_wall_values(const tgs_walls* w, const double* f, double* bc_dense, hipStream_t stream) {
   const tgs_dag* d = w->dag;
-  if (w->n_walls == 0) return BGK_OK;
-  hipLaunchKernelGGL(k_wall_values, dim3(grid_of(w->n_walls * d->n_v)), dim3(256), 0, stream,
-                     w->d_wall, w->d_map, d->d_pos, f, bc_dense, w->n_walls, d->n_v, d->n_cells,
-                     d->n_p, d->n_fp);
+  if (w->n_walls == 0 || w->max_in == 0) return BGK_OK;
+  hipLaunchKernelGGL(k_wall_values, dim3(grid_of(w->n_walls * w->max_in)), dim3(256), 0, stream,
+                     w->d_wall, w->d_map, w->d_in, w->d_in_off, d->d_pos, f, bc_dense, w->n_walls,
+                     w->max_in, d->n_v, d->n_cells, d->n_p, d->n_fp);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -155,6 +167,8 @@ extern "C" int tgs_walls_destroy(tgs_walls* w) {
   if (!w) return BGK_OK;
   if (w->d_wall) (void)hipFree(w->d_wall);
   if (w->d_map) (void)hipFree(w->d_map);
+  if (w->d_in) (void)hipFree(w->d_in);
+  if (w->d_in_off) (void)hipFree(w->d_in_off);
   delete w;
   return BGK_OK;
 }
@@ -164,17 +178,18 @@ extern "C" int tgs_walls_create(const tgs_dag* d, const int8_t* kind, tgs_walls*
   *out = nullptr;
   const int dim = d->dim;
   std::vector<int4> wall;
-  std::vector<int32_t> maps;
-  std::map<std::array<double, 4>, int> map_id;   // (kind, normal) -> map
+  std::vector<int32_t> maps, in, in_off{0};
+  std::map<std::array<double, 4>, int> map_id;   // (kind, unit normal) -> map
   for (int64_t bf = 0; bf < d->n_bfaces; ++bf) {
     const int k = kind[bf];
     if (k != BGK_BC_INFLOW && k != BGK_BC_BOUNCE_BACK && k != BGK_BC_REFLECT)
       return fail(BGK_E_INVALID, "unknown boundary kind at facet " + std::to_string(bf));
     if (k == BGK_BC_INFLOW) continue;
     const double* nrm = &d->bface_normal[(size_t)bf * dim];
+    // one map per (kind, normal): the velocity map of bounce-back does not
+    // depend on the normal, but the incoming velocities do
     std::array<double, 4> key{(double)k, 0, 0, 0};
-    if (k == BGK_BC_REFLECT)
-      for (int a = 0; a < dim; ++a) key[1 + a] = nrm[a];
+    for (int a = 0; a < dim; ++a) key[1 + a] = nrm[a];
     auto it = map_id.find(key);
     int id;
     if (it == map_id.end()) {
@@ -184,6 +199,18 @@ extern "C" int tgs_walls_create(const tgs_dag* d, const int8_t* kind, tgs_walls*
       id = (int)map_id.size();
       map_id.emplace(key, id);
       maps.insert(maps.end(), m.begin(), m.end());
+      // incoming velocities of this map (a superset of those the sweep reads:
+      // it treats |v.N| <= 1e-12 |v| |N| as tangential)
+      for (int j = 0; j < d->n_v; ++j) {
+        double vn = 0.0, v2 = 0.0;
+        for (int a = 0; a < dim; ++a) {
+          const double x = d->v_host[(size_t)j * dim + a];
+          vn += x * nrm[a];
+          v2 += x * x;
+        }
+        if (vn <= 1e-9 * std::sqrt(v2)) in.push_back(j);
+      }
+      in_off.push_back((int32_t)in.size());
     } else {
       id = it->second;
     }
@@ -194,16 +221,25 @@ extern "C" int tgs_walls_create(const tgs_dag* d, const int8_t* kind, tgs_walls*
   w->dag = d;
   w->n_walls = (int64_t)wall.size();
   w->n_maps = (int)map_id.size();
+  for (size_t m = 0; m + 1 < in_off.size(); ++m)
+    w->max_in = std::max(w->max_in, in_off[m + 1] - in_off[m]);
   if (!wall.empty()) {
     if (hipMalloc((void**)&w->d_wall, wall.size() * sizeof(int4)) != hipSuccess ||
-        hipMalloc((void**)&w->d_map, maps.size() * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc((void**)&w->d_map, maps.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&w->d_in, std::max<size_t>(in.size(), 1) * sizeof(int32_t)) !=
+            hipSuccess ||
+        hipMalloc((void**)&w->d_in_off, in_off.size() * sizeof(int32_t)) != hipSuccess) {
       tgs_walls_destroy(w);
       return fail(BGK_E_NOMEM, "wall arrays");
     }
     if (hipMemcpy(w->d_wall, wall.data(), wall.size() * sizeof(int4), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(w->d_map, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-            hipSuccess) {
+            hipSuccess ||
+        (!in.empty() && hipMemcpy(w->d_in, in.data(), in.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(w->d_in_off, in_off.data(), in_off.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
       tgs_walls_destroy(w);
       return fail(BGK_E_HIP, "wall arrays copy");
     }
