@@ -163,3 +163,36 @@ def test_projected_mode_and_q2_grid_validation():
     d2, f0, bc2, dt = B.problem_setup(pr)
     s = B.Solver(d2, dt=dt, bc_coef=bc2, mode="PROJECTED")
     assert code(lambda: B.Batch([s])) == B.BGK_E_UNSUPPORTED
+
+
+def test_fp32_refined_projected_steps_with_walls_match_fp64_oracle_moments():
+    """The FP32 correction sweep on the paper-literal set-up (Q2 velocities,
+    projected Maxwellian, reflecting walls): converged moments equal the
+    FP64 oracle's (tau = 1e-13) within the FP32 form's 1e-9."""
+    from oracle import walls as owalls
+    base = P.sod_strip_problem(3, 10.0)
+    mesh = P.rectangle_mesh(16, 2, -1.0, 1.0, -P.SOD_STRIP_HALF_HEIGHT, P.SOD_STRIP_HALF_HEIGHT)
+    pr = P.Problem(mesh, 1, base.vgrid, base.state, nu_const=10.0)
+    d, f, bc, _ = B.problem_setup(pr)
+    kinds = P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d))
+    s = B.Solver(d, dt=P.SOD_STRIP_DT, bc_coef=bc, walls=B.Walls(d, kinds), tau=1e-12,
+                 mode="PROJECTED", nu_const=10.0, precision=B.TGS_FP32_CORRECTION)
+    for _ in range(2):
+        s.step(f)
+    geo = geometry.build(mesh.vert, mesh.cells, 1)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    okinds = owalls.boundary_kinds(geo, lambda x, n: owalls.REFLECT if abs(n[1]) > 0.5 else
+                                   owalls.INFLOW)
+    gens, lags = odag.build_all(geo, V)
+    fr = solver.initial_condition(geo, V, pr.state)
+    g = solver.boundary_values(geo, V, pr.state)
+    for _ in range(2):
+        fr, _ = solver.bgk_step(geo, V, w, fr, g, P.SOD_STRIP_DT, gens, lags, mode="PROJECTED",
+                                nu_const=10.0, tau=1e-13, L=7.0, vcells=3, walls=okinds)
+    U = kinetic.moments(d.unpack(f).cpu().numpy(), V, w).reshape(-1, 4)
+    Uref = kinetic.moments(fr, V, w).reshape(-1, 4)
+    err = 0.0
+    for sl in (slice(0, 1), slice(1, 3), slice(3, 4)):
+        den = max(np.linalg.norm(Uref[:, sl]), np.linalg.norm(Uref[:, 0]))
+        err = max(err, np.linalg.norm(U[:, sl] - Uref[:, sl]) / den)
+    assert err <= 1e-9, err
