@@ -712,17 +712,39 @@ __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep
 
 // Packed walk (FP64): a 64-lane workgroup serves 64/L velocities, lane
 // group t (lanes t L .. t L + L - 1) sweeping velocity vpack[block][t]
-// through its generations L cells per step.  Every group advances one
-// chunk per step; the stores of a step are made visible to the whole
-// workgroup before the next step, so a cell reads its upwind values (from
-// earlier generations, possibly written by other lanes of its group) from
-// memory.  L = 1 is a thread walking its velocity's whole graph in order.
-// Each cell is prepared and solved by the same code as in the workgroup
-// walk, so the results are bitwise equal.
+// through its generations L cells per step; every group advances one chunk
+// per step, with a workgroup barrier between steps.  L = 1 is a thread
+// walking its velocity's whole graph in order.  With 4 or more lanes per
+// group each group keeps its last RS outputs in an LDS ring (RS a power of
+// two >= 16 and >= L, from an 8 KB budget): a cell of generation g (slots
+// [s0, s1)) reads upwind slots >= s1 - RS there, which no write of
+// generation g can have overwritten (the same argument as the workgroup
+// walk's ring), and older ones from memory; the barrier between steps then
+// fences global memory only when some group is about to read such an older
+// slot that may not be visible yet.  With 1 or 2 lanes (32-64 groups) the
+// ring would hold too few slots to pay for its registers: every upwind
+// value is read from memory, with a full fence between steps.  Each cell is
+// prepared and solved by the same code as in the workgroup walk, so the
+// results are bitwise equal.
+template <int DIM, int ORDER, int L>
+struct LanesCfg {
+  static constexpr int NP = SweepCfg<DIM, ORDER>::NP, VPB = 64 / L;
+  static constexpr int fit(int budget) {
+    int r = 1;
+    while (2 * r * VPB * NP * 8 <= budget) r *= 2;
+    return r;
+  }
+  static constexpr int RS = fit(8192) < L ? L : fit(8192);
+  static constexpr bool RING = RS >= 16;
+};
+
 template <int DIM, int ORDER, bool TAB, int L>
 __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
-  constexpr int NP = SweepCfg<DIM, ORDER>::NP, VPB = 64 / L;
+  using C = LanesCfg<DIM, ORDER, L>;
+  constexpr int NP = C::NP, VPB = C::VPB, RS = C::RS;
+  __shared__ double ring_all[C::RING ? VPB * RS * NP : 1];
   const int lane = threadIdx.x, t = lane / L, r = lane - t * L;
+  double* ring = ring_all + t * RS * NP;
   const int jj = a.vorder[blockIdx.x * VPB + t];   // the packed order, -1: none
   const int j = jj < 0 ? 0 : jj;
   double v[DIM], v2 = 0.0;
@@ -733,6 +755,7 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
   }
   const size_t base = (size_t)j * a.n_cells;
   const int32_t* go = a.goff + a.gbase[j];
+  const int32_t* gm = a.gmin + a.gbase[j];
   const int G = jj < 0 ? 0 : a.G[j];
   const double* mrow[2] = {nullptr, nullptr};
   if (a.mtab) {
@@ -741,14 +764,25 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
     mrow[1] = a.mtab + TL.at(1, j % TL.nr, 0);
   }
   int g = 0, s = 0, e = G > 0 ? go[1] : 0;
+  int synced = 0;  // this group's slots below it are visible in global memory
   while (__ballot(g < G)) {
+    // with the ring: a full fence when some group reads an upwind slot older
+    // than its ring that was written after the last full fence
+    const int ring_lo = C::RING ? e - RS : INT_MAX;
+    if constexpr (C::RING) {
+      const bool need = g < G && gm[g] < ring_lo && ring_lo > synced;
+      if (__ballot(need)) {
+        __syncthreads();
+        synced = s;
+      }
+    }
     if (g < G) {
       if (s + r < e) {
         Prep<DIM, ORDER> P;
         P.s = s + r;
         load_rec<DIM>(a, base, P.s, P.K, P.code, P.pack);
         prepare<DIM, ORDER, TAB>(a, v, v2, base, mrow, P);
-        finish64<DIM, ORDER, false>(a, P, base, j, v, v2, nullptr, 0, INT_MAX);
+        finish64<DIM, ORDER, C::RING>(a, P, base, j, v, v2, ring, RS - 1, ring_lo);
       }
       s += L;
       if (s >= e) {
@@ -757,7 +791,10 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
         if (g < G) e = go[g + 1];
       }
     }
-    __syncthreads();
+    if constexpr (C::RING)
+      lds_barrier();
+    else
+      __syncthreads();
   }
 }
 
