@@ -411,6 +411,39 @@ def run_x7(steps):
     return out
 
 
+def run_x2(cells, nus, tableaux, steps, tau):
+    """Picard iterations per step on the 1D Sod strip (the paper's iteration
+    table): for each nu, tableau and Q2 velocity resolution, the minimum,
+    maximum, mean and total of the iterations per step (all stages) over
+    `steps` steps with the projected Maxwellian.  The paper does not state
+    its tolerance; this reports ours beside it."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    out = {"setup": {"steps": steps, "tau": tau, "dt": P.SOD_STRIP_DT}, "rows": []}
+    for nu in nus:
+        for vc in cells:
+            row = {"nu": nu, "cells": vc}
+            for tab in tableaux:
+                pr = P.sod_strip_problem(vc, nu, tab)
+                d, f, bc, _ = B.problem_setup(pr)
+                walls = B.Walls(d, P.sod_strip_wall_kinds(B.boundary_facet_midpoints(d)))
+                s = B.Solver(d, dt=P.SOD_STRIP_DT, bc_coef=bc, tableau=tab, tau=tau,
+                             mode="PROJECTED", nu_const=nu, walls=walls)
+                try:
+                    it = [s.step(f)["total_iters"] for _ in range(steps)]
+                    row[tab] = {"min": min(it), "max": max(it), "avg": sum(it) / len(it),
+                                "tot": sum(it)}
+                except B.BGKError as e:
+                    row[tab] = {"error": str(e)}
+                print(f"[x2] nu={nu} cells={vc} {tab}: {row[tab]}", file=sys.stderr, flush=True)
+                del s, f, walls, d
+                torch.cuda.empty_cache()
+            out["rows"].append(row)
+    return out
+
+
 def run_x3(cells, ref_cells, nus, tableaux, steps, tau, threads):
     """Projection against interpolation of the Maxwellian on the 1D Sod
     problem embedded in 2D (reflecting top and bottom walls, Q2 velocity
@@ -570,6 +603,9 @@ def main():
     ap.add_argument("--x7", action="store_true",
                     help="only run the L2-stability study in a reflecting box")
     ap.add_argument("--x7-steps", type=int, default=40)
+    ap.add_argument("--x2", action="store_true",
+                    help="only run the Picard iteration table on the 1D Sod strip")
+    ap.add_argument("--x2-tau", type=float, default=1e-6)
     ap.add_argument("--x3", action="store_true",
                     help="only run the projection-vs-interpolation study on the 1D Sod strip")
     ap.add_argument("--x3-cells", default="4,8,16,32")
@@ -592,6 +628,12 @@ def main():
     if args.x7:
         res = run_x7(args.x7_steps)
         print(json.dumps({"study": "l2_stability_reflecting_box", **res}), flush=True)
+        return
+    if args.x2:
+        res = run_x2([int(x) for x in args.x3_cells.split(",")] + [args.x3_ref],
+                     [float(x) for x in args.x3_nu.split(",")], args.x3_tableaux.split(","),
+                     args.x3_steps, args.x2_tau)
+        print(json.dumps({"study": "picard_iterations_sod_strip", **res}), flush=True)
         return
     if args.x3:
         res = run_x3([int(x) for x in args.x3_cells.split(",")], args.x3_ref,
