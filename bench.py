@@ -17,7 +17,17 @@ Extra JSON fields: the FP32-solve + FP64-refinement form on the same
 workload (its rate, iterations and the moment error against the FP64 run),
 the sweep kernel's roofline (algorithmic 16 B per unknown: read the stage
 source, write the new iterate) from HIP events inside the library, and the
-FP64 CPU oracle's sweep rate on a bounded sample of velocities.
+FP64 CPU oracle's sweep rate on a bounded sample of velocities.  Further
+sections (each skippable): the 3D workload (c3_3d), batched uneven
+instances (c4_batched), the learned Picard guess (c5_learned_guess), the
+Q2 Gauss-Legendre velocity space with the projected Maxwellian
+(q2_projected), the narrow-generation Sod strip on the packed and the
+workgroup sweep walks (strip_walks) and the duct with walls at one GPU's
+scale (duct).
+
+Studies (each prints its own JSON line instead): --x2 Picard iterations on
+the Sod strip, --x3 projection against interpolation of the Maxwellian,
+--x7 L2 stability in a reflecting box.
 """
 from __future__ import annotations
 
