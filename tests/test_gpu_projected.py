@@ -56,7 +56,10 @@ def _seeded_prim(n_nodes, dim, seed, L):
     return prim
 
 
-@pytest.mark.parametrize("dim,order,vcells", [(2, 1, 5), (2, 2, 4), (3, 1, 3)])
+# vcells = 1: the only cell is both the first and the last (extended to
+# both infinities); vcells = 2: every cell is an end cell
+@pytest.mark.parametrize("dim,order,vcells", [(2, 1, 5), (2, 2, 4), (3, 1, 3), (2, 1, 1),
+                                              (3, 1, 2)])
 def test_projected_maxwellian_matches_oracle_and_conserves_moments(dim, order, vcells):
     say("projected maxwellian", dim, order, vcells)
     L = 6.0
