@@ -274,6 +274,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       b.U[0] = s->U[0];
       b.U[1] = s->U[1];
       b.mtab = mtab;
+      b.geo = d->d_geo;
       b.x1 = d->d_nodes1d;
       b.n1 = d->n_1d;
       b.mom_vl = moment_vl(d);

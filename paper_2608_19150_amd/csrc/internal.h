@@ -241,6 +241,18 @@ struct TabLayout {
   }
 };
 
+// P2 triangles: the padding of a cell's records carries its geometry, so the
+// sweep's table gathers bring it with no access of their own.  Axis 0's
+// record (16 doubles, 12 used) holds (|det J|-scaled volume, N_0, N_1.x) in
+// its last four doubles, the rest's record (8 doubles, 6 used) N_1.y in
+// double 6; the third facet's area-weighted normal is -(N_0 + N_1), the
+// normals of a closed triangle summing to zero.
+template <int DIM, int NP>
+struct TabGeo {
+  static constexpr bool ON = DIM == 2 && NP == 6;
+  static constexpr int E0_AT = 12, REST_AT = 6;
+};
+
 // 16-byte chunks of the tables (the unit the table kernels write)
 __host__ __device__ inline int64_t table_chunks(int dim, int64_t n_cells, int n1, int np) {
   return TabLayout(n_cells, n1, np, dim).size() / 2;

@@ -644,10 +644,24 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // node b of a record as (E_0, nu) (the sweep gathers both with one access),
 // a chunk of the rest holds two nodes' entries.  Chunks are numbered
 // through axis 0's records first, then through the rest's.
+// Padding chunk h of cell c's record (axis 0 if first): zeros, or for P2
+// triangles the cell's geometry (TabGeo)
+template <int DIM>
+__device__ __forceinline__ double2 pad_chunk(const double* __restrict__ geo, int np, bool first,
+                                             int h, int64_t c) {
+  if (DIM == 2 && np == 6) {
+    const double* g = geo + c * GeoLayout<2>::STRIDE;
+    if (first) return h == 6 ? make_double2(g[0], g[1]) : make_double2(g[2], g[3]);
+    return make_double2(g[4], 0.0);
+  }
+  return make_double2(0.0, 0.0);
+}
+
 template <int DIM>
 __device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
                                             const double* __restrict__ nu,
                                             const double* __restrict__ x1,
+                                            const double* __restrict__ geo,
                                             double* __restrict__ tab, int64_t n_cells, int n1,
                                             int np, int64_t t) {
   constexpr int NM = DIM + 2;
@@ -676,22 +690,23 @@ __device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
     return bgk_exp(e);
   };
   double2 v;
-  if (first) {
-    v = h < np ? make_double2(entry(h), nu[c * np + h]) : make_double2(0.0, 0.0);
-  } else {
-    v = make_double2(2 * h < np ? entry(2 * h) : 0.0, 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
-  }
+  if (first)
+    v = h < np ? make_double2(entry(h), nu[c * np + h]) : pad_chunk<DIM>(geo, np, true, h, c);
+  else if (2 * h >= np)
+    v = pad_chunk<DIM>(geo, np, false, h, c);
+  else
+    v = make_double2(entry(2 * h), 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
   reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] = v;
 }
 
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
-                              const double* __restrict__ x1, double* __restrict__ tab,
-                              int64_t n_cells, int n1, int np) {
+                              const double* __restrict__ x1, const double* __restrict__ geo,
+                              double* __restrict__ tab, int64_t n_cells, int n1, int np) {
   const int64_t total = table_chunks(DIM, n_cells, n1, np);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x)
-    table_chunk<DIM>(coef, nu, x1, tab, n_cells, n1, np, t);
+    table_chunk<DIM>(coef, nu, x1, geo, tab, n_cells, n1, np, t);
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
@@ -701,10 +716,10 @@ int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, d
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_cells, d->n_1d, np);
+                       d->d_geo, tab, d->n_cells, d->n_1d, np);
   else
     hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       tab, d->n_cells, d->n_1d, np);
+                       d->d_geo, tab, d->n_cells, d->n_1d, np);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -740,8 +755,11 @@ __global__ __launch_bounds__(256) void k_proj_axes(const double* __restrict__ pr
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ pr, const double* __restrict__ nu,
-                              double* __restrict__ tab, int64_t n_cells, int n1, int np) {
+__global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ pr,
+                                                     const double* __restrict__ nu,
+                                                     const double* __restrict__ geo,
+                                                     double* __restrict__ tab, int64_t n_cells,
+                                                     int n1, int np) {
   const TabLayout L(n_cells, n1, np, DIM);
   const int64_t nn = n_cells * np;
   const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
@@ -764,9 +782,11 @@ __global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ 
     double2 v;
     if (first)
       v = h < np ? make_double2(pr[(int64_t)row * nn + c * np + h], nu[c * np + h])
-                 : make_double2(0.0, 0.0);
+                 : pad_chunk<DIM>(geo, np, true, h, c);
+    else if (2 * h >= np)
+      v = pad_chunk<DIM>(geo, np, false, h, c);
     else
-      v = make_double2(2 * h < np ? rest(2 * h) : 0.0, 2 * h + 1 < np ? rest(2 * h + 1) : 0.0);
+      v = make_double2(rest(2 * h), 2 * h + 1 < np ? rest(2 * h + 1) : 0.0);
     reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] = v;
   }
 }
@@ -782,13 +802,13 @@ int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, d
   if (d->dim == 2) {
     hipLaunchKernelGGL(k_proj_axes<2>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
                        d->n_1d, d->dg_cells, d->L);
-    hipLaunchKernelGGL(k_proj_tables<2>, dim3(g2), dim3(256), 0, stream, pr, nu, tab, d->n_cells,
-                       d->n_1d, np);
+    hipLaunchKernelGGL(k_proj_tables<2>, dim3(g2), dim3(256), 0, stream, pr, nu, d->d_geo, tab,
+                       d->n_cells, d->n_1d, np);
   } else {
     hipLaunchKernelGGL(k_proj_axes<3>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
                        d->n_1d, d->dg_cells, d->L);
-    hipLaunchKernelGGL(k_proj_tables<3>, dim3(g2), dim3(256), 0, stream, pr, nu, tab, d->n_cells,
-                       d->n_1d, np);
+    hipLaunchKernelGGL(k_proj_tables<3>, dim3(g2), dim3(256), 0, stream, pr, nu, d->d_geo, tab,
+                       d->n_cells, d->n_1d, np);
   }
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -958,7 +978,7 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
       continue;
     }
     const BatchKin& k = kin[i];
-    table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.mtab, k.n_nodes / k.np, k.n1, k.np,
+    table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.geo, k.mtab, k.n_nodes / k.np, k.n1, k.np,
                      g - first[i]);
   }
 }

@@ -49,6 +49,7 @@ struct BatchKin {
   MomArgs mom;         // .U / .U_prev are replaced by U[par ^ 1] / U[par]
   const double* U[2];
   double* mtab;        // factorised tables or null
+  const double* geo;   // cell geometry (carried in the tables' padding for P2 triangles)
   const double* x1;
   int n1;
   int mom_vl;          // velocity lanes of the moment kernel (1, 4, 16)

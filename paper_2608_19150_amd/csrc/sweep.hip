@@ -182,9 +182,12 @@ __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s,
                                          Raw<DIM, ORDER, TAB>& R) {
   using RW = Raw<DIM, ORDER, TAB>;
   constexpr int NP = Elem<DIM, ORDER>::NP;
-  const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
+  constexpr bool TG = TAB && TabGeo<DIM, NP>::ON;
+  if constexpr (!TG) {
+    const double* __restrict__ gk = a.geo + (size_t)K * GeoLayout<DIM>::STRIDE;
 #pragma unroll
-  for (int i = 0; i < RW::NG; ++i) R.g[i] = gk[i];
+    for (int i = 0; i < RW::NG; ++i) R.g[i] = gk[i];
+  }
   const double* __restrict__ q = a.q + (base + s) * NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) R.q[b] = q[b];
@@ -196,6 +199,12 @@ __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s,
     for (int b = 0; b < RW::NM; ++b) R.m[b] = e0[b];
 #pragma unroll
     for (int b = 0; b < NP; ++b) R.x[b] = mrow[1][u * S1 + b];
+    if constexpr (TG) {
+      using T = TabGeo<DIM, NP>;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) R.g[i] = e0[T::E0_AT + i];
+      R.g[4] = mrow[1][u * S1 + T::REST_AT];
+    }
   } else {
 #pragma unroll
     for (int b = 0; b < NP; ++b) R.m[b] = a.nu[u * NP + b];
@@ -212,9 +221,16 @@ __device__ __forceinline__ void compute_prep(const SweepArgs& a, const double* v
                                              Prep<DIM, ORDER>& P) {
   using RW = Raw<DIM, ORDER, TAB>;
   constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1;
-  P.vol = R.g[0];
+  double g[RW::NG];
+#pragma unroll
+  for (int i = 0; i < RW::NG; ++i) g[i] = R.g[i];
+  if constexpr (TAB && TabGeo<DIM, NP>::ON) {
+    g[5] = -(g[1] + g[3]);
+    g[6] = -(g[2] + g[4]);
+  }
+  P.vol = g[0];
   double raw[NF];
-  facet_flux_raw<DIM>(R.g, v, v2, P.fl, raw);
+  facet_flux_raw<DIM>(g, v, v2, P.fl, raw);
   constexpr double wf = (DIM == 2) ? -1.0 : -2.0;
 #pragma unroll
   for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
@@ -238,14 +254,28 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
                                         size_t base, const double* const (&mrow)[2],
                                         Prep<DIM, ORDER>& P) {
   constexpr int NP = Elem<DIM, ORDER>::NP, NF = DIM + 1, NC = DIM + 2;
-  const double* __restrict__ gk = a.geo + (size_t)P.K * GeoLayout<DIM>::STRIDE;
+  constexpr int NG = 1 + (DIM + 1) * DIM;
+  const size_t u = (size_t)P.K;  // nodal arrays in the internal cell order
+  double gk[NG];
+  if constexpr (TAB && TabGeo<DIM, NP>::ON) {
+    using T = TabGeo<DIM, NP>;
+    const double* __restrict__ e0 = mrow[0] + u * TabLayout::pow2(2 * NP);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gk[i] = e0[T::E0_AT + i];
+    gk[4] = mrow[1][u * TabLayout::pow2(NP) + T::REST_AT];
+    gk[5] = -(gk[1] + gk[3]);
+    gk[6] = -(gk[2] + gk[4]);
+  } else {
+    const double* __restrict__ g = a.geo + (size_t)P.K * GeoLayout<DIM>::STRIDE;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) gk[i] = g[i];
+  }
   P.vol = gk[0];
   double raw[NF];
   facet_flux_raw<DIM>(gk, v, v2, P.fl, raw);
   constexpr double wf = (DIM == 2) ? -1.0 : -2.0;
 #pragma unroll
   for (int b = 0; b < DIM; ++b) P.w[b] = wf * raw[b + 1];
-  const size_t u = (size_t)P.K;  // nodal arrays in the internal cell order
   const double* __restrict__ q = a.q + (base + P.s) * NP;
   double M[NP], nu[NP];
   if constexpr (TAB) {
