@@ -957,10 +957,19 @@ __global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __rest
   if (g >= total) return;
   const int i = find_instance<int64_t>(first, n_inst, g);
   if (done[i]) return;
-  // arguments into registers: the Newton loop reads them repeatedly
-  const MaxwArgs p = kin[i].maxw;
-  const double* U = kin[i].U[par[i]];
-  maxwellian_node<DIM>(p, U, g - first[i]);
+  // A wave inside one instance (all but a few per launch) reads that
+  // instance's arguments through a wave-uniform index, so they are scalar
+  // loads into scalar registers and the Newton loop's trip counts and
+  // per-axis node reads are uniform; a wave straddling two instances keeps
+  // per-lane copies.
+  const int i0 = __builtin_amdgcn_readfirstlane(i);
+  if (__ballot(i != i0) == 0) {
+    const MaxwArgs p = kin[i0].maxw;
+    maxwellian_node<DIM>(p, kin[i0].U[par[i0]], g - first[i0]);
+  } else {
+    const MaxwArgs p = kin[i].maxw;
+    maxwellian_node<DIM>(p, kin[i].U[par[i]], g - first[i]);
+  }
 }
 
 // Grid-stride over every instance's table chunks; a thread that meets a
@@ -977,9 +986,18 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
       if (end > g + stride) g += (end - g - 1) / stride * stride;
       continue;
     }
-    const BatchKin& k = kin[i];
-    table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.geo, k.mtab, k.n_nodes / k.np, k.n1, k.np,
-                     g - first[i]);
+    // through a wave-uniform index when the wave is inside one instance
+    // (scalar loads of its arguments), as in k_maxwellian_batch
+    const auto chunk = [&](int ii) {
+      const BatchKin& k = kin[ii];
+      table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.geo, k.mtab, k.n_nodes / k.np, k.n1, k.np,
+                       g - first[ii]);
+    };
+    const int i0 = __builtin_amdgcn_readfirstlane(i);
+    if (__ballot(i != i0) == 0)
+      chunk(i0);
+    else
+      chunk(i);
   }
 }
 
