@@ -657,23 +657,15 @@ __device__ __forceinline__ double2 pad_chunk(const double* __restrict__ geo, int
   return make_double2(0.0, 0.0);
 }
 
+// entry chunk h of cell c's record on row `row` of part `first` (axis 0) or
+// the rest
 template <int DIM>
-__device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
-                                            const double* __restrict__ nu,
-                                            const double* __restrict__ x1,
-                                            const double* __restrict__ geo,
-                                            double* __restrict__ tab, int64_t n_cells, int n1,
-                                            int np, int64_t t) {
+__device__ __forceinline__ double2 table_value(const double* __restrict__ coef,
+                                               const double* __restrict__ nu,
+                                               const double* __restrict__ x1,
+                                               const double* __restrict__ geo, int n1, int np,
+                                               bool first, int64_t c, int h, int row) {
   constexpr int NM = DIM + 2;
-  const TabLayout L(n_cells, n1, np, DIM);
-  const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
-  const bool first = t < a0;
-  const int64_t u = first ? t : t - a0;
-  const int half = (first ? L.s0 : L.s1) / 2;
-  const int64_t q = u / half;
-  const int h = (int)(u - q * half);
-  const int64_t c = q % n_cells;
-  const int row = (int)(q / n_cells);
   const auto entry = [&](int b) {
     const double* cf = coef + (c * np + b) * NM;
     double e;
@@ -689,30 +681,63 @@ __device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
     }
     return bgk_exp(e);
   };
-  double2 v;
   if (first)
-    v = h < np ? make_double2(entry(h), nu[c * np + h]) : pad_chunk<DIM>(geo, np, true, h, c);
-  else if (2 * h >= np)
-    v = pad_chunk<DIM>(geo, np, false, h, c);
-  else
-    v = make_double2(entry(2 * h), 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
-  reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] = v;
+    return h < np ? make_double2(entry(h), nu[c * np + h]) : pad_chunk<DIM>(geo, np, true, h, c);
+  if (2 * h >= np) return pad_chunk<DIM>(geo, np, false, h, c);
+  return make_double2(entry(2 * h), 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
 }
 
+// chunk t of the tables, numbered through axis 0's records first (row by
+// row), then through the rest's
+template <int DIM>
+__device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
+                                            const double* __restrict__ nu,
+                                            const double* __restrict__ x1,
+                                            const double* __restrict__ geo,
+                                            double* __restrict__ tab, int64_t n_cells, int n1,
+                                            int np, int64_t t) {
+  const TabLayout L(n_cells, n1, np, DIM);
+  const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
+  const bool first = t < a0;
+  const int64_t u = first ? t : t - a0;
+  const int half = (first ? L.s0 : L.s1) / 2;
+  const int64_t q = u / half;
+  const int h = (int)(u - q * half);
+  const int64_t c = q % n_cells;
+  const int row = (int)(q / n_cells);
+  reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] =
+      table_value<DIM>(coef, nu, x1, geo, n1, np, first, c, h, row);
+}
+
+// One thread per (part, cell, chunk) walks all rows, so each node's
+// coefficients are read once rather than once per row; for every row,
+// consecutive threads write consecutive chunks.
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
                               const double* __restrict__ x1, const double* __restrict__ geo,
                               double* __restrict__ tab, int64_t n_cells, int n1, int np) {
-  const int64_t total = table_chunks(DIM, n_cells, n1, np);
+  const TabLayout L(n_cells, n1, np, DIM);
+  const int h0 = L.s0 / 2, h1 = L.s1 / 2;
+  const int64_t n0 = n_cells * h0, total = n0 + n_cells * h1;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x)
-    table_chunk<DIM>(coef, nu, x1, geo, tab, n_cells, n1, np, t);
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const bool first = t < n0;
+    const int64_t u = first ? t : t - n0;
+    const int half = first ? h0 : h1;
+    const int64_t c = u / half;
+    const int h = (int)(u - c * half);
+    const int rows = first ? n1 : L.nr;
+    for (int row = 0; row < rows; ++row)
+      reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] =
+          table_value<DIM>(coef, nu, x1, geo, n1, np, first, c, h, row);
+  }
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream) {
   const int np = (int)(d->n_nodes / d->n_cells);
-  const int64_t total = table_chunks(d->dim, d->n_cells, d->n_1d, np);
+  const TabLayout L(d->n_cells, d->n_1d, np, d->dim);
+  const int64_t total = d->n_cells * (L.s0 / 2 + L.s1 / 2);
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
