@@ -448,7 +448,7 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     const tgs_dag* d = solvers[i]->dag;
     nfirst[i + 1] = nfirst[i] + d->n_nodes;
     tfirst[i + 1] =
-        tfirst[i] + (tab ? table_chunks(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table chunks
+        tfirst[i] + (tab ? table_threads(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table threads
     mfirst[i + 1] = mfirst[i] + moment_blocks(d);
     npart += (int64_t)moment_blocks(d) * 6;
   }

@@ -253,6 +253,13 @@ struct TabGeo {
   static constexpr int E0_AT = 12, REST_AT = 6;
 };
 
+// threads of the table kernels: one per (part, cell, 16-byte chunk of the
+// cell's record), each writing its chunk on every row of its part
+__host__ __device__ inline int64_t table_threads(int dim, int64_t n_cells, int n1, int np) {
+  const TabLayout L(n_cells, n1, np, dim);
+  return n_cells * (L.s0 / 2 + L.s1 / 2);
+}
+
 // 16-byte chunks of the tables (the unit the table kernels write)
 __host__ __device__ inline int64_t table_chunks(int dim, int64_t n_cells, int n1, int np) {
   return TabLayout(n_cells, n1, np, dim).size() / 2;

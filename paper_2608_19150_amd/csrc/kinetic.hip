@@ -687,57 +687,45 @@ __device__ __forceinline__ double2 table_value(const double* __restrict__ coef,
   return make_double2(entry(2 * h), 2 * h + 1 < np ? entry(2 * h + 1) : 0.0);
 }
 
-// chunk t of the tables, numbered through axis 0's records first (row by
-// row), then through the rest's
+// Thread t of the table kernels (table_threads): part, cell and chunk, the
+// chunk written on every row of the part, so each node's coefficients are
+// read once rather than once per row; for every row, consecutive threads
+// write consecutive chunks.
 template <int DIM>
-__device__ __forceinline__ void table_chunk(const double* __restrict__ coef,
-                                            const double* __restrict__ nu,
-                                            const double* __restrict__ x1,
-                                            const double* __restrict__ geo,
-                                            double* __restrict__ tab, int64_t n_cells, int n1,
-                                            int np, int64_t t) {
+__device__ __forceinline__ void table_rows(const double* __restrict__ coef,
+                                           const double* __restrict__ nu,
+                                           const double* __restrict__ x1,
+                                           const double* __restrict__ geo,
+                                           double* __restrict__ tab, int64_t n_cells, int n1,
+                                           int np, int64_t t) {
   const TabLayout L(n_cells, n1, np, DIM);
-  const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
-  const bool first = t < a0;
-  const int64_t u = first ? t : t - a0;
-  const int half = (first ? L.s0 : L.s1) / 2;
-  const int64_t q = u / half;
-  const int h = (int)(u - q * half);
-  const int64_t c = q % n_cells;
-  const int row = (int)(q / n_cells);
-  reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] =
-      table_value<DIM>(coef, nu, x1, geo, n1, np, first, c, h, row);
+  const int h0 = L.s0 / 2, h1 = L.s1 / 2;
+  const int64_t n0 = n_cells * h0;
+  const bool first = t < n0;
+  const int64_t u = first ? t : t - n0;
+  const int half = first ? h0 : h1;
+  const int64_t c = u / half;
+  const int h = (int)(u - c * half);
+  const int rows = first ? n1 : L.nr;
+  for (int row = 0; row < rows; ++row)
+    reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] =
+        table_value<DIM>(coef, nu, x1, geo, n1, np, first, c, h, row);
 }
 
-// One thread per (part, cell, chunk) walks all rows, so each node's
-// coefficients are read once rather than once per row; for every row,
-// consecutive threads write consecutive chunks.
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
                               const double* __restrict__ x1, const double* __restrict__ geo,
                               double* __restrict__ tab, int64_t n_cells, int n1, int np) {
-  const TabLayout L(n_cells, n1, np, DIM);
-  const int h0 = L.s0 / 2, h1 = L.s1 / 2;
-  const int64_t n0 = n_cells * h0, total = n0 + n_cells * h1;
+  const int64_t total = table_threads(DIM, n_cells, n1, np);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const bool first = t < n0;
-    const int64_t u = first ? t : t - n0;
-    const int half = first ? h0 : h1;
-    const int64_t c = u / half;
-    const int h = (int)(u - c * half);
-    const int rows = first ? n1 : L.nr;
-    for (int row = 0; row < rows; ++row)
-      reinterpret_cast<double2*>(tab + L.at(first ? 0 : 1, row, c))[h] =
-          table_value<DIM>(coef, nu, x1, geo, n1, np, first, c, h, row);
-  }
+       t += (int64_t)gridDim.x * blockDim.x)
+    table_rows<DIM>(coef, nu, x1, geo, tab, n_cells, n1, np, t);
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
                        hipStream_t stream) {
   const int np = (int)(d->n_nodes / d->n_cells);
-  const TabLayout L(d->n_cells, d->n_1d, np, d->dim);
-  const int64_t total = d->n_cells * (L.s0 / 2 + L.s1 / 2);
+  const int64_t total = table_threads(d->dim, d->n_cells, d->n_1d, np);
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
@@ -997,7 +985,7 @@ __global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __rest
   }
 }
 
-// Grid-stride over every instance's table chunks; a thread that meets a
+// Grid-stride over every instance's table threads; a thread that meets a
 // finished instance (or one without tables) jumps to its first position past
 // that instance's range, so finished instances cost O(instances) per thread.
 template <int DIM>
@@ -1015,8 +1003,8 @@ __global__ void k_tables_batch(const BatchKin* __restrict__ kin, const int32_t* 
     // (scalar loads of its arguments), as in k_maxwellian_batch
     const auto chunk = [&](int ii) {
       const BatchKin& k = kin[ii];
-      table_chunk<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.geo, k.mtab, k.n_nodes / k.np, k.n1, k.np,
-                       g - first[ii]);
+      table_rows<DIM>(k.maxw.coef, k.maxw.nu, k.x1, k.geo, k.mtab, k.n_nodes / k.np, k.n1, k.np,
+                      g - first[ii]);
     };
     const int i0 = __builtin_amdgcn_readfirstlane(i);
     if (__ballot(i != i0) == 0)
