@@ -22,7 +22,7 @@ from scipy.spatial import Delaunay
 
 __all__ = [
     "Mesh", "VelocityGrid", "State", "Problem",
-    "jittered_square_mesh", "graded_square_mesh", "jittered_cube_mesh",
+    "jittered_square_mesh", "graded_square_mesh", "jittered_cube_mesh", "flipped_cube_mesh",
     "structured_square_mesh",
     "tensor_velocity_grid",
     "sod_state", "planar_riemann_state", "fourier_state", "uniform_state",
@@ -241,6 +241,75 @@ def jittered_cube_mesh(n_side: int, jitter: float, seed: int) -> Mesh:
     pts = pts + np.where(free, rng.uniform(-jitter * h, jitter * h, size=pts.shape), 0.0)
     cells = _drop_degenerate(pts, _delaunay(pts))
     return Mesh(pts, cells)
+
+
+def flipped_cube_mesh(n_interior: int = 30, n_flips: int = 40, seed: int = 3) -> Mesh:
+    """A valid tetrahedral mesh of [0,1]^3 that is not Delaunay: the Delaunay
+    mesh of the cube's corners and ``n_interior`` seeded random points, then
+    ``n_flips`` random 2-3 flips (two tetrahedra abcd, abce whose union is
+    convex across abc become abde, bcde, cade).  Such meshes have upwind
+    cycles for some directions (Delaunay meshes never do).  Cells are
+    positively oriented; flips that would leave a tetrahedron thinner than
+    1e-3 of its neighbours' volume are skipped."""
+    rng = np.random.default_rng(seed)
+    corners = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], float)
+    pts = np.vstack([corners, rng.uniform(0.1, 0.9, size=(n_interior, 3))])
+
+    def det(c):
+        x = pts[list(c)]
+        return float(np.linalg.det(np.stack([x[1] - x[0], x[2] - x[0], x[3] - x[0]])))
+
+    cells = [list(c) for c in Delaunay(pts).simplices.astype(np.int64)]
+    for c in cells:
+        if det(c) < 0:
+            c[0], c[1] = c[1], c[0]
+    done = 0
+    for _ in range(200000):
+        if done >= n_flips:
+            break
+        fmap = {}
+        for t, c in enumerate(cells):
+            for k in range(4):
+                key = tuple(sorted(c[i] for i in range(4) if i != k))
+                fmap.setdefault(key, []).append((t, c[k]))
+        faces = [(f, w) for f, w in fmap.items() if len(w) == 2]
+        (a, b, c), ((t1, d), (t2, e)) = faces[rng.integers(len(faces))]
+        # does segment d-e pass through the inside of triangle abc?
+        M = np.stack([pts[e] - pts[d], pts[a] - pts[b], pts[a] - pts[c]], 1)
+        try:
+            s_, u_, w_ = np.linalg.solve(M, pts[a] - pts[d])
+        except np.linalg.LinAlgError:
+            continue
+        if not (0 < s_ < 1 and u_ > 0.05 and w_ > 0.05 and 1 - u_ - w_ > 0.05):
+            continue
+        new = [[a, b, d, e], [b, c, d, e], [c, a, d, e]]
+        ref = 0.5 * (abs(det(cells[t1])) + abs(det(cells[t2])))
+        if min(abs(det(q)) for q in new) < 1e-3 * ref:
+            continue
+        for q in new:
+            if det(q) < 0:
+                q[0], q[1] = q[1], q[0]
+        for t in sorted([t1, t2], reverse=True):
+            cells.pop(t)
+        cells.extend(new)
+        done += 1
+    out = np.array(cells, dtype=np.int32)
+    if abs(_simplex_measures(pts, out).sum() - 1.0) > 1e-12:
+        raise RuntimeError("flipped mesh does not tile the cube")
+    return Mesh(pts, out)
+
+
+def load_mesh_text(path: str) -> Mesh:
+    """Reads a mesh written as text: '#' comment lines, "vert N" then N lines
+    of coordinates, "cells M" then M lines of vertex indices."""
+    with open(path) as fh:
+        lines = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    nv = int(lines[0][1])
+    vert = np.array([[float(x) for x in ln] for ln in lines[1:1 + nv]], dtype=np.float64)
+    assert lines[1 + nv][0] == "cells"
+    nc = int(lines[1 + nv][1])
+    cells = np.array([[int(x) for x in ln] for ln in lines[2 + nv:2 + nv + nc]], dtype=np.int32)
+    return Mesh(vert, cells)
 
 
 def jittered_box_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float,

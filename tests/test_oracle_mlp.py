@@ -112,3 +112,50 @@ def test_targets_measure_the_departure_from_linear_extrapolation():
                                         np.r_[1, np.ones(dim), np.zeros(3 - dim), 1], dim)
         np.testing.assert_allclose(mlp.guess(mlp.targets(Uo, U1, U2, dim), U1, U2, dim), Uo,
                                    rtol=1e-13, atol=1e-13)
+
+
+def _adam_run(p0, grads_seq, **kw):
+    params = {"w": np.array(p0, dtype=np.float64)}
+    state = {}
+    for g in grads_seq:
+        mlp.adam(params, {"w": np.array(g, dtype=np.float64)}, state, **kw)
+    return params["w"]
+
+
+def test_adam_first_step_is_normalised_gradient():
+    """After one step the bias-corrected moments are exactly g and g^2, so
+    the update is -lr g / (|g| + eps) per parameter, whatever b1 and b2 are
+    (Kingma & Ba, Alg. 1).  Small gradients check where eps enters."""
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=50) * np.logspace(-9, 1, 50)
+    p0 = rng.normal(size=50)
+    for b1, b2 in [(0.9, 0.999), (0.5, 0.9)]:
+        p1 = _adam_run(p0, [g], lr=1e-3, b1=b1, b2=b2, eps=1e-8)
+        np.testing.assert_allclose(p1 - p0, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    # a zero gradient leaves the parameter unchanged
+    assert _adam_run([2.5], [[0.0]])[0] == 2.5
+
+
+def test_adam_constant_gradient_moves_equal_steps():
+    """With a constant gradient the bias correction is exact at every step
+    (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so every step is the first
+    step's size; a wrong correction exponent breaks this."""
+    g = np.array([0.3, -2.0, 1e-7])
+    p0 = np.zeros(3)
+    step = -1e-2 * g / (np.abs(g) + 1e-8)
+    for t in (1, 2, 5, 20):
+        pt = _adam_run(p0, [g] * t, lr=1e-2)
+        np.testing.assert_allclose(pt, t * step, rtol=1e-12, atol=0)
+
+
+def test_adam_two_steps_hand_computed():
+    """p0 = 1, g1 = 0.5, g2 = -0.25, lr 1e-3, b1 0.9, b2 0.999, eps 1e-8:
+    step 1 gives m = 0.05, v = 2.5e-4, m^ = 0.5, v^ = 0.25, p1 = 1 - 1e-3 *
+    0.5 / (0.5 + 1e-8) = 0.99900000002; step 2 gives m = 0.045 - 0.025 =
+    0.02, v = 2.4975e-4 + 6.25e-5 = 3.1225e-4, m^ = 0.02 / 0.19 = 2/19,
+    v^ = 3.1225e-4 / 0.001999, p2 = p1 - 1e-3 (2/19) / (sqrt(v^) + 1e-8)
+    = 0.9987336629870784."""
+    p = _adam_run([1.0], [[0.5]])
+    assert abs(p[0] - 0.99900000002) < 1e-15
+    p = _adam_run([1.0], [[0.5], [-0.25]])
+    assert abs(p[0] - 0.9987336629870784) < 1e-15

@@ -177,12 +177,49 @@ def test_l2_stability(mode, nu):
         prev = cur
 
 
-def test_explicit_dt_formula():
-    pr = P.config_c1()
-    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, 1)
-    dt = solver.explicit_dt(geo, pr.vgrid.v, 10.0)
-    hmin = math.sqrt(geo.vol.min())
-    assert np.isclose(dt, 10.0 * 0.5 * (1 / 3) * hmin / (6 * math.sqrt(2)))
+def test_explicit_dt_hand_built_meshes():
+    """eq. explicit-dt, dt = C (1/d) (1/(2k+1)) h_min / max_j |v_j| with
+    h_min = (min cell measure)^(1/d), on meshes whose numbers are known by
+    hand:
+    * two triangles (0,0),(1,0),(0,1) [area 1/2] and (1,0),(3,0),(0,1)
+      [area 1]: h_min = sqrt(1/2); velocities (3,4) and (-1,0): max |v| = 5;
+      P1, C = 10: dt = 10 (1/2)(1/3) sqrt(1/2) / 5 = 0.23570226039551584;
+      P2 (1/(2k+1) = 1/5): 0.6 of that;
+    * the unit corner tetrahedron (volume 1/6), velocity (1, 2, 2) (|v| = 3),
+      P1, C = 10: 10 (1/3)(1/3) (1/6)^(1/3) / 3 = 0.2038226696848535."""
+    vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [3.0, 0.0]])
+    cells = np.array([[0, 1, 2], [1, 3, 2]])
+    V = np.array([[3.0, 4.0], [-1.0, 0.0]])
+    geo = geometry.build(vert, cells, 1)
+    assert abs(solver.explicit_dt(geo, V, 10.0) - 0.23570226039551584) < 1e-15
+    geo2 = geometry.build(vert, cells, 2)
+    assert abs(solver.explicit_dt(geo2, V, 10.0) - 0.6 * 0.23570226039551584) < 1e-15
+    tet = geometry.build(np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]),
+                         np.array([[0, 1, 2, 3]]), 1)
+    assert abs(solver.explicit_dt(tet, np.array([[1.0, 2.0, 2.0], [0.5, 0, 0]]), 10.0)
+               - 0.2038226696848535) < 1e-15
+
+
+def test_relative_changes_hand_computed():
+    """eq. convergence-criteria with the A13 guard on two 2D nodes
+    (U = (n, n u_1, n u_2, E) per node).
+    * A gas at rest: U_old = [(1,0,0,1), (2,0,0,3)], U_new = [(1.1,0.3,-0.4,1),
+      (2,0,0,2.5)].  Density: |(0.1, 0)| / |(1, 2)| = 0.1/sqrt5.  Momentum:
+      the old momentum is 0, so the denominator is |n_old| = sqrt5 and the
+      change |((0.3,-0.4),(0,0))| = 0.5 gives 0.5/sqrt5.  Energy: |(0,-0.5)| /
+      |(1,3)| = 0.5/sqrt10.
+    * A moving gas whose momentum norm (5) exceeds its density norm (2 sqrt2):
+      no guard.  Energy is never guarded: |E_old| = 0.5 sqrt2 < |n_old| and
+      the ratio is 0.1 sqrt2 / (0.5 sqrt2) = 0.2."""
+    Uo = np.array([[1.0, 0, 0, 1], [2, 0, 0, 3]])
+    Un = np.array([[1.1, 0.3, -0.4, 1], [2, 0, 0, 2.5]])
+    r = solver.relative_changes(Un, Uo, 2)
+    np.testing.assert_allclose(r, [0.044721359549995794, 0.22360679774997896,
+                                   0.15811388300841897], rtol=1e-15)
+    Uo = np.array([[2.0, 3, 4, 0.5], [2, 0, 0, 0.5]])
+    Un = np.array([[2.0, 3, 4.5, 0.6], [2, 0, 0, 0.6]])
+    r = solver.relative_changes(Un, Uo, 2)
+    np.testing.assert_allclose(r, [0.0, 0.1, 0.2], rtol=1e-15, atol=0)
 
 
 def test_converged_step_does_not_depend_on_lagged_facets():
