@@ -172,6 +172,14 @@ int tgs_dag_sweep_lanes(const tgs_dag* dag);
  * coordinates, vol [n_cells] cell measures. */
 int tgs_dag_geometry(const tgs_dag* dag, double* node_x, double* bnode_x, double* vol);
 
+/* The time step of eq. explicit-dt (Sec. 5) scaled by a CFL factor:
+ * dt = cfl * (1/d) * (1/(2k+1)) * h_min / max_j |v_j|, with
+ * h_min = (min_K |K|)^(1/d) over the DAG's cells and the maximum over its
+ * velocity set (k the DG order).  Host computation on data the DAG keeps;
+ * no device work.  BGK_E_INVALID for a null argument, cfl <= 0 or a velocity
+ * set of zero speed. */
+int tgs_dag_explicit_dt(const tgs_dag* dag, double cfl, double* dt);
+
 /* Canonical -> sweep layout and back (device pointers, no aliasing). */
 int tgs_pack(const tgs_dag* dag, const double* f_canonical, double* f_sweep, bgk_stream_t stream);
 int tgs_unpack(const tgs_dag* dag, const double* f_sweep, double* f_canonical, bgk_stream_t stream);

@@ -33,7 +33,8 @@ TABLEAU = {"BE": 0, "DIRK2": 1, "DIRK3": 2, "BDIRK2": 3}
 
 EXPORTED = [
     "bgk_last_error", "build_mesh_dag", "tgs_dag_destroy", "tgs_dag_sizes",
-    "tgs_dag_generations", "tgs_dag_lagged", "tgs_dag_geometry", "tgs_pack", "tgs_unpack",
+    "tgs_dag_generations", "tgs_dag_lagged", "tgs_dag_geometry", "tgs_dag_explicit_dt",
+    "tgs_pack", "tgs_unpack",
     "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
     "tgs_eval_maxwellian", "bgk_solver_create", "bgk_solver_destroy", "bgk_step",
     "bgk_mlp_create", "bgk_mlp_destroy", "bgk_mlp_set_params", "bgk_mlp_get_params",
@@ -129,6 +130,7 @@ _lib.tgs_dag_sweep_lanes.argtypes = [C.c_void_p]
 _lib.tgs_dag_generations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_dag_lagged.argtypes = [C.c_void_p, C.c_void_p]
 _lib.tgs_dag_geometry.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tgs_dag_explicit_dt.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_double)]
 _lib.tgs_pack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_unpack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_sweep.argtypes = [C.c_void_p, C.POINTER(SweepIO), C.c_void_p]
@@ -241,11 +243,10 @@ class Dag:
         return out
 
     def explicit_dt(self, cfl):
-        """dt = C (1/d) (1/(2k+1)) h_min / max|v| with h_min = (min |K|)^(1/d) (eq. explicit-dt)."""
-        _, _, vol = self.geometry()
-        hmin = float(vol.min()) ** (1.0 / self.dim)
-        vmax = float(torch.linalg.norm(self.v, dim=1).max())
-        return cfl * (1.0 / self.dim) * (1.0 / (2 * self.order + 1)) * hmin / vmax
+        """dt = C dt_e of eq. explicit-dt, computed by the library."""
+        dt = C.c_double()
+        _check(_lib.tgs_dag_explicit_dt(self.h, C.c_double(cfl), C.byref(dt)))
+        return dt.value
 
 
 def tgs_sweep(dag, *, q, nu, mcoef, f_out, sigma_shift, q_scale=1.0, bc_coef=None,

@@ -1,5 +1,8 @@
 """Build the HIP shared library libbgktgs.so for gfx950 in-tree.
 
+Each source is compiled to an object of its own (in parallel, under
+``_build/``), then the objects are linked into ``libbgktgs.so``.
+
 Usage: python -m paper_2608_19150_amd.build   (or call build()).
 """
 from __future__ import annotations
@@ -8,10 +11,15 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libbgktgs.so")
+OBJ_DIR = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("BGK_OFFLOAD_ARCH", "gfx950")
+FLAGS = ["-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
 
 
 def hip_sources():
@@ -19,20 +27,28 @@ def hip_sources():
                   glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source of the library into libbgktgs.so."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    out_tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-o", out_tmp] + hip_sources()
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libbgktgs.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP/C++ source of the library and link libbgktgs.so."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    srcs = hip_sources()
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + ".o") for s in srcs]
+    cmds = [[hipcc, f"--offload-arch={ARCH}"] + FLAGS + ["-c", s, "-o", o]
+            for s, o in zip(srcs, objs)]
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    out_tmp = LIB + ".tmp"
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs, verbose)
     os.replace(out_tmp, LIB)
     return LIB
 

@@ -12,6 +12,14 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+int fail_static(int code, const char* msg) noexcept {
+  try {
+    g_last_error = msg;
+  } catch (...) {
+    g_last_error.clear();
+  }
+  return code;
+}
 const char* last_error_cstr() { return g_last_error.c_str(); }
 }  // namespace bgk
 

@@ -392,286 +392,294 @@ int capture_graphs(bgk_batch* B) {
 
 extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_batch_opts* opts,
                                 bgk_batch** out) {
-  if (!solvers || n <= 0 || !out) return fail(BGK_E_INVALID, "bad arguments");
-  *out = nullptr;
-  bgk_batch_opts o{};
-  if (opts) o = *opts;
-  if (o.chunk_iters <= 0) o.chunk_iters = 4;
-  if (o.sweep_threads <= 0) o.sweep_threads = 128;
-  if (o.sweep_threads % 64 || o.sweep_threads > 256)
-    return fail(BGK_E_INVALID, "sweep_threads must be a multiple of 64 up to 256");
-  const bgk_solver* s0 = solvers[0];
-  if (!s0) return fail(BGK_E_INVALID, "null solver");
-  bool tab = true;
-  int64_t n_nodes = 0, n_tab = 0;
-  for (int i = 0; i < n; ++i) {
-    const bgk_solver* s = solvers[i];
-    if (!s) return fail(BGK_E_INVALID, "null solver");
-    const tgs_dag* d = s->dag;
-    if (d->dim != s0->dag->dim) return fail(BGK_E_UNSUPPORTED, "instances must share the dimension");
-    if (s->opts.tableau != s0->opts.tableau)
-      return fail(BGK_E_UNSUPPORTED, "instances must share the tableau");
-    if (s->opts.precision != TGS_FP64)
-      return fail(BGK_E_UNSUPPORTED, "batched stepping runs the FP64 sweep");
-    if (d->d_lag) return fail(BGK_E_UNSUPPORTED, "batched stepping needs acyclic sweep graphs");
-    if (d->dim == 3 && d->order != 1) return fail(BGK_E_UNSUPPORTED, "3D instances must be P1");
-    if (s->opts.maxw_mode == BGK_MAXW_PROJECTED)
-      return fail(BGK_E_UNSUPPORTED, "batched stepping has no projected Maxwellian");
-    if (s->opts.walls) return fail(BGK_E_UNSUPPORTED, "batched stepping has no wall boundaries");
-    tab = tab && s->mtab != nullptr;
-    n_nodes += d->n_nodes;
-  }
-  bgk_batch* B = new (std::nothrow) bgk_batch();
-  if (!B) return fail(BGK_E_NOMEM, "host allocation failed");
-  B->n = n;
-  B->dim = s0->dag->dim;
-  B->S = s0->S;
-  B->stiffly_accurate = s0->stiffly_accurate;
-  B->tab = tab;
-  B->opts = o;
-  B->solvers.assign(solvers, solvers + n);
-  B->n_nodes = n_nodes;
-  int rc = BGK_OK;
-  auto check = [&](hipError_t e, const char* what) {
-    if (!rc && e != hipSuccess) rc = fail(BGK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-  };
-  check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
-  check(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming), "hipEventCreate");
-  check(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming), "hipEventCreate");
-  check(hipEventCreate(&B->t0), "hipEventCreate");
-  check(hipEventCreate(&B->t1), "hipEventCreate");
-  // per-instance layout tables
-  std::vector<int64_t> nfirst(n + 1, 0), tfirst(n + 1, 0);
-  std::vector<int32_t> mfirst(n + 1, 0);
-  int64_t npart = 0;
-  for (int i = 0; i < n; ++i) {
-    const tgs_dag* d = solvers[i]->dag;
-    nfirst[i + 1] = nfirst[i] + d->n_nodes;
-    tfirst[i + 1] =
-        tfirst[i] + (tab ? table_threads(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table threads
-    mfirst[i + 1] = mfirst[i] + moment_blocks(d);
-    npart += (int64_t)moment_blocks(d) * 6;
-  }
-  n_tab = tfirst[n];
-  B->n_tab = n_tab;
-  B->mom_blocks = mfirst[n];
-  // sweep blocks: every instance's velocities, longest generation count first
-  std::vector<std::pair<int, int2>> blocks;
-  for (int i = 0; i < n && !rc; ++i) {
-    const tgs_dag* d = solvers[i]->dag;
-    std::vector<int32_t> vorder(d->n_v);
-    check(hipMemcpy(vorder.data(), d->d_vorder, d->n_v * sizeof(int32_t), hipMemcpyDeviceToHost),
-          "hipMemcpy");
-    for (int y = 0; y < d->n_v; ++y) blocks.push_back({d->G_host[vorder[y]], make_int2(i, y)});
-  }
-  std::stable_sort(blocks.begin(), blocks.end(),
-                   [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) {
-                     return a.first > b.first;
-                   });
-  std::vector<int2> map(blocks.size());
-  for (size_t b = 0; b < blocks.size(); ++b) map[b] = blocks[b].second;
-  B->nblocks = (int)map.size();
-  std::vector<ConvArgs> conv(n);
-  for (int i = 0; i < n; ++i) {
-    const bgk_solver_opts& so = solvers[i]->opts;
-    conv[i] = ConvArgs{so.tau, so.dt, so.l_max, so.fixed_iters};
-  }
-  if (!rc) rc = dalloc(&B->sargs, (size_t)B->S * n);
-  if (!rc) rc = dalloc(&B->sargs_tune, (size_t)n);
-  if (!rc) rc = dalloc(&B->kin, (size_t)(B->S + 2) * n);
-  if (!rc) rc = dalloc(&B->comb, (size_t)(B->S + 1) * n);
-  if (!rc) rc = dalloc(&B->conv, (size_t)n);
-  if (!rc) rc = dalloc(&B->map, map.size());
-  if (!rc) rc = dalloc(&B->mom_first, (size_t)n + 1);
-  if (!rc) rc = dalloc(&B->node_first, (size_t)n + 1);
-  if (!rc) rc = dalloc(&B->tab_first, (size_t)n + 1);
-  if (!rc) rc = dalloc(&B->ctl_mem, (size_t)5 * n);
-  if (!rc) rc = dalloc(&B->last, (size_t)n);
-  if (!rc) rc = dalloc(&B->status, (size_t)2 * n);
-  if (!rc) rc = dalloc(&B->numax, (size_t)n);
-  if (!rc) rc = dalloc(&B->ratio, (size_t)4 * n);
-  if (!rc) rc = dalloc(&B->partial, (size_t)npart);
-  if (!rc) rc = dalloc(&B->sticky, (size_t)n_nodes);
-  if (!rc && hipHostMalloc((void**)&B->h_ctl, (size_t)5 * n * sizeof(int32_t)) != hipSuccess)
-    rc = fail(BGK_E_NOMEM, "pinned allocation failed");
-  if (!rc && hipHostMalloc((void**)&B->h_last, (size_t)n * sizeof(double)) != hipSuccess)
-    rc = fail(BGK_E_NOMEM, "pinned allocation failed");
-  if (!rc) {
-    check(hipMemcpy(B->map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice), "hipMemcpy");
-    check(hipMemcpy(B->mom_first, mfirst.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
-          "hipMemcpy");
-    check(hipMemcpy(B->node_first, nfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
-          "hipMemcpy");
-    check(hipMemcpy(B->tab_first, tfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
-          "hipMemcpy");
-    check(hipMemcpy(B->conv, conv.data(), n * sizeof(ConvArgs), hipMemcpyHostToDevice), "hipMemcpy");
-  }
-  if (rc) {
-    bgk_batch_destroy(B);
-    return rc;
-  }
-  *out = B;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!solvers || n <= 0 || !out) return fail(BGK_E_INVALID, "bad arguments");
+    *out = nullptr;
+    bgk_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.chunk_iters <= 0) o.chunk_iters = 4;
+    if (o.sweep_threads <= 0) o.sweep_threads = 128;
+    if (o.sweep_threads % 64 || o.sweep_threads > 256)
+      return fail(BGK_E_INVALID, "sweep_threads must be a multiple of 64 up to 256");
+    const bgk_solver* s0 = solvers[0];
+    if (!s0) return fail(BGK_E_INVALID, "null solver");
+    bool tab = true;
+    int64_t n_nodes = 0, n_tab = 0;
+    for (int i = 0; i < n; ++i) {
+      const bgk_solver* s = solvers[i];
+      if (!s) return fail(BGK_E_INVALID, "null solver");
+      const tgs_dag* d = s->dag;
+      if (d->dim != s0->dag->dim) return fail(BGK_E_UNSUPPORTED, "instances must share the dimension");
+      if (s->opts.tableau != s0->opts.tableau)
+        return fail(BGK_E_UNSUPPORTED, "instances must share the tableau");
+      if (s->opts.precision != TGS_FP64)
+        return fail(BGK_E_UNSUPPORTED, "batched stepping runs the FP64 sweep");
+      if (d->d_lag) return fail(BGK_E_UNSUPPORTED, "batched stepping needs acyclic sweep graphs");
+      if (d->dim == 3 && d->order != 1) return fail(BGK_E_UNSUPPORTED, "3D instances must be P1");
+      if (s->opts.maxw_mode == BGK_MAXW_PROJECTED)
+        return fail(BGK_E_UNSUPPORTED, "batched stepping has no projected Maxwellian");
+      if (s->opts.walls) return fail(BGK_E_UNSUPPORTED, "batched stepping has no wall boundaries");
+      tab = tab && s->mtab != nullptr;
+      n_nodes += d->n_nodes;
+    }
+    bgk_batch* B = new (std::nothrow) bgk_batch();
+    if (!B) return fail(BGK_E_NOMEM, "host allocation failed");
+    B->n = n;
+    B->dim = s0->dag->dim;
+    B->S = s0->S;
+    B->stiffly_accurate = s0->stiffly_accurate;
+    B->tab = tab;
+    B->opts = o;
+    B->solvers.assign(solvers, solvers + n);
+    B->n_nodes = n_nodes;
+    int rc = BGK_OK;
+    auto check = [&](hipError_t e, const char* what) {
+      if (!rc && e != hipSuccess) rc = fail(BGK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
+    check(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming), "hipEventCreate");
+    check(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming), "hipEventCreate");
+    check(hipEventCreate(&B->t0), "hipEventCreate");
+    check(hipEventCreate(&B->t1), "hipEventCreate");
+    // per-instance layout tables
+    std::vector<int64_t> nfirst(n + 1, 0), tfirst(n + 1, 0);
+    std::vector<int32_t> mfirst(n + 1, 0);
+    int64_t npart = 0;
+    for (int i = 0; i < n; ++i) {
+      const tgs_dag* d = solvers[i]->dag;
+      nfirst[i + 1] = nfirst[i] + d->n_nodes;
+      tfirst[i + 1] =
+          tfirst[i] + (tab ? table_threads(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table threads
+      mfirst[i + 1] = mfirst[i] + moment_blocks(d);
+      npart += (int64_t)moment_blocks(d) * 6;
+    }
+    n_tab = tfirst[n];
+    B->n_tab = n_tab;
+    B->mom_blocks = mfirst[n];
+    // sweep blocks: every instance's velocities, longest generation count first
+    std::vector<std::pair<int, int2>> blocks;
+    for (int i = 0; i < n && !rc; ++i) {
+      const tgs_dag* d = solvers[i]->dag;
+      std::vector<int32_t> vorder(d->n_v);
+      check(hipMemcpy(vorder.data(), d->d_vorder, d->n_v * sizeof(int32_t), hipMemcpyDeviceToHost),
+            "hipMemcpy");
+      for (int y = 0; y < d->n_v; ++y) blocks.push_back({d->G_host[vorder[y]], make_int2(i, y)});
+    }
+    std::stable_sort(blocks.begin(), blocks.end(),
+                     [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) {
+                       return a.first > b.first;
+                     });
+    std::vector<int2> map(blocks.size());
+    for (size_t b = 0; b < blocks.size(); ++b) map[b] = blocks[b].second;
+    B->nblocks = (int)map.size();
+    std::vector<ConvArgs> conv(n);
+    for (int i = 0; i < n; ++i) {
+      const bgk_solver_opts& so = solvers[i]->opts;
+      conv[i] = ConvArgs{so.tau, so.dt, so.l_max, so.fixed_iters};
+    }
+    if (!rc) rc = dalloc(&B->sargs, (size_t)B->S * n);
+    if (!rc) rc = dalloc(&B->sargs_tune, (size_t)n);
+    if (!rc) rc = dalloc(&B->kin, (size_t)(B->S + 2) * n);
+    if (!rc) rc = dalloc(&B->comb, (size_t)(B->S + 1) * n);
+    if (!rc) rc = dalloc(&B->conv, (size_t)n);
+    if (!rc) rc = dalloc(&B->map, map.size());
+    if (!rc) rc = dalloc(&B->mom_first, (size_t)n + 1);
+    if (!rc) rc = dalloc(&B->node_first, (size_t)n + 1);
+    if (!rc) rc = dalloc(&B->tab_first, (size_t)n + 1);
+    if (!rc) rc = dalloc(&B->ctl_mem, (size_t)5 * n);
+    if (!rc) rc = dalloc(&B->last, (size_t)n);
+    if (!rc) rc = dalloc(&B->status, (size_t)2 * n);
+    if (!rc) rc = dalloc(&B->numax, (size_t)n);
+    if (!rc) rc = dalloc(&B->ratio, (size_t)4 * n);
+    if (!rc) rc = dalloc(&B->partial, (size_t)npart);
+    if (!rc) rc = dalloc(&B->sticky, (size_t)n_nodes);
+    if (!rc && hipHostMalloc((void**)&B->h_ctl, (size_t)5 * n * sizeof(int32_t)) != hipSuccess)
+      rc = fail(BGK_E_NOMEM, "pinned allocation failed");
+    if (!rc && hipHostMalloc((void**)&B->h_last, (size_t)n * sizeof(double)) != hipSuccess)
+      rc = fail(BGK_E_NOMEM, "pinned allocation failed");
+    if (!rc) {
+      check(hipMemcpy(B->map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice), "hipMemcpy");
+      check(hipMemcpy(B->mom_first, mfirst.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
+            "hipMemcpy");
+      check(hipMemcpy(B->node_first, nfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
+            "hipMemcpy");
+      check(hipMemcpy(B->tab_first, tfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
+            "hipMemcpy");
+      check(hipMemcpy(B->conv, conv.data(), n * sizeof(ConvArgs), hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    if (rc) {
+      bgk_batch_destroy(B);
+      return rc;
+    }
+    *out = B;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_batch_destroy(bgk_batch* B) {
-  if (!B) return BGK_OK;
-  for (hipGraphExec_t e : B->exec)
-    if (e) (void)hipGraphExecDestroy(e);
-  for (hipGraph_t g : B->graphs)
-    if (g) (void)hipGraphDestroy(g);
-  void* ptrs[] = {B->sargs,  B->sargs_tune, B->kin,    B->comb,   B->conv,   B->map,
-                  B->mom_first, B->node_first, B->tab_first, B->ctl_mem, B->last, B->status,
-                  B->numax,  B->ratio,      B->partial, B->sticky};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (B->h_ctl) (void)hipHostFree(B->h_ctl);
-  if (B->h_last) (void)hipHostFree(B->h_last);
-  hipEvent_t evs[] = {B->ev_in, B->ev_out, B->t0, B->t1};
-  for (hipEvent_t e : evs)
-    if (e) (void)hipEventDestroy(e);
-  if (B->stream) (void)hipStreamDestroy(B->stream);
-  delete B;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!B) return BGK_OK;
+    for (hipGraphExec_t e : B->exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : B->graphs)
+      if (g) (void)hipGraphDestroy(g);
+    void* ptrs[] = {B->sargs,  B->sargs_tune, B->kin,    B->comb,   B->conv,   B->map,
+                    B->mom_first, B->node_first, B->tab_first, B->ctl_mem, B->last, B->status,
+                    B->numax,  B->ratio,      B->partial, B->sticky};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    if (B->h_ctl) (void)hipHostFree(B->h_ctl);
+    if (B->h_last) (void)hipHostFree(B->h_last);
+    hipEvent_t evs[] = {B->ev_in, B->ev_out, B->t0, B->t1};
+    for (hipEvent_t e : evs)
+      if (e) (void)hipEventDestroy(e);
+    if (B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_batch_step(bgk_batch* B, double* const* f, bgk_batch_stats* stats,
                               bgk_stream_t stream_) {
-  if (!B || !f) return fail(BGK_E_INVALID, "null argument");
-  for (int i = 0; i < B->n; ++i)
-    if (!f[i]) return fail(BGK_E_INVALID, "null f for instance " + std::to_string(i));
-  const auto t_start = std::chrono::steady_clock::now();
-  const int n = B->n, S = B->S;
-  hipStream_t caller = (hipStream_t)stream_;
-  int rc;
-  // order after the caller's prior work
-  BGK_HIP(hipEventRecord(B->ev_in, caller));
-  BGK_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
-  if (B->f_bound.size() != (size_t)n || !std::equal(B->f_bound.begin(), B->f_bound.end(), f)) {
-    if ((rc = batch_upload(B, f))) return rc;
-  }
-  if (B->opts.graph && B->exec.empty() && (rc = capture_graphs(B))) return rc;
-  const Ctl c = B->ctl();
-  std::vector<bgk_batch_stats> st(n);
-  for (int i = 0; i < n; ++i) st[i].stages = S;
-  std::vector<double> finish(n, 0.0);
-  hipLaunchKernelGGL(k_step_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
-  BGK_HIP(hipGetLastError());
-  if ((rc = launch_combine(B, 0, nullptr))) return rc;  // f^k
-  if ((rc = launch_moments_batch(B->dim, B->kin, c.par, c.done, B->mom_first, n, B->mom_blocks,
-                                 false, B->stream)))
-    return rc;
-  hipLaunchKernelGGL(k_set_par, inst_grid(n), dim3(64), 0, B->stream, c.par, 0, n);
-  BGK_HIP(hipGetLastError());
-  for (int s = 0; s < S; ++s) {
-    if (s > 0 && (rc = launch_combine(B, s, c.done))) return rc;
-    hipLaunchKernelGGL(k_stage_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
-    BGK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_clear_bytes, dim3((unsigned)std::min<int64_t>((B->n_nodes + 255) / 256, 4096)),
-                       dim3(256), 0, B->stream, B->sticky, B->n_nodes);
-    BGK_HIP(hipGetLastError());
-    std::vector<int> running(n, 1);
-    for (;;) {
-      if (B->opts.graph) {
-        BGK_HIP(hipGraphLaunch(B->exec[s], B->stream));
-      } else if ((rc = run_chunk(B, s))) {
-        return rc;
-      }
-      BGK_HIP(hipMemcpyAsync(B->h_ctl, B->ctl_mem, (size_t)5 * n * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, B->stream));
-      BGK_HIP(hipMemcpyAsync(B->h_last, B->last, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
-                             B->stream));
-      BGK_HIP(hipStreamSynchronize(B->stream));
-      const double now =
-          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-      bool all = true;
-      for (int i = 0; i < n; ++i) {
-        const int done = B->h_ctl[i];
-        if (done == 0) {
-          all = false;
-          continue;
-        }
-        if (running[i]) {
-          running[i] = 0;
-          st[i].iters[s] = B->h_ctl[2 * n + i];
-          st[i].total_iters += st[i].iters[s];
-          st[i].last_ratio[s] = B->h_last[i];
-          if (done == 2 && st[i].status == BGK_OK) st[i].status = B->h_ctl[4 * n + i];
-          if ((s == S - 1 || done == 2) && finish[i] == 0.0) finish[i] = now;
-        }
-      }
-      if (all) break;
+  return guarded([&]() -> int {
+    if (!B || !f) return fail(BGK_E_INVALID, "null argument");
+    for (int i = 0; i < B->n; ++i)
+      if (!f[i]) return fail(BGK_E_INVALID, "null f for instance " + std::to_string(i));
+    const auto t_start = std::chrono::steady_clock::now();
+    const int n = B->n, S = B->S;
+    hipStream_t caller = (hipStream_t)stream_;
+    int rc;
+    // order after the caller's prior work
+    BGK_HIP(hipEventRecord(B->ev_in, caller));
+    BGK_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
+    if (B->f_bound.size() != (size_t)n || !std::equal(B->f_bound.begin(), B->f_bound.end(), f)) {
+      if ((rc = batch_upload(B, f))) return rc;
     }
-  }
-  if (!B->stiffly_accurate && (rc = launch_combine(B, S, c.done))) return rc;
-  BGK_HIP(hipMemcpyAsync(B->h_ctl, B->ctl_mem, (size_t)5 * n * sizeof(int32_t),
-                         hipMemcpyDeviceToHost, B->stream));
-  BGK_HIP(hipStreamSynchronize(B->stream));
-  BGK_HIP(hipEventRecord(B->ev_out, B->stream));
-  BGK_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
-  int first_err = BGK_OK, first_inst = -1;
-  for (int i = 0; i < n; ++i) {
-    st[i].maxw_fallbacks = B->h_ctl[3 * n + i];
-    st[i].finish_ms = finish[i];
-    if (st[i].status != BGK_OK && first_err == BGK_OK) {
-      first_err = st[i].status;
-      first_inst = i;
+    if (B->opts.graph && B->exec.empty() && (rc = capture_graphs(B))) return rc;
+    const Ctl c = B->ctl();
+    std::vector<bgk_batch_stats> st(n);
+    for (int i = 0; i < n; ++i) st[i].stages = S;
+    std::vector<double> finish(n, 0.0);
+    hipLaunchKernelGGL(k_step_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
+    BGK_HIP(hipGetLastError());
+    if ((rc = launch_combine(B, 0, nullptr))) return rc;  // f^k
+    if ((rc = launch_moments_batch(B->dim, B->kin, c.par, c.done, B->mom_first, n, B->mom_blocks,
+                                   false, B->stream)))
+      return rc;
+    hipLaunchKernelGGL(k_set_par, inst_grid(n), dim3(64), 0, B->stream, c.par, 0, n);
+    BGK_HIP(hipGetLastError());
+    for (int s = 0; s < S; ++s) {
+      if (s > 0 && (rc = launch_combine(B, s, c.done))) return rc;
+      hipLaunchKernelGGL(k_stage_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
+      BGK_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_clear_bytes, dim3((unsigned)std::min<int64_t>((B->n_nodes + 255) / 256, 4096)),
+                         dim3(256), 0, B->stream, B->sticky, B->n_nodes);
+      BGK_HIP(hipGetLastError());
+      std::vector<int> running(n, 1);
+      for (;;) {
+        if (B->opts.graph) {
+          BGK_HIP(hipGraphLaunch(B->exec[s], B->stream));
+        } else if ((rc = run_chunk(B, s))) {
+          return rc;
+        }
+        BGK_HIP(hipMemcpyAsync(B->h_ctl, B->ctl_mem, (size_t)5 * n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, B->stream));
+        BGK_HIP(hipMemcpyAsync(B->h_last, B->last, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                               B->stream));
+        BGK_HIP(hipStreamSynchronize(B->stream));
+        const double now =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        bool all = true;
+        for (int i = 0; i < n; ++i) {
+          const int done = B->h_ctl[i];
+          if (done == 0) {
+            all = false;
+            continue;
+          }
+          if (running[i]) {
+            running[i] = 0;
+            st[i].iters[s] = B->h_ctl[2 * n + i];
+            st[i].total_iters += st[i].iters[s];
+            st[i].last_ratio[s] = B->h_last[i];
+            if (done == 2 && st[i].status == BGK_OK) st[i].status = B->h_ctl[4 * n + i];
+            if ((s == S - 1 || done == 2) && finish[i] == 0.0) finish[i] = now;
+          }
+        }
+        if (all) break;
+      }
     }
-  }
-  if (stats) std::copy(st.begin(), st.end(), stats);
-  if (first_err != BGK_OK)
-    return fail(first_err, "instance " + std::to_string(first_inst) +
-                               (first_err == BGK_E_NONPHYSICAL ? ": non-physical moments"
-                                                               : ": Picard iteration reached l_max"));
-  return BGK_OK;
+    if (!B->stiffly_accurate && (rc = launch_combine(B, S, c.done))) return rc;
+    BGK_HIP(hipMemcpyAsync(B->h_ctl, B->ctl_mem, (size_t)5 * n * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, B->stream));
+    BGK_HIP(hipStreamSynchronize(B->stream));
+    BGK_HIP(hipEventRecord(B->ev_out, B->stream));
+    BGK_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
+    int first_err = BGK_OK, first_inst = -1;
+    for (int i = 0; i < n; ++i) {
+      st[i].maxw_fallbacks = B->h_ctl[3 * n + i];
+      st[i].finish_ms = finish[i];
+      if (st[i].status != BGK_OK && first_err == BGK_OK) {
+        first_err = st[i].status;
+        first_inst = i;
+      }
+    }
+    if (stats) std::copy(st.begin(), st.end(), stats);
+    if (first_err != BGK_OK)
+      return fail(first_err, "instance " + std::to_string(first_inst) +
+                                 (first_err == BGK_E_NONPHYSICAL ? ": non-physical moments"
+                                                                 : ": Picard iteration reached l_max"));
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads, int reps,
                                     float* ms, bgk_stream_t stream_) {
-  if (!B || !f || !ms || reps <= 0) return fail(BGK_E_INVALID, "bad arguments");
-  if (threads <= 0 || threads % 64 || threads > 256)
-    return fail(BGK_E_INVALID, "threads must be a multiple of 64 up to 256");
-  for (int i = 0; i < B->n; ++i)
-    if (!f[i]) return fail(BGK_E_INVALID, "null f");
-  const int n = B->n;
-  int rc;
-  hipStream_t caller = (hipStream_t)stream_;
-  BGK_HIP(hipEventRecord(B->ev_in, caller));
-  BGK_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
-  if (B->f_bound.size() != (size_t)n || !std::equal(B->f_bound.begin(), B->f_bound.end(), f)) {
-    if ((rc = batch_upload(B, f))) return rc;
-  }
-  const Ctl c = B->ctl();
-  // the Maxwellian of f's moments, then `reps` sweeps of f into f^k
-  hipLaunchKernelGGL(k_step_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
-  BGK_HIP(hipGetLastError());
-  if ((rc = launch_moments_batch(B->dim, B->kin + (size_t)(B->S + 1) * n, c.par, c.done,
-                                 B->mom_first, n, B->mom_blocks, false, B->stream)))
-    return rc;
-  hipLaunchKernelGGL(k_set_par, inst_grid(n), dim3(64), 0, B->stream, c.par, 0, n);
-  hipLaunchKernelGGL(k_clear_bytes, dim3((unsigned)std::min<int64_t>((B->n_nodes + 255) / 256, 4096)),
-                     dim3(256), 0, B->stream, B->sticky, B->n_nodes);
-  hipLaunchKernelGGL(k_iter_reset, inst_grid(n), dim3(64), 0, B->stream, c.done, B->status,
-                     B->numax, n);
-  BGK_HIP(hipGetLastError());
-  const BatchKin* kin = B->kin + (size_t)n;
-  if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->node_first, n, B->n_nodes,
-                                    B->stream)))
-    return rc;
-  if (B->tab &&
-      (rc = launch_tables_batch(B->dim, kin, c.done, B->tab_first, n, B->n_tab, B->stream)))
-    return rc;
-  BGK_HIP(hipEventRecord(B->t0, B->stream));
-  for (int r = 0; r < reps; ++r)
-    if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, B->map, B->nblocks, c.done,
-                                 threads, B->stream)))
+  return guarded([&]() -> int {
+    if (!B || !f || !ms || reps <= 0) return fail(BGK_E_INVALID, "bad arguments");
+    if (threads <= 0 || threads % 64 || threads > 256)
+      return fail(BGK_E_INVALID, "threads must be a multiple of 64 up to 256");
+    for (int i = 0; i < B->n; ++i)
+      if (!f[i]) return fail(BGK_E_INVALID, "null f");
+    const int n = B->n;
+    int rc;
+    hipStream_t caller = (hipStream_t)stream_;
+    BGK_HIP(hipEventRecord(B->ev_in, caller));
+    BGK_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
+    if (B->f_bound.size() != (size_t)n || !std::equal(B->f_bound.begin(), B->f_bound.end(), f)) {
+      if ((rc = batch_upload(B, f))) return rc;
+    }
+    const Ctl c = B->ctl();
+    // the Maxwellian of f's moments, then `reps` sweeps of f into f^k
+    hipLaunchKernelGGL(k_step_init, inst_grid(n), dim3(64), 0, B->stream, c, n);
+    BGK_HIP(hipGetLastError());
+    if ((rc = launch_moments_batch(B->dim, B->kin + (size_t)(B->S + 1) * n, c.par, c.done,
+                                   B->mom_first, n, B->mom_blocks, false, B->stream)))
       return rc;
-  BGK_HIP(hipEventRecord(B->t1, B->stream));
-  BGK_HIP(hipEventSynchronize(B->t1));
-  float t = 0.0f;
-  BGK_HIP(hipEventElapsedTime(&t, B->t0, B->t1));
-  *ms = t / reps;
-  BGK_HIP(hipEventRecord(B->ev_out, B->stream));
-  BGK_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
-  return BGK_OK;
+    hipLaunchKernelGGL(k_set_par, inst_grid(n), dim3(64), 0, B->stream, c.par, 0, n);
+    hipLaunchKernelGGL(k_clear_bytes, dim3((unsigned)std::min<int64_t>((B->n_nodes + 255) / 256, 4096)),
+                       dim3(256), 0, B->stream, B->sticky, B->n_nodes);
+    hipLaunchKernelGGL(k_iter_reset, inst_grid(n), dim3(64), 0, B->stream, c.done, B->status,
+                       B->numax, n);
+    BGK_HIP(hipGetLastError());
+    const BatchKin* kin = B->kin + (size_t)n;
+    if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->node_first, n, B->n_nodes,
+                                      B->stream)))
+      return rc;
+    if (B->tab &&
+        (rc = launch_tables_batch(B->dim, kin, c.done, B->tab_first, n, B->n_tab, B->stream)))
+      return rc;
+    BGK_HIP(hipEventRecord(B->t0, B->stream));
+    for (int r = 0; r < reps; ++r)
+      if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, B->map, B->nblocks, c.done,
+                                   threads, B->stream)))
+        return rc;
+    BGK_HIP(hipEventRecord(B->t1, B->stream));
+    BGK_HIP(hipEventSynchronize(B->t1));
+    float t = 0.0f;
+    BGK_HIP(hipEventElapsedTime(&t, B->t0, B->t1));
+    *ms = t / reps;
+    BGK_HIP(hipEventRecord(B->ev_out, B->stream));
+    BGK_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
+    return BGK_OK;
+  });
 }

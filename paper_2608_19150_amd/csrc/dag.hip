@@ -279,7 +279,7 @@ struct DagArgs {
   const FacetRec* facet;
   const double* v;
   const uint8_t* user_lag;   // [n_v][n_cells] internal order, or null
-  uint8_t* lag;              // [n_v][n_cells] output lag bits, or null
+  uint8_t* lag;              // [n_v][n_cells] output lag bits (may alias user_lag)
   int32_t* perm;             // [n_v][n_cells]
   int32_t* pos;              // [n_v][n_cells]
   int32_t* scratch_cnt;      // [batch][n_cells+1]  generation offsets (batch-local)
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
     const int bits = inflow_bits<DIM>(a.geo, a.facet, K, v, ul);
     indeg[K] = __popc(bits);
     gen[K] = -1;
-    if (lag) lag[K] = (uint8_t)ul;
+    lag[K] = (uint8_t)ul;
   }
   __syncthreads();
   for (int K = tid; K < nc; K += bs)
@@ -326,8 +326,16 @@ __global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
   int head = 0, tail = s_tail, g = 0;
   while (head < nc) {
     if (head == tail) {
-      // the remaining cells form cycles: release the lowest-numbered one and
-      // lag its in-edges from unreleased cells
+      // Every remaining cell still has an in-edge from another remaining
+      // cell, so the remaining graph has a cycle.  Walk in-edges backwards
+      // from the lowest-numbered remaining cell (each step to the in-neighbour
+      // across the lowest-indexed facet) until a cell repeats: the edge that
+      // closes that loop lies on a cycle and is lagged (its downwind cell
+      // takes that facet's inflow from the previous iterate, Sec. 4.1).  One
+      // edge per walk, walks repeated until a cell loses its last remaining
+      // in-edge and is released.  Only edges that lie on a cycle are lagged.
+      // The levels of this pass are not longest paths once something was
+      // lagged; the host then repeats the pass on the final lagged set.
       if (tid == 0) s_min = INT32_MAX;
       __syncthreads();
       int mymin = INT32_MAX;
@@ -335,26 +343,53 @@ __global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
         if (gen[K] < 0) mymin = min(mymin, K);
       atomicMin(&s_min, mymin);
       __syncthreads();
-      const int K = s_min;
-      if (K == INT32_MAX) break;  // inconsistent bookkeeping: stop (G < cells flags it)
+      const int K0 = s_min;
+      if (K0 == INT32_MAX) break;  // inconsistent bookkeeping: stop (G < cells flags it)
       if (tid == 0) {
-        const int ul = ulag ? ulag[K] : 0;
-        const int bits = inflow_bits<DIM>(a.geo, a.facet, K, v, ul);
-        int extra = 0;
-        for (int k = 0; k <= DIM; ++k)
-          if ((bits >> k) & 1) {
-            const int nbk = a.facet[(size_t)K * (DIM + 1) + k].nb;
-            if (gen[nbk] < 0) extra |= 1 << k;
+        int32_t* path = cnt;  // scratch: free until the histogram below
+        bool released = false, stuck = false;
+        while (!released && !stuck) {
+          int c = K0, len = 0;
+          gen[c] = -2;
+          path[len++] = c;
+          for (;;) {
+            const int cur = lag[c];
+            const int bits = inflow_bits<DIM>(a.geo, a.facet, c, v, cur);
+            int p = -1, kp = -1;
+            for (int k = 0; k <= DIM && p < 0; ++k)
+              if ((bits >> k) & 1) {
+                const int nbk = a.facet[(size_t)c * (DIM + 1) + k].nb;
+                if (gen[nbk] < 0) {
+                  p = nbk;
+                  kp = k;
+                }
+              }
+            if (p < 0) {  // no remaining in-edge: cannot happen with indeg[c] > 0
+              stuck = true;
+              break;
+            }
+            if (gen[p] <= -2) {  // p is on this walk: the edge p -> c closes a cycle
+              lag[c] = (uint8_t)(cur | (1 << kp));
+              atomicAdd(a.n_lagged, 1ull);
+              if (--indeg[c] == 0) {
+                queue[tail] = c;
+                gen[c] = g;
+                released = true;
+              }
+              break;
+            }
+            gen[p] = -2;
+            path[len++] = p;
+            c = p;
           }
-        if (lag) lag[K] = (uint8_t)(ul | extra);
-        atomicAdd(a.n_lagged, (unsigned long long)__popc(extra));
-        indeg[K] = 0;
-        queue[tail] = K;
-        gen[K] = g;
-        s_tail = tail + 1;
+          for (int i = 0; i < len; ++i)
+            if (gen[path[i]] == -2) gen[path[i]] = -1;
+        }
+        s_tail = released ? tail + 1 : tail;
       }
       __syncthreads();
       tail = s_tail;
+      if (tail == head) break;  // nothing released: G < cells flags it
     }
     __syncthreads();
     if (tid == 0) s_tail = tail;
@@ -366,8 +401,8 @@ __global__ __launch_bounds__(DAG_THREADS) void k_dag_levels(DagArgs a, int j0) {
         const FacetRec fr = a.facet[(size_t)K * (DIM + 1) + k];
         if (fr.nb < 0) continue;
         const int b = fr.nb, kb = fr.pack & 3;
-        const int ul = ulag ? ulag[b] : 0;
-        const int bits = inflow_bits<DIM>(a.geo, a.facet, b, v, ul);
+        // lag[] holds the caller's bits and those added by cycle walks
+        const int bits = inflow_bits<DIM>(a.geo, a.facet, b, v, lag[b]);
         if (!((bits >> kb) & 1)) continue;
         if (atomicSub(&indeg[b], 1) == 1) {
           const int p = atomicAdd(&s_tail, 1);
@@ -763,38 +798,57 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   D->G_host.resize(nv);
   D->gbase_host.resize(nv);
   int64_t total_goff = 0;
-  // first pass: levels per batch; offsets copied to host per batch
   std::vector<int32_t> goff_host;
-  for (int j0 = 0; j0 < nv; j0 += batch) {
-    const int nb = std::min(batch, nv - j0);
-    if (dim == 2)
-      hipLaunchKernelGGL(k_dag_levels<2>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
-    else
-      hipLaunchKernelGGL(k_dag_levels<3>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
-    BGK_HIP(hipGetLastError());
-    BGK_HIP(hipMemcpyAsync(D->G_host.data() + j0, D->d_G + j0, nb * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, stream));
-    BGK_HIP(hipStreamSynchronize(stream));
-    std::vector<int32_t> cnt_host((size_t)nb * (nc + 1));
-    BGK_HIP(hipMemcpy(cnt_host.data(), s_cnt, cnt_host.size() * sizeof(int32_t),
-                      hipMemcpyDeviceToHost));
-    for (int jb = 0; jb < nb; ++jb) {
-      const int j = j0 + jb;
-      D->gbase_host[j] = total_goff;
-      const int G = D->G_host[j];
-      BGK_CHECK(G > 0, BGK_E_INVALID, "generation construction failed for velocity " + std::to_string(j));
-      goff_host.insert(goff_host.end(), cnt_host.begin() + (size_t)jb * (nc + 1),
-                       cnt_host.begin() + (size_t)jb * (nc + 1) + G + 1);
-      total_goff += G + 1;
+  // levels per batch of velocities; offsets copied to host per batch
+  const auto levels = [&]() -> int {
+    total_goff = 0;
+    goff_host.clear();
+    for (int j0 = 0; j0 < nv; j0 += batch) {
+      const int nb = std::min(batch, nv - j0);
+      if (dim == 2)
+        hipLaunchKernelGGL(k_dag_levels<2>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
+      else
+        hipLaunchKernelGGL(k_dag_levels<3>, dim3(nb), dim3(DAG_THREADS), 0, stream, a, j0);
+      BGK_HIP(hipGetLastError());
+      BGK_HIP(hipMemcpyAsync(D->G_host.data() + j0, D->d_G + j0, nb * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, stream));
+      BGK_HIP(hipStreamSynchronize(stream));
+      std::vector<int32_t> cnt_host((size_t)nb * (nc + 1));
+      BGK_HIP(hipMemcpy(cnt_host.data(), s_cnt, cnt_host.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+      for (int jb = 0; jb < nb; ++jb) {
+        const int j = j0 + jb;
+        D->gbase_host[j] = total_goff;
+        const int G = D->G_host[j];
+        BGK_CHECK(G > 0, BGK_E_INVALID,
+                  "generation construction failed for velocity " + std::to_string(j));
+        goff_host.insert(goff_host.end(), cnt_host.begin() + (size_t)jb * (nc + 1),
+                         cnt_host.begin() + (size_t)jb * (nc + 1) + G + 1);
+        total_goff += G + 1;
+      }
     }
+    return BGK_OK;
+  };
+  if ((rc = levels())) return rc;
+  unsigned long long nlag = 0;
+  BGK_HIP(hipMemcpyAsync(&nlag, d_nlag, sizeof(nlag), hipMemcpyDeviceToHost, stream));
+  BGK_HIP(hipStreamSynchronize(stream));
+  if (nlag > 0) {
+    // cycles were broken: the levels of that pass are not longest paths of
+    // the lagged graph; repeat it with every lagged facet given (the graph is
+    // now acyclic, so nothing more is lagged)
+    a.user_lag = D->d_lag;
+    if ((rc = levels())) return rc;
+    unsigned long long nlag2 = 0;
+    BGK_HIP(hipMemcpyAsync(&nlag2, d_nlag, sizeof(nlag2), hipMemcpyDeviceToHost, stream));
+    BGK_HIP(hipStreamSynchronize(stream));
+    BGK_CHECK(nlag2 == nlag, BGK_E_INVALID, "cycle breaking left a cycle");
   }
   if ((rc = dalloc(&D->d_goff, (size_t)total_goff))) return rc;
   BGK_HIP(hipMemcpyAsync(D->d_goff, goff_host.data(), total_goff * sizeof(int32_t),
                          hipMemcpyHostToDevice, stream));
   BGK_HIP(hipMemcpyAsync(D->d_gbase, D->gbase_host.data(), nv * sizeof(int64_t),
                          hipMemcpyHostToDevice, stream));
-  unsigned long long nlag = 0;
-  BGK_HIP(hipMemcpyAsync(&nlag, d_nlag, sizeof(nlag), hipMemcpyDeviceToHost, stream));
   BGK_HIP(hipStreamSynchronize(stream));
   (void)hipFree(s_cnt);
   (void)hipFree(s_cur);
@@ -894,85 +948,117 @@ using namespace bgk;
 
 extern "C" int build_mesh_dag(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vgrid,
                               const tgs_dag_opts* opts, bgk_stream_t stream, tgs_dag** out) {
-  if (!mesh || !vgrid || !out) return fail(BGK_E_INVALID, "null argument");
-  *out = nullptr;
-  if (vgrid->n_v <= 0) return fail(BGK_E_INVALID, "n_v must be positive");
-  tgs_dag* D = new (std::nothrow) tgs_dag();
-  if (!D) return fail(BGK_E_NOMEM, "host allocation failed");
-  int rc;
-  try {
-    rc = build_dag_impl(mesh, vgrid, opts, (hipStream_t)stream, D);
-  } catch (const std::exception& e) {
-    rc = fail(BGK_E_NOMEM, std::string("host exception: ") + e.what());
-  }
-  if (rc) {
-    free_dag(D);
-    return rc;
-  }
-  *out = D;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!mesh || !vgrid || !out) return fail(BGK_E_INVALID, "null argument");
+    *out = nullptr;
+    if (vgrid->n_v <= 0) return fail(BGK_E_INVALID, "n_v must be positive");
+    tgs_dag* D = new (std::nothrow) tgs_dag();
+    if (!D) return fail(BGK_E_NOMEM, "host allocation failed");
+    int rc;
+    try {
+      rc = build_dag_impl(mesh, vgrid, opts, (hipStream_t)stream, D);
+    } catch (const std::exception& e) {
+      rc = fail(BGK_E_NOMEM, std::string("host exception: ") + e.what());
+    }
+    if (rc) {
+      free_dag(D);
+      return rc;
+    }
+    *out = D;
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_dag_destroy(tgs_dag* dag) {
-  free_dag(dag);
-  return BGK_OK;
+  return guarded([&]() -> int {
+    free_dag(dag);
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_dag_sizes(const tgs_dag* d, int64_t s[9]) {
-  if (!d || !s) return fail(BGK_E_INVALID, "null argument");
-  s[0] = d->dim;
-  s[1] = d->order;
-  s[2] = d->n_p;
-  s[3] = d->n_fp;
-  s[4] = d->n_cells;
-  s[5] = d->n_v;
-  s[6] = d->n_bfaces;
-  s[7] = d->max_G;
-  s[8] = d->n_lagged;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !s) return fail(BGK_E_INVALID, "null argument");
+    s[0] = d->dim;
+    s[1] = d->order;
+    s[2] = d->n_p;
+    s[3] = d->n_fp;
+    s[4] = d->n_cells;
+    s[5] = d->n_v;
+    s[6] = d->n_bfaces;
+    s[7] = d->max_G;
+    s[8] = d->n_lagged;
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_dag_generations(const tgs_dag* d, int32_t* gen, int32_t* G) {
-  if (!d) return fail(BGK_E_INVALID, "null dag");
-  if (G) std::copy(d->G_host.begin(), d->G_host.end(), G);
-  if (!gen) return BGK_OK;
-  const int64_t nc = d->n_cells;
-  std::vector<int32_t> perm((size_t)d->n_v * nc);
-  std::vector<int32_t> goff;
-  BGK_HIP(hipMemcpy(perm.data(), d->d_perm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  int64_t total = 0;
-  for (int j = 0; j < d->n_v; ++j) total += d->G_host[j] + 1;
-  goff.resize(total);
-  BGK_HIP(hipMemcpy(goff.data(), d->d_goff, total * sizeof(int32_t), hipMemcpyDeviceToHost));
-  for (int j = 0; j < d->n_v; ++j) {
-    const int32_t* go = goff.data() + d->gbase_host[j];
-    for (int g = 0; g < d->G_host[j]; ++g)
-      for (int s = go[g]; s < go[g + 1]; ++s)
-        gen[(size_t)j * nc + d->uid_host[perm[(size_t)j * nc + s]]] = g;
-  }
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d) return fail(BGK_E_INVALID, "null dag");
+    if (G) std::copy(d->G_host.begin(), d->G_host.end(), G);
+    if (!gen) return BGK_OK;
+    const int64_t nc = d->n_cells;
+    std::vector<int32_t> perm((size_t)d->n_v * nc);
+    std::vector<int32_t> goff;
+    BGK_HIP(hipMemcpy(perm.data(), d->d_perm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int64_t total = 0;
+    for (int j = 0; j < d->n_v; ++j) total += d->G_host[j] + 1;
+    goff.resize(total);
+    BGK_HIP(hipMemcpy(goff.data(), d->d_goff, total * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int j = 0; j < d->n_v; ++j) {
+      const int32_t* go = goff.data() + d->gbase_host[j];
+      for (int g = 0; g < d->G_host[j]; ++g)
+        for (int s = go[g]; s < go[g + 1]; ++s)
+          gen[(size_t)j * nc + d->uid_host[perm[(size_t)j * nc + s]]] = g;
+    }
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_dag_lagged(const tgs_dag* d, uint8_t* lagged) {
-  if (!d || !lagged) return fail(BGK_E_INVALID, "null argument");
-  const int64_t nc = d->n_cells;
-  if (!d->d_lag) {
-    std::memset(lagged, 0, (size_t)d->n_v * nc);
+  return guarded([&]() -> int {
+    if (!d || !lagged) return fail(BGK_E_INVALID, "null argument");
+    const int64_t nc = d->n_cells;
+    if (!d->d_lag) {
+      std::memset(lagged, 0, (size_t)d->n_v * nc);
+      return BGK_OK;
+    }
+    std::vector<uint8_t> tmp((size_t)d->n_v * nc);
+    BGK_HIP(hipMemcpy(tmp.data(), d->d_lag, tmp.size(), hipMemcpyDeviceToHost));
+    for (int j = 0; j < d->n_v; ++j)
+      for (int64_t i = 0; i < nc; ++i) lagged[(size_t)j * nc + d->uid_host[i]] = tmp[(size_t)j * nc + i];
     return BGK_OK;
-  }
-  std::vector<uint8_t> tmp((size_t)d->n_v * nc);
-  BGK_HIP(hipMemcpy(tmp.data(), d->d_lag, tmp.size(), hipMemcpyDeviceToHost));
-  for (int j = 0; j < d->n_v; ++j)
-    for (int64_t i = 0; i < nc; ++i) lagged[(size_t)j * nc + d->uid_host[i]] = tmp[(size_t)j * nc + i];
-  return BGK_OK;
+  });
 }
 
 extern "C" int tgs_dag_sweep_lanes(const tgs_dag* d) { return d ? d->sweep_lanes : 0; }
 
+extern "C" int tgs_dag_explicit_dt(const tgs_dag* d, double cfl, double* dt) {
+  return guarded([&]() -> int {
+    if (!d || !dt) return fail(BGK_E_INVALID, "null argument");
+    if (!(cfl > 0.0)) return fail(BGK_E_INVALID, "cfl must be positive");
+    // eq. explicit-dt: h_min from the smallest cell measure, the largest speed
+    double vmin = d->vol_user.empty() ? 0.0 : d->vol_user[0];
+    for (double x : d->vol_user) vmin = std::min(vmin, x);
+    double s2 = 0.0;
+    for (int64_t j = 0; j < d->n_v; ++j) {
+      double a = 0.0;
+      for (int k = 0; k < d->dim; ++k) a += d->v_host[j * d->dim + k] * d->v_host[j * d->dim + k];
+      s2 = std::max(s2, a);
+    }
+    if (!(s2 > 0.0) || !(vmin > 0.0)) return fail(BGK_E_INVALID, "zero speed or cell measure");
+    const double hmin = std::pow(vmin, 1.0 / d->dim);
+    *dt = cfl * (1.0 / d->dim) * (1.0 / (2 * d->order + 1)) * hmin / std::sqrt(s2);
+    return BGK_OK;
+  });
+}
+
 extern "C" int tgs_dag_geometry(const tgs_dag* d, double* node_x, double* bnode_x, double* vol) {
-  if (!d) return fail(BGK_E_INVALID, "null dag");
-  if (node_x) std::copy(d->node_x.begin(), d->node_x.end(), node_x);
-  if (bnode_x) std::copy(d->bnode_x.begin(), d->bnode_x.end(), bnode_x);
-  if (vol) std::copy(d->vol_user.begin(), d->vol_user.end(), vol);
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d) return fail(BGK_E_INVALID, "null dag");
+    if (node_x) std::copy(d->node_x.begin(), d->node_x.end(), node_x);
+    if (bnode_x) std::copy(d->bnode_x.begin(), d->bnode_x.end(), bnode_x);
+    if (vol) std::copy(d->vol_user.begin(), d->vol_user.end(), vol);
+    return BGK_OK;
+  });
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -29,6 +31,29 @@ int fail(int code, const std::string& msg);
   do {                                   \
     if (!(cond)) return ::bgk::fail(code, msg); \
   } while (0)
+
+// Records a fixed message without allocating (safe inside a catch handler).
+int fail_static(int code, const char* msg) noexcept;
+
+// Runs the body of an entry point so that no C++ exception crosses the C
+// ABI: a host allocation failure (std::bad_alloc from a std::vector or
+// std::map) or any other exception becomes BGK_E_NOMEM with its message.
+template <class F>
+int guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail_static(BGK_E_NOMEM, "host allocation failed (std::bad_alloc)");
+  } catch (const std::exception& e) {
+    try {
+      return fail(BGK_E_NOMEM, std::string("host exception: ") + e.what());
+    } catch (...) {
+      return fail_static(BGK_E_NOMEM, "host exception");
+    }
+  } catch (...) {
+    return fail_static(BGK_E_NOMEM, "unknown host exception");
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Reference-element matrices, evaluated at compile time.

@@ -1116,46 +1116,52 @@ using namespace bgk;
 
 extern "C" int moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                        double* rel3, bgk_stream_t stream) {
-  if (!d || !f || !U) return fail(BGK_E_INVALID, "null argument");
-  if ((U_prev == nullptr) != (rel3 == nullptr))
-    return fail(BGK_E_INVALID, "U_prev and rel3 go together");
-  double* partial = nullptr;
-  double* ratio = nullptr;
-  hipStream_t s = (hipStream_t)stream;
-  if (U_prev) {
-    if (hipMallocAsync((void**)&partial, (size_t)moment_blocks(d) * 6 * sizeof(double), s) !=
-            hipSuccess ||
-        hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)
-      return fail(BGK_E_NOMEM, "scratch allocation failed");
-  }
-  int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
-  if (rc == BGK_OK && U_prev) {
-    if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-      rc = fail(BGK_E_HIP, "copy of ratios failed");
-  }
-  if (partial) (void)hipFreeAsync(partial, s);
-  if (ratio) (void)hipFreeAsync(ratio, s);
-  return rc;
+  return guarded([&]() -> int {
+    if (!d || !f || !U) return fail(BGK_E_INVALID, "null argument");
+    if ((U_prev == nullptr) != (rel3 == nullptr))
+      return fail(BGK_E_INVALID, "U_prev and rel3 go together");
+    double* partial = nullptr;
+    double* ratio = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (U_prev) {
+      if (hipMallocAsync((void**)&partial, (size_t)moment_blocks(d) * 6 * sizeof(double), s) !=
+              hipSuccess ||
+          hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)
+        return fail(BGK_E_NOMEM, "scratch allocation failed");
+    }
+    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
+    if (rc == BGK_OK && U_prev) {
+      if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = fail(BGK_E_HIP, "copy of ratios failed");
+    }
+    if (partial) (void)hipFreeAsync(partial, s);
+    if (ratio) (void)hipFreeAsync(ratio, s);
+    return rc;
+  });
 }
 
 extern "C" int maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                           double* coef, double* nu, double* M_dense, int32_t* status,
                           bgk_stream_t stream) {
-  if (!d || !U || !coef || !nu) return fail(BGK_E_INVALID, "null argument");
-  return launch_maxwellian(d, mode, U, nm, coef, nu, M_dense, status, nullptr, nullptr,
-                           (hipStream_t)stream);
+  return guarded([&]() -> int {
+    if (!d || !U || !coef || !nu) return fail(BGK_E_INVALID, "null argument");
+    return launch_maxwellian(d, mode, U, nm, coef, nu, M_dense, status, nullptr, nullptr,
+                             (hipStream_t)stream);
+  });
 }
 
 extern "C" int maxwellian_coef_from_primitive(int dim, int64_t n, const double* prim, double* coef,
                                               bgk_stream_t stream) {
-  if (!prim || !coef || n < 0 || (dim != 2 && dim != 3))
-    return fail(BGK_E_INVALID, "bad arguments");
-  if (n == 0) return BGK_OK;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (dim == 2)
-    hipLaunchKernelGGL(k_coef_from_prim<2>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
-  else
-    hipLaunchKernelGGL(k_coef_from_prim<3>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!prim || !coef || n < 0 || (dim != 2 && dim != 3))
+      return fail(BGK_E_INVALID, "bad arguments");
+    if (n == 0) return BGK_OK;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (dim == 2)
+      hipLaunchKernelGGL(k_coef_from_prim<2>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
+    else
+      hipLaunchKernelGGL(k_coef_from_prim<3>, grid, block, 0, (hipStream_t)stream, prim, coef, n);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }

@@ -541,89 +541,101 @@ int grid_tiles(int64_t ntiles) { return (int)std::max<int64_t>(1, std::min<int64
 }  // namespace
 
 extern "C" int bgk_mlp_create(const float* params, bgk_mlp** out) {
-  if (!out) return fail(BGK_E_INVALID, "null argument");
-  *out = nullptr;
-  bgk_mlp* m = new (std::nothrow) bgk_mlp();
-  if (!m) return fail(BGK_E_NOMEM, "host allocation failed");
-  bool ok = hipMalloc((void**)&m->master, NPAD * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->m1, NPAD * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->m2, NPAD * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->grad, NPAD * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->frag, NFRAG * sizeof(uint16_t)) == hipSuccess &&
-            hipMalloc((void**)&m->stats, 32 * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->partial, (size_t)GRAD_BLOCKS * NPAD * sizeof(float)) == hipSuccess &&
-            hipMalloc((void**)&m->ploss, (size_t)GRAD_BLOCKS * sizeof(float)) == hipSuccess;
-  if (!ok) {
-    bgk_mlp_destroy(m);
-    return fail(BGK_E_NOMEM, "MLP allocation failed");
-  }
-  std::vector<float> stats(32, 0.0f);
-  for (int c = 0; c < NI; ++c) stats[NI + c] = 1.0f;
-  for (int c = 0; c < NO; ++c) stats[2 * NI + NO + c] = 1.0f;
-  if (hipMemcpy(m->stats, stats.data(), 32 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-    bgk_mlp_destroy(m);
-    return fail(BGK_E_HIP, "stats upload failed");
-  }
-  int rc = bgk_mlp_set_params(m, params);
-  if (rc) {
-    bgk_mlp_destroy(m);
-    return rc;
-  }
-  *out = m;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!out) return fail(BGK_E_INVALID, "null argument");
+    *out = nullptr;
+    bgk_mlp* m = new (std::nothrow) bgk_mlp();
+    if (!m) return fail(BGK_E_NOMEM, "host allocation failed");
+    bool ok = hipMalloc((void**)&m->master, NPAD * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->m1, NPAD * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->m2, NPAD * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->grad, NPAD * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->frag, NFRAG * sizeof(uint16_t)) == hipSuccess &&
+              hipMalloc((void**)&m->stats, 32 * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->partial, (size_t)GRAD_BLOCKS * NPAD * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&m->ploss, (size_t)GRAD_BLOCKS * sizeof(float)) == hipSuccess;
+    if (!ok) {
+      bgk_mlp_destroy(m);
+      return fail(BGK_E_NOMEM, "MLP allocation failed");
+    }
+    std::vector<float> stats(32, 0.0f);
+    for (int c = 0; c < NI; ++c) stats[NI + c] = 1.0f;
+    for (int c = 0; c < NO; ++c) stats[2 * NI + NO + c] = 1.0f;
+    if (hipMemcpy(m->stats, stats.data(), 32 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      bgk_mlp_destroy(m);
+      return fail(BGK_E_HIP, "stats upload failed");
+    }
+    int rc = bgk_mlp_set_params(m, params);
+    if (rc) {
+      bgk_mlp_destroy(m);
+      return rc;
+    }
+    *out = m;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_destroy(bgk_mlp* m) {
-  if (!m) return BGK_OK;
-  void* ptrs[] = {m->master, m->m1, m->m2, m->frag, m->stats, m->grad, m->partial, m->ploss};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  delete m;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m) return BGK_OK;
+    void* ptrs[] = {m->master, m->m1, m->m2, m->frag, m->stats, m->grad, m->partial, m->ploss};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    delete m;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_set_params(bgk_mlp* m, const float* params) {
-  if (!m) return fail(BGK_E_INVALID, "null mlp");
-  std::vector<float> pad(NPAD, 0.0f);
-  if (params) logical_to_padded(params, pad.data());
-  BGK_HIP(hipMemcpy(m->master, pad.data(), NPAD * sizeof(float), hipMemcpyHostToDevice));
-  BGK_HIP(hipMemset(m->m1, 0, NPAD * sizeof(float)));
-  BGK_HIP(hipMemset(m->m2, 0, NPAD * sizeof(float)));
-  m->step = 0;
-  int rc = mlp_sync(m, nullptr);
-  if (rc) return rc;
-  BGK_HIP(hipDeviceSynchronize());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m) return fail(BGK_E_INVALID, "null mlp");
+    std::vector<float> pad(NPAD, 0.0f);
+    if (params) logical_to_padded(params, pad.data());
+    BGK_HIP(hipMemcpy(m->master, pad.data(), NPAD * sizeof(float), hipMemcpyHostToDevice));
+    BGK_HIP(hipMemset(m->m1, 0, NPAD * sizeof(float)));
+    BGK_HIP(hipMemset(m->m2, 0, NPAD * sizeof(float)));
+    m->step = 0;
+    int rc = mlp_sync(m, nullptr);
+    if (rc) return rc;
+    BGK_HIP(hipDeviceSynchronize());
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_get_params(const bgk_mlp* m, float* params) {
-  if (!m || !params) return fail(BGK_E_INVALID, "null argument");
-  std::vector<float> pad(NPAD);
-  BGK_HIP(hipDeviceSynchronize());
-  BGK_HIP(hipMemcpy(pad.data(), m->master, NPAD * sizeof(float), hipMemcpyDeviceToHost));
-  padded_to_logical(pad.data(), params);
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m || !params) return fail(BGK_E_INVALID, "null argument");
+    std::vector<float> pad(NPAD);
+    BGK_HIP(hipDeviceSynchronize());
+    BGK_HIP(hipMemcpy(pad.data(), m->master, NPAD * sizeof(float), hipMemcpyDeviceToHost));
+    padded_to_logical(pad.data(), params);
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_set_normalization(bgk_mlp* m, const float* stats) {
-  if (!m || !stats) return fail(BGK_E_INVALID, "null argument");
-  for (int c = 0; c < NI; ++c)
-    if (!(stats[NI + c] > 0.0f)) return fail(BGK_E_INVALID, "input std must be positive");
-  for (int c = 0; c < NO; ++c)
-    if (!(stats[2 * NI + NO + c] > 0.0f)) return fail(BGK_E_INVALID, "output std must be positive");
-  BGK_HIP(hipMemcpy(m->stats, stats, 32 * sizeof(float), hipMemcpyHostToDevice));
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m || !stats) return fail(BGK_E_INVALID, "null argument");
+    for (int c = 0; c < NI; ++c)
+      if (!(stats[NI + c] > 0.0f)) return fail(BGK_E_INVALID, "input std must be positive");
+    for (int c = 0; c < NO; ++c)
+      if (!(stats[2 * NI + NO + c] > 0.0f)) return fail(BGK_E_INVALID, "output std must be positive");
+    BGK_HIP(hipMemcpy(m->stats, stats, 32 * sizeof(float), hipMemcpyHostToDevice));
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_forward(bgk_mlp* m, const float* X, int64_t n, float* Y,
                                bgk_stream_t stream) {
-  if (!m || !X || !Y || n < 0) return fail(BGK_E_INVALID, "bad arguments");
-  if (n == 0) return BGK_OK;
-  const int64_t ntiles = (n + 15) / 16;
-  hipLaunchKernelGGL(k_mlp_forward, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
-                     (hipStream_t)stream, margs(m), X, n, Y);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m || !X || !Y || n < 0) return fail(BGK_E_INVALID, "bad arguments");
+    if (n == 0) return BGK_OK;
+    const int64_t ntiles = (n + 15) / 16;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
+                       (hipStream_t)stream, margs(m), X, n, Y);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }
 
 namespace {
@@ -643,75 +655,85 @@ int mlp_grad(bgk_mlp* m, const float* X, const float* T, int64_t n, float* loss,
 
 extern "C" int bgk_mlp_loss_grad(bgk_mlp* m, const float* X, const float* T, int64_t n, float* grad,
                                  float* loss, bgk_stream_t stream) {
-  if (!m || !X || !T || n <= 0) return fail(BGK_E_INVALID, "bad arguments");
-  hipStream_t s = (hipStream_t)stream;
-  int rc = mlp_grad(m, X, T, n, loss, s);
-  if (rc) return rc;
-  if (grad) {
-    hipLaunchKernelGGL(k_padded_to_logical, dim3((BGK_MLP_PARAMS + 255) / 256), dim3(256), 0, s,
-                       m->grad, grad);
-    BGK_HIP(hipGetLastError());
-  }
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m || !X || !T || n <= 0) return fail(BGK_E_INVALID, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = mlp_grad(m, X, T, n, loss, s);
+    if (rc) return rc;
+    if (grad) {
+      hipLaunchKernelGGL(k_padded_to_logical, dim3((BGK_MLP_PARAMS + 255) / 256), dim3(256), 0, s,
+                         m->grad, grad);
+      BGK_HIP(hipGetLastError());
+    }
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_adam_step(bgk_mlp* m, const float* X, const float* T, int64_t n, float lr,
                                  float* loss, bgk_stream_t stream) {
-  if (!m || !X || !T || n <= 0 || !(lr > 0.0f)) return fail(BGK_E_INVALID, "bad arguments");
-  hipStream_t s = (hipStream_t)stream;
-  int rc = mlp_grad(m, X, T, n, loss, s);
-  if (rc) return rc;
-  m->step += 1;
-  const float c1 = 1.0f - std::pow(0.9f, (float)m->step);
-  const float c2 = 1.0f - std::pow(0.999f, (float)m->step);
-  hipLaunchKernelGGL(k_mlp_adam, dim3((NPAD + 255) / 256), dim3(256), 0, s, m->master, m->m1, m->m2,
-                     m->grad, lr, c1, c2);
-  BGK_HIP(hipGetLastError());
-  return mlp_sync(m, s);
+  return guarded([&]() -> int {
+    if (!m || !X || !T || n <= 0 || !(lr > 0.0f)) return fail(BGK_E_INVALID, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = mlp_grad(m, X, T, n, loss, s);
+    if (rc) return rc;
+    m->step += 1;
+    const float c1 = 1.0f - std::pow(0.9f, (float)m->step);
+    const float c2 = 1.0f - std::pow(0.999f, (float)m->step);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((NPAD + 255) / 256), dim3(256), 0, s, m->master, m->m1, m->m2,
+                       m->grad, lr, c1, c2);
+    BGK_HIP(hipGetLastError());
+    return mlp_sync(m, s);
+  });
 }
 
 extern "C" int bgk_mlp_features(const tgs_dag* d, const double* U1, const double* U2,
                                 const tgs_nu_model* nm, double dt, float* X, bgk_stream_t stream) {
-  if (!d || !U1 || !U2 || !nm || !X) return fail(BGK_E_INVALID, "null argument");
-  const int64_t n = d->n_nodes;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (d->dim == 2)
-    hipLaunchKernelGGL(k_mlp_features<2>, grid, block, 0, (hipStream_t)stream, U1, U2, n, nm->kind,
-                       nm->nu_const, nm->kn, dt, X);
-  else
-    hipLaunchKernelGGL(k_mlp_features<3>, grid, block, 0, (hipStream_t)stream, U1, U2, n, nm->kind,
-                       nm->nu_const, nm->kn, dt, X);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !U1 || !U2 || !nm || !X) return fail(BGK_E_INVALID, "null argument");
+    const int64_t n = d->n_nodes;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (d->dim == 2)
+      hipLaunchKernelGGL(k_mlp_features<2>, grid, block, 0, (hipStream_t)stream, U1, U2, n, nm->kind,
+                         nm->nu_const, nm->kn, dt, X);
+    else
+      hipLaunchKernelGGL(k_mlp_features<3>, grid, block, 0, (hipStream_t)stream, U1, U2, n, nm->kind,
+                         nm->nu_const, nm->kn, dt, X);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_targets(const tgs_dag* d, const double* Ut, const double* U1,
                                const double* U2, float* T, bgk_stream_t stream) {
-  if (!d || !Ut || !U1 || !U2 || !T) return fail(BGK_E_INVALID, "null argument");
-  const int64_t n = d->n_nodes;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (d->dim == 2)
-    hipLaunchKernelGGL(k_mlp_targets<2>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
-  else
-    hipLaunchKernelGGL(k_mlp_targets<3>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !Ut || !U1 || !U2 || !T) return fail(BGK_E_INVALID, "null argument");
+    const int64_t n = d->n_nodes;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (d->dim == 2)
+      hipLaunchKernelGGL(k_mlp_targets<2>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
+    else
+      hipLaunchKernelGGL(k_mlp_targets<3>, grid, block, 0, (hipStream_t)stream, Ut, U1, U2, n, T);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_mlp_guess(bgk_mlp* m, const tgs_dag* d, const double* U1, const double* U2,
                              const tgs_nu_model* nm, double dt, double* Ug, int32_t* fallback,
                              bgk_stream_t stream) {
-  if (!m || !d || !U1 || !U2 || !nm || !Ug) return fail(BGK_E_INVALID, "null argument");
-  const int64_t n = d->n_nodes;
-  const int64_t ntiles = (n + 15) / 16;
-  if (d->dim == 2)
-    hipLaunchKernelGGL(k_mlp_guess<2>, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
-                       (hipStream_t)stream, margs(m), U1, U2, n, nm->kind, nm->nu_const, nm->kn,
-                       dt, Ug, fallback);
-  else
-    hipLaunchKernelGGL(k_mlp_guess<3>, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
-                       (hipStream_t)stream, margs(m), U1, U2, n, nm->kind, nm->nu_const, nm->kn,
-                       dt, Ug, fallback);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!m || !d || !U1 || !U2 || !nm || !Ug) return fail(BGK_E_INVALID, "null argument");
+    const int64_t n = d->n_nodes;
+    const int64_t ntiles = (n + 15) / 16;
+    if (d->dim == 2)
+      hipLaunchKernelGGL(k_mlp_guess<2>, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
+                         (hipStream_t)stream, margs(m), U1, U2, n, nm->kind, nm->nu_const, nm->kn,
+                         dt, Ug, fallback);
+    else
+      hipLaunchKernelGGL(k_mlp_guess<3>, dim3(grid_tiles(ntiles)), dim3(MLP_THREADS), 0,
+                         (hipStream_t)stream, margs(m), U1, U2, n, nm->kind, nm->nu_const, nm->kn,
+                         dt, Ug, fallback);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }

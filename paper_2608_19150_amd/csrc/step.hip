@@ -189,231 +189,237 @@ int combine(double* out, const double* const* xs, const double* cs, int nin, siz
 }  // namespace
 
 extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk_solver** out) {
-  if (!d || !o || !out) return fail(BGK_E_INVALID, "null argument");
-  *out = nullptr;
-  if (!(o->dt > 0) || !(o->tau > 0) || o->l_max <= 0)
-    return fail(BGK_E_INVALID, "dt, tau and l_max must be positive");
-  if (!o->bc_coef) return fail(BGK_E_INVALID, "bc_coef is required");
-  if (o->precision != TGS_FP64 && o->precision != TGS_FP32_CORRECTION)
-    return fail(BGK_E_INVALID, "unknown precision");
-  if (o->walls && walls_dag(o->walls) != d)
-    return fail(BGK_E_INVALID, "walls belong to another DAG");
-  if (o->maxw_mode == BGK_MAXW_PROJECTED && d->dg_cells <= 0)
-    return fail(BGK_E_INVALID, "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
-  bgk_solver* s = new (std::nothrow) bgk_solver();
-  if (!s) return fail(BGK_E_NOMEM, "host allocation failed");
-  s->dag = d;
-  s->opts = *o;
-  int rc = set_tableau(s, o->tableau);
-  const size_t nf = f_elems(d);
-  const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
-  if (!rc) rc = dmalloc(&s->fk, nf);
-  for (int i = 0; i + 1 < s->S && !rc; ++i) rc = dmalloc(&s->fst[i], nf);
-  if (!rc && !s->stiffly_accurate) rc = dmalloc(&s->fst[s->S - 1], nf);
-  if (!rc && s->S > 1) rc = dmalloc(&s->q, nf);
-  if (!rc && (d->d_lag || o->precision == TGS_FP32_CORRECTION)) rc = dmalloc(&s->fping, nf);
-  if (!rc && o->precision == TGS_FP32_CORRECTION) rc = dmalloc(&s->d32, nf);
-  if (!rc) rc = dmalloc(&s->U[0], nn);
-  if (!rc) rc = dmalloc(&s->U[1], nn);
-  if (!rc) rc = dmalloc(&s->mcoef, nn);
-  if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
-  if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
-  if (!rc && o->walls) rc = dmalloc(&s->bcd, (size_t)d->n_bfaces * d->n_fp * d->n_v);
-  if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
-  if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
-  if (!rc) rc = dmalloc(&s->ratio, 4);
-  if (!rc) rc = dmalloc(&s->status, 2);
-  if (!rc) rc = dmalloc(&s->numax, 1);
-  if (!rc) rc = dmalloc(&s->sticky, (size_t)d->n_nodes);
-  if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
-    rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
-  if (!rc && o->timing)
-    for (int i = 0; i < 4 && !rc; ++i)
-      if (hipEventCreate(&s->ev[i]) != hipSuccess) rc = fail(BGK_E_HIP, "hipEventCreate failed");
-  if (rc) {
-    bgk_solver_destroy(s);
-    return rc;
-  }
-  *out = s;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !o || !out) return fail(BGK_E_INVALID, "null argument");
+    *out = nullptr;
+    if (!(o->dt > 0) || !(o->tau > 0) || o->l_max <= 0)
+      return fail(BGK_E_INVALID, "dt, tau and l_max must be positive");
+    if (!o->bc_coef) return fail(BGK_E_INVALID, "bc_coef is required");
+    if (o->precision != TGS_FP64 && o->precision != TGS_FP32_CORRECTION)
+      return fail(BGK_E_INVALID, "unknown precision");
+    if (o->walls && walls_dag(o->walls) != d)
+      return fail(BGK_E_INVALID, "walls belong to another DAG");
+    if (o->maxw_mode == BGK_MAXW_PROJECTED && d->dg_cells <= 0)
+      return fail(BGK_E_INVALID, "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
+    bgk_solver* s = new (std::nothrow) bgk_solver();
+    if (!s) return fail(BGK_E_NOMEM, "host allocation failed");
+    s->dag = d;
+    s->opts = *o;
+    int rc = set_tableau(s, o->tableau);
+    const size_t nf = f_elems(d);
+    const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
+    if (!rc) rc = dmalloc(&s->fk, nf);
+    for (int i = 0; i + 1 < s->S && !rc; ++i) rc = dmalloc(&s->fst[i], nf);
+    if (!rc && !s->stiffly_accurate) rc = dmalloc(&s->fst[s->S - 1], nf);
+    if (!rc && s->S > 1) rc = dmalloc(&s->q, nf);
+    if (!rc && (d->d_lag || o->precision == TGS_FP32_CORRECTION)) rc = dmalloc(&s->fping, nf);
+    if (!rc && o->precision == TGS_FP32_CORRECTION) rc = dmalloc(&s->d32, nf);
+    if (!rc) rc = dmalloc(&s->U[0], nn);
+    if (!rc) rc = dmalloc(&s->U[1], nn);
+    if (!rc) rc = dmalloc(&s->mcoef, nn);
+    if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
+    if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
+    if (!rc && o->walls) rc = dmalloc(&s->bcd, (size_t)d->n_bfaces * d->n_fp * d->n_v);
+    if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
+    if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
+    if (!rc) rc = dmalloc(&s->ratio, 4);
+    if (!rc) rc = dmalloc(&s->status, 2);
+    if (!rc) rc = dmalloc(&s->numax, 1);
+    if (!rc) rc = dmalloc(&s->sticky, (size_t)d->n_nodes);
+    if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
+      rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
+    if (!rc && o->timing)
+      for (int i = 0; i < 4 && !rc; ++i)
+        if (hipEventCreate(&s->ev[i]) != hipSuccess) rc = fail(BGK_E_HIP, "hipEventCreate failed");
+    if (rc) {
+      bgk_solver_destroy(s);
+      return rc;
+    }
+    *out = s;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_solver_destroy(bgk_solver* s) {
-  if (!s) return BGK_OK;
-  void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
-                  s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
-                  s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr,
-                  s->bcd};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (s->h_info) (void)hipHostFree(s->h_info);
-  for (hipEvent_t e : s->ev)
-    if (e) (void)hipEventDestroy(e);
-  delete s;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!s) return BGK_OK;
+    void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
+                    s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
+                    s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr,
+                    s->bcd};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    if (s->h_info) (void)hipHostFree(s->h_info);
+    for (hipEvent_t e : s->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete s;
+    return BGK_OK;
+  });
 }
 
 extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double* U_out,
                         bgk_step_stats* stats, bgk_stream_t stream_) {
-  if (!s || !f) return fail(BGK_E_INVALID, "null argument");
-  const auto t0 = std::chrono::steady_clock::now();
-  const tgs_dag* d = s->dag;
-  const bgk_solver_opts& o = s->opts;
-  hipStream_t stream = (hipStream_t)stream_;
-  const size_t nf = f_elems(d);
-  const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
-  const bool need_prev = d->d_lag != nullptr || o.precision == TGS_FP32_CORRECTION;
-  bgk_step_stats st{};
-  st.stages = s->S;
-  int rc;
-  // f^k is read by every stage's source and by the final combination.  The
-  // last stage of a stiffly accurate tableau writes its iterates into f; with
-  // two or more stages f^k is no longer needed by then (that stage's source
-  // was formed before its first sweep), so only a one-stage tableau copies it
-  const double* fk = f;
-  if (s->stiffly_accurate && s->S == 1) {
-    BGK_HIP(hipMemcpyAsync(s->fk, f, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    fk = s->fk;
-  }
-  double* fst[4] = {s->fst[0], s->fst[1], s->fst[2], s->fst[3]};
-  if (s->stiffly_accurate) fst[s->S - 1] = f;
-  const double* stage_init = fk;   // initial Picard iterate of the stage
-  int ucur = 0;
-  // with walls the sweep reads dense boundary data: the inflow facets'
-  // Maxwellians once per step, the wall facets' rows before every sweep
-  if (o.walls && (rc = launch_bc_dense(d, o.bc_coef, s->bcd, stream))) return rc;
-  // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
-  // order during the step; U_guess / U_out are in user order
-  if (U_guess) {
-    if ((rc = launch_nodal_perm(d, U_guess, s->U[0], 1, stream))) return rc;
-  } else {
-    if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
-      return rc;
-  }
-  for (int stg = 0; stg < s->S; ++stg) {
-    const double shift = 1.0 / (o.dt * s->A[stg][stg]);
-    const double* qsrc;
-    double qscale;
-    if (stg == 0) {
-      qsrc = fk;
-      qscale = s->qcoef[0][0];
-    } else {
-      const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
-      if ((rc = combine(s->q, xs, s->qcoef[stg], stg + 1, nf, stream))) return rc;
-      qsrc = s->q;
-      qscale = 1.0;
+  return guarded([&]() -> int {
+    if (!s || !f) return fail(BGK_E_INVALID, "null argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    const tgs_dag* d = s->dag;
+    const bgk_solver_opts& o = s->opts;
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t nf = f_elems(d);
+    const size_t nn = (size_t)d->n_nodes * (d->dim + 2);
+    const bool need_prev = d->d_lag != nullptr || o.precision == TGS_FP32_CORRECTION;
+    bgk_step_stats st{};
+    st.stages = s->S;
+    int rc;
+    // f^k is read by every stage's source and by the final combination.  The
+    // last stage of a stiffly accurate tableau writes its iterates into f; with
+    // two or more stages f^k is no longer needed by then (that stage's source
+    // was formed before its first sweep), so only a one-stage tableau copies it
+    const double* fk = f;
+    if (s->stiffly_accurate && s->S == 1) {
+      BGK_HIP(hipMemcpyAsync(s->fk, f, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      fk = s->fk;
     }
-    double* out = fst[stg];
-    // with lagged facets or the FP32 form the previous iterate is kept in
-    // fping; the first iteration reads the stage's initial iterate
-    const double* prev = stage_init;
-    double* cur_out = out;
-    int it = 0;
-    bool converged = false;
-    double last = 0.0;
-    // a node whose MATCHED solve fails stays on DIRECT for the rest of the
-    // stage: an iterate switching between the two would not settle
-    hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)std::min<int64_t>((d->n_nodes + 255) / 256, 1024)),
-                       dim3(256), 0, stream, s->sticky, d->n_nodes);
-    while (it < o.l_max) {
-      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
-      if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], stream));
-      if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
-                                  nullptr, s->status, s->numax, s->sticky, stream)))
+    double* fst[4] = {s->fst[0], s->fst[1], s->fst[2], s->fst[3]};
+    if (s->stiffly_accurate) fst[s->S - 1] = f;
+    const double* stage_init = fk;   // initial Picard iterate of the stage
+    int ucur = 0;
+    // with walls the sweep reads dense boundary data: the inflow facets'
+    // Maxwellians once per step, the wall facets' rows before every sweep
+    if (o.walls && (rc = launch_bc_dense(d, o.bc_coef, s->bcd, stream))) return rc;
+    // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
+    // order during the step; U_guess / U_out are in user order
+    if (U_guess) {
+      if ((rc = launch_nodal_perm(d, U_guess, s->U[0], 1, stream))) return rc;
+    } else {
+      if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
         return rc;
-      if (s->pr)
-        rc = launch_proj_tables(d, s->mcoef, s->nu, s->pr, s->mtab, stream);
-      else if (s->mtab)
-        rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream);
-      if (rc) return rc;
-      if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
-      if (need_prev) cur_out = (prev == out) ? s->fping : out;
-      tgs_sweep_io io{};
-      io.precision = o.precision;
-      io.sigma_shift = shift;
-      io.q_scale = qscale;
-      io.nu = s->nu;
-      io.mcoef = s->mcoef;
-      io.q = qsrc;
-      io.bc_coef = o.walls ? nullptr : o.bc_coef;
-      io.bc_dense = o.walls ? s->bcd : nullptr;
-      io.f_prev = need_prev ? prev : nullptr;
-      if (o.walls && (rc = launch_wall_values(o.walls, prev, s->bcd, stream))) return rc;
-      io.f_out = cur_out;
-      if ((rc = launch_sweep(d, &io, s->mtab, s->d32, stream, 0))) return rc;
-      if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
-      if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
-                               stream, false)))
-        return rc;
-      if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], stream));
-      BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                             stream));
-      BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, stream));
-      BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                             stream));
-      BGK_HIP(hipStreamSynchronize(stream));
-      if (o.timing) {
-        float t01, t12, t23;
-        BGK_HIP(hipEventElapsedTime(&t01, s->ev[0], s->ev[1]));
-        BGK_HIP(hipEventElapsedTime(&t12, s->ev[1], s->ev[2]));
-        BGK_HIP(hipEventElapsedTime(&t23, s->ev[2], s->ev[3]));
-        st.maxwellian_ms += t01;
-        st.sweep_ms += t12;
-        st.moments_ms += t23;
+    }
+    for (int stg = 0; stg < s->S; ++stg) {
+      const double shift = 1.0 / (o.dt * s->A[stg][stg]);
+      const double* qsrc;
+      double qscale;
+      if (stg == 0) {
+        qsrc = fk;
+        qscale = s->qcoef[0][0];
+      } else {
+        const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
+        if ((rc = combine(s->q, xs, s->qcoef[stg], stg + 1, nf, stream))) return rc;
+        qsrc = s->q;
+        qscale = 1.0;
       }
-      ++st.sweeps;
-      ++it;
-      ucur ^= 1;
-      prev = cur_out;
-      int32_t stat[2];
-      std::memcpy(stat, s->h_info + 5, sizeof(stat));
-      st.maxw_fallbacks += stat[0];
-      if (stat[1] > 0) {
-        return fail(BGK_E_NONPHYSICAL,
-                    "non-physical moments (n <= 0 or theta <= 0) at " + std::to_string(stat[1]) +
-                        " nodes");
-      }
-      double numax;
-      std::memcpy(&numax, s->h_info + 4, sizeof(double));
-      last = s->h_info[3];
-      if (!std::isfinite(last))
-        return fail(BGK_E_NONPHYSICAL, "non-finite moments in the Picard iteration");
-      if (o.fixed_iters > 0) {
-        if (it >= o.fixed_iters) {
+      double* out = fst[stg];
+      // with lagged facets or the FP32 form the previous iterate is kept in
+      // fping; the first iteration reads the stage's initial iterate
+      const double* prev = stage_init;
+      double* cur_out = out;
+      int it = 0;
+      bool converged = false;
+      double last = 0.0;
+      // a node whose MATCHED solve fails stays on DIRECT for the rest of the
+      // stage: an iterate switching between the two would not settle
+      hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)std::min<int64_t>((d->n_nodes + 255) / 256, 1024)),
+                         dim3(256), 0, stream, s->sticky, d->n_nodes);
+      while (it < o.l_max) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], stream));
+        if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
+                                    nullptr, s->status, s->numax, s->sticky, stream)))
+          return rc;
+        if (s->pr)
+          rc = launch_proj_tables(d, s->mcoef, s->nu, s->pr, s->mtab, stream);
+        else if (s->mtab)
+          rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream);
+        if (rc) return rc;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
+        if (need_prev) cur_out = (prev == out) ? s->fping : out;
+        tgs_sweep_io io{};
+        io.precision = o.precision;
+        io.sigma_shift = shift;
+        io.q_scale = qscale;
+        io.nu = s->nu;
+        io.mcoef = s->mcoef;
+        io.q = qsrc;
+        io.bc_coef = o.walls ? nullptr : o.bc_coef;
+        io.bc_dense = o.walls ? s->bcd : nullptr;
+        io.f_prev = need_prev ? prev : nullptr;
+        if (o.walls && (rc = launch_wall_values(o.walls, prev, s->bcd, stream))) return rc;
+        io.f_out = cur_out;
+        if ((rc = launch_sweep(d, &io, s->mtab, s->d32, stream, 0))) return rc;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
+        if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
+                                 stream, false)))
+          return rc;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], stream));
+        BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                               stream));
+        BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, stream));
+        BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               stream));
+        BGK_HIP(hipStreamSynchronize(stream));
+        if (o.timing) {
+          float t01, t12, t23;
+          BGK_HIP(hipEventElapsedTime(&t01, s->ev[0], s->ev[1]));
+          BGK_HIP(hipEventElapsedTime(&t12, s->ev[1], s->ev[2]));
+          BGK_HIP(hipEventElapsedTime(&t23, s->ev[2], s->ev[3]));
+          st.maxwellian_ms += t01;
+          st.sweep_ms += t12;
+          st.moments_ms += t23;
+        }
+        ++st.sweeps;
+        ++it;
+        ucur ^= 1;
+        prev = cur_out;
+        int32_t stat[2];
+        std::memcpy(stat, s->h_info + 5, sizeof(stat));
+        st.maxw_fallbacks += stat[0];
+        if (stat[1] > 0) {
+          return fail(BGK_E_NONPHYSICAL,
+                      "non-physical moments (n <= 0 or theta <= 0) at " + std::to_string(stat[1]) +
+                          " nodes");
+        }
+        double numax;
+        std::memcpy(&numax, s->h_info + 4, sizeof(double));
+        last = s->h_info[3];
+        if (!std::isfinite(last))
+          return fail(BGK_E_NONPHYSICAL, "non-finite moments in the Picard iteration");
+        if (o.fixed_iters > 0) {
+          if (it >= o.fixed_iters) {
+            converged = true;
+            break;
+          }
+          continue;
+        }
+        if (last < o.tau / std::max(1.0, numax * o.dt)) {
           converged = true;
           break;
         }
-        continue;
       }
-      if (last < o.tau / std::max(1.0, numax * o.dt)) {
-        converged = true;
-        break;
+      if (prev != out) {
+        BGK_HIP(hipMemcpyAsync(out, prev, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
       }
+      st.iters[stg] = it;
+      st.last_ratio[stg] = last;
+      st.total_iters += it;
+      if (!converged) {
+        if (stats) *stats = st;
+        return fail(BGK_E_NOT_CONVERGED, "Picard iteration reached l_max in stage " +
+                                             std::to_string(stg + 1));
+      }
+      stage_init = out;
     }
-    if (prev != out) {
-      BGK_HIP(hipMemcpyAsync(out, prev, nf * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if (!s->stiffly_accurate) {
+      const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
+      if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
+      if (U_out &&
+          (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false)))
+        return rc;
     }
-    st.iters[stg] = it;
-    st.last_ratio[stg] = last;
-    st.total_iters += it;
-    if (!converged) {
-      if (stats) *stats = st;
-      return fail(BGK_E_NOT_CONVERGED, "Picard iteration reached l_max in stage " +
-                                           std::to_string(stg + 1));
-    }
-    stage_init = out;
-  }
-  if (!s->stiffly_accurate) {
-    const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
-    if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
-    if (U_out &&
-        (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false)))
-      return rc;
-  }
-  if (U_out && (rc = launch_nodal_perm(d, s->U[ucur], U_out, 0, stream))) return rc;
-  BGK_HIP(hipStreamSynchronize(stream));
-  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (stats) *stats = st;
-  return BGK_OK;
+    if (U_out && (rc = launch_nodal_perm(d, s->U[ucur], U_out, 0, stream))) return rc;
+    BGK_HIP(hipStreamSynchronize(stream));
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return BGK_OK;
+  });
 }

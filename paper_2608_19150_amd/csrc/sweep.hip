@@ -1013,76 +1013,84 @@ int grid_for(size_t total) {
 using namespace bgk;
 
 extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t stream) {
-  if (!d || !io) return fail(BGK_E_INVALID, "null argument");
-  if (!io->q || !io->f_out || !io->nu || !io->mcoef)
-    return fail(BGK_E_INVALID, "q, f_out, nu and mcoef are required");
-  if ((io->bc_coef == nullptr) == (io->bc_dense == nullptr))
-    return fail(BGK_E_INVALID, "exactly one of bc_coef / bc_dense must be given");
-  if (io->precision != TGS_FP64 && io->precision != TGS_FP32_CORRECTION)
-    return fail(BGK_E_INVALID, "unknown precision");
-  if ((d->d_lag || io->precision == TGS_FP32_CORRECTION) && !io->f_prev)
-    return fail(BGK_E_INVALID, "f_prev is required with lagged facets or the FP32 form");
-  if (io->f_prev && io->f_prev == io->f_out) return fail(BGK_E_INVALID, "f_out aliases f_prev");
-  // the kernels read nodal arrays in the internal cell order: nu and the
-  // coefficients are permuted into scratch first; on a tensor velocity grid
-  // the factorised Maxwellian tables are built from them, as in bgk_step, so
-  // this is the solver's sweep kernel
-  hipStream_t st = (hipStream_t)stream;
-  const int np = d->n_p, nm = d->dim + 2;
-  const size_t ntab = d->n_1d > 0 ? maxw_table_size(d) : 0;
-  float* d32 = nullptr;
-  double* nodal = nullptr;  // [n_nodes] nu, [n_nodes][dim+2] coefficients, tables
-  if (hipMallocAsync((void**)&nodal, ((size_t)d->n_nodes * (1 + nm) + ntab) * sizeof(double),
-                     st) != hipSuccess)
-    return fail(BGK_E_NOMEM, "scratch allocation failed");
-  if (io->precision == TGS_FP32_CORRECTION &&
-      hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), st) != hipSuccess) {
+  return guarded([&]() -> int {
+    if (!d || !io) return fail(BGK_E_INVALID, "null argument");
+    if (!io->q || !io->f_out || !io->nu || !io->mcoef)
+      return fail(BGK_E_INVALID, "q, f_out, nu and mcoef are required");
+    if ((io->bc_coef == nullptr) == (io->bc_dense == nullptr))
+      return fail(BGK_E_INVALID, "exactly one of bc_coef / bc_dense must be given");
+    if (io->precision != TGS_FP64 && io->precision != TGS_FP32_CORRECTION)
+      return fail(BGK_E_INVALID, "unknown precision");
+    if ((d->d_lag || io->precision == TGS_FP32_CORRECTION) && !io->f_prev)
+      return fail(BGK_E_INVALID, "f_prev is required with lagged facets or the FP32 form");
+    if (io->f_prev && io->f_prev == io->f_out) return fail(BGK_E_INVALID, "f_out aliases f_prev");
+    // the kernels read nodal arrays in the internal cell order: nu and the
+    // coefficients are permuted into scratch first; on a tensor velocity grid
+    // the factorised Maxwellian tables are built from them, as in bgk_step, so
+    // this is the solver's sweep kernel
+    hipStream_t st = (hipStream_t)stream;
+    const int np = d->n_p, nm = d->dim + 2;
+    const size_t ntab = d->n_1d > 0 ? maxw_table_size(d) : 0;
+    float* d32 = nullptr;
+    double* nodal = nullptr;  // [n_nodes] nu, [n_nodes][dim+2] coefficients, tables
+    if (hipMallocAsync((void**)&nodal, ((size_t)d->n_nodes * (1 + nm) + ntab) * sizeof(double),
+                       st) != hipSuccess)
+      return fail(BGK_E_NOMEM, "scratch allocation failed");
+    if (io->precision == TGS_FP32_CORRECTION &&
+        hipMallocAsync((void**)&d32, f_elems(d) * sizeof(float), st) != hipSuccess) {
+      (void)hipFreeAsync(nodal, st);
+      return fail(BGK_E_NOMEM, "correction buffer allocation failed");
+    }
+    tgs_sweep_io io_i = *io;
+    io_i.nu = nodal;
+    io_i.mcoef = nodal + d->n_nodes;
+    double* tab = ntab ? nodal + (size_t)d->n_nodes * (1 + nm) : nullptr;
+    int rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
+    if (!rc) rc = launch_nodal_rows(d, io->mcoef, nodal + d->n_nodes, np * nm, 1, st);
+    if (!rc && tab) rc = launch_maxw_tables(d, io_i.mcoef, io_i.nu, tab, st);
+    if (!rc) rc = launch_sweep(d, &io_i, tab, d32, st, 0);
+    if (d32) (void)hipFreeAsync(d32, st);
     (void)hipFreeAsync(nodal, st);
-    return fail(BGK_E_NOMEM, "correction buffer allocation failed");
-  }
-  tgs_sweep_io io_i = *io;
-  io_i.nu = nodal;
-  io_i.mcoef = nodal + d->n_nodes;
-  double* tab = ntab ? nodal + (size_t)d->n_nodes * (1 + nm) : nullptr;
-  int rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
-  if (!rc) rc = launch_nodal_rows(d, io->mcoef, nodal + d->n_nodes, np * nm, 1, st);
-  if (!rc && tab) rc = launch_maxw_tables(d, io_i.mcoef, io_i.nu, tab, st);
-  if (!rc) rc = launch_sweep(d, &io_i, tab, d32, st, 0);
-  if (d32) (void)hipFreeAsync(d32, st);
-  (void)hipFreeAsync(nodal, st);
-  return rc;
+    return rc;
+  });
 }
 
 extern "C" int tgs_pack(const tgs_dag* d, const double* fc, double* fs, bgk_stream_t stream) {
-  if (!d || !fc || !fs || (const void*)fc == (const void*)fs)
-    return fail(BGK_E_INVALID, "bad arguments");
-  const size_t total = f_elems(d);
-  hipLaunchKernelGGL(k_pack, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, fc, fs,
-                     d->d_pos, d->d_uid, (int)d->n_cells, d->n_v, d->n_p, 1);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !fc || !fs || (const void*)fc == (const void*)fs)
+      return fail(BGK_E_INVALID, "bad arguments");
+    const size_t total = f_elems(d);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, fc, fs,
+                       d->d_pos, d->d_uid, (int)d->n_cells, d->n_v, d->n_p, 1);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_unpack(const tgs_dag* d, const double* fs, double* fc, bgk_stream_t stream) {
-  if (!d || !fc || !fs || (const void*)fc == (const void*)fs)
-    return fail(BGK_E_INVALID, "bad arguments");
-  const size_t total = f_elems(d);
-  hipLaunchKernelGGL(k_pack, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, fs, fc,
-                     d->d_pos, d->d_uid, (int)d->n_cells, d->n_v, d->n_p, 0);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !fc || !fs || (const void*)fc == (const void*)fs)
+      return fail(BGK_E_INVALID, "bad arguments");
+    const size_t total = f_elems(d);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, fs, fc,
+                       d->d_pos, d->d_uid, (int)d->n_cells, d->n_v, d->n_p, 0);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_eval_maxwellian(const tgs_dag* d, const double* coef, double* f,
                                    bgk_stream_t stream) {
-  if (!d || !coef || !f) return fail(BGK_E_INVALID, "null argument");
-  const size_t total = f_elems(d);
-  if (d->dim == 2)
-    hipLaunchKernelGGL(k_eval_maxw<2>, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream,
-                       coef, f, d->d_perm, d->d_uid, d->d_v, (int)d->n_cells, d->n_v, d->n_p);
-  else
-    hipLaunchKernelGGL(k_eval_maxw<3>, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream,
-                       coef, f, d->d_perm, d->d_uid, d->d_v, (int)d->n_cells, d->n_v, d->n_p);
-  BGK_HIP(hipGetLastError());
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!d || !coef || !f) return fail(BGK_E_INVALID, "null argument");
+    const size_t total = f_elems(d);
+    if (d->dim == 2)
+      hipLaunchKernelGGL(k_eval_maxw<2>, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream,
+                         coef, f, d->d_perm, d->d_uid, d->d_v, (int)d->n_cells, d->n_v, d->n_p);
+    else
+      hipLaunchKernelGGL(k_eval_maxw<3>, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream,
+                         coef, f, d->d_perm, d->d_uid, d->d_v, (int)d->n_cells, d->n_v, d->n_p);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  });
 }

@@ -164,94 +164,100 @@ int launch_bc_dense(const tgs_dag* d, const double* bc_coef, double* bc_dense,
 using namespace bgk;
 
 extern "C" int tgs_walls_destroy(tgs_walls* w) {
-  if (!w) return BGK_OK;
-  if (w->d_wall) (void)hipFree(w->d_wall);
-  if (w->d_map) (void)hipFree(w->d_map);
-  if (w->d_in) (void)hipFree(w->d_in);
-  if (w->d_in_off) (void)hipFree(w->d_in_off);
-  delete w;
-  return BGK_OK;
+  return guarded([&]() -> int {
+    if (!w) return BGK_OK;
+    if (w->d_wall) (void)hipFree(w->d_wall);
+    if (w->d_map) (void)hipFree(w->d_map);
+    if (w->d_in) (void)hipFree(w->d_in);
+    if (w->d_in_off) (void)hipFree(w->d_in_off);
+    delete w;
+    return BGK_OK;
+  });
 }
 
 extern "C" int tgs_walls_create(const tgs_dag* d, const int8_t* kind, tgs_walls** out) {
-  if (!d || !out || (!kind && d->n_bfaces > 0)) return fail(BGK_E_INVALID, "null argument");
-  *out = nullptr;
-  const int dim = d->dim;
-  std::vector<int4> wall;
-  std::vector<int32_t> maps, in, in_off{0};
-  std::map<std::array<double, 4>, int> map_id;   // (kind, unit normal) -> map
-  for (int64_t bf = 0; bf < d->n_bfaces; ++bf) {
-    const int k = kind[bf];
-    if (k != BGK_BC_INFLOW && k != BGK_BC_BOUNCE_BACK && k != BGK_BC_REFLECT)
-      return fail(BGK_E_INVALID, "unknown boundary kind at facet " + std::to_string(bf));
-    if (k == BGK_BC_INFLOW) continue;
-    const double* nrm = &d->bface_normal[(size_t)bf * dim];
-    // one map per (kind, normal): the velocity map of bounce-back does not
-    // depend on the normal, but the incoming velocities do
-    std::array<double, 4> key{(double)k, 0, 0, 0};
-    for (int a = 0; a < dim; ++a) key[1 + a] = nrm[a];
-    auto it = map_id.find(key);
-    int id;
-    if (it == map_id.end()) {
-      std::vector<int32_t> m;
-      const int rc = velocity_map(d, k, nrm, m);
-      if (rc) return rc;
-      id = (int)map_id.size();
-      map_id.emplace(key, id);
-      maps.insert(maps.end(), m.begin(), m.end());
-      // incoming velocities of this map (a superset of those the sweep reads:
-      // it treats |v.N| <= 1e-12 |v| |N| as tangential)
-      for (int j = 0; j < d->n_v; ++j) {
-        double vn = 0.0, v2 = 0.0;
-        for (int a = 0; a < dim; ++a) {
-          const double x = d->v_host[(size_t)j * dim + a];
-          vn += x * nrm[a];
-          v2 += x * x;
+  return guarded([&]() -> int {
+    if (!d || !out || (!kind && d->n_bfaces > 0)) return fail(BGK_E_INVALID, "null argument");
+    *out = nullptr;
+    const int dim = d->dim;
+    std::vector<int4> wall;
+    std::vector<int32_t> maps, in, in_off{0};
+    std::map<std::array<double, 4>, int> map_id;   // (kind, unit normal) -> map
+    for (int64_t bf = 0; bf < d->n_bfaces; ++bf) {
+      const int k = kind[bf];
+      if (k != BGK_BC_INFLOW && k != BGK_BC_BOUNCE_BACK && k != BGK_BC_REFLECT)
+        return fail(BGK_E_INVALID, "unknown boundary kind at facet " + std::to_string(bf));
+      if (k == BGK_BC_INFLOW) continue;
+      const double* nrm = &d->bface_normal[(size_t)bf * dim];
+      // one map per (kind, normal): the velocity map of bounce-back does not
+      // depend on the normal, but the incoming velocities do
+      std::array<double, 4> key{(double)k, 0, 0, 0};
+      for (int a = 0; a < dim; ++a) key[1 + a] = nrm[a];
+      auto it = map_id.find(key);
+      int id;
+      if (it == map_id.end()) {
+        std::vector<int32_t> m;
+        const int rc = velocity_map(d, k, nrm, m);
+        if (rc) return rc;
+        id = (int)map_id.size();
+        map_id.emplace(key, id);
+        maps.insert(maps.end(), m.begin(), m.end());
+        // incoming velocities of this map (a superset of those the sweep reads:
+        // it treats |v.N| <= 1e-12 |v| |N| as tangential)
+        for (int j = 0; j < d->n_v; ++j) {
+          double vn = 0.0, v2 = 0.0;
+          for (int a = 0; a < dim; ++a) {
+            const double x = d->v_host[(size_t)j * dim + a];
+            vn += x * nrm[a];
+            v2 += x * x;
+          }
+          if (vn <= 1e-9 * std::sqrt(v2)) in.push_back(j);
         }
-        if (vn <= 1e-9 * std::sqrt(v2)) in.push_back(j);
+        in_off.push_back((int32_t)in.size());
+      } else {
+        id = it->second;
       }
-      in_off.push_back((int32_t)in.size());
-    } else {
-      id = it->second;
+      wall.push_back(make_int4((int)bf, d->iid_host[d->bface_cell[bf]], id, d->bface_pack[bf]));
     }
-    wall.push_back(make_int4((int)bf, d->iid_host[d->bface_cell[bf]], id, d->bface_pack[bf]));
-  }
-  tgs_walls* w = new (std::nothrow) tgs_walls();
-  if (!w) return fail(BGK_E_NOMEM, "host allocation failed");
-  w->dag = d;
-  w->n_walls = (int64_t)wall.size();
-  w->n_maps = (int)map_id.size();
-  for (size_t m = 0; m + 1 < in_off.size(); ++m)
-    w->max_in = std::max(w->max_in, in_off[m + 1] - in_off[m]);
-  if (!wall.empty()) {
-    if (hipMalloc((void**)&w->d_wall, wall.size() * sizeof(int4)) != hipSuccess ||
-        hipMalloc((void**)&w->d_map, maps.size() * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void**)&w->d_in, std::max<size_t>(in.size(), 1) * sizeof(int32_t)) !=
-            hipSuccess ||
-        hipMalloc((void**)&w->d_in_off, in_off.size() * sizeof(int32_t)) != hipSuccess) {
-      tgs_walls_destroy(w);
-      return fail(BGK_E_NOMEM, "wall arrays");
+    tgs_walls* w = new (std::nothrow) tgs_walls();
+    if (!w) return fail(BGK_E_NOMEM, "host allocation failed");
+    w->dag = d;
+    w->n_walls = (int64_t)wall.size();
+    w->n_maps = (int)map_id.size();
+    for (size_t m = 0; m + 1 < in_off.size(); ++m)
+      w->max_in = std::max(w->max_in, in_off[m + 1] - in_off[m]);
+    if (!wall.empty()) {
+      if (hipMalloc((void**)&w->d_wall, wall.size() * sizeof(int4)) != hipSuccess ||
+          hipMalloc((void**)&w->d_map, maps.size() * sizeof(int32_t)) != hipSuccess ||
+          hipMalloc((void**)&w->d_in, std::max<size_t>(in.size(), 1) * sizeof(int32_t)) !=
+              hipSuccess ||
+          hipMalloc((void**)&w->d_in_off, in_off.size() * sizeof(int32_t)) != hipSuccess) {
+        tgs_walls_destroy(w);
+        return fail(BGK_E_NOMEM, "wall arrays");
+      }
+      if (hipMemcpy(w->d_wall, wall.data(), wall.size() * sizeof(int4), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(w->d_map, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          (!in.empty() && hipMemcpy(w->d_in, in.data(), in.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
+          hipMemcpy(w->d_in_off, in_off.data(), in_off.size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice) != hipSuccess) {
+        tgs_walls_destroy(w);
+        return fail(BGK_E_HIP, "wall arrays copy");
+      }
     }
-    if (hipMemcpy(w->d_wall, wall.data(), wall.size() * sizeof(int4), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(w->d_map, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        (!in.empty() && hipMemcpy(w->d_in, in.data(), in.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(w->d_in_off, in_off.data(), in_off.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice) != hipSuccess) {
-      tgs_walls_destroy(w);
-      return fail(BGK_E_HIP, "wall arrays copy");
-    }
-  }
-  *out = w;
-  return BGK_OK;
+    *out = w;
+    return BGK_OK;
+  });
 }
 
 extern "C" int64_t tgs_walls_count(const tgs_walls* w) { return w ? w->n_walls : 0; }
 
 extern "C" int tgs_wall_values(const tgs_walls* w, const double* f, double* bc_dense,
                                bgk_stream_t stream) {
-  if (!w || !f || !bc_dense) return fail(BGK_E_INVALID, "null argument");
-  return launch_wall_values(w, f, bc_dense, (hipStream_t)stream);
+  return guarded([&]() -> int {
+    if (!w || !f || !bc_dense) return fail(BGK_E_INVALID, "null argument");
+    return launch_wall_values(w, f, bc_dense, (hipStream_t)stream);
+  });
 }
