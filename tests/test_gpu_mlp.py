@@ -77,6 +77,13 @@ def test_gradients_match_bf16_oracle(n):
     assert abs(float(loss.item()) - lref) <= 1e-4 * lref
     for k in gref:
         assert _rel(g[k], gref[k]) <= 1e-2, (k, _rel(g[k], gref[k]))
+        # every element: within 2% of itself plus 1e-3 of the tensor's largest
+        # entry (the two sides accumulate FP32 partial sums in different orders,
+        # which only matters where an element is a cancellation of large terms)
+        dev = np.abs(g[k] - gref[k])
+        bound = 2e-2 * np.abs(gref[k]) + 1e-3 * np.abs(gref[k]).max()
+        print(k, "worst element deviation / bound", float((dev / bound).max()), flush=True)
+        assert np.all(dev <= bound), (k, float((dev / bound).max()))
     # and close to the exact FP64 gradient (BF16 operand rounding only)
     _, g64 = om.loss_and_grads({k: v.astype(np.float64) for k, v in params.items()},
                                _normalise(X, st[0], st[1]).astype(np.float64),

@@ -302,7 +302,14 @@ def test_moments_and_ratios_match_oracle(dim, order, n_side, n1):
     Uold_ref = kinetic.moments(f_old, V, w).reshape(-1, dim + 2)
     assert rel(U.cpu().numpy(), Uref) <= TOL64
     rref = solver.relative_changes(Uref, Uold_ref, dim)
-    assert np.allclose(ratio.cpu().numpy(), rref, rtol=1e-9)
+    rg = ratio.cpu().numpy()
+    say("ratios", rg, rref, np.abs(rg - rref))
+    # each ratio is a norm of moment differences (here ~1e-5 of the moments)
+    # over a norm of moments: moments that agree to 1e-12 of their size give
+    # ratios that agree to about 2e-12 in absolute terms, whatever their own
+    # size; checked against 1e-13 (the relative error of a 2e-5 ratio is
+    # rounding of order 1e-11 and says nothing about the kernel)
+    assert np.all(np.abs(rg - rref) <= 1e-13)
     # bitwise reproducible
     U2 = B.moments(d, fs)
     assert torch.equal(U, U2)
@@ -416,6 +423,28 @@ def test_bgk_step_3d_matches_oracle(state):
     pr = P.small_problem(dim=3, order=1, n_side=3, n_1d=6, state=state, nu_model="kn", kn=0.1)
     d, f, st, dt = _run_steps(pr, 2, fixed_iters=3)
     geo, fref, _ = _oracle_steps(pr, 2, dt, fixed_iters=3)
+    assert rel(f, fref) <= TOL64
+
+
+@pytest.mark.parametrize("kn,nsteps,fixed", [(1.0, 2, None), (1e-2, 2, None), (1e-4, 1, None)])
+def test_bgk_step_3d_knudsen_range_matches_oracle(kn, nsteps, fixed):
+    """The 3D workload's three Knudsen numbers (nu = n theta^(-1/2) / Kn) at a
+    size the oracle runs in seconds: the same smoothed planar Riemann set-up
+    (180 P1 tetrahedra, 8^3 velocities on [-6, 6]^3, BE, CFL 10); f within
+    1e-12.  Kn = 1 and 1e-2: two steps converged to tau = 1e-10 with equal
+    iteration counts.  Kn = 1e-4 is collision-dominated (nu dt ~ 1e2, so
+    Picard contracts by about nu dt / (1 + nu dt) per iteration and a step
+    needs ~700 iterations, minutes for the oracle): one step of 40 fixed
+    iterations."""
+    say("bgk_step 3d kn", kn)
+    mesh = P.jittered_cube_mesh(3, 0.2, seed=3000)
+    pr = P.Problem(mesh, 1, P.tensor_velocity_grid(8, 6.0, 3),
+                   P.planar_riemann_state(3, seed=3001, width=0.5), nu_model="kn", kn=kn,
+                   tableau="BE", name=f"c3_small_kn{kn:g}")
+    d, f, st, dt = _run_steps(pr, nsteps, fixed_iters=fixed or 0)
+    geo, fref, ost = _oracle_steps(pr, nsteps, dt, fixed_iters=fixed)
+    say("iters", [s["iters"] for s in st], [s["iters"] for s in ost])
+    assert [s["iters"] for s in st] == [s["iters"] for s in ost]
     assert rel(f, fref) <= TOL64
 
 
