@@ -234,6 +234,20 @@ int tgs_sweep(const tgs_dag* dag, const tgs_sweep_io* io, bgk_stream_t stream);
 int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
             double* rel3, bgk_stream_t stream);
 
+/* moments() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, bit for bit, with no hipMalloc/hipFree or
+ * allocating call.  The ratio scratch (6 doubles per moment block, 256
+ * cells per block on meshes of 65,536 cells or more, at most 1024 blocks
+ * below) lives in a fixed 2 MiB device array per GPU, held until the
+ * process ends and shared by every call on that GPU: calls that overlap on
+ * one GPU race on it and must be ordered by the caller (one stream, or
+ * events).  Nothing in it needs clearing between calls.  BGK_E_INVALID when
+ * U_prev is given and the mesh needs more scratch than that (about 11
+ * million cells); without U_prev no scratch is used. */
+int moments_noalloc(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
+                    double* rel3, bgk_stream_t stream);
+
 /* DIRECT: the Maxwellian of (n, u, theta) at the nodes; MATCHED: the nodal
  * Gaussian whose discrete moments equal U (Newton from DIRECT); LINEAR:
  * n/|V|; PROJECTED (Q2 velocity space only, App. B): the projection of

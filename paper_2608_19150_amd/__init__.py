@@ -35,7 +35,7 @@ EXPORTED = [
     "bgk_last_error", "build_mesh_dag", "tgs_dag_destroy", "tgs_dag_sizes",
     "tgs_dag_generations", "tgs_dag_lagged", "tgs_dag_geometry", "tgs_dag_explicit_dt",
     "tgs_pack", "tgs_unpack",
-    "tgs_sweep", "moments", "maxwellian", "maxwellian_coef_from_primitive",
+    "tgs_sweep", "moments", "moments_noalloc", "maxwellian", "maxwellian_coef_from_primitive",
     "tgs_eval_maxwellian", "bgk_solver_create", "bgk_solver_destroy", "bgk_step",
     "bgk_mlp_create", "bgk_mlp_destroy", "bgk_mlp_set_params", "bgk_mlp_get_params",
     "bgk_mlp_set_normalization", "bgk_mlp_forward", "bgk_mlp_loss_grad", "bgk_mlp_adam_step",
@@ -135,6 +135,8 @@ _lib.tgs_pack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_unpack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_sweep.argtypes = [C.c_void_p, C.POINTER(SweepIO), C.c_void_p]
 _lib.moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.moments_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]
 _lib.maxwellian.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(NuModel), C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.maxwellian_coef_from_primitive.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
@@ -263,6 +265,13 @@ def moments(dag, f, U=None, U_prev=None, stream=None):
     rel = torch.empty(3, dtype=torch.float64, device="cuda") if U_prev is not None else None
     _check(_lib.moments(dag.h, _p(f), _p(U), _p(U_prev), _p(rel), _stream(stream)))
     return (U, rel) if U_prev is not None else U
+
+
+def moments_noalloc(dag, f, U, U_prev=None, rel3=None, stream=None):
+    """moments() into caller-provided buffers (U [n_nodes][d+2], and rel3 [3]
+    when U_prev is given); the library allocates nothing."""
+    _check(_lib.moments_noalloc(dag.h, _p(f), _p(U), _p(U_prev), _p(rel3), _stream(stream)))
+    return (U, rel3) if U_prev is not None else U
 
 
 def maxwellian(dag, U, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0, dense=False,

@@ -2,6 +2,7 @@
 // (eq. convergence-criteria) and the discrete Maxwellian
 // (eq. Maxwellian-projection) with the collision frequency.
 #include <cmath>
+#include <mutex>
 
 #include "device_common.h"
 #include "kinetic_args.h"
@@ -1110,6 +1111,37 @@ int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const
   return BGK_OK;
 }
 
+// Scratch of the allocation-free moments entry point (moments_noalloc):
+// the per-block partial norms of the convergence ratios, then the ratios.
+// One copy per device, held until the process ends.  Host code never uses
+// the array's name as an address: it takes the device address from
+// hipGetSymbolAddress once per device (noalloc_scratch below).
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 18;  // 2 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with it current).
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  BGK_HIP(hipGetDevice(&dev));
+  BGK_CHECK(dev >= 0 && dev < NOALLOC_MAX_DEVICES, BGK_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    BGK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    BGK_CHECK(p != nullptr, BGK_E_HIP, "hipGetSymbolAddress returned no address");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BGK_OK;
+}
+
 }  // namespace bgk
 
 using namespace bgk;
@@ -1136,6 +1168,41 @@ extern "C" int moments(const tgs_dag* d, const double* f, double* U, const doubl
     }
     if (partial) (void)hipFreeAsync(partial, s);
     if (ratio) (void)hipFreeAsync(ratio, s);
+    return rc;
+  });
+}
+
+extern "C" int moments_noalloc(const tgs_dag* d, const double* f, double* U,
+                               const double* U_prev, double* rel3, bgk_stream_t stream) {
+  return guarded([&]() -> int {
+    if (!d || !f || !U) return fail(BGK_E_INVALID, "null argument");
+    if ((U_prev == nullptr) != (rel3 == nullptr))
+      return fail(BGK_E_INVALID, "U_prev and rel3 go together");
+    hipStream_t s = (hipStream_t)stream;
+    double* partial = nullptr;
+    double* ratio = nullptr;
+    if (U_prev) {
+      // partial norms: 6 per moment block; the ratios after them, 256-byte aligned
+      const int64_t need = (int64_t)moment_blocks(d) * 6;
+      const int64_t at = (need + 31) / 32 * 32;
+      if (at + 4 > NOALLOC_SCRATCH_DOUBLES)
+        return fail(BGK_E_INVALID,
+                    "moments_noalloc: the mesh needs " + std::to_string(at + 4) +
+                        " doubles of ratio scratch, above the fixed " +
+                        std::to_string(NOALLOC_SCRATCH_DOUBLES) + " (use moments)");
+      double* base = nullptr;
+      int rc = noalloc_scratch(&base);
+      if (rc) return rc;
+      partial = base;
+      ratio = base + at;
+    }
+    // every block writes its own 6 partial norms before k_ratio reads them:
+    // nothing in the scratch needs clearing
+    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
+    if (rc == BGK_OK && U_prev) {
+      if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = fail(BGK_E_HIP, "copy of ratios failed");
+    }
     return rc;
   });
 }
