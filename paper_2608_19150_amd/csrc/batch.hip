@@ -23,6 +23,7 @@
 #include "kinetic_args.h"
 #include "solver.h"
 #include "sweep_args.h"
+#include "walls.h"
 
 namespace bgk {
 namespace {
@@ -229,7 +230,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       io.nu = s->nu;
       io.mcoef = s->mcoef;
       io.q = st == 0 ? s->fk : s->q;
-      io.bc_coef = o.bc_coef;
+      io.bc_dense = s->bcd;
       io.f_out = out[st];
       sargs[(size_t)st * n + i] = make_sweep_args(d, &io, mtab, nullptr);
     }
@@ -242,7 +243,7 @@ int batch_upload(bgk_batch* B, double* const* f) {
       io.nu = s->nu;
       io.mcoef = s->mcoef;
       io.q = f[i];
-      io.bc_coef = o.bc_coef;
+      io.bc_dense = s->bcd;
       io.f_out = s->fk;
       tune[i] = make_sweep_args(d, &io, mtab, nullptr);
     }
@@ -310,6 +311,13 @@ int batch_upload(bgk_batch* B, double* const* f) {
       }
       for (int r = c.nin; r < 5; ++r) c.x[r] = c.x[0];
     }
+  }
+  // the sweep reads dense boundary data: each instance's inflow Maxwellians,
+  // evaluated once (batched instances have no walls)
+  for (int i = 0; i < n; ++i) {
+    const bgk_solver* s = B->solvers[i];
+    int rc = launch_bc_dense(s->dag, s->opts.bc_coef, s->bcd, B->stream);
+    if (rc) return rc;
   }
   BGK_HIP(hipMemcpyAsync(B->sargs, sargs.data(), sargs.size() * sizeof(SweepArgs),
                          hipMemcpyHostToDevice, B->stream));

@@ -20,7 +20,7 @@ struct bgk_solver {
   double* mcoef = nullptr;
   double* mtab = nullptr;        // factorised Maxwellian tables (tensor grids)
   double* pr = nullptr;          // per-axis projections (PROJECTED mode)
-  double* bcd = nullptr;         // dense boundary data [n_bfaces][n_fp][n_v] (walls)
+  double* bcd = nullptr;         // dense boundary data [n_bfaces][n_fp][n_v]
   double* nu = nullptr;
   double* partial = nullptr;
   double* ratio = nullptr;       // [4]

@@ -9,6 +9,7 @@
 //   f^{k+1} = f^k + dt sum_s b_s F^(s)   (= f^(S) for stiffly accurate tableaus).
 // The first stage's source is f^k itself scaled inside the sweep (no extra
 // pass); later stages materialise q^(s) with one fused combination kernel.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -219,7 +220,7 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
     if (!rc) rc = dmalloc(&s->mcoef, nn);
     if (!rc && d->n_1d > 0) rc = dmalloc(&s->mtab, maxw_table_size(d));
     if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
-    if (!rc && o->walls) rc = dmalloc(&s->bcd, (size_t)d->n_bfaces * d->n_fp * d->n_v);
+    if (!rc) rc = dmalloc(&s->bcd, std::max<size_t>(1, (size_t)d->n_bfaces * d->n_fp * d->n_v));
     if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
     if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
     if (!rc) rc = dmalloc(&s->ratio, 4);
@@ -284,9 +285,10 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     if (s->stiffly_accurate) fst[s->S - 1] = f;
     const double* stage_init = fk;   // initial Picard iterate of the stage
     int ucur = 0;
-    // with walls the sweep reads dense boundary data: the inflow facets'
-    // Maxwellians once per step, the wall facets' rows before every sweep
-    if (o.walls && (rc = launch_bc_dense(d, o.bc_coef, s->bcd, stream))) return rc;
+    // the sweep reads dense boundary data: the inflow facets' Maxwellians are
+    // evaluated once per step (with walls, the wall facets' rows are replaced
+    // before every sweep)
+    if ((rc = launch_bc_dense(d, o.bc_coef, s->bcd, stream))) return rc;
     // nodal arrays (U, Maxwellian coefficients, nu) stay in the internal cell
     // order during the step; U_guess / U_out are in user order
     if (U_guess) {
@@ -340,8 +342,8 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         io.nu = s->nu;
         io.mcoef = s->mcoef;
         io.q = qsrc;
-        io.bc_coef = o.walls ? nullptr : o.bc_coef;
-        io.bc_dense = o.walls ? s->bcd : nullptr;
+        io.bc_coef = nullptr;
+        io.bc_dense = s->bcd;
         io.f_prev = need_prev ? prev : nullptr;
         if (o.walls && (rc = launch_wall_values(o.walls, prev, s->bcd, stream))) return rc;
         io.f_out = cur_out;

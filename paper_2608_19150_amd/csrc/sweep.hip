@@ -32,6 +32,7 @@
 
 #include "device_common.h"
 #include "sweep_args.h"
+#include "walls.h"
 
 namespace bgk {
 
@@ -390,22 +391,73 @@ __device__ __forceinline__ void upwind_values(const SweepArgs& a, const Prep<DIM
   }
 }
 
-// FP64 solve of a prepared cell into rhs, which also goes to the LDS ring
-// (RING; without it every upwind value is read from HBM)
+// Issues the reads of facet k's upwind values without waiting for them: new
+// values of recent slots from the LDS ring, older ones and lagged facets from
+// HBM, boundary values from the dense boundary array (every launch of the
+// FP64 sweep passes boundary data in dense form).
+template <int DIM, int ORDER, typename RT>
+__device__ __forceinline__ void fetch_upwind(const SweepArgs& a, const Prep<DIM, ORDER>& P, int k,
+                                             size_t base, int j, const RT* ring, int rmask,
+                                             int ring_lo, double (&fh)[Elem<DIM, ORDER>::NFP]) {
+  constexpr int NP = Elem<DIM, ORDER>::NP, NFP = Elem<DIM, ORDER>::NFP;
+  constexpr int NB = NP <= 4 ? 2 : 3, NM = (1 << NB) - 1;
+  const int c = P.code[k];
+  if (c >= 0) {
+    const int sl = c & REC_SLOT_MASK;
+    const int pk = P.pack >> (NB * k * NFP);
+    if (c & REC_LAG_BIT) {
+      const double* src = a.f_prev + (base + sl) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+    } else if (sl >= ring_lo) {
+      // the ring is LDS: an explicit LDS pointer keeps these reads apart from
+      // the global ones in the other branches
+      using lds_rt = __attribute__((address_space(3))) const RT;
+      const lds_rt* src = (const lds_rt*)(ring + (sl & rmask) * NP);
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = (double)src[(pk >> (NB * p)) & NM];
+    } else {
+      const double* src = a.f_out + (base + sl) * NP;
+#pragma unroll
+      for (int p = 0; p < NFP; ++p) fh[p] = src[(pk >> (NB * p)) & NM];
+    }
+    return;
+  }
+  const size_t bf = (size_t)(-2 - c);
+#pragma unroll
+  for (int p = 0; p < NFP; ++p) fh[p] = a.bc_dense[(bf * NFP + p) * a.n_v + j];
+}
+
+// The upwind values of every inflow facet of a prepared cell, read without
+// waiting for them (facets with code -1 are left unset).
+template <int DIM, int ORDER>
+__device__ __forceinline__ void fetch_inflow(const SweepArgs& a, const Prep<DIM, ORDER>& P,
+                                             size_t base, int j, const double* ring, int rmask,
+                                             int ring_lo,
+                                             double (&fh)[DIM + 1][Elem<DIM, ORDER>::NFP]) {
+#pragma unroll
+  for (int k = 0; k < DIM + 1; ++k)
+    if (P.code[k] != -1) fetch_upwind<DIM, ORDER, double>(a, P, k, base, j, ring, rmask, ring_lo, fh[k]);
+}
+
+// FP64 solve of a prepared cell whose upwind values were fetched into fh:
+// the local matrix is assembled (while those reads are in flight), the
+// inflow terms are added in facet order, and the solution goes to rhs and,
+// with RING, to the LDS ring.
 template <int DIM, int ORDER, bool RING = true>
-__device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDER>& P, size_t base,
-                                        int j, const double* v, double v2, double* ring,
-                                        int rmask, int ring_lo,
-                                        double (&rhs)[Elem<DIM, ORDER>::NP]) {
+__device__ __forceinline__ void solve64_fetched(const Prep<DIM, ORDER>& P, double* ring, int rmask,
+                                                double (&fh)[DIM + 1][Elem<DIM, ORDER>::NFP],
+                                                double (&rhs)[Elem<DIM, ORDER>::NP]) {
   using S = Scaled<DIM, ORDER>;
   constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
   double A[NP][NP];
   assemble<DIM, ORDER>(P, A, rhs);
+  // keep the assembly ahead of the first use of the upwind values: the waits
+  // for their loads then come after it
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
     if (P.code[k] == -1) continue;
-    double fh[NFP];
-    upwind_values<DIM, ORDER, double>(a, P, k, base, j, v, v2, ring, rmask, ring_lo, false, fh);
     const double inflow = -P.fl[k] * (1.0 / S::FS);
 #pragma unroll
     for (int ia = 0; ia < NFP; ++ia) {
@@ -413,7 +465,7 @@ __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDE
       double r = 0.0;
 #pragma unroll
       for (int p = 0; p < NFP; ++p)
-        r = fma(S::T.f[k][ra][Elem<DIM, ORDER>::T.fnode[k][p]], fh[p], r);
+        r = fma(S::T.f[k][ra][Elem<DIM, ORDER>::T.fnode[k][p]], fh[k][p], r);
       rhs[ra] = fma(inflow, r, rhs[ra]);
     }
   }
@@ -423,6 +475,20 @@ __device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDE
 #pragma unroll
     for (int b = 0; b < NP; ++b) rg[b] = rhs[b];
   }
+}
+
+// FP64 solve of a prepared cell into rhs, which also goes to the LDS ring
+// (RING; without it every upwind value is read from HBM).  The upwind reads
+// of every inflow facet are issued first, the local matrix is assembled while
+// they are in flight, and the inflow terms are then added in facet order.
+template <int DIM, int ORDER, bool RING = true>
+__device__ __forceinline__ void solve64(const SweepArgs& a, const Prep<DIM, ORDER>& P, size_t base,
+                                        int j, const double* v, double v2, double* ring,
+                                        int rmask, int ring_lo,
+                                        double (&rhs)[Elem<DIM, ORDER>::NP]) {
+  double fh[DIM + 1][Elem<DIM, ORDER>::NFP];
+  fetch_inflow<DIM, ORDER>(a, P, base, j, ring, rmask, ring_lo, fh);
+  solve64_fetched<DIM, ORDER, RING>(P, ring, rmask, fh, rhs);
 }
 
 // FP64 solve of a prepared cell; the result goes to HBM and the LDS ring
@@ -597,10 +663,12 @@ __device__ __forceinline__ void sweep_velocity(
       return s < go[g + 1] ? s : -1;
     };
     Prep<DIM, ORDER> P;
-    RawT R;
+    RawT R, R2;
     int g0 = 0, k0 = 0;
     int g1 = 0, k1 = 0;
     next(g1, k1);
+    int g2 = g1, k2 = k1;
+    next(g2, k2);
     P.s = slot_of(g0, k0);
     if (P.s >= 0) {
       load_rec<DIM>(a, base, P.s, P.K, P.code, P.pack);
@@ -611,35 +679,54 @@ __device__ __forceinline__ void sweep_velocity(
     int n1s = slot_of(g1, k1), n1K = 0, n1code[NF], n1pack = 0;
     load_rec<DIM>(a, base, n1s >= 0 ? n1s : 0, n1K, n1code, n1pack);
     load_raw<DIM, ORDER, TAB>(a, base, n1s >= 0 ? n1s : 0, n1K, mrow, R);
+    // record of step i+2, in flight at the start of step i
+    int rsl = slot_of(g2, k2), rK, rcode[NF], rpack;
+    load_rec<DIM>(a, base, rsl >= 0 ? rsl : 0, rK, rcode, rpack);
     int synced = 0;
-    while (g0 < G) {
-      // step i+2: its record
-      int g2 = g1, k2 = k1;
-      next(g2, k2);
-      const int n2s = slot_of(g2, k2);
-      int n2K, n2code[NF], n2pack;
-      load_rec<DIM>(a, base, n2s >= 0 ? n2s : 0, n2K, n2code, n2pack);
-      // step i
+    // One step of the walk (step i).  At its start `cur` holds the raw inputs
+    // of step i+1 and the record of step i+2 is in flight, both issued a whole
+    // step earlier.  The step issues step i's upwind reads, takes the record
+    // of i+2 and issues its raw-input loads into `nxt`, issues the record load
+    // of step i+3, then solves step i, turns `cur` into step i+1's Prep and
+    // stores step i's result.  Every load has at least a whole step to
+    // arrive, and the upwind reads, issued before the prefetches, are waited
+    // for without waiting for those (the vector-memory counter retires in
+    // order).  The loop alternates the two raw buffers and the record always
+    // lands in the same registers, so no register that a load in flight will
+    // write is copied at the loop's back edge (a copy would wait for it).
+    const auto step = [&](RawT& cur, RawT& nxt) {
       const int s1 = go[g0 + 1];
       const int ring_lo = s1 - rs;
       if (k0 == 0 && gm[g0] < ring_lo && ring_lo > synced) {
         __syncthreads();
         synced = go[g0];
       }
+      double fh[NF][Elem<DIM, ORDER>::NFP];
+      if (P.s >= 0) fetch_inflow<DIM, ORDER>(a, P, base, j, ring, rmask, ring_lo, fh);
+      // step i+2: its record (issued a step ago) and its raw-input loads
+      const int n2s = rsl, n2K = rK, n2pack = rpack;
+      int n2code[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) n2code[k] = rcode[k];
+      load_raw<DIM, ORDER, TAB>(a, base, n2s >= 0 ? n2s : 0, n2K, mrow, nxt);
+      // step i+3: its record
+      int g3 = g2, k3 = k2;
+      next(g3, k3);
+      rsl = slot_of(g3, k3);
+      load_rec<DIM>(a, base, rsl >= 0 ? rsl : 0, rK, rcode, rpack);
+      // step i
       double out[NP];
       const int out_s = P.s;
-      if (P.s >= 0) solve64<DIM, ORDER>(a, P, base, j, v, v2, ring, rmask, ring_lo, out);
+      if (P.s >= 0) solve64_fetched<DIM, ORDER>(P, ring, rmask, fh, out);
       const bool last_chunk = go[g0] + (k0 + 1) * T >= s1;
       const bool wide = s1 - go[g0] > rs;
-      // step i+1: Prep from the raw inputs loaded one step ago
+      // step i+1: Prep from the raw inputs loaded a step ago
       P.s = n1s;
       P.K = n1K;
       P.pack = n1pack;
 #pragma unroll
       for (int k = 0; k < NF; ++k) P.code[k] = n1code[k];
-      compute_prep<DIM, ORDER, TAB>(a, v, v2, R, P);
-      // step i+2: its raw-input loads
-      load_raw<DIM, ORDER, TAB>(a, base, n2s >= 0 ? n2s : 0, n2K, mrow, R);
+      compute_prep<DIM, ORDER, TAB>(a, v, v2, cur, P);
       n1s = n2s;
       n1K = n2K;
       n1pack = n2pack;
@@ -655,10 +742,17 @@ __device__ __forceinline__ void sweep_velocity(
       k0 = k1;
       g1 = g2;
       k1 = k2;
+      g2 = g3;
+      k2 = k3;
       // after a generation's last chunk; and between the chunks of a
       // generation wider than the ring, whose cells rs slots apart share a
       // ring slot and must write it in slot order
       if (last_chunk || wide) lds_barrier();
+    };
+    while (g0 < G) {
+      step(R, R2);
+      if (g0 >= G) break;
+      step(R2, R);
     }
     return;
   }
@@ -1031,9 +1125,13 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
     hipStream_t st = (hipStream_t)stream;
     const int np = d->n_p, nm = d->dim + 2;
     const size_t ntab = d->n_1d > 0 ? maxw_table_size(d) : 0;
+    // boundary Maxwellians given by coefficients are evaluated once into the
+    // dense boundary array the sweep reads
+    const size_t nbc = io->bc_coef ? (size_t)d->n_bfaces * d->n_fp * d->n_v : 0;
     float* d32 = nullptr;
-    double* nodal = nullptr;  // [n_nodes] nu, [n_nodes][dim+2] coefficients, tables
-    if (hipMallocAsync((void**)&nodal, ((size_t)d->n_nodes * (1 + nm) + ntab) * sizeof(double),
+    double* nodal = nullptr;  // [n_nodes] nu, [n_nodes][dim+2] coefficients, tables, boundary
+    if (hipMallocAsync((void**)&nodal,
+                       ((size_t)d->n_nodes * (1 + nm) + ntab + nbc) * sizeof(double),
                        st) != hipSuccess)
       return fail(BGK_E_NOMEM, "scratch allocation failed");
     if (io->precision == TGS_FP32_CORRECTION &&
@@ -1045,7 +1143,14 @@ extern "C" int tgs_sweep(const tgs_dag* d, const tgs_sweep_io* io, bgk_stream_t 
     io_i.nu = nodal;
     io_i.mcoef = nodal + d->n_nodes;
     double* tab = ntab ? nodal + (size_t)d->n_nodes * (1 + nm) : nullptr;
-    int rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
+    int rc = BGK_OK;
+    if (nbc) {
+      double* bcd = nodal + (size_t)d->n_nodes * (1 + nm) + ntab;
+      rc = launch_bc_dense(d, io->bc_coef, bcd, st);
+      io_i.bc_coef = nullptr;
+      io_i.bc_dense = bcd;
+    }
+    if (!rc) rc = launch_nodal_rows(d, io->nu, nodal, np, 1, st);
     if (!rc) rc = launch_nodal_rows(d, io->mcoef, nodal + d->n_nodes, np * nm, 1, st);
     if (!rc && tab) rc = launch_maxw_tables(d, io_i.mcoef, io_i.nu, tab, st);
     if (!rc) rc = launch_sweep(d, &io_i, tab, d32, st, 0);
