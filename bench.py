@@ -77,9 +77,22 @@ def _oracle_sweep(args):
     return time.perf_counter() - t0
 
 
+def _oracle_moments(args):
+    from oracle import kinetic
+    j, = args
+    st = _ORACLE_STATE
+    geo, V, w = st["geo"], st["V"], st["w"]
+    f = np.random.default_rng(j).uniform(0.0, 1.0, (geo.n_cells, geo.n_p, 1))
+    t0 = time.perf_counter()
+    kinetic.moments(f, V[j:j + 1], w[j:j + 1])
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(pr, n_vel, dt):
-    """The oracle's sweep on `n_vel` sampled velocities of the same mesh, one
-    velocity per worker process; returns unknowns swept per second."""
+    """The oracle's sweep and moment pass on `n_vel` sampled velocities of the
+    same mesh, one velocity per worker process (at most 16 workers, the
+    host's share per GPU); the rate is extrapolated to the whole velocity set
+    (per-velocity work is the same up to the shape of its graph)."""
     import multiprocessing as mp
 
     from oracle import geometry
@@ -87,21 +100,40 @@ def cpu_baseline(pr, n_vel, dt):
     geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
     rng = np.random.default_rng(99)
     js = np.sort(rng.choice(pr.vgrid.n_v, size=n_vel, replace=False))
-    state = {"geo": geo, "V": pr.vgrid.v, "sigma": 1.0 / dt, "nu": 100.0}
+    state = {"geo": geo, "V": pr.vgrid.v, "w": pr.vgrid.w, "sigma": 1.0 / dt, "nu": 100.0}
     ctx = mp.get_context("fork")
     with ctx.Pool(cores, initializer=_oracle_worker_init, initargs=(state,)) as pool:
         gens = pool.map(_oracle_dag, list(js))
         t0 = time.perf_counter()
         times = pool.map(_oracle_sweep, list(zip(js, gens)))
+        mtimes = pool.map(_oracle_moments, [(j,) for j in js])
         wall = time.perf_counter() - t0
     unknowns = geo.n_cells * geo.n_p * n_vel
     return {"value": unknowns / wall, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 NumPy oracle sweep of {n_vel} sampled velocities on the full mesh "
-                      f"({geo.n_cells} cells, P{pr.order}), one velocity per process; "
-                      f"{sum(times):.1f} s of CPU work"}
+            "extrapolated": True,
+            "sample": f"FP64 NumPy oracle sweep and moment pass of {n_vel} sampled velocities "
+                      f"on the full mesh ({geo.n_cells} cells, P{pr.order}), one velocity per "
+                      f"process; {sum(times):.1f} s (sweep) + {sum(mtimes):.2f} s (moments) of "
+                      f"CPU work; rate extrapolated to all {pr.vgrid.n_v} velocities"}
 
 
-def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED"):
+def generation_stats(d, threads=128):
+    """Per-velocity generation counts G_j and widths W_j(g) (Sec. 4.1), and
+    the share of workgroup lanes a generation-by-generation walk keeps busy."""
+    gen, G = d.generations()
+    widths_max, widths_mean, fill = [], [], []
+    for j in range(d.n_v):
+        w = np.bincount(gen[j], minlength=int(G[j]))
+        widths_max.append(int(w.max()))
+        widths_mean.append(float(w.mean()))
+        fill.append(float(w.sum() / (np.ceil(w / threads).sum() * threads)))
+    G = np.asarray(G, dtype=np.float64)
+    return {"G_min": int(G.min()), "G_mean": float(G.mean()), "G_max": int(G.max()),
+            "W_mean": float(np.mean(widths_mean)), "W_max": int(max(widths_max)),
+            "lane_fill_128": float(np.mean(fill))}
+
+
+def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED", gen_stats=False):
     import torch
 
     import paper_2608_19150_amd as B
@@ -143,6 +175,8 @@ def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED"):
         "fallbacks": sum(st["fallbacks"] for st in stats),
     }
     out["U"] = U.cpu().numpy()
+    if gen_stats:
+        out["generations"] = generation_stats(d)
     del s, f, d
     torch.cuda.empty_cache()
     return out
@@ -218,19 +252,70 @@ def run_c4(steps, warmup, tune_cache):
             "sequential_single_instance_ms_per_step": 1e3 * seq, "setup_s": setup_s}
 
 
-def run_c3(steps, warmup, kn):
+def run_c3(steps, warmup, kn, gen_stats=False):
     """3D x 3D: ~55k tetrahedra, P1, 16^3 velocities, backward Euler."""
     import problems as P
     pr = P.config_c3(kn=kn)
-    r = run_gpu(pr, steps, warmup, 0)
+    r = run_gpu(pr, steps, warmup, 0, gen_stats=gen_stats)
     sweep_s = r["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r["n_unknown"] / sweep_s / 1e9
-    return {"workload": pr.name, "kn": kn, "unknowns": r["n_unknown"], "max_generations": r["max_G"],
-            "value": r["value"], "unit": "unknowns/s", "ms_per_step": r["ms_per_step"],
-            "picard_iters": r["iters"], "kernel_ms": {"sweep": r["sweep_ms_avg"],
-                                                     "moments": r["moments_ms_avg"],
-                                                     "maxwellian": r["maxwellian_ms_avg"]},
-            "sweep_roofline_frac": achieved / HBM_PEAK_GBS, "sweep_achieved_gbs": achieved}
+    out = {"workload": pr.name, "kn": kn, "unknowns": r["n_unknown"],
+           "max_generations": r["max_G"], "steps": steps,
+           "value": r["value"], "unit": "unknowns/s", "ms_per_step": r["ms_per_step"],
+           "picard_iters": r["iters"], "kernel_ms": {"sweep": r["sweep_ms_avg"],
+                                                    "moments": r["moments_ms_avg"],
+                                                    "maxwellian": r["maxwellian_ms_avg"]},
+           "sweep_roofline_frac": achieved / HBM_PEAK_GBS, "sweep_achieved_gbs": achieved,
+           "sweep_traffic_bytes": measured_traffic(TRAFFIC_FILE_3D, SWEEP_KERNEL_3D)}
+    if gen_stats:
+        out["generations"] = r["generations"]
+    return out
+
+
+def run_c1(steps=5):
+    """The small 2D case end to end: 512 P1 triangles x 16^2 velocities, Sod,
+    nu = 1, backward Euler at CFL 10, 5 steps to tau = 1e-10, on the GPU and
+    with the FP64 oracle on one host core; both take the same iterations and
+    their final f agree."""
+    import torch
+
+    import paper_2608_19150_amd as B
+    import problems as P
+    from oracle import dag as odag
+    from oracle import geometry, solver
+    pr = P.config_c1()
+    d, f, bc, dt = B.problem_setup(pr)
+    s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, mode="MATCHED",
+                 nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn)
+    s.step(f.clone())                      # warm-up on a copy (kernels loaded)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpu_iters = [s.step(f)["iters"] for _ in range(steps)]
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    f_gpu = d.unpack(f).cpu().numpy()
+    t0 = time.perf_counter()
+    geo = geometry.build(pr.mesh.vert, pr.mesh.cells, pr.order)
+    V, w = pr.vgrid.v, pr.vgrid.w
+    gens, lags = odag.build_all(geo, V)
+    fo = solver.initial_condition(geo, V, pr.state)
+    g = solver.boundary_values(geo, V, pr.state)
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cpu_iters = []
+    for _ in range(steps):
+        fo, st = solver.bgk_step(geo, V, w, fo, g, dt, gens, lags, tau=pr.tau, L=pr.vgrid.L)
+        cpu_iters.append(st["iters"])
+    cpu_s = time.perf_counter() - t0
+    n_unk = d.n_cells * d.n_p * d.n_v
+    sweeps = sum(sum(x) for x in gpu_iters)
+    return {"workload": pr.name, "steps": steps, "unknowns": n_unk,
+            "gpu": {"s_total": gpu_s, "ms_per_step": 1e3 * gpu_s / steps, "iters": gpu_iters,
+                    "value": n_unk * sweeps / gpu_s},
+            "oracle": {"s_total": cpu_s, "ms_per_step": 1e3 * cpu_s / steps,
+                       "iters": cpu_iters, "cores": 1, "setup_s": setup_s,
+                       "value": n_unk * sum(sum(x) for x in cpu_iters) / cpu_s},
+            "f_rel_diff": float(np.abs(f_gpu - fo).max() / np.abs(fo).max())}
 
 
 def run_c5(steps, n_train, kn):
@@ -569,20 +654,24 @@ def sweep_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
+TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "k_sweep_p1_c3_traffic.txt")
+SWEEP_KERNEL_3D = "k_sweep<3, 1, false, true, true>"
+
+
+def measured_traffic(path=TRAFFIC_FILE, kernel=SWEEP_KERNEL):
     """HBM bytes per sweep launch from the committed counter summary, or
     None when the sweep source has changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
     if fields.get("sweep_source_sha256") != sweep_source_digest():
         return None
-    if fields.get("kernel") != SWEEP_KERNEL:
+    if fields.get("kernel") != kernel:
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -599,8 +688,11 @@ def main():
                     help="mesh lattice size (2*n^2 triangles; 316 -> 199,712)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-velocities", type=int, default=32)
+    ap.add_argument("--cpu-velocities", type=int, default=64)
+    ap.add_argument("--no-c1", action="store_true", help="skip the small 2D case end to end")
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D workload")
+    ap.add_argument("--c3-kn", default="0.01,1,0.0001",
+                    help="Knudsen numbers of the 3D workload (comma separated)")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-duct", action="store_true",
@@ -659,7 +751,7 @@ def main():
     torch.cuda.set_device(0)
     pr = P.config_c2(args.n_side)
     print(f"[bench] workload {pr.name}: building", file=sys.stderr, flush=True)
-    r64 = run_gpu(pr, args.steps, args.warmup, 0)
+    r64 = run_gpu(pr, args.steps, args.warmup, 0, gen_stats=True)
     print(f"[bench] fp64 {r64['value']:.3e} unknowns/s, {r64['ms_per_step']:.1f} ms/step, "
           f"iters {r64['iters']}", file=sys.stderr, flush=True)
     fp32 = None
@@ -682,7 +774,13 @@ def main():
         print(f"[bench] {name}: " + report(out), file=sys.stderr, flush=True)
         return out
 
-    c3 = c4 = c5 = q2 = strip = duct = None
+    c1 = c3 = c4 = c5 = q2 = strip = duct = None
+    if not args.no_c1:
+        c1 = section("c1", run_c1,
+                     lambda c: f"GPU {c['gpu']['ms_per_step']:.1f} ms/step, oracle "
+                               f"{c['oracle']['ms_per_step']:.0f} ms/step, iters "
+                               f"{c['gpu']['iters']} vs {c['oracle']['iters']}, "
+                               f"f diff {c['f_rel_diff']:.1e}")
     if not args.no_duct:
         duct = section("duct", lambda: run_duct(1, 1),
                        lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.0f} ms/step, "
@@ -698,9 +796,17 @@ def main():
                                f"{c['projected']['ms_per_step']:.1f} ms/step vs MATCHED "
                                f"{c['matched']['value']:.3e} {c['matched']['ms_per_step']:.1f}")
     if not args.no_c3:
-        c3 = section("c3", lambda: run_c3(2, 1, 1e-2),
-                     lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.1f} ms/step, "
-                               f"sweep {c['kernel_ms']['sweep']:.2f} ms, G {c['max_generations']}")
+        # the three Knudsen numbers of the 3D workload; Kn = 1e-4 is
+        # collision-dominated (hundreds of Picard iterations per step): one step
+        c3 = {}
+        runs = {1e-2: (2, 1), 1.0: (2, 1), 1e-4: (1, 0)}
+        for kn in [float(x) for x in args.c3_kn.split(",")]:
+            st_, wu = runs.get(kn, (2, 1))
+            c3[f"kn{kn:g}"] = section(
+                f"c3 kn={kn:g}", lambda: run_c3(st_, wu, kn, gen_stats=(kn == 1e-2)),
+                lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.1f} ms/step, "
+                          f"iters {c['picard_iters']}, sweep {c['kernel_ms']['sweep']:.2f} ms, "
+                          f"G {c['max_generations']}")
     if not args.no_c4:
         import tempfile
         with tempfile.TemporaryDirectory() as tdir:
@@ -731,6 +837,7 @@ def main():
                    "kn": pr.kn, "tau": pr.tau, "max_generations": r64["max_G"],
                    "parallelism": "single GPU"},
         "picard_iters": r64["iters"],
+        "generations": r64["generations"],
         "kernel_ms": {"sweep": r64["sweep_ms_avg"], "moments": r64["moments_ms_avg"],
                       "maxwellian": r64["maxwellian_ms_avg"]},
         "fp32_refine": fp32,
@@ -739,6 +846,7 @@ def main():
                      "kernel": SWEEP_KERNEL,
                      "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},
         "cpu_baseline": cpu,
+        "c1_small": c1,
         "c3_3d": c3,
         "c4_batched": c4,
         "c5_learned_guess": c5,
