@@ -318,25 +318,58 @@ def run_c1(steps=5):
             "f_rel_diff": float(np.abs(f_gpu - fo).max() / np.abs(fo).max())}
 
 
-def run_c5(steps, n_train, kn):
-    """Learned initial guess: train on solver trajectories of seeded 3D
-    Riemann problems (jittered 4^3..8^3 lattices, 12^3..16^3 velocities, Kn
-    log-uniform in [1e-3, 1]), then step the 3D workload with the
-    plain previous-step guess, linear extrapolation, and the network; report
-    Picard iterations and seconds per step and the moment difference."""
+def run_c5(steps, n_train, kn, n_heldout=24):
+    """Learned initial guess.  Training data: n_train seeded Riemann
+    trajectories generated by the solver, half 2D (2,048 triangles, 16^2
+    velocities) and half 3D (~5,000 tetrahedra, 12^3 velocities), random
+    Sod-like states and normals, Kn log-uniform in [1e-3, 1], 8 backward-
+    Euler steps each.  Two networks: one trained on the mixed set, one on
+    the 3D trajectories alone (the ablation of the learned guess's training
+    set).  Evaluated on held-out 3D problems of the same kind (seeds 7000+)
+    and on the 3D workload, against the plain previous-step guess and linear
+    extrapolation, by Picard iterations and seconds per step at tau 1e-9."""
     import torch
 
+    import paper_2608_19150_amd as B
     import problems as P
     from paper_2608_19150_amd import learned
-    train = [P.learned_guess_problem(3, 5000 + i, 4 + i % 5, 12 + 2 * (i % 3),
-                                     kn_range=(1e-3, 1.0)) for i in range(n_train)]
-    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=12, batch=4096, lr=2e-3, seed=0)
+    n2 = n_train // 2
+    n3 = n_train - n2
+    kn_range = (1e-3, 1.0)
+    pr2 = [P.learned_guess_problem(2, 5000 + i, 32, 16, kn_range=kn_range) for i in range(n2)]
+    pr3 = [P.learned_guess_problem(3, 6000 + i, 9, 12, kn_range=kn_range) for i in range(n3)]
+    d2, sk2, g2 = learned.generate(pr2, n_steps=8, tau=1e-9, max_rows=20000, log_every=250)
+    d3, sk3, g3 = learned.generate(pr3, n_steps=8, tau=1e-9, max_rows=20000, log_every=250)
+    nets, train_info = {}, {}
+    for name, data in (("mixed", d2 + d3), ("3d_only", d3)):
+        mlp, info = learned.fit_samples(data, epochs=24, batch=4096, lr=2e-3, seed=0)
+        nets[name] = mlp
+        train_info[name] = {"trajectories": info["trajectories"], "samples": info["samples"],
+                            "loss_first_last": [info["loss"][0], info["loss"][-1]],
+                            "train_s": info["train_s"]}
+    del d2, d3
+    torch.cuda.empty_cache()
+    held = {k: 0 for k in ("plain", "linear", "mixed", "3d_only")}
+    evaluated = 0
+    for i in range(n_heldout):
+        pr = P.learned_guess_problem(3, 7000 + i, 9, 12, kn_range=kn_range)
+        try:
+            res = learned.compare(pr, None, n_steps=8, tau=1e-9, modes=("plain", "linear"))
+            for name, mlp in nets.items():
+                res[name] = learned.compare(pr, mlp, n_steps=8, tau=1e-9,
+                                            modes=("learned",))["learned"]
+        except B.BGKError:
+            continue
+        evaluated += 1
+        for k in held:
+            held[k] += int(sum(res[k]["iters"][1:]))
     pr = P.config_c3(kn=kn)
-    res = learned.compare(pr, mlp, n_steps=steps, tau=1e-9)
-    out = {"workload": pr.name, "tau": 1e-9, "train_trajectories": info["trajectories"],
-           "train_skipped": len(info["skipped"]), "train_samples": info["samples"],
-           "train_loss_first_last": [info["loss"][0], info["loss"][-1]],
-           "generate_s": info["generate_s"], "train_s": info["train_s"]}
+    res = learned.compare(pr, nets["3d_only"], n_steps=steps, tau=1e-9)
+    out = {"workload": pr.name, "tau": 1e-9, "train_kn_range": list(kn_range),
+           "train_trajectories_2d": len(pr2) - len(sk2), "train_trajectories_3d": len(pr3) - len(sk3),
+           "train_skipped": len(sk2) + len(sk3), "generate_s": g2 + g3, "train": train_info,
+           "heldout_problems": evaluated,
+           "heldout_iters_after_first_step": held}
     ref = res["plain"]["U"][-1]
     for mode, r in res.items():
         # step 0 has no history and uses the plain guess in every mode
@@ -344,7 +377,7 @@ def run_c5(steps, n_train, kn):
                      "s_per_step_after_first": float(np.mean(r["seconds"][1:])),
                      "fallbacks": r["fallbacks"],
                      "moment_diff_vs_plain": learned.moment_difference(r["U"][-1], ref, 3)}
-    del res
+    del res, nets
     torch.cuda.empty_cache()
     return out
 
@@ -701,7 +734,8 @@ def main():
                     help="skip the narrow-generation strip (packed vs workgroup sweep walk)")
     ap.add_argument("--no-q2", action="store_true",
                     help="skip the Q2 velocity space (projected vs matched Maxwellian)")
-    ap.add_argument("--c5-train", type=int, default=240, help="training trajectories")
+    ap.add_argument("--c5-train", type=int, default=2000,
+                    help="training trajectories (half 2D, half 3D)")
     ap.add_argument("--x7", action="store_true",
                     help="only run the L2-stability study in a reflecting box")
     ap.add_argument("--x7-steps", type=int, default=40)
@@ -817,9 +851,11 @@ def main():
                                    f"{c['p99_instance_step_ms']:.1f} ms")
     if not args.no_c5:
         c5 = section("c5", lambda: run_c5(4, args.c5_train, 1e-2),
-                     lambda c: f"iters after step 1: plain {c['plain']['iters_after_first']} "
-                               f"linear {c['linear']['iters_after_first']} "
-                               f"learned {c['learned']['iters_after_first']}")
+                     lambda c: f"3D workload, iters after step 1: plain "
+                               f"{c['plain']['iters_after_first']} linear "
+                               f"{c['linear']['iters_after_first']} learned "
+                               f"{c['learned']['iters_after_first']}; held-out "
+                               f"{c['heldout_iters_after_first_step']}")
     sweep_s = r64["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r64["n_unknown"] / sweep_s / 1e9
     cpu = None

@@ -133,35 +133,60 @@ def glorot_params(seed, arch=None):
     return out
 
 
-def fit(problems, *, n_steps=8, tau=1e-9, epochs=20, batch=4096, lr=1e-3, seed=0,
-        init_params=None, log_every=0):
-    """Generates one trajectory per problem, fits a network (Glorot start
-    from `seed` unless init_params is given) to all of them and returns
-    (mlp, info).  Problems whose run fails (non-physical or not converged)
-    are skipped and listed with their error."""
+def generate(problems, *, n_steps=8, tau=1e-9, max_rows=0, seed=0, log_every=0):
+    """Runs one trajectory per problem and returns (per-problem samples,
+    skipped, seconds).  Each entry is (problem name, dim, X, T); with
+    max_rows > 0 a trajectory keeps a seeded random subset of that many
+    rows.  Problems whose run fails (non-physical or not converged) are
+    skipped and listed with their error."""
     from . import BGKError
-    Xs, Ts, skipped = [], [], []
+    out, skipped = [], []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
     t0 = time.perf_counter()
-    for pr in problems:
+    for i, pr in enumerate(problems):
+        if log_every and i and i % log_every == 0:
+            print(f"[learned] {i} trajectories, {time.perf_counter() - t0:.1f} s", flush=True)
         try:
             tr = Trajectory(pr, tau=tau)
-            out = tr.run(n_steps)
+            res = tr.run(n_steps)
         except BGKError as e:
             skipped.append((pr.name, str(e)))
             continue
-        X, T = samples(tr, out["U"])
-        Xs.append(X)
-        Ts.append(T)
+        X, T = samples(tr, res["U"])
+        if max_rows and X.shape[0] > max_rows:
+            keep = torch.randperm(X.shape[0], device="cuda", generator=gen)[:max_rows]
+            X, T = X.index_select(0, keep).contiguous(), T.index_select(0, keep).contiguous()
+        out.append((pr.name, pr.mesh.dim, X, T))
         del tr
-    gen_s = time.perf_counter() - t0
-    X, T = torch.cat(Xs), torch.cat(Ts)
+    torch.cuda.synchronize()
+    return out, skipped, time.perf_counter() - t0
+
+
+def fit_samples(data, *, epochs=20, batch=4096, lr=1e-3, seed=0, init_params=None, log_every=0):
+    """Fits a network (Glorot start from `seed` unless init_params is given)
+    to the rows of the given trajectories; returns (mlp, info)."""
+    X = torch.cat([d[2] for d in data])
+    T = torch.cat([d[3] for d in data])
     mlp = Mlp(glorot_params(seed) if init_params is None else init_params)
     mlp.set_normalization(*normalization(X, T))
     t0 = time.perf_counter()
     hist = train(mlp, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, log_every=log_every)
     torch.cuda.synchronize()
-    return mlp, {"samples": int(X.shape[0]), "trajectories": len(Xs), "skipped": skipped,
-                 "loss": hist, "generate_s": gen_s, "train_s": time.perf_counter() - t0}
+    return mlp, {"samples": int(X.shape[0]), "trajectories": len(data), "loss": hist,
+                 "train_s": time.perf_counter() - t0}
+
+
+def fit(problems, *, n_steps=8, tau=1e-9, epochs=20, batch=4096, lr=1e-3, seed=0,
+        init_params=None, log_every=0, max_rows=0):
+    """Generates one trajectory per problem, fits a network to all of them
+    and returns (mlp, info) (generate, then fit_samples)."""
+    data, skipped, gen_s = generate(problems, n_steps=n_steps, tau=tau, max_rows=max_rows,
+                                    seed=seed)
+    mlp, info = fit_samples(data, epochs=epochs, batch=batch, lr=lr, seed=seed,
+                            init_params=init_params, log_every=log_every)
+    info.update({"skipped": skipped, "generate_s": gen_s})
+    return mlp, info
 
 
 def compare(pr, mlp, *, n_steps=8, tau=1e-9, modes=GUESS_MODES):

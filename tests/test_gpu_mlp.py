@@ -212,30 +212,34 @@ def test_guess_matches_oracle_and_falls_back(dim):
 KN = (1e-3, 1e-1)   # collision-dominated: Picard contracts slowly (rho ~ nu dt / (1 + nu dt))
 
 
-def test_learned_guess_cuts_picard_iterations():
-    """Trained on solver trajectories of seeded 3D Riemann problems, the
-    network's initial iterate needs fewer Picard iterations on held-out
-    problems than the plain previous-step guess, and the converged moments
-    agree with the plain run to the stopping tolerance."""
-    train = [P.learned_guess_problem(3, 5000 + i, 4, 12, kn_range=KN) for i in range(240)]
-    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=12, batch=4096, lr=2e-3, seed=0)
-    print({k: v for k, v in info.items() if k != "loss"}, info["loss"][::8], flush=True)
+def test_learned_guess_beats_extrapolation_and_plain_guess():
+    """Trained on 400 solver trajectories of seeded 3D Riemann problems, the
+    network's initial iterate needs fewer Picard iterations on 12 held-out
+    problems (seeds 7000-7011) than both the plain previous-step guess and
+    linear extrapolation 2 U^k - U^(k-1) (the network predicts a correction
+    to it), and the converged moments agree with the plain run to the
+    stopping tolerance.  Training is seeded and the gradients are
+    reproducible, so the counts are too."""
+    train = [P.learned_guess_problem(3, 5000 + i, 4 + i % 3, 12, kn_range=KN) for i in range(400)]
+    mlp, info = learned.fit(train, n_steps=8, tau=1e-9, epochs=24, batch=4096, lr=2e-3, seed=0)
+    print({k: v for k, v in info.items() if k != "loss"}, info["loss"][::6], flush=True)
     # sharp Riemann data can drive a node's DG moments non-physical (no
     # limiter in the method); such runs are reported and left out
     assert len(info["skipped"]) <= 10
     assert all("[-5]" in msg for _, msg in info["skipped"])
-    assert info["loss"][-1] < 0.9 * info["loss"][0]
-    plain_tot = learned_tot = evaluated = 0
-    for i in range(4):
-        pr = P.learned_guess_problem(3, 7000 + i, 4, 12, kn_range=KN)
+    assert info["loss"][-1] < 0.6 * info["loss"][0]
+    tot = {"plain": 0, "linear": 0, "learned": 0}
+    evaluated = 0
+    for i in range(12):
+        pr = P.learned_guess_problem(3, 7000 + i, 4 + i % 3, 12, kn_range=KN)
         try:
             res = learned.compare(pr, mlp, n_steps=8, tau=1e-9)
         except B.BGKError as e:
             assert e.code == B.BGK_E_NONPHYSICAL
             continue
         evaluated += 1
-        plain_tot += sum(res["plain"]["iters"][1:])
-        learned_tot += sum(res["learned"]["iters"][1:])
+        for k in tot:
+            tot[k] += sum(res[k]["iters"][1:])
         print(pr.name, {k: v["iters"] for k, v in res.items()},
               {k: v["fallbacks"] for k, v in res.items()}, flush=True)
         # each step stops at a relative change below tau / max(1, nu dt); with
@@ -243,5 +247,6 @@ def test_learned_guess_cuts_picard_iterations():
         # of the fixed point per step; allow 18 tau per step over 8 steps
         err = learned.moment_difference(res["learned"]["U"][-1], res["plain"]["U"][-1], 3)
         assert max(err) <= 8 * 18 * 1e-9, err
-    assert evaluated >= 2
-    assert learned_tot < plain_tot, (learned_tot, plain_tot)
+    print("Picard iterations after step 1:", tot, flush=True)
+    assert evaluated >= 10
+    assert tot["learned"] < tot["linear"] < tot["plain"], tot
