@@ -166,15 +166,17 @@ struct bgk_batch {
   std::vector<bgk_solver*> solvers;
   std::vector<double*> f_bound;      // caller f pointers the device arguments refer to
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;        // the P1 sweep kernel of mixed 2D batches
   hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // device arrays
   SweepArgs* sargs = nullptr;        // [S][n]
   SweepArgs* sargs_tune = nullptr;   // [n]
   BatchKin* kin = nullptr;           // [S + 2][n]: 0 init (f^k), 1 + s stage s, S + 1 caller f
   CombArgs* comb = nullptr;          // [S + 1][n]: 0 copy f -> f^k, s q^(s), S final
   ConvArgs* conv = nullptr;          // [n]
-  int2* map = nullptr;               // sweep blocks
-  int nblocks = 0;
+  int2* map = nullptr;               // sweep blocks: P2 instances' first, then P1's
+  int nb2 = 0, nb1 = 0;
   int32_t* mom_first = nullptr;      // [n + 1]
   int mom_blocks = 0;
   int64_t* node_first = nullptr;     // [n + 1]
@@ -357,8 +359,8 @@ int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, int threads) {
   if (B->tab &&
       (rc = launch_tables_batch(B->dim, kin, c.done, B->tab_first, n, B->n_tab, B->stream)))
     return rc;
-  if ((rc = launch_sweep_batch(B->dim, B->tab, sargs, B->map, B->nblocks, c.done, threads,
-                               B->stream)))
+  if ((rc = launch_sweep_batch(B->dim, B->tab, sargs, B->map, B->nb2, B->nb1, c.done, threads,
+                               B->stream, B->side, B->ev_fork, B->ev_join)))
     return rc;
   if ((rc = launch_moments_batch(B->dim, kin, c.par, c.done, B->mom_first, n, B->mom_blocks, true,
                                  B->stream)))
@@ -445,6 +447,9 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
       if (!rc && e != hipSuccess) rc = fail(BGK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
     };
     check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
+    check(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking), "hipStreamCreate");
+    check(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    check(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming), "hipEventCreate");
     check(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming), "hipEventCreate");
     check(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming), "hipEventCreate");
     check(hipEventCreate(&B->t0), "hipEventCreate");
@@ -464,22 +469,27 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     n_tab = tfirst[n];
     B->n_tab = n_tab;
     B->mom_blocks = mfirst[n];
-    // sweep blocks: every instance's velocities, longest generation count first
-    std::vector<std::pair<int, int2>> blocks;
+    // sweep blocks: every instance's velocities, P2 instances' first, each
+    // part longest generation count first
+    std::vector<std::pair<int, int2>> blocks[2];
     for (int i = 0; i < n && !rc; ++i) {
       const tgs_dag* d = solvers[i]->dag;
       std::vector<int32_t> vorder(d->n_v);
       check(hipMemcpy(vorder.data(), d->d_vorder, d->n_v * sizeof(int32_t), hipMemcpyDeviceToHost),
             "hipMemcpy");
-      for (int y = 0; y < d->n_v; ++y) blocks.push_back({d->G_host[vorder[y]], make_int2(i, y)});
+      auto& part = blocks[d->dim == 2 && d->order == 2 ? 0 : 1];
+      for (int y = 0; y < d->n_v; ++y) part.push_back({d->G_host[vorder[y]], make_int2(i, y)});
     }
-    std::stable_sort(blocks.begin(), blocks.end(),
-                     [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) {
-                       return a.first > b.first;
-                     });
-    std::vector<int2> map(blocks.size());
-    for (size_t b = 0; b < blocks.size(); ++b) map[b] = blocks[b].second;
-    B->nblocks = (int)map.size();
+    std::vector<int2> map;
+    for (auto& part : blocks) {
+      std::stable_sort(part.begin(), part.end(),
+                       [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) {
+                         return a.first > b.first;
+                       });
+      for (const auto& b : part) map.push_back(b.second);
+    }
+    B->nb2 = (int)blocks[0].size();
+    B->nb1 = (int)blocks[1].size();
     std::vector<ConvArgs> conv(n);
     for (int i = 0; i < n; ++i) {
       const bgk_solver_opts& so = solvers[i]->opts;
@@ -538,9 +548,10 @@ extern "C" int bgk_batch_destroy(bgk_batch* B) {
       if (p) (void)hipFree(p);
     if (B->h_ctl) (void)hipHostFree(B->h_ctl);
     if (B->h_last) (void)hipHostFree(B->h_last);
-    hipEvent_t evs[] = {B->ev_in, B->ev_out, B->t0, B->t1};
+    hipEvent_t evs[] = {B->ev_in, B->ev_out, B->t0, B->t1, B->ev_fork, B->ev_join};
     for (hipEvent_t e : evs)
       if (e) (void)hipEventDestroy(e);
+    if (B->side) (void)hipStreamDestroy(B->side);
     if (B->stream) (void)hipStreamDestroy(B->stream);
     delete B;
     return BGK_OK;
@@ -678,8 +689,8 @@ extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads,
       return rc;
     BGK_HIP(hipEventRecord(B->t0, B->stream));
     for (int r = 0; r < reps; ++r)
-      if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, B->map, B->nblocks, c.done,
-                                   threads, B->stream)))
+      if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, B->map, B->nb2, B->nb1,
+                                   c.done, threads, B->stream, B->side, B->ev_fork, B->ev_join)))
         return rc;
     BGK_HIP(hipEventRecord(B->t1, B->stream));
     BGK_HIP(hipEventSynchronize(B->t1));

@@ -922,43 +922,64 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
   }
 }
 
-// Batched FP64 sweep over many instances in one launch: block b sweeps
-// velocity map[b].y (a position in its instance's velocity order) of
-// instance map[b].x; instances flagged done skip.  2D instances may mix P1
-// and P2 (both rings hold 3072 values).
-template <int DIM, bool TAB>
+// Batched FP64 sweep over many instances of one element type in one launch:
+// block b sweeps velocity map[b].y (a position in its instance's velocity
+// order) of instance map[b].x; instances flagged done skip.  One kernel per
+// element type: a kernel holding both 2D walks would need the registers of
+// both at once.
+template <int DIM, int ORDER, bool TAB>
 __global__ __launch_bounds__(256, 2) void k_sweep_batch(const SweepArgs* __restrict__ args,
                                                         const int2* __restrict__ map,
                                                         const int32_t* __restrict__ done) {
-  constexpr int RING = SweepCfg<DIM, 1>::RS * SweepCfg<DIM, 1>::NP;
-  static_assert(DIM == 3 || SweepCfg<2, 2>::RS * SweepCfg<2, 2>::NP <= RING, "ring size");
-  __shared__ double ring[RING];
+  constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
+  __shared__ double ring[RS * NP];
+  // the block's instance and velocity are uniform: read them once through
+  // the scalar unit, so the instance's arguments sit in scalar registers
   const int2 m = map[blockIdx.x];
-  if (done[m.x]) return;
-  const SweepArgs a = args[m.x];
-  const int j = a.vorder[m.y];
-  // batched instances are FP64 in the internal node order: pipelined walk
-  if constexpr (DIM == 2) {
-    if (a.order == 1)
-      sweep_velocity<2, 1, false, TAB, true>(a, j, ring);
-    else
-      sweep_velocity<2, 2, false, TAB, true>(a, j, ring);
-  } else {
-    sweep_velocity<3, 1, false, TAB, true>(a, j, ring);
-  }
+  const int inst = __builtin_amdgcn_readfirstlane(m.x);
+  const int vpos = __builtin_amdgcn_readfirstlane(m.y);
+  if (done[inst]) return;
+  const SweepArgs a = args[inst];
+  const int j = __builtin_amdgcn_readfirstlane(a.vorder[vpos]);
+  // batched instances are FP64 in the internal node order: pipelined walk on
+  // factorised tables, the plain walk for node coefficients
+  sweep_velocity<DIM, ORDER, false, TAB, TAB>(a, j, ring);
 }
 
-int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nblocks,
-                       const int32_t* done, int threads, hipStream_t stream) {
-  const dim3 grid(nblocks), block(threads);
-  if (dim == 2 && tab)
-    hipLaunchKernelGGL((k_sweep_batch<2, true>), grid, block, 0, stream, args, map, done);
-  else if (dim == 2)
-    hipLaunchKernelGGL((k_sweep_batch<2, false>), grid, block, 0, stream, args, map, done);
-  else if (tab)
-    hipLaunchKernelGGL((k_sweep_batch<3, true>), grid, block, 0, stream, args, map, done);
+template <int DIM, int ORDER>
+void launch_batch_kernel(bool tab, const SweepArgs* args, const int2* map, int nblocks,
+                         const int32_t* done, int threads, hipStream_t stream) {
+  if (tab)
+    hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, true>), dim3(nblocks), dim3(threads), 0, stream,
+                       args, map, done);
   else
-    hipLaunchKernelGGL((k_sweep_batch<3, false>), grid, block, 0, stream, args, map, done);
+    hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, false>), dim3(nblocks), dim3(threads), 0,
+                       stream, args, map, done);
+}
+
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nb2, int nb1,
+                       const int32_t* done, int threads, hipStream_t stream, hipStream_t side,
+                       hipEvent_t fork, hipEvent_t join) {
+  if (dim == 3) {
+    if (nb1 > 0) launch_batch_kernel<3, 1>(tab, args, map, nb1, done, threads, stream);
+    BGK_HIP(hipGetLastError());
+    return BGK_OK;
+  }
+  if (nb2 > 0 && nb1 > 0) {
+    // P1 instances on the side stream, forked from and joined back to the
+    // main stream (under graph capture the two become parallel branches)
+    BGK_HIP(hipEventRecord(fork, stream));
+    BGK_HIP(hipStreamWaitEvent(side, fork, 0));
+    launch_batch_kernel<2, 1>(tab, args, map + nb2, nb1, done, threads, side);
+    BGK_HIP(hipGetLastError());
+    launch_batch_kernel<2, 2>(tab, args, map, nb2, done, threads, stream);
+    BGK_HIP(hipGetLastError());
+    BGK_HIP(hipEventRecord(join, side));
+    BGK_HIP(hipStreamWaitEvent(stream, join, 0));
+    return BGK_OK;
+  }
+  if (nb2 > 0) launch_batch_kernel<2, 2>(tab, args, map, nb2, done, threads, stream);
+  if (nb1 > 0) launch_batch_kernel<2, 1>(tab, args, map + nb2, nb1, done, threads, stream);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -1024,9 +1045,10 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
     return BGK_OK;
   }
   const dim3 grid(d->n_v), block(threads);
-  // FP64 sweeps take the pipelined walk (P1 triangles keep the plain walk:
-  // their 4-waves-per-SIMD register budget has no room for a second cell's
-  // inputs)
+  // FP64 sweeps on factorised tables take the pipelined walk (P1 triangles
+  // keep the plain walk: their 4-waves-per-SIMD register budget has no room
+  // for a second cell's inputs; so do sweeps that evaluate the Maxwellian
+  // from node coefficients, whose inputs do not fit twice in registers)
   const bool pipe = !fp32 && !(d->dim == 2 && d->order == 1);
 #define BGK_LAUNCH(D_, O_)                                                                 \
   if (fp32 && mtab)                                                                        \
@@ -1038,9 +1060,6 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
                        stream, a);                                                         \
   else if (mtab)                                                                           \
     hipLaunchKernelGGL((k_sweep<D_, O_, false, true, false>), grid, block, 0, stream, a);  \
-  else if (pipe)                                                                           \
-    hipLaunchKernelGGL((k_sweep<D_, O_, false, false, (D_ != 2 || O_ != 1)>), grid, block, 0, \
-                       stream, a);                                                         \
   else                                                                                     \
     hipLaunchKernelGGL((k_sweep<D_, O_, false, false, false>), grid, block, 0, stream, a);
   if (d->dim == 2 && d->order == 1) {

@@ -34,10 +34,15 @@ struct SweepArgs {
   int order;
 };
 
-// One launch of the batched FP64 sweep: block b sweeps velocity position
-// map[b].y of instance map[b].x with args[map[b].x], unless done[map[b].x].
-int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nblocks,
-                       const int32_t* done, int threads, hipStream_t stream);
+// One batched FP64 sweep: block b sweeps velocity position map[b].y of
+// instance map[b].x with args[map[b].x], unless done[map[b].x].  The map
+// holds the blocks of P2 instances first (nb2 of them), then those of P1
+// instances (nb1; every 3D instance is P1); in 2D with both present the two
+// kernels run concurrently, the P1 one on `side` between the events fork
+// (recorded on stream) and join (recorded on side, waited for on stream).
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nb2, int nb1,
+                       const int32_t* done, int threads, hipStream_t stream, hipStream_t side,
+                       hipEvent_t fork, hipEvent_t join);
 SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32);
 // factorised Maxwellian tables of a tensor velocity grid from nodal
