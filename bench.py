@@ -133,7 +133,25 @@ def generation_stats(d, threads=128):
             "lane_fill_128": float(np.mean(fill))}
 
 
-def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED", gen_stats=False):
+def tune_walk(B, d, f, bc, dt):
+    """Autotuned sweep walk of a DAG (timed on the initial state as the
+    source); returns the choice and the per-candidate milliseconds."""
+    import torch
+
+    from paper_2608_19150_amd import autotune
+    nn = d.n_nodes
+    kw = {"q": f, "nu": torch.full((nn,), 1.0, dtype=torch.float64, device="cuda"),
+          "mcoef": B.state_coefficients(d, STATE_OF_DAG[id(d)], "nodes"),
+          "sigma_shift": 1.0 / dt, "bc_coef": bc, "f_out": torch.empty_like(f)}
+    best, ms = autotune.tune_sweep_walk(d, kw, use_cache=False, reps=2)
+    return {"best": list(best), "ms": {f"{k}:{v}": round(t, 3) for (k, v), t in ms.items()}}
+
+
+STATE_OF_DAG = {}
+
+
+def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED", gen_stats=False,
+            tune=False):
     import torch
 
     import paper_2608_19150_amd as B
@@ -141,6 +159,11 @@ def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED", gen_stats
     d, f, bc, dt = B.problem_setup(pr)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    walk = None
+    if tune:
+        STATE_OF_DAG[id(d)] = pr.state
+        walk = tune_walk(B, d, f, bc, dt)
+        del STATE_OF_DAG[id(d)]
     s = B.Solver(d, dt=dt, bc_coef=bc, tableau=pr.tableau, tau=pr.tau, precision=precision,
                  mode=mode, nu_model=pr.nu_model, nu_const=pr.nu_const, kn=pr.kn,
                  timing=timing)
@@ -175,6 +198,7 @@ def run_gpu(pr, steps, warmup, precision, timing=True, mode="MATCHED", gen_stats
         "fallbacks": sum(st["fallbacks"] for st in stats),
     }
     out["U"] = U.cpu().numpy()
+    out["walk"] = walk
     if gen_stats:
         out["generations"] = generation_stats(d)
     del s, f, d
@@ -256,7 +280,7 @@ def run_c3(steps, warmup, kn, gen_stats=False):
     """3D x 3D: ~55k tetrahedra, P1, 16^3 velocities, backward Euler."""
     import problems as P
     pr = P.config_c3(kn=kn)
-    r = run_gpu(pr, steps, warmup, 0, gen_stats=gen_stats)
+    r = run_gpu(pr, steps, warmup, 0, gen_stats=gen_stats, tune=gen_stats)
     sweep_s = r["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r["n_unknown"] / sweep_s / 1e9
     out = {"workload": pr.name, "kn": kn, "unknowns": r["n_unknown"],
@@ -269,6 +293,7 @@ def run_c3(steps, warmup, kn, gen_stats=False):
            "sweep_traffic_bytes": measured_traffic(TRAFFIC_FILE_3D, SWEEP_KERNEL_3D)}
     if gen_stats:
         out["generations"] = r["generations"]
+        out["walk"] = r["walk"]
     return out
 
 
@@ -785,7 +810,7 @@ def main():
     torch.cuda.set_device(0)
     pr = P.config_c2(args.n_side)
     print(f"[bench] workload {pr.name}: building", file=sys.stderr, flush=True)
-    r64 = run_gpu(pr, args.steps, args.warmup, 0, gen_stats=True)
+    r64 = run_gpu(pr, args.steps, args.warmup, 0, gen_stats=True, tune=True)
     print(f"[bench] fp64 {r64['value']:.3e} unknowns/s, {r64['ms_per_step']:.1f} ms/step, "
           f"iters {r64['iters']}", file=sys.stderr, flush=True)
     fp32 = None
@@ -874,6 +899,7 @@ def main():
                    "parallelism": "single GPU"},
         "picard_iters": r64["iters"],
         "generations": r64["generations"],
+        "walk": r64["walk"],
         "kernel_ms": {"sweep": r64["sweep_ms_avg"], "moments": r64["moments_ms_avg"],
                       "maxwellian": r64["maxwellian_ms_avg"]},
         "fp32_refine": fp32,

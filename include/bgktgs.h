@@ -167,6 +167,17 @@ int tgs_dag_lagged(const tgs_dag* dag, uint8_t* lagged);
  * chosen at build: 1..32 = the packed walk, 64 = the workgroup walk). */
 int tgs_dag_sweep_lanes(const tgs_dag* dag);
 
+/* Sets the sweep walk of an existing DAG, as tgs_dag_opts.sweep_threads and
+ * sweep_lanes do at build time: threads = workgroup size of the workgroup
+ * walk (a multiple of 64 in [64, 256]; 0 = the element type's default),
+ * lanes = lanes per velocity of the packed walk (a power of two up to 32;
+ * 64 = the workgroup walk; 0 = the library's automatic rule); threads and
+ * packed lanes exclude each other.  Every walk gives the same results bit
+ * for bit; this is the sweep autotuner's knob (tile shape: velocities per
+ * workgroup and cells per wave).  Solvers on the DAG take the new walk from
+ * their next sweep.  Synchronises the device.  Errors: BGK_E_INVALID. */
+int tgs_dag_set_walk(tgs_dag* dag, int threads, int lanes);
+
 /* Host outputs (any may be NULL): node_x [n_cells][n_p][dim] node
  * coordinates, bnode_x [n_bfaces][n_fp][dim] boundary facet node
  * coordinates, vol [n_cells] cell measures. */

@@ -42,7 +42,7 @@ EXPORTED = [
     "bgk_mlp_features", "bgk_mlp_targets", "bgk_mlp_guess",
     "bgk_batch_create", "bgk_batch_destroy", "bgk_batch_step", "bgk_batch_time_sweep",
     "tgs_walls_create", "tgs_walls_destroy", "tgs_walls_count", "tgs_wall_values",
-    "tgs_dag_sweep_lanes",
+    "tgs_dag_sweep_lanes", "tgs_dag_set_walk",
 ]
 
 
@@ -131,6 +131,7 @@ _lib.tgs_dag_generations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_dag_lagged.argtypes = [C.c_void_p, C.c_void_p]
 _lib.tgs_dag_geometry.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_dag_explicit_dt.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_double)]
+_lib.tgs_dag_set_walk.argtypes = [C.c_void_p, C.c_int, C.c_int]
 _lib.tgs_pack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_unpack.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tgs_sweep.argtypes = [C.c_void_p, C.POINTER(SweepIO), C.c_void_p]
@@ -243,6 +244,12 @@ class Dag:
         out = torch.empty(self.f_numel(), dtype=torch.float64, device="cuda") if out is None else out
         _check(_lib.tgs_eval_maxwellian(self.h, _p(coef), _p(out), _stream(stream)))
         return out
+
+    def set_walk(self, threads=0, lanes=0):
+        """Sweep walk: workgroup walk of `threads` per workgroup, or packed
+        walk of `lanes` per velocity (0, 0: the library's automatic rule)."""
+        _check(_lib.tgs_dag_set_walk(self.h, int(threads), int(lanes)))
+        self.sweep_lanes = int(_lib.tgs_dag_sweep_lanes(self.h))
 
     def explicit_dt(self, cfl):
         """dt = C dt_e of eq. explicit-dt, computed by the library."""

@@ -1,6 +1,16 @@
-"""Tile autotuner for the batched sweep.
+"""Tile autotuners for the sweep.
 
-The batched sweep's tile is the workgroup size: how many cells of a
+Single-instance sweeps (tune_sweep_walk): the tile is the walk, i.e. how
+many velocities a workgroup serves and how many cells of a generation each
+has in flight: the workgroup walk (one velocity per workgroup of 64-256
+threads) or the packed walk (64/L velocities per 64-lane workgroup, L
+lanes each).  Narrow generations favour packing, wide ones the workgroup
+walk; each candidate times real sweeps of the caller's inputs
+(`tgs_sweep`) and the fastest is kept in a JSON cache keyed by the DAG's
+shape, then set on the DAG (`tgs_dag_set_walk`; every walk gives the same
+results bit for bit).
+
+Batched sweeps (tune_sweep_threads): the batched sweep's tile is the workgroup size: how many cells of a
 generation one velocity's workgroup has in flight (the rest of a wider
 generation is walked in further passes).  Small workgroups leave more room
 per CU for other velocities' workgroups (more velocities in flight), large
@@ -15,9 +25,14 @@ import hashlib
 import json
 import os
 
-from . import Batch
+import numpy as np
+import torch
+
+from . import Batch, tgs_sweep
 
 CANDIDATES = (64, 128, 192, 256)
+WALK_CANDIDATES = tuple(("wg", t) for t in (64, 128, 192, 256)) + tuple(
+    ("packed", l) for l in (2, 4, 8, 16, 32))
 
 
 def default_cache_path():
@@ -71,3 +86,61 @@ def autotuned_batch(solvers, fs, *, graph=True, chunk_iters=4, cache_path=None, 
     """A Batch whose sweep workgroup size was chosen by tune_sweep_threads."""
     best, ms = tune_sweep_threads(solvers, fs, cache_path=cache_path, **kw)
     return Batch(solvers, graph=graph, chunk_iters=chunk_iters, sweep_threads=best), best, ms
+
+
+def dag_key(dag):
+    """A key for a single instance's sweep shape: element type, cells,
+    velocities and the generation counts (which fix the walk's chain)."""
+    _, G = dag.generations()
+    G = np.asarray(G)
+    parts = f"{dag.dim}:{dag.order}:{dag.n_cells}:{dag.n_v}:{int(G.sum())}:{int(G.max())}"
+    return "walk:" + hashlib.sha256(parts.encode()).hexdigest()[:16]
+
+
+def time_sweep(dag, sweep_kw, reps=3):
+    """Median milliseconds of `reps` tgs_sweep calls with the DAG's current
+    walk (one untimed call first)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    tgs_sweep(dag, **sweep_kw)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        ev[0].record()
+        tgs_sweep(dag, **sweep_kw)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    return float(np.median(ts))
+
+
+def tune_sweep_walk(dag, sweep_kw, *, candidates=WALK_CANDIDATES, reps=3, cache_path=None,
+                    use_cache=True):
+    """Chooses the single-instance sweep walk by timing `tgs_sweep` with
+    `sweep_kw` (q, nu, mcoef, f_out, sigma_shift, boundary data, ...) under
+    every candidate, sets the fastest on the DAG and returns
+    (best, {candidate: ms}); candidates are ("wg", threads) and
+    ("packed", lanes).  Packed walks need FP64 sweeps."""
+    path = cache_path or default_cache_path()
+    key = dag_key(dag)
+    table = _load(path) if use_cache else {}
+    if use_cache and key in table:
+        kind, val = table[key]["best"]
+        _apply(dag, kind, int(val))
+        return (kind, int(val)), {tuple(k.split(":")[:1]) + (int(k.split(":")[1]),): v
+                                  for k, v in table[key]["ms"].items()}
+    ms = {}
+    for kind, val in candidates:
+        _apply(dag, kind, val)
+        ms[(kind, val)] = time_sweep(dag, sweep_kw, reps=reps)
+    best = min(ms, key=ms.get)
+    _apply(dag, *best)
+    table[key] = {"best": list(best), "ms": {f"{k}:{v}": t for (k, v), t in ms.items()}}
+    _store(path, table)
+    return best, ms
+
+
+def _apply(dag, kind, val):
+    if kind == "wg":
+        dag.set_walk(threads=val, lanes=0)
+    else:
+        dag.set_walk(threads=0, lanes=val)

@@ -608,6 +608,58 @@ std::vector<int32_t> deal_sectors(int n) {
   return out;
 }
 
+// The sweep walk: the workgroup walk with `threads` per workgroup (0: the
+// element type's default), or the packed walk with `lanes` per velocity.
+// lanes == 0 with threads == 0 takes the automatic rule: lanes from the mean
+// generation width; a wavefront takes 64/L velocities that are angular
+// neighbours (similar graphs, so its lane groups finish together), and the
+// groups are dealt to the XCDs by sector like the workgroup walk's blocks.
+int set_sweep_walk(tgs_dag* D, int threads, int lanes, hipStream_t stream) {
+  const int nv = D->n_v, dim = D->dim;
+  const int64_t nc = D->n_cells;
+  D->sweep_threads = threads;
+  if (lanes == 0 && threads == 0) {
+    double sumG = 0.0;
+    for (int j = 0; j < nv; ++j) sumG += D->G_host[j];
+    const double width = (double)nc * nv / std::max(sumG, 1.0);
+    int l0 = 1;
+    while (l0 < 64 && l0 * 1.5 < width) l0 *= 2;
+    // enough wavefronts to fill the GPU (4 per CU): fewer velocities per
+    // wavefront when there are few velocities
+    lanes = l0;
+    while (lanes < 32 && (double)nv * lanes / 64 < 1024) lanes *= 2;
+    if (l0 >= 32 || (double)nv * lanes / 64 < 1024) lanes = 64;
+  }
+  if (lanes == 0) lanes = 64;
+  D->sweep_lanes = lanes;
+  if (D->d_vpack) {
+    (void)hipFree(D->d_vpack);
+    D->d_vpack = nullptr;
+  }
+  D->vpack_blocks = 0;
+  if (lanes < 64) {
+    const int vpb = 64 / lanes;
+    std::vector<std::pair<double, int32_t>> key(nv);
+    for (int j = 0; j < nv; ++j) key[j] = {velocity_key(&D->v_host[(size_t)j * dim], dim), j};
+    std::stable_sort(key.begin(), key.end());
+    const int ng = (nv + vpb - 1) / vpb;
+    const std::vector<int32_t> gorder = deal_sectors(ng);
+    D->vpack_blocks = ng;
+    std::vector<int32_t> vpack((size_t)ng * vpb, -1);
+    for (int b = 0; b < ng; ++b)
+      for (int t = 0; t < vpb; ++t) {
+        const int pos = gorder[b] * vpb + t;
+        if (pos < nv) vpack[(size_t)b * vpb + t] = key[pos].second;
+      }
+    int rc;
+    if ((rc = dalloc(&D->d_vpack, vpack.size()))) return rc;
+    BGK_HIP(hipMemcpyAsync(D->d_vpack, vpack.data(), vpack.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream));
+    BGK_HIP(hipStreamSynchronize(stream));
+  }
+  return BGK_OK;
+}
+
 int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tgs_dag_opts* opts,
                    hipStream_t stream, tgs_dag* D) {
   HostMesh H;
@@ -899,45 +951,7 @@ int build_dag_impl(const tgs_mesh_desc* mesh, const tgs_vgrid_desc* vg, const tg
   }
   BGK_HIP(hipMemcpyAsync(D->d_vorder, vorder.data(), nv * sizeof(int32_t), hipMemcpyHostToDevice,
                          stream));
-  // packed walk: lanes per velocity from the mean generation width (or the
-  // caller's choice); a wavefront takes 64/L velocities that are angular
-  // neighbours (similar graphs, so its lane groups finish together), and the
-  // groups are dealt to the XCDs by sector like the workgroup walk's blocks
-  {
-    int lanes = lanes_opt;
-    if (lanes == 0 && !(opts && opts->sweep_threads)) {
-      double sumG = 0.0;
-      for (int j = 0; j < nv; ++j) sumG += D->G_host[j];
-      const double width = (double)nc * nv / std::max(sumG, 1.0);
-      int l0 = 1;
-      while (l0 < 64 && l0 * 1.5 < width) l0 *= 2;
-      // enough wavefronts to fill the GPU (4 per CU): fewer velocities per
-      // wavefront when there are few velocities
-      lanes = l0;
-      while (lanes < 32 && (double)nv * lanes / 64 < 1024) lanes *= 2;
-      if (l0 >= 32 || (double)nv * lanes / 64 < 1024) lanes = 64;
-    }
-    if (lanes == 0) lanes = 64;
-    D->sweep_lanes = lanes;
-    if (lanes < 64) {
-      const int vpb = 64 / lanes;
-      std::vector<std::pair<double, int32_t>> key(nv);
-      for (int j = 0; j < nv; ++j) key[j] = {velocity_key(&D->v_host[(size_t)j * dim], dim), j};
-      std::stable_sort(key.begin(), key.end());
-      const int ng = (nv + vpb - 1) / vpb;
-      const std::vector<int32_t> gorder = deal_sectors(ng);
-      D->vpack_blocks = ng;
-      std::vector<int32_t> vpack((size_t)ng * vpb, -1);
-      for (int b = 0; b < ng; ++b)
-        for (int t = 0; t < vpb; ++t) {
-          const int pos = gorder[b] * vpb + t;
-          if (pos < nv) vpack[(size_t)b * vpb + t] = key[pos].second;
-        }
-      if ((rc = dalloc(&D->d_vpack, vpack.size()))) return rc;
-      BGK_HIP(hipMemcpyAsync(D->d_vpack, vpack.data(), vpack.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice, stream));
-    }
-  }
+  if ((rc = set_sweep_walk(D, opts ? opts->sweep_threads : 0, lanes_opt, stream))) return rc;
   BGK_HIP(hipStreamSynchronize(stream));
   return BGK_OK;
 }
@@ -1032,6 +1046,20 @@ extern "C" int tgs_dag_lagged(const tgs_dag* d, uint8_t* lagged) {
 }
 
 extern "C" int tgs_dag_sweep_lanes(const tgs_dag* d) { return d ? d->sweep_lanes : 0; }
+extern "C" int tgs_dag_set_walk(tgs_dag* d, int threads, int lanes) {
+  return guarded([&]() -> int {
+    if (!d) return fail(BGK_E_INVALID, "null argument");
+    BGK_CHECK(threads == 0 || (threads >= 64 && threads <= 256 && threads % 64 == 0), BGK_E_INVALID,
+              "threads must be 0 or a multiple of 64 in [64, 256]");
+    BGK_CHECK(lanes == 0 || (lanes >= 1 && lanes <= 64 && (lanes & (lanes - 1)) == 0),
+              BGK_E_INVALID, "lanes must be 0 or a power of two up to 64");
+    BGK_CHECK(!(threads && lanes && lanes < 64), BGK_E_INVALID,
+              "threads sets the workgroup walk; it cannot be combined with packed lanes");
+    BGK_HIP(hipSetDevice(d->device));
+    BGK_HIP(hipDeviceSynchronize());
+    return set_sweep_walk(d, threads, lanes, nullptr);
+  });
+}
 
 extern "C" int tgs_dag_explicit_dt(const tgs_dag* d, double cfl, double* dt) {
   return guarded([&]() -> int {

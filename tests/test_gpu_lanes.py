@@ -187,3 +187,47 @@ def test_fp32_and_batched_sweeps_on_packed_walk_dags():
         outs[("step", L)] = d2.unpack(f).cpu().numpy()
     assert np.array_equal(outs[("fp32", 64)], outs[("fp32", 4)])
     assert np.array_equal(outs[("step", 64)], outs[("step", 4)])
+
+
+def test_sweep_walk_autotuner_sets_the_fastest_walk_and_results_do_not_change(tmp_path):
+    """The single-instance walk autotuner times every candidate walk
+    (workgroup walk of 64-256 threads, packed walk of 2-32 lanes per
+    velocity) on real sweeps, sets the fastest on the DAG and caches it by
+    the DAG's shape; a second call takes it from the cache.  The sweep
+    results are the same bit for bit under every walk."""
+    from paper_2608_19150_amd import autotune
+    pr = P.sod_strip_problem(8, 1.0)          # narrow generations: packing can win
+    d = B.Dag.from_problem(pr)
+    geo_inputs = _walk_inputs(d, pr)
+    ref = None
+    for kind, val in autotune.WALK_CANDIDATES:
+        autotune._apply(d, kind, val)
+        out = torch.empty_like(geo_inputs["q"])
+        B.tgs_sweep(d, **dict(geo_inputs, f_out=out))
+        if ref is None:
+            ref = out.clone()
+        assert torch.equal(out, ref), (kind, val)
+    cache = str(tmp_path / "tune.json")
+    best, ms = autotune.tune_sweep_walk(d, dict(geo_inputs, f_out=torch.empty_like(ref)),
+                                        cache_path=cache, reps=2)
+    print("walk timings (ms):", ms, "best", best, flush=True)
+    assert best == min(ms, key=ms.get)
+    expect_lanes = 64 if best[0] == "wg" else best[1]
+    assert d.sweep_lanes == expect_lanes
+    d.set_walk(0, 0)
+    best2, _ = autotune.tune_sweep_walk(d, dict(geo_inputs, f_out=torch.empty_like(ref)),
+                                        cache_path=cache)
+    assert best2 == best and d.sweep_lanes == expect_lanes
+
+
+def _walk_inputs(d, pr):
+    nn = d.n_nodes
+    prim = torch.zeros((nn, d.dim + 2), dtype=torch.float64, device="cuda")
+    prim[:, 0] = 1.0
+    prim[:, -1] = 1.0
+    prim[:, 1] = 0.2
+    mcoef = B.maxwellian_coef_from_primitive(prim, d.dim)
+    q = d.eval_maxwellian(mcoef)
+    return {"q": q, "nu": torch.full((nn,), 5.0, dtype=torch.float64, device="cuda"),
+            "mcoef": mcoef, "sigma_shift": 20.0,
+            "bc_coef": B.state_coefficients(d, pr.state, "boundary")}
