@@ -358,6 +358,18 @@ typedef struct {
                              previous Picard iterate (the first iteration of a
                              stage: the stage's initial iterate); bc_coef
                              gives the data of the inflow facets */
+  int chunk_iters;        /* 0 or 1: the host tests convergence after every
+                             Picard iteration; K >= 2: K iterations are
+                             enqueued at a time, the stopping test runs on the
+                             device after each, and once it has fired the
+                             rest of the chunk does nothing; the host reads a
+                             small control block once per chunk.  Iteration
+                             counts and results equal K = 1's.  Needs
+                             timing = 0. */
+  int graph;              /* with chunk_iters >= 2: each chunk is captured once
+                             in a hipGraph (per stage, moment-buffer parity and
+                             the f passed to bgk_step; at most 16 kept) and
+                             replayed on the step's stream */
 } bgk_solver_opts;
 
 typedef struct {
@@ -386,7 +398,8 @@ int bgk_solver_destroy(bgk_solver* solver);
  * With MATCHED Maxwellians a node whose Newton solve fails keeps the DIRECT
  * coefficients for the rest of the stage (maxw_fallbacks counts such nodes
  * in every iteration).
- * Synchronises `stream` once per Picard iteration to test convergence.
+ * Synchronises `stream` once per Picard iteration to test convergence, or
+ * once per chunk of opts.chunk_iters iterations.
  * Errors: BGK_E_NOT_CONVERGED, BGK_E_NONPHYSICAL, BGK_E_HIP.  After an error
  * f still holds f^k unless the failure came where f is written: in the last
  * stage of a stiffly accurate tableau (backward Euler's only stage), which

@@ -91,7 +91,8 @@ class SolverOpts(C.Structure):
     _fields_ = [("tableau", C.c_int), ("dt", C.c_double), ("tau", C.c_double),
                 ("l_max", C.c_int), ("fixed_iters", C.c_int), ("precision", C.c_int),
                 ("maxw_mode", C.c_int), ("nu_model", NuModel), ("bc_coef", C.c_void_p),
-                ("timing", C.c_int), ("walls", C.c_void_p)]
+                ("timing", C.c_int), ("walls", C.c_void_p), ("chunk_iters", C.c_int),
+                ("graph", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -318,13 +319,14 @@ class Solver:
 
     def __init__(self, dag, *, dt, bc_coef, tableau="BE", tau=1e-10, l_max=2000, fixed_iters=0,
                  precision=TGS_FP64, mode="MATCHED", nu_model="const", nu_const=1.0, kn=1.0,
-                 timing=False, walls=None):
+                 timing=False, walls=None, chunk_iters=0, graph=False):
         self.dag = dag
         self.bc_coef = bc_coef
         self.walls = walls            # keep the wall handle alive with the solver
         o = SolverOpts(TABLEAU[tableau], float(dt), float(tau), int(l_max), int(fixed_iters),
                        int(precision), MAXW[mode], NuModel(NU[nu_model], float(nu_const), float(kn)),
-                       _p(bc_coef), int(bool(timing)), walls.h if walls is not None else None)
+                       _p(bc_coef), int(bool(timing)), walls.h if walls is not None else None,
+                       int(chunk_iters), int(bool(graph)))
         h = C.c_void_p()
         _check(_lib.bgk_solver_create(dag.h, C.byref(o), C.byref(h)))
         self.h = h

@@ -5,6 +5,14 @@
 
 namespace bgk {
 
+// A kernel of a Picard iteration that was enqueued ahead of the host's view
+// of convergence does nothing once the device-side stopping test has set
+// *flag (null: always runs).  The flag is written by an earlier kernel on
+// the same stream, so it is visible at launch.
+__device__ __forceinline__ bool skip_launch(const int32_t* flag) {
+  return flag != nullptr && *flag != 0;
+}
+
 // Facet fluxes fl_k = v.N_k (N_k = |e_k| n_k, outward) from the stored
 // area-weighted normals, in a fixed operation order so that the DAG builder
 // and the sweep classify every facet identically (inflow iff fl_k < 0).  A

@@ -150,6 +150,7 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
 template <int DIM, int NP, int VL>
 __global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
   __shared__ double smem[MomSmem<DIM, NP, VL>::TOTAL];
+  if (skip_launch(a.skip)) return;
   moments_block<DIM, NP, VL>(a, blockIdx.x, smem);
 }
 
@@ -186,8 +187,9 @@ __device__ __forceinline__ void ratio_block(const double* __restrict__ partial, 
 }
 
 __global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partial, int nblk,
-                                               double* out) {
+                                               double* out, const int32_t* skip) {
   __shared__ double s[6][256];
+  if (skip_launch(skip)) return;
   ratio_block(partial, nblk, out, s);
 }
 
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(256) void k_proj_dense(const double* __restrict__ p
 template <int DIM>
 __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= p.n_nodes) return;
+  if (i >= p.n_nodes || skip_launch(p.skip)) return;
   maxwellian_node<DIM>(p, p.U, i);
 }
 
@@ -716,7 +718,9 @@ __device__ __forceinline__ void table_rows(const double* __restrict__ coef,
 template <int DIM>
 __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __restrict__ nu,
                               const double* __restrict__ x1, const double* __restrict__ geo,
-                              double* __restrict__ tab, int64_t n_cells, int n1, int np) {
+                              double* __restrict__ tab, int64_t n_cells, int n1, int np,
+                              const int32_t* skip) {
+  if (skip_launch(skip)) return;
   const int64_t total = table_threads(DIM, n_cells, n1, np);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -724,16 +728,16 @@ __global__ void k_maxw_tables(const double* __restrict__ coef, const double* __r
 }
 
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
-                       hipStream_t stream) {
+                       hipStream_t stream, const int32_t* skip) {
   const int np = (int)(d->n_nodes / d->n_cells);
   const int64_t total = table_threads(d->dim, d->n_cells, d->n_1d, np);
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxw_tables<2>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       d->d_geo, tab, d->n_cells, d->n_1d, np);
+                       d->d_geo, tab, d->n_cells, d->n_1d, np, skip);
   else
     hipLaunchKernelGGL(k_maxw_tables<3>, dim3(grid), dim3(256), 0, stream, coef, nu, d->d_nodes1d,
-                       d->d_geo, tab, d->n_cells, d->n_1d, np);
+                       d->d_geo, tab, d->n_cells, d->n_1d, np, skip);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -748,8 +752,10 @@ int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, d
 template <int DIM>
 __global__ __launch_bounds__(256) void k_proj_axes(const double* __restrict__ prim,
                                                    double* __restrict__ pr, int64_t n_nodes,
-                                                   int n1, int nc1, double L) {
+                                                   int n1, int nc1, double L,
+                                                   const int32_t* skip) {
   constexpr int NM = DIM + 2;
+  if (skip_launch(skip)) return;
   const int64_t total = (int64_t)DIM * nc1 * n_nodes;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -773,7 +779,8 @@ __global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ 
                                                      const double* __restrict__ nu,
                                                      const double* __restrict__ geo,
                                                      double* __restrict__ tab, int64_t n_cells,
-                                                     int n1, int np) {
+                                                     int n1, int np, const int32_t* skip) {
+  if (skip_launch(skip)) return;
   const TabLayout L(n_cells, n1, np, DIM);
   const int64_t nn = n_cells * np;
   const int64_t a0 = (int64_t)n1 * n_cells * (L.s0 / 2);
@@ -806,7 +813,7 @@ __global__ __launch_bounds__(256) void k_proj_tables(const double* __restrict__ 
 }
 
 int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, double* pr,
-                       double* tab, hipStream_t stream) {
+                       double* tab, hipStream_t stream, const int32_t* skip) {
   BGK_CHECK(d->dg_cells > 0, BGK_E_INVALID, "projected tables need a Q2 velocity space");
   const int np = (int)(d->n_nodes / d->n_cells);
   const int64_t n_pr = (int64_t)d->dim * d->dg_cells * d->n_nodes;
@@ -815,14 +822,14 @@ int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, d
   const int g2 = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (d->dim == 2) {
     hipLaunchKernelGGL(k_proj_axes<2>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
-                       d->n_1d, d->dg_cells, d->L);
+                       d->n_1d, d->dg_cells, d->L, skip);
     hipLaunchKernelGGL(k_proj_tables<2>, dim3(g2), dim3(256), 0, stream, pr, nu, d->d_geo, tab,
-                       d->n_cells, d->n_1d, np);
+                       d->n_cells, d->n_1d, np, skip);
   } else {
     hipLaunchKernelGGL(k_proj_axes<3>, dim3(g1), dim3(256), 0, stream, prim, pr, d->n_nodes,
-                       d->n_1d, d->dg_cells, d->L);
+                       d->n_1d, d->dg_cells, d->L, skip);
     hipLaunchKernelGGL(k_proj_tables<3>, dim3(g2), dim3(256), 0, stream, pr, nu, d->d_geo, tab,
-                       d->n_cells, d->n_1d, np);
+                       d->n_cells, d->n_1d, np, skip);
   }
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -881,9 +888,10 @@ int moment_blocks(const tgs_dag* d) {
 }
 
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
-                   double* partial, double* ratio_out, hipStream_t stream, bool user_order) {
+                   double* partial, double* ratio_out, hipStream_t stream, bool user_order,
+                   const int32_t* skip) {
   MomArgs a{f,      d->d_pos, user_order ? d->d_uid : nullptr, d->d_v, d->d_w, U, U_prev, partial,
-            (int)d->n_cells, d->n_v};
+            (int)d->n_cells, d->n_v, skip};
   const int vl = moment_vl(d);
   const int nblk = moment_blocks(d);
   const dim3 grid((unsigned)nblk), block(MOM_THREADS);
@@ -903,7 +911,7 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
 #undef BGK_MOM
   BGK_HIP(hipGetLastError());
   if (U_prev && ratio_out) {
-    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, nblk, ratio_out);
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, nblk, ratio_out, skip);
     BGK_HIP(hipGetLastError());
   }
   return BGK_OK;
@@ -911,7 +919,8 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
 
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
-                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream) {
+                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream,
+                      const int32_t* skip) {
   BGK_CHECK(mode == BGK_MAXW_DIRECT || mode == BGK_MAXW_MATCHED || mode == BGK_MAXW_LINEAR ||
                 mode == BGK_MAXW_PROJECTED,
             BGK_E_INVALID, "unknown Maxwellian mode");
@@ -923,7 +932,8 @@ int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_
             "LINEAR mode needs the velocity box half-width L");
   MaxwArgs p{U,      coef,     nu,          M_dense,       status, numax,
              d->d_v, d->d_w,   d->d_nodes1d, d->d_weights1d, d->n_1d, d->n_v,
-             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L, d->dg_cells, sticky};
+             d->n_nodes, mode, nm->kind,    nm->nu_const,  nm->kn, d->L, d->dg_cells, sticky,
+             skip};
   const dim3 grid((unsigned)((d->n_nodes + 127) / 128)), block(128);
   if (d->dim == 2)
     hipLaunchKernelGGL(k_maxwellian<2>, grid, block, 0, stream, p);

@@ -17,6 +17,7 @@ struct MomArgs {
   double* partial;  // [gridDim][6]: |dU_m|^2 (m = 0,1,2), |U_prev_m|^2
   int n_cells;
   int n_v;
+  const int32_t* skip;  // nonzero *skip: the launch does nothing (nullable)
 };
 
 struct MaxwArgs {
@@ -40,6 +41,7 @@ struct MaxwArgs {
   // MATCHED: per node, set once its Newton solve has failed; such a node
   // keeps the DIRECT coefficients while the flag stays set (nullable)
   uint8_t* sticky;
+  const int32_t* skip;  // nonzero *skip: the launch does nothing (nullable)
 };
 
 // Per-instance description for the batched kinetic kernels.  Nodal moments
@@ -72,5 +74,15 @@ int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const
                          hipStream_t stream);
 int moment_vl(const tgs_dag* d);
 int moment_blocks(const tgs_dag* d);
+
+// Single-instance launchers (kinetic.hip).  A non-null `skip` turns the
+// launch into a no-op on the device while *skip is nonzero.
+int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
+                   double* partial, double* ratio_out, hipStream_t stream, bool user_order,
+                   const int32_t* skip = nullptr);
+int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
+                      double* coef, double* nu, double* M_dense, int32_t* status,
+                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream,
+                      const int32_t* skip = nullptr);
 
 }  // namespace bgk

@@ -1,7 +1,21 @@
 // The DIRK/Picard solver object (shared by the single-instance and the
 // batched drivers).
 #pragma once
+#include <vector>
+
 #include "internal.h"
+
+// A captured chunk of Picard iterations, keyed by everything the captured
+// launches depend on: the stage, the moments' buffer parity and the buffers
+// read and written at the chunk's start.
+struct ChunkKey {
+  int stage, ucur;
+  const void *prev, *out, *fk, *q;
+  bool operator==(const ChunkKey& o) const {
+    return stage == o.stage && ucur == o.ucur && prev == o.prev && out == o.out && fk == o.fk &&
+           q == o.q;
+  }
+};
 
 struct bgk_solver {
   const tgs_dag* dag = nullptr;
@@ -30,6 +44,13 @@ struct bgk_solver {
   // pinned host mirror: ratio[4], numax bits, status[2]
   double* h_info = nullptr;
   hipEvent_t ev[4] = {};  // kernel timing: before maxw, before sweep, before moments, after
+  // device control block of the chunked iteration: int32 [0] done (0 running,
+  // 1 converged, 2 failed), [1] iterations of the stage, [2] MATCHED
+  // fallbacks of the stage, [3] error code, [4] non-physical nodes; double at
+  // byte 32: the last max ratio
+  int32_t* ctl = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (graph mode)
+  std::vector<std::pair<ChunkKey, hipGraphExec_t>> graphs;
 };
 
 namespace bgk {

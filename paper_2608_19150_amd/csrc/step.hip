@@ -15,21 +15,14 @@
 #include <cstring>
 
 #include "device_common.h"
+#include "kinetic_args.h"
 #include "solver.h"
 #include "sweep_args.h"
 #include "walls.h"
 
 namespace bgk {
-int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
-                 hipStream_t stream, int threads);
-int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
-                   double* partial, double* ratio_out, hipStream_t stream, bool user_order);
 int launch_nodal_perm(const tgs_dag* d, const double* src, double* dst, int to_internal,
                       hipStream_t stream);
-int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
-                      double* coef, double* nu, double* M_dense, int32_t* status,
-                      unsigned long long* numax, uint8_t* sticky, hipStream_t stream);
-int moment_blocks(const tgs_dag* d);
 
 // out = sum_i c_i x_i (up to 5 inputs), grid-stride; out may be x0 (each
 // element is read before it is written by the same thread).  V = 2: pairs of
@@ -74,11 +67,61 @@ __global__ __launch_bounds__(256) void k_combine(double* out, const double* x0, 
 
 // zero the per-iteration status words (a kernel, so the sequence stays
 // capturable in a graph)
-__global__ void k_reset(int32_t* status, unsigned long long* numax) {
-  if (threadIdx.x == 0) {
+__global__ void k_reset(int32_t* status, unsigned long long* numax, const int32_t* skip) {
+  if (threadIdx.x == 0 && !skip_launch(skip)) {
     status[0] = 0;
     status[1] = 0;
     *numax = 0ull;
+  }
+}
+
+// control block of the chunked iteration at the start of a stage
+__global__ void k_ctl_init(int32_t* ctl) {
+  if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
+  if (threadIdx.x == 0) reinterpret_cast<double*>(ctl)[4] = 0.0;
+}
+
+// The stopping test of one Picard iteration on the device (the host loop's
+// rule: a non-physical or non-finite iterate fails the stage; with
+// fixed_iters the count decides, else the max ratio of eq.
+// convergence-criteria against tau / max(1, max nu dt); l_max iterations
+// without stopping fail).  Once ctl[0] is set, later iterations skip.
+__global__ void k_converge1(int32_t* ctl, const int32_t* __restrict__ status,
+                            const unsigned long long* __restrict__ numax,
+                            const double* __restrict__ ratio, double tau, double dt,
+                            int fixed_iters, int l_max) {
+  if (threadIdx.x != 0 || ctl[0] != 0) return;
+  const int it = ctl[1] + 1;
+  ctl[1] = it;
+  ctl[2] += status[0];
+  if (status[1] > 0) {
+    ctl[0] = 2;
+    ctl[3] = BGK_E_NONPHYSICAL;
+    ctl[4] = status[1];
+    return;
+  }
+  const double last = ratio[3];
+  reinterpret_cast<double*>(ctl)[4] = last;
+  if (!isfinite(last)) {
+    ctl[0] = 2;
+    ctl[3] = BGK_E_NONPHYSICAL;
+    return;
+  }
+  if (fixed_iters > 0) {
+    if (it >= fixed_iters) {
+      ctl[0] = 1;
+      return;
+    }
+  } else {
+    const double nm = __longlong_as_double((long long)numax[0]);
+    if (last < tau / fmax(1.0, nm * dt)) {
+      ctl[0] = 1;
+      return;
+    }
+  }
+  if (it >= l_max) {
+    ctl[0] = 2;
+    ctl[3] = BGK_E_NOT_CONVERGED;
   }
 }
 
@@ -202,6 +245,9 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
       return fail(BGK_E_INVALID, "walls belong to another DAG");
     if (o->maxw_mode == BGK_MAXW_PROJECTED && d->dg_cells <= 0)
       return fail(BGK_E_INVALID, "PROJECTED mode needs a Q2 velocity space (dg_cells > 0)");
+    if (o->chunk_iters < 0) return fail(BGK_E_INVALID, "chunk_iters must be >= 0");
+    if (o->chunk_iters > 1 && o->timing)
+      return fail(BGK_E_INVALID, "per-kernel timing needs chunk_iters <= 1");
     bgk_solver* s = new (std::nothrow) bgk_solver();
     if (!s) return fail(BGK_E_NOMEM, "host allocation failed");
     s->dag = d;
@@ -227,6 +273,10 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
     if (!rc) rc = dmalloc(&s->status, 2);
     if (!rc) rc = dmalloc(&s->numax, 1);
     if (!rc) rc = dmalloc(&s->sticky, (size_t)d->n_nodes);
+    if (!rc) rc = dmalloc(&s->ctl, 16);
+    if (!rc && o->chunk_iters > 1 && o->graph &&
+        hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess)
+      rc = fail(BGK_E_HIP, "hipStreamCreate failed");
     if (!rc && hipHostMalloc((void**)&s->h_info, 8 * sizeof(double)) != hipSuccess)
       rc = fail(BGK_E_NOMEM, "pinned host allocation failed");
     if (!rc && o->timing)
@@ -247,7 +297,9 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
     void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
                     s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
                     s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr,
-                    s->bcd};
+                    s->bcd,   s->ctl};
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (s->h_info) (void)hipHostFree(s->h_info);
@@ -297,6 +349,14 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
         return rc;
     }
+    const int K = o.chunk_iters > 1 ? o.chunk_iters : 1;
+    // the buffer a Picard iteration writes, given the one it reads: with
+    // lagged facets or the FP32 form the previous iterate must survive the
+    // sweep, so iterates alternate between the stage's output and fping
+    // (the first iteration reads the stage's initial iterate)
+    const auto next_out = [&](const double* prev, double* out) -> double* {
+      return need_prev ? (prev == out ? s->fping : out) : out;
+    };
     for (int stg = 0; stg < s->S; ++stg) {
       const double shift = 1.0 / (o.dt * s->A[stg][stg]);
       const double* qsrc;
@@ -311,30 +371,23 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         qscale = 1.0;
       }
       double* out = fst[stg];
-      // with lagged facets or the FP32 form the previous iterate is kept in
-      // fping; the first iteration reads the stage's initial iterate
-      const double* prev = stage_init;
-      double* cur_out = out;
-      int it = 0;
-      bool converged = false;
-      double last = 0.0;
-      // a node whose MATCHED solve fails stays on DIRECT for the rest of the
-      // stage: an iterate switching between the two would not settle
-      hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)std::min<int64_t>((d->n_nodes + 255) / 256, 1024)),
-                         dim3(256), 0, stream, s->sticky, d->n_nodes);
-      while (it < o.l_max) {
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, s->status, s->numax);
-        if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], stream));
-        if ((rc = launch_maxwellian(d, o.maxw_mode, s->U[ucur], &o.nu_model, s->mcoef, s->nu,
-                                    nullptr, s->status, s->numax, s->sticky, stream)))
-          return rc;
+      // one Picard iteration reading moments U[ucur] and iterate prev,
+      // writing U[ucur ^ 1] and cur_out; with `skip` every launch is a no-op
+      // once the device-side stopping test has fired
+      const auto enqueue_iter = [&](hipStream_t sm, int uc, const double* prv, double* cur,
+                                    const int32_t* skip) -> int {
+        int r;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, sm, s->status, s->numax, skip);
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], sm));
+        if ((r = launch_maxwellian(d, o.maxw_mode, s->U[uc], &o.nu_model, s->mcoef, s->nu,
+                                   nullptr, s->status, s->numax, s->sticky, sm, skip)))
+          return r;
         if (s->pr)
-          rc = launch_proj_tables(d, s->mcoef, s->nu, s->pr, s->mtab, stream);
+          r = launch_proj_tables(d, s->mcoef, s->nu, s->pr, s->mtab, sm, skip);
         else if (s->mtab)
-          rc = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, stream);
-        if (rc) return rc;
-        if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], stream));
-        if (need_prev) cur_out = (prev == out) ? s->fping : out;
+          r = launch_maxw_tables(d, s->mcoef, s->nu, s->mtab, sm, skip);
+        if (r) return r;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[1], sm));
         tgs_sweep_io io{};
         io.precision = o.precision;
         io.sigma_shift = shift;
@@ -344,58 +397,148 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         io.q = qsrc;
         io.bc_coef = nullptr;
         io.bc_dense = s->bcd;
-        io.f_prev = need_prev ? prev : nullptr;
-        if (o.walls && (rc = launch_wall_values(o.walls, prev, s->bcd, stream))) return rc;
-        io.f_out = cur_out;
-        if ((rc = launch_sweep(d, &io, s->mtab, s->d32, stream, 0))) return rc;
-        if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], stream));
-        if ((rc = launch_moments(d, cur_out, s->U[ucur ^ 1], s->U[ucur], s->partial, s->ratio,
-                                 stream, false)))
-          return rc;
-        if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], stream));
-        BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                               stream));
-        BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, stream));
-        BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                               stream));
-        BGK_HIP(hipStreamSynchronize(stream));
-        if (o.timing) {
-          float t01, t12, t23;
-          BGK_HIP(hipEventElapsedTime(&t01, s->ev[0], s->ev[1]));
-          BGK_HIP(hipEventElapsedTime(&t12, s->ev[1], s->ev[2]));
-          BGK_HIP(hipEventElapsedTime(&t23, s->ev[2], s->ev[3]));
-          st.maxwellian_ms += t01;
-          st.sweep_ms += t12;
-          st.moments_ms += t23;
+        io.f_prev = need_prev ? prv : nullptr;
+        if (o.walls && (r = launch_wall_values(o.walls, prv, s->bcd, sm, skip))) return r;
+        io.f_out = cur;
+        if ((r = launch_sweep(d, &io, s->mtab, s->d32, sm, 0, skip))) return r;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], sm));
+        if ((r = launch_moments(d, cur, s->U[uc ^ 1], s->U[uc], s->partial, s->ratio, sm, false,
+                                skip)))
+          return r;
+        if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], sm));
+        return BGK_OK;
+      };
+      // K iterations from (uc, prv), each followed by the device-side test
+      const auto enqueue_chunk = [&](hipStream_t sm, int uc, const double* prv) -> int {
+        for (int k = 0; k < K; ++k) {
+          double* cur = next_out(prv, out);
+          int r = enqueue_iter(sm, uc, prv, cur, s->ctl);
+          if (r) return r;
+          hipLaunchKernelGGL(k_converge1, dim3(1), dim3(64), 0, sm, s->ctl, s->status, s->numax,
+                             s->ratio, o.tau, o.dt, o.fixed_iters, o.l_max);
+          BGK_HIP(hipGetLastError());
+          uc ^= 1;
+          prv = cur;
         }
-        ++st.sweeps;
-        ++it;
-        ucur ^= 1;
-        prev = cur_out;
-        int32_t stat[2];
-        std::memcpy(stat, s->h_info + 5, sizeof(stat));
-        st.maxw_fallbacks += stat[0];
-        if (stat[1] > 0) {
-          return fail(BGK_E_NONPHYSICAL,
-                      "non-physical moments (n <= 0 or theta <= 0) at " + std::to_string(stat[1]) +
-                          " nodes");
-        }
-        double numax;
-        std::memcpy(&numax, s->h_info + 4, sizeof(double));
-        last = s->h_info[3];
-        if (!std::isfinite(last))
-          return fail(BGK_E_NONPHYSICAL, "non-finite moments in the Picard iteration");
-        if (o.fixed_iters > 0) {
-          if (it >= o.fixed_iters) {
+        return BGK_OK;
+      };
+      const double* prev = stage_init;
+      int it = 0;
+      bool converged = false;
+      double last = 0.0;
+      // a node whose MATCHED solve fails stays on DIRECT for the rest of the
+      // stage: an iterate switching between the two would not settle
+      hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)std::min<int64_t>((d->n_nodes + 255) / 256, 1024)),
+                         dim3(256), 0, stream, s->sticky, d->n_nodes);
+      if (K == 1) {
+        while (it < o.l_max) {
+          double* cur_out = next_out(prev, out);
+          if ((rc = enqueue_iter(stream, ucur, prev, cur_out, nullptr))) return rc;
+          BGK_HIP(hipMemcpyAsync(s->h_info, s->ratio, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                                 stream));
+          BGK_HIP(hipMemcpyAsync(s->h_info + 4, s->numax, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, stream));
+          BGK_HIP(hipMemcpyAsync(s->h_info + 5, s->status, 2 * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, stream));
+          BGK_HIP(hipStreamSynchronize(stream));
+          if (o.timing) {
+            float t01, t12, t23;
+            BGK_HIP(hipEventElapsedTime(&t01, s->ev[0], s->ev[1]));
+            BGK_HIP(hipEventElapsedTime(&t12, s->ev[1], s->ev[2]));
+            BGK_HIP(hipEventElapsedTime(&t23, s->ev[2], s->ev[3]));
+            st.maxwellian_ms += t01;
+            st.sweep_ms += t12;
+            st.moments_ms += t23;
+          }
+          ++st.sweeps;
+          ++it;
+          ucur ^= 1;
+          prev = cur_out;
+          int32_t stat[2];
+          std::memcpy(stat, s->h_info + 5, sizeof(stat));
+          st.maxw_fallbacks += stat[0];
+          if (stat[1] > 0) {
+            return fail(BGK_E_NONPHYSICAL, "non-physical moments (n <= 0 or theta <= 0) at " +
+                                               std::to_string(stat[1]) + " nodes");
+          }
+          double numax;
+          std::memcpy(&numax, s->h_info + 4, sizeof(double));
+          last = s->h_info[3];
+          if (!std::isfinite(last))
+            return fail(BGK_E_NONPHYSICAL, "non-finite moments in the Picard iteration");
+          if (o.fixed_iters > 0) {
+            if (it >= o.fixed_iters) {
+              converged = true;
+              break;
+            }
+            continue;
+          }
+          if (last < o.tau / std::max(1.0, numax * o.dt)) {
             converged = true;
             break;
           }
-          continue;
         }
-        if (last < o.tau / std::max(1.0, numax * o.dt)) {
-          converged = true;
-          break;
+      } else {
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, s->ctl);
+        BGK_HIP(hipGetLastError());
+        int32_t done = 0;
+        while (done == 0) {
+          if (o.graph) {
+            const ChunkKey key{stg, ucur, prev, out, fk, qsrc};
+            hipGraphExec_t exec = nullptr;
+            for (auto& g : s->graphs)
+              if (g.first == key) exec = g.second;
+            if (!exec) {
+              if (s->graphs.size() >= 16) {
+                for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+                s->graphs.clear();
+              }
+              BGK_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+              const int r = enqueue_chunk(s->cap, ucur, prev);
+              hipGraph_t g = nullptr;
+              const hipError_t e = hipStreamEndCapture(s->cap, &g);
+              if (r || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return r ? r : fail(BGK_E_HIP, std::string("graph capture: ") +
+                                                   hipGetErrorString(e));
+              }
+              const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+              (void)hipGraphDestroy(g);
+              if (ei != hipSuccess)
+                return fail(BGK_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+              s->graphs.emplace_back(key, exec);
+            }
+            BGK_HIP(hipGraphLaunch(exec, stream));
+          } else if ((rc = enqueue_chunk(stream, ucur, prev))) {
+            return rc;
+          }
+          BGK_HIP(hipMemcpyAsync(s->h_info, s->ctl, 16 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 stream));
+          BGK_HIP(hipStreamSynchronize(stream));
+          int32_t c[5];
+          std::memcpy(c, s->h_info, sizeof(c));
+          done = c[0];
+          // the iterations that ran are a prefix of the chunk: follow their
+          // buffer alternation
+          for (int k = it; k < c[1]; ++k) {
+            prev = next_out(prev, out);
+            ucur ^= 1;
+            ++st.sweeps;
+          }
+          it = c[1];
+          last = s->h_info[4];
+          if (done != 0) {
+            st.maxw_fallbacks += c[2];
+            if (done == 1) {
+              converged = true;
+            } else if (c[3] == BGK_E_NONPHYSICAL) {
+              return c[4] > 0 ? fail(BGK_E_NONPHYSICAL,
+                                     "non-physical moments (n <= 0 or theta <= 0) at " +
+                                         std::to_string(c[4]) + " nodes")
+                              : fail(BGK_E_NONPHYSICAL,
+                                     "non-finite moments in the Picard iteration");
+            }
+          }
         }
       }
       if (prev != out) {

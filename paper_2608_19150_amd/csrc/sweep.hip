@@ -831,6 +831,7 @@ __global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep
   constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
   using RT = typename std::conditional<F32, float, double>::type;
   __shared__ RT ring[RS * NP];
+  if (skip_launch(a.skip)) return;
   sweep_velocity<DIM, ORDER, F32, TAB, PIPE>(a, a.vorder[blockIdx.x], ring);
 }
 
@@ -867,6 +868,7 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
   using C = LanesCfg<DIM, ORDER, L>;
   constexpr int NP = C::NP, VPB = C::VPB, RS = C::RS;
   __shared__ double ring_all[C::RING ? VPB * RS * NP : 1];
+  if (skip_launch(a.skip)) return;
   const int lane = threadIdx.x, t = lane / L, r = lane - t * L;
   double* ring = ring_all + t * RS * NP;
   const int jj = a.vorder[blockIdx.x * VPB + t];   // the packed order, -1: none
@@ -997,12 +999,13 @@ SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                    d->d_goff,  d->d_gmin,  d->d_gbase,  d->d_G,     d->d_vorder, io->nu,
                    io->mcoef,  mtab,       io->q,       io->bc_coef, io->bc_dense, io->f_prev,
                    io->f_out,  d32,        io->sigma_shift, io->q_scale, (int)d->n_cells, d->n_v,
-                   d->n_1d,    ring_slots(d), d->order};
+                   d->n_1d,    ring_slots(d), d->order, nullptr};
 }
 
 int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
-                 hipStream_t stream, int threads) {
-  const SweepArgs a = make_sweep_args(d, io, mtab, d32);
+                 hipStream_t stream, int threads, const int32_t* skip) {
+  SweepArgs a = make_sweep_args(d, io, mtab, d32);
+  a.skip = skip;
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {

@@ -32,6 +32,7 @@ struct SweepArgs {
   int n1;                    // points per axis of a tensor velocity grid (mtab)
   int ring_slots;            // LDS ring of recent outputs, slots (power of two)
   int order;
+  const int32_t* skip;       // nonzero *skip: the launch does nothing (nullable)
 };
 
 // One batched FP64 sweep: block b sweeps velocity position map[b].y of
@@ -45,14 +46,19 @@ int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map
                        hipEvent_t fork, hipEvent_t join);
 SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32);
+// One single-instance sweep (sweep.hip): the DAG's walk, or the workgroup
+// walk with `threads` per workgroup when threads > 0.  A non-null `skip`
+// turns the launch into a no-op on the device while *skip is nonzero.
+int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, float* d32,
+                 hipStream_t stream, int threads, const int32_t* skip = nullptr);
 // factorised Maxwellian tables of a tensor velocity grid from nodal
 // coefficients and nu (kinetic.hip), and their size in doubles
 int launch_maxw_tables(const tgs_dag* d, const double* coef, const double* nu, double* tab,
-                       hipStream_t stream);
+                       hipStream_t stream, const int32_t* skip = nullptr);
 // the same tables for the projected Maxwellian from primitive (n, u, theta)
 // coefficients; pr is scratch of proj_scratch_size(d) doubles
 int launch_proj_tables(const tgs_dag* d, const double* prim, const double* nu, double* pr,
-                       double* tab, hipStream_t stream);
+                       double* tab, hipStream_t stream, const int32_t* skip = nullptr);
 inline size_t proj_scratch_size(const tgs_dag* d) {
   return (size_t)d->dim * d->n_1d * d->n_nodes;
 }

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(256) void k_wall_values(const int4* __restrict__ wa
                                                      const double* __restrict__ f,
                                                      double* __restrict__ bc, int64_t n_walls,
                                                      int max_in, int n_v, int64_t n_cells,
-                                                     int np, int nfp) {
+                                                     int np, int nfp, const int32_t* skip) {
+  if (skip_launch(skip)) return;
   const int64_t total = n_walls * max_in;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -135,12 +136,13 @@ int velocity_map(const tgs_dag* d, int kind, const double* nrm, std::vector<int3
 
 const tgs_dag* walls_dag(const tgs_walls* w) { return w->dag; }
 
-int launch_wall_values(const tgs_walls* w, const double* f, double* bc_dense, hipStream_t stream) {
+int launch_wall_values(const tgs_walls* w, const double* f, double* bc_dense, hipStream_t stream,
+                       const int32_t* skip) {
   const tgs_dag* d = w->dag;
   if (w->n_walls == 0 || w->max_in == 0) return BGK_OK;
   hipLaunchKernelGGL(k_wall_values, dim3(grid_of(w->n_walls * w->max_in)), dim3(256), 0, stream,
                      w->d_wall, w->d_map, w->d_in, w->d_in_off, d->d_pos, f, bc_dense, w->n_walls,
-                     w->max_in, d->n_v, d->n_cells, d->n_p, d->n_fp);
+                     w->max_in, d->n_v, d->n_cells, d->n_p, d->n_fp, skip);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
