@@ -179,7 +179,9 @@ struct bgk_batch {
   int nb2 = 0, nb1 = 0;
   int32_t* mom_first = nullptr;      // [n + 1]
   int mom_blocks = 0;
-  int64_t* node_first = nullptr;     // [n + 1]
+  int32_t* mx_inst = nullptr;        // Maxwellian blocks (128 nodes of one instance): instance
+  int32_t* mx_first = nullptr;       // [n + 1] first Maxwellian block of each instance
+  int mx_blocks = 0;
   int64_t n_nodes = 0;
   int64_t* tab_first = nullptr;      // [n + 1]
   int64_t n_tab = 0;
@@ -353,7 +355,7 @@ int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, int threads) {
   hipLaunchKernelGGL(k_iter_reset, inst_grid(n), dim3(64), 0, B->stream, c.done, B->status,
                      B->numax, n);
   BGK_HIP(hipGetLastError());
-  if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->node_first, n, B->n_nodes,
+  if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->mx_inst, B->mx_first, B->mx_blocks,
                                     B->stream)))
     return rc;
   if (B->tab &&
@@ -414,7 +416,7 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     const bgk_solver* s0 = solvers[0];
     if (!s0) return fail(BGK_E_INVALID, "null solver");
     bool tab = true;
-    int64_t n_nodes = 0, n_tab = 0;
+    int64_t n_nodes = 0, n_tab = 0, mx_total = 0;
     for (int i = 0; i < n; ++i) {
       const bgk_solver* s = solvers[i];
       if (!s) return fail(BGK_E_INVALID, "null solver");
@@ -431,7 +433,9 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
       if (s->opts.walls) return fail(BGK_E_UNSUPPORTED, "batched stepping has no wall boundaries");
       tab = tab && s->mtab != nullptr;
       n_nodes += d->n_nodes;
+      mx_total += (d->n_nodes + 127) / 128;
     }
+    if (mx_total > INT32_MAX) return fail(BGK_E_INVALID, "too many nodes in the batch");
     bgk_batch* B = new (std::nothrow) bgk_batch();
     if (!B) return fail(BGK_E_NOMEM, "host allocation failed");
     B->n = n;
@@ -455,12 +459,14 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     check(hipEventCreate(&B->t0), "hipEventCreate");
     check(hipEventCreate(&B->t1), "hipEventCreate");
     // per-instance layout tables
-    std::vector<int64_t> nfirst(n + 1, 0), tfirst(n + 1, 0);
-    std::vector<int32_t> mfirst(n + 1, 0);
+    std::vector<int64_t> tfirst(n + 1, 0);
+    std::vector<int32_t> mfirst(n + 1, 0), xfirst(n + 1, 0), xinst;
     int64_t npart = 0;
     for (int i = 0; i < n; ++i) {
       const tgs_dag* d = solvers[i]->dag;
-      nfirst[i + 1] = nfirst[i] + d->n_nodes;
+      const int64_t nb = (d->n_nodes + 127) / 128;
+      xfirst[i + 1] = xfirst[i] + (int32_t)nb;
+      xinst.insert(xinst.end(), (size_t)nb, i);
       tfirst[i + 1] =
           tfirst[i] + (tab ? table_threads(d->dim, d->n_cells, d->n_1d, d->n_p) : 0);  // table threads
       mfirst[i + 1] = mfirst[i] + moment_blocks(d);
@@ -502,7 +508,9 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     if (!rc) rc = dalloc(&B->conv, (size_t)n);
     if (!rc) rc = dalloc(&B->map, map.size());
     if (!rc) rc = dalloc(&B->mom_first, (size_t)n + 1);
-    if (!rc) rc = dalloc(&B->node_first, (size_t)n + 1);
+    B->mx_blocks = xfirst[n];
+    if (!rc) rc = dalloc(&B->mx_inst, xinst.size());
+    if (!rc) rc = dalloc(&B->mx_first, (size_t)n + 1);
     if (!rc) rc = dalloc(&B->tab_first, (size_t)n + 1);
     if (!rc) rc = dalloc(&B->ctl_mem, (size_t)5 * n);
     if (!rc) rc = dalloc(&B->last, (size_t)n);
@@ -519,7 +527,9 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
       check(hipMemcpy(B->map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice), "hipMemcpy");
       check(hipMemcpy(B->mom_first, mfirst.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
             "hipMemcpy");
-      check(hipMemcpy(B->node_first, nfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
+      check(hipMemcpy(B->mx_inst, xinst.data(), xinst.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice), "hipMemcpy");
+      check(hipMemcpy(B->mx_first, xfirst.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
             "hipMemcpy");
       check(hipMemcpy(B->tab_first, tfirst.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
             "hipMemcpy");
@@ -542,7 +552,8 @@ extern "C" int bgk_batch_destroy(bgk_batch* B) {
     for (hipGraph_t g : B->graphs)
       if (g) (void)hipGraphDestroy(g);
     void* ptrs[] = {B->sargs,  B->sargs_tune, B->kin,    B->comb,   B->conv,   B->map,
-                    B->mom_first, B->node_first, B->tab_first, B->ctl_mem, B->last, B->status,
+                    B->mom_first, B->mx_inst, B->mx_first, B->tab_first, B->ctl_mem, B->last,
+                    B->status,
                     B->numax,  B->ratio,      B->partial, B->sticky};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -681,7 +692,7 @@ extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads,
                        B->numax, n);
     BGK_HIP(hipGetLastError());
     const BatchKin* kin = B->kin + (size_t)n;
-    if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->node_first, n, B->n_nodes,
+    if ((rc = launch_maxwellian_batch(B->dim, kin, c.par, c.done, B->mx_inst, B->mx_first, B->mx_blocks,
                                       B->stream)))
       return rc;
     if (B->tab &&

@@ -474,9 +474,37 @@ __device__ __forceinline__ double proj_node(double u, double sig, int i, int nc1
   return k == 0 ? p[0] : (k == 1 ? p[1] : p[2]);
 }
 
+// What one node contributes to the kernel-wide status words; the caller
+// adds a wavefront's contributions with one atomic each (flush_status).
+struct NodeStatus {
+  unsigned long long nubits = 0ull;  // bit pattern of nu (>= 0) of a physical node, else 0
+  bool fallback = false;             // MATCHED solve failed or held on DIRECT
+  bool nonphysical = false;
+};
+
+// One atomic per wavefront and status word: the wave's maximum nu bit
+// pattern, its fallback and non-physical counts.  Every lane of the wave
+// must call it (no lane may have left the kernel) and the targets must be
+// the same for the whole wave.
+__device__ __forceinline__ void flush_status(const NodeStatus& st, int32_t* status,
+                                             unsigned long long* numax) {
+  unsigned long long m = st.nubits;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off);
+    m = o > m ? o : m;
+  }
+  const unsigned long long fb = __ballot(st.fallback), np = __ballot(st.nonphysical);
+  if (__lane_id() == 0) {
+    if (numax && m) atomicMax(numax, m);
+    if (status && fb) atomicAdd(&status[0], (int)__popcll(fb));
+    if (status && np) atomicAdd(&status[1], (int)__popcll(np));
+  }
+}
+
 template <int DIM>
 __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double* __restrict__ Uin,
-                                                int64_t i) {
+                                                int64_t i, NodeStatus& st) {
   constexpr int NM = DIM + 2;
   double U[NM];
 #pragma unroll
@@ -505,10 +533,10 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
       for (int j = 0; j < p.n_v; ++j) p.M_dense[i * p.n_v + j] = 0.0;
     return;
   }
-  if (!physical && p.status) atomicAdd(&p.status[1], 1);
+  st.nonphysical = !physical;
   double nu = p.nu_kind == BGK_NU_CONST ? p.nu_const : n / sqrt(th) / p.kn;
   if (p.nu) p.nu[i] = nu;
-  if (p.numax && physical) atomicMax(p.numax, (unsigned long long)__double_as_longlong(nu));
+  if (physical) st.nubits = (unsigned long long)__double_as_longlong(nu);
   if (p.mode == BGK_MAXW_PROJECTED) {
     // coefficients are the primitive variables (the values, if asked for,
     // come from k_proj_dense)
@@ -534,7 +562,7 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
     for (int d = 0; d < DIM; ++d) x[1 + d] = u[d] / th;
     x[1 + DIM] = -0.5 / th;
     if (p.mode == BGK_MAXW_MATCHED && physical && p.sticky && p.sticky[i]) {
-      if (p.status) atomicAdd(&p.status[0], 1);
+      st.fallback = true;
     } else if (p.mode == BGK_MAXW_MATCHED && physical) {
       double Unorm = 0.0;
 #pragma unroll
@@ -570,7 +598,7 @@ __device__ __forceinline__ void maxwellian_node(const MaxwArgs& p, const double*
 #pragma unroll
         for (int m = 0; m < NM; ++m) x[m] = y[m];
       } else {
-        if (p.status) atomicAdd(&p.status[0], 1);
+        st.fallback = true;
         if (p.sticky) p.sticky[i] = 1;
       }
     }
@@ -618,9 +646,11 @@ __global__ __launch_bounds__(256) void k_proj_dense(const double* __restrict__ p
 
 template <int DIM>
 __global__ __launch_bounds__(128) void k_maxwellian(MaxwArgs p) {
+  if (skip_launch(p.skip)) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= p.n_nodes || skip_launch(p.skip)) return;
-  maxwellian_node<DIM>(p, p.U, i);
+  NodeStatus st;
+  if (i < p.n_nodes) maxwellian_node<DIM>(p, p.U, i, st);
+  flush_status(st, p.status, p.numax);
 }
 
 template <int DIM>
@@ -971,29 +1001,23 @@ __device__ __forceinline__ int find_instance(const T* __restrict__ first, int n,
   return lo;
 }
 
+// One block per 128 nodes of one instance (instances' node ranges padded to
+// whole blocks, blk_inst[b] the instance of block b, blk_first[i] its first
+// block): the instance's arguments are wave-uniform, read through the scalar
+// unit, and a finished instance's blocks leave at once.
 template <int DIM>
 __global__ __launch_bounds__(128) void k_maxwellian_batch(const BatchKin* __restrict__ kin,
                                                           const int32_t* __restrict__ par,
                                                           const int32_t* __restrict__ done,
-                                                          const int64_t* __restrict__ first,
-                                                          int n_inst, int64_t total) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const int i = find_instance<int64_t>(first, n_inst, g);
+                                                          const int32_t* __restrict__ blk_inst,
+                                                          const int32_t* __restrict__ blk_first) {
+  const int i = blk_inst[blockIdx.x];
   if (done[i]) return;
-  // A wave inside one instance (all but a few per launch) reads that
-  // instance's arguments through a wave-uniform index, so they are scalar
-  // loads into scalar registers and the Newton loop's trip counts and
-  // per-axis node reads are uniform; a wave straddling two instances keeps
-  // per-lane copies.
-  const int i0 = __builtin_amdgcn_readfirstlane(i);
-  if (__ballot(i != i0) == 0) {
-    const MaxwArgs p = kin[i0].maxw;
-    maxwellian_node<DIM>(p, kin[i0].U[par[i0]], g - first[i0]);
-  } else {
-    const MaxwArgs p = kin[i].maxw;
-    maxwellian_node<DIM>(p, kin[i].U[par[i]], g - first[i]);
-  }
+  const MaxwArgs& p = kin[i].maxw;
+  const int64_t node = (int64_t)(blockIdx.x - blk_first[i]) * 128 + threadIdx.x;
+  NodeStatus st;
+  if (node < p.n_nodes) maxwellian_node<DIM>(p, kin[i].U[par[i]], node, st);
+  flush_status(st, p.status, p.numax);
 }
 
 // Grid-stride over every instance's table threads; a thread that meets a
@@ -1075,16 +1099,16 @@ __global__ __launch_bounds__(256) void k_ratio_batch(const BatchKin* __restrict_
 }
 
 int launch_maxwellian_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
-                            const int64_t* node_first, int n_inst, int64_t n_total,
+                            const int32_t* blk_inst, const int32_t* blk_first, int n_blocks,
                             hipStream_t stream) {
-  if (n_total == 0) return BGK_OK;
-  const dim3 grid((unsigned)((n_total + 127) / 128)), block(128);
+  if (n_blocks == 0) return BGK_OK;
+  const dim3 grid((unsigned)n_blocks), block(128);
   if (dim == 2)
-    hipLaunchKernelGGL(k_maxwellian_batch<2>, grid, block, 0, stream, kin, par, done, node_first,
-                       n_inst, n_total);
+    hipLaunchKernelGGL(k_maxwellian_batch<2>, grid, block, 0, stream, kin, par, done, blk_inst,
+                       blk_first);
   else
-    hipLaunchKernelGGL(k_maxwellian_batch<3>, grid, block, 0, stream, kin, par, done, node_first,
-                       n_inst, n_total);
+    hipLaunchKernelGGL(k_maxwellian_batch<3>, grid, block, 0, stream, kin, par, done, blk_inst,
+                       blk_first);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

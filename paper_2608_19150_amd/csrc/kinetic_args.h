@@ -63,8 +63,11 @@ struct BatchKin {
 
 // Launchers over all instances; done[i] != 0 skips instance i.  blk_first
 // is the exclusive prefix of per-instance block counts (n + 1 entries).
+// The Maxwellian takes one 128-thread block per 128 nodes of an instance:
+// blk_inst[b] is the instance of block b (n_blocks of them) and
+// blk_first[i] the first block of instance i.
 int launch_maxwellian_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
-                            const int64_t* node_first, int n_inst, int64_t n_total,
+                            const int32_t* blk_inst, const int32_t* blk_first, int n_blocks,
                             hipStream_t stream);
 int launch_tables_batch(int dim, const BatchKin* kin, const int32_t* done,
                         const int64_t* entry_first, int n_inst, int64_t n_total,
