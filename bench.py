@@ -210,7 +210,7 @@ def run_c4(steps, warmup, tune_cache):
     """Batched uneven instances (64 seeded 2D problems, P1/P2, 8^2..32^2
     velocities, Kn log-uniform in [1e-4, 1], DIRK2): one batched launch per
     kernel per Picard iteration, hipGraph-replayed chunks, autotuned sweep
-    workgroup size.  Instances that go non-physical in the warm-up step are
+    walk (workgroup size, or lanes per velocity of the packed walk).  Instances that go non-physical in the warm-up step are
     dropped and counted.  Also times the same step with each instance stepped
     alone, one after another."""
     import torch
@@ -237,9 +237,8 @@ def run_c4(steps, warmup, tune_cache):
     del probe, fcopy
     setups = [setups[i] for i in keep]
     solvers, fs = [x[1] for x in setups], [x[2] for x in setups]
-    best, tune_ms = autotune.tune_sweep_threads(solvers, fs, cache_path=tune_cache,
-                                                use_cache=False)
-    batch = B.Batch(solvers, graph=True, chunk_iters=4, sweep_threads=best)
+    best, tune_ms = autotune.tune_batch_walk(solvers, fs, cache_path=tune_cache, use_cache=False)
+    batch = B.Batch(solvers, graph=True, chunk_iters=4, **autotune.batch_walk_kwargs(best))
     for _ in range(warmup):
         batch.step(fs, check=False)
     torch.cuda.synchronize()
@@ -271,7 +270,8 @@ def run_c4(steps, warmup, tune_cache):
             "unknowns_total": int(sum(nu)), "steps": steps, "ms_per_step": 1e3 * elapsed / steps,
             "value": sweeps / elapsed, "unit": "unknowns/s",
             "p50_instance_step_ms": float(pct[0]), "p99_instance_step_ms": float(pct[1]),
-            "sweep_threads": best, "autotune_ms_per_sweep": tune_ms,
+            "sweep_walk": f"{best[0]}:{best[1]}",
+            "autotune_ms_per_sweep": {f"{k}:{v}": t for (k, v), t in tune_ms.items()},
             "sequential_single_instance_value": seq_sweeps / seq,
             "sequential_single_instance_ms_per_step": 1e3 * seq, "setup_s": setup_s}
 

@@ -433,6 +433,11 @@ typedef struct {
   int chunk_iters;    /* Picard iterations between convergence polls (0: 4) */
   int sweep_threads;  /* workgroup size of the batched sweep, a multiple of 64 up to 256
                          (0: 128) */
+  int sweep_lanes;    /* 0 or 64: the workgroup walk (one velocity per workgroup
+                         of sweep_threads); 1, 2, 4, 8, 16 or 32: the packed walk,
+                         64/sweep_lanes velocities of one instance per 64-lane
+                         workgroup, sweep_lanes lanes each (as tgs_dag_set_walk;
+                         results are the same bit for bit) */
 } bgk_batch_opts;
 
 typedef struct {
@@ -461,11 +466,13 @@ int bgk_batch_step(bgk_batch* batch, double* const* f, bgk_batch_stats* stats,
                    bgk_stream_t stream);
 
 /* Autotuning probe: from f's moments builds the Maxwellians, then times
- * `reps` batched sweeps of the first stage with `threads` per workgroup
- * (reading f, writing the solvers' f^k scratch); *ms = milliseconds per
- * sweep (host float).  Leaves f unchanged. */
-int bgk_batch_time_sweep(bgk_batch* batch, double* const* f, int threads, int reps, float* ms,
-                         bgk_stream_t stream);
+ * `reps` batched sweeps of the first stage with the workgroup walk of
+ * `threads` per workgroup (lanes 0 or 64) or the packed walk of `lanes` per
+ * velocity (1, 2, 4, 8, 16 or 32; threads is then ignored but must be
+ * valid), reading f and writing the solvers' f^k scratch; *ms = milliseconds
+ * per sweep (host float).  Leaves f unchanged. */
+int bgk_batch_time_sweep(bgk_batch* batch, double* const* f, int threads, int lanes, int reps,
+                         float* ms, bgk_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Learned Picard initial guess (an addition to the paper's method: the       */

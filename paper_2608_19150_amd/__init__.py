@@ -413,7 +413,8 @@ def problem_setup(pr, dag=None, **dag_kw):
 # batched instances
 # ---------------------------------------------------------------------------
 class BatchOpts(C.Structure):
-    _fields_ = [("graph", C.c_int), ("chunk_iters", C.c_int), ("sweep_threads", C.c_int)]
+    _fields_ = [("graph", C.c_int), ("chunk_iters", C.c_int), ("sweep_threads", C.c_int),
+                ("sweep_lanes", C.c_int)]
 
 
 class BatchStats(C.Structure):
@@ -428,17 +429,17 @@ _lib.bgk_batch_destroy.argtypes = [C.c_void_p]
 _lib.bgk_batch_step.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(BatchStats),
                                 C.c_void_p]
 _lib.bgk_batch_time_sweep.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int,
-                                      C.POINTER(C.c_float), C.c_void_p]
+                                      C.c_int, C.POINTER(C.c_float), C.c_void_p]
 
 
 class Batch:
     """bgk_batch: many solvers stepped together (one launch per kernel per
     Picard iteration, optional hipGraph replay of iteration chunks)."""
 
-    def __init__(self, solvers, *, graph=True, chunk_iters=4, sweep_threads=0):
+    def __init__(self, solvers, *, graph=True, chunk_iters=4, sweep_threads=0, sweep_lanes=0):
         self.solvers = list(solvers)          # keep them (and their DAGs) alive
         arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
-        o = BatchOpts(int(bool(graph)), int(chunk_iters), int(sweep_threads))
+        o = BatchOpts(int(bool(graph)), int(chunk_iters), int(sweep_threads), int(sweep_lanes))
         h = C.c_void_p()
         _check(_lib.bgk_batch_create(arr, len(self.solvers), C.byref(o), C.byref(h)))
         self.h = h
@@ -463,10 +464,12 @@ class Batch:
                  "total_iters": s.total_iters, "last_ratio": list(s.last_ratio[:s.stages]),
                  "fallbacks": s.maxw_fallbacks, "finish_ms": s.finish_ms} for s in st]
 
-    def time_sweep(self, fs, threads, reps=3, stream=None):
+    def time_sweep(self, fs, threads, reps=3, stream=None, lanes=0):
+        """Milliseconds per batched sweep with the workgroup walk of `threads`
+        (lanes 0) or the packed walk of `lanes` per velocity."""
         ms = C.c_float()
-        _check(_lib.bgk_batch_time_sweep(self.h, self._fptrs(fs), int(threads), int(reps),
-                                         C.byref(ms), _stream(stream)))
+        _check(_lib.bgk_batch_time_sweep(self.h, self._fptrs(fs), int(threads), int(lanes),
+                                         int(reps), C.byref(ms), _stream(stream)))
         return ms.value
 
 

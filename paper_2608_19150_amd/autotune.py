@@ -10,14 +10,17 @@ walk; each candidate times real sweeps of the caller's inputs
 shape, then set on the DAG (`tgs_dag_set_walk`; every walk gives the same
 results bit for bit).
 
-Batched sweeps (tune_sweep_threads): the batched sweep's tile is the workgroup size: how many cells of a
-generation one velocity's workgroup has in flight (the rest of a wider
-generation is walked in further passes).  Small workgroups leave more room
-per CU for other velocities' workgroups (more velocities in flight), large
-ones cover wide generations in one pass; the best choice depends on the
-instances' generation widths and element types, so it is measured: each
-candidate times a few real sweeps of the batch (`bgk_batch_time_sweep`) and
-the fastest is kept in a JSON cache keyed by the batch's shape.
+Batched sweeps (tune_batch_walk): the same two walks over every instance's
+velocities at once.  With the workgroup walk the tile is the workgroup
+size: how many cells of a generation one velocity's workgroup has in flight
+(the rest of a wider generation is walked in further passes); small
+workgroups leave more room per CU for other velocities' workgroups, large
+ones cover wide generations in one pass.  With the packed walk 64/L
+velocities of one instance share a 64-lane workgroup, which suits the
+narrow generations of small instances once the batch has velocities enough
+to fill the GPU.  Each candidate times a few real sweeps of the batch
+(`bgk_batch_time_sweep`) and the fastest is kept in a JSON cache keyed by
+the batch's shape (tune_sweep_threads: the workgroup sizes alone).
 """
 from __future__ import annotations
 
@@ -31,6 +34,8 @@ import torch
 from . import Batch, tgs_sweep
 
 CANDIDATES = (64, 128, 192, 256)
+BATCH_WALK_CANDIDATES = tuple(("wg", t) for t in (64, 128, 256)) + tuple(
+    ("packed", l) for l in (4, 8, 16, 32))
 WALK_CANDIDATES = tuple(("wg", t) for t in (64, 128, 192, 256)) + tuple(
     ("packed", l) for l in (2, 4, 8, 16, 32))
 
@@ -82,10 +87,43 @@ def tune_sweep_threads(solvers, fs, *, candidates=CANDIDATES, reps=3, cache_path
     return best, ms
 
 
+def tune_batch_walk(solvers, fs, *, candidates=BATCH_WALK_CANDIDATES, reps=3, cache_path=None,
+                    use_cache=True):
+    """Returns ((kind, value), {(kind, value): ms per sweep}) for the batched
+    sweep: ("wg", threads) or ("packed", lanes).  `fs` are the instances'
+    current states (read only)."""
+    path = cache_path or default_cache_path()
+    key = "batchwalk:" + batch_key(solvers)
+    table = _load(path) if use_cache else {}
+    if use_cache and key in table:
+        kind, val = table[key]["best"]
+        return (kind, int(val)), {(k.split(":")[0], int(k.split(":")[1])): v
+                                  for k, v in table[key]["ms"].items()}
+    probe = Batch(solvers, graph=False)
+    probe.time_sweep(fs, 128, reps=1)      # warm-up
+    ms = {}
+    for kind, val in candidates:
+        if kind == "wg":
+            ms[(kind, val)] = probe.time_sweep(fs, val, reps=reps)
+        else:
+            ms[(kind, val)] = probe.time_sweep(fs, 128, reps=reps, lanes=val)
+    best = min(ms, key=ms.get)
+    table[key] = {"best": list(best), "ms": {f"{k}:{v}": t for (k, v), t in ms.items()}}
+    _store(path, table)
+    return best, ms
+
+
+def batch_walk_kwargs(best):
+    """Batch keyword arguments for a tune_batch_walk choice."""
+    kind, val = best
+    return {"sweep_threads": val} if kind == "wg" else {"sweep_lanes": val}
+
+
 def autotuned_batch(solvers, fs, *, graph=True, chunk_iters=4, cache_path=None, **kw):
-    """A Batch whose sweep workgroup size was chosen by tune_sweep_threads."""
-    best, ms = tune_sweep_threads(solvers, fs, cache_path=cache_path, **kw)
-    return Batch(solvers, graph=graph, chunk_iters=chunk_iters, sweep_threads=best), best, ms
+    """A Batch whose sweep walk was chosen by tune_batch_walk."""
+    best, ms = tune_batch_walk(solvers, fs, cache_path=cache_path, **kw)
+    return (Batch(solvers, graph=graph, chunk_iters=chunk_iters, **batch_walk_kwargs(best)),
+            best, ms)
 
 
 def dag_key(dag):

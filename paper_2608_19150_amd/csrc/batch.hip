@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <vector>
 
@@ -177,6 +178,14 @@ struct bgk_batch {
   ConvArgs* conv = nullptr;          // [n]
   int2* map = nullptr;               // sweep blocks: P2 instances' first, then P1's
   int nb2 = 0, nb1 = 0;
+  // packed-walk block maps by lanes per velocity (built on first use, kept:
+  // captured graphs refer to them)
+  struct Packed {
+    int2* map = nullptr;
+    int32_t* pvel = nullptr;
+    int nb2 = 0, nb1 = 0;
+  };
+  std::map<int, Packed> packed;
   int32_t* mom_first = nullptr;      // [n + 1]
   int mom_blocks = 0;
   int32_t* mx_inst = nullptr;        // Maxwellian blocks (128 nodes of one instance): instance
@@ -346,8 +355,82 @@ int launch_combine(bgk_batch* B, int k, const int32_t* done) {
 
 dim3 inst_grid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 
+// The packed walk's blocks for `lanes` per velocity: each instance's
+// velocities in direction order, 64/lanes to a block (angular neighbours,
+// whose graphs are alike, so a block's lane groups finish together); P2
+// instances' blocks first, then P1's, each part longest generation count
+// first.
+int packed_map(bgk_batch* B, int lanes, const bgk_batch::Packed** out) {
+  auto it = B->packed.find(lanes);
+  if (it == B->packed.end()) {
+    const int vpb = 64 / lanes;
+    std::vector<std::pair<int, int2>> blocks[2];
+    std::vector<int32_t> pvel;
+    for (int i = 0; i < B->n; ++i) {
+      const tgs_dag* d = B->solvers[i]->dag;
+      const std::vector<int32_t> order = angular_order(d);
+      auto& part = blocks[d->dim == 2 && d->order == 2 ? 0 : 1];
+      for (int b0 = 0; b0 < d->n_v; b0 += vpb) {
+        const int off = (int)pvel.size();
+        int gmax = 0;
+        for (int t = 0; t < vpb; ++t) {
+          const int j = b0 + t < d->n_v ? order[b0 + t] : -1;
+          pvel.push_back(j);
+          if (j >= 0) gmax = std::max(gmax, d->G_host[j]);
+        }
+        part.push_back({gmax, make_int2(i, off)});
+      }
+    }
+    std::vector<int2> map;
+    for (auto& part : blocks) {
+      std::stable_sort(part.begin(), part.end(),
+                       [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) {
+                         return a.first > b.first;
+                       });
+      for (const auto& b : part) map.push_back(b.second);
+    }
+    bgk_batch::Packed P;
+    P.nb2 = (int)blocks[0].size();
+    P.nb1 = (int)blocks[1].size();
+    int rc = dalloc(&P.map, map.size());
+    if (!rc) rc = dalloc(&P.pvel, pvel.size());
+    if (!rc && (hipMemcpy(P.map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                hipMemcpy(P.pvel, pvel.data(), pvel.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice) != hipSuccess))
+      rc = fail(BGK_E_HIP, "copy of the packed-walk map failed");
+    if (rc) {
+      if (P.map) (void)hipFree(P.map);
+      if (P.pvel) (void)hipFree(P.pvel);
+      return rc;
+    }
+    it = B->packed.emplace(lanes, P).first;
+  }
+  *out = &it->second;
+  return BGK_OK;
+}
+
+// the walk of a batched sweep: the workgroup walk with `threads` (lanes 0
+// or 64) or the packed walk with `lanes` per velocity
+int batch_walk(bgk_batch* B, int threads, int lanes, BatchWalk* w) {
+  if (lanes <= 0 || lanes >= 64) {
+    *w = BatchWalk{threads, 64, B->map, B->nb2, B->nb1, nullptr};
+    return BGK_OK;
+  }
+  const bgk_batch::Packed* P = nullptr;
+  const int rc = packed_map(B, lanes, &P);
+  if (rc) return rc;
+  *w = BatchWalk{64, lanes, P->map, P->nb2, P->nb1, P->pvel};
+  return BGK_OK;
+}
+
+bool valid_lanes(int lanes) {
+  return lanes == 0 || lanes == 64 ||
+         (lanes > 0 && lanes <= 32 && (lanes & (lanes - 1)) == 0);
+}
+
 // one Picard iteration of stage st for every running instance
-int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, int threads) {
+int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, const BatchWalk& walk) {
   const int n = B->n;
   const Ctl c = B->ctl();
   const BatchKin* kin = B->kin + (size_t)(1 + st) * n;
@@ -361,8 +444,8 @@ int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, int threads) {
   if (B->tab &&
       (rc = launch_tables_batch(B->dim, kin, c.done, B->tab_first, n, B->n_tab, B->stream)))
     return rc;
-  if ((rc = launch_sweep_batch(B->dim, B->tab, sargs, B->map, B->nb2, B->nb1, c.done, threads,
-                               B->stream, B->side, B->ev_fork, B->ev_join)))
+  if ((rc = launch_sweep_batch(B->dim, B->tab, sargs, walk, c.done, B->stream, B->side,
+                               B->ev_fork, B->ev_join)))
     return rc;
   if ((rc = launch_moments_batch(B->dim, kin, c.par, c.done, B->mom_first, n, B->mom_blocks, true,
                                  B->stream)))
@@ -374,11 +457,12 @@ int run_iteration(bgk_batch* B, int st, const SweepArgs* sargs, int threads) {
 }
 
 int run_chunk(bgk_batch* B, int st) {
-  for (int k = 0; k < B->opts.chunk_iters; ++k) {
-    int rc = run_iteration(B, st, B->sargs + (size_t)st * B->n, B->opts.sweep_threads);
-    if (rc) return rc;
-  }
-  return BGK_OK;
+  // the walk's maps were built at creation: nothing here allocates or copies
+  BatchWalk walk;
+  int rc = batch_walk(B, B->opts.sweep_threads, B->opts.sweep_lanes, &walk);
+  for (int k = 0; k < B->opts.chunk_iters && !rc; ++k)
+    rc = run_iteration(B, st, B->sargs + (size_t)st * B->n, walk);
+  return rc;
 }
 
 int capture_graphs(bgk_batch* B) {
@@ -413,6 +497,8 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
     if (o.sweep_threads <= 0) o.sweep_threads = 128;
     if (o.sweep_threads % 64 || o.sweep_threads > 256)
       return fail(BGK_E_INVALID, "sweep_threads must be a multiple of 64 up to 256");
+    if (!valid_lanes(o.sweep_lanes))
+      return fail(BGK_E_INVALID, "sweep_lanes must be 0, 64 or a power of two up to 32");
     const bgk_solver* s0 = solvers[0];
     if (!s0) return fail(BGK_E_INVALID, "null solver");
     bool tab = true;
@@ -535,6 +621,9 @@ extern "C" int bgk_batch_create(bgk_solver* const* solvers, int n, const bgk_bat
             "hipMemcpy");
       check(hipMemcpy(B->conv, conv.data(), n * sizeof(ConvArgs), hipMemcpyHostToDevice), "hipMemcpy");
     }
+    // the packed walk's map now, so that captured chunks find it built
+    BatchWalk walk;
+    if (!rc) rc = batch_walk(B, o.sweep_threads, o.sweep_lanes, &walk);
     if (rc) {
       bgk_batch_destroy(B);
       return rc;
@@ -557,6 +646,10 @@ extern "C" int bgk_batch_destroy(bgk_batch* B) {
                     B->numax,  B->ratio,      B->partial, B->sticky};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
+    for (auto& kv : B->packed) {
+      if (kv.second.map) (void)hipFree(kv.second.map);
+      if (kv.second.pvel) (void)hipFree(kv.second.pvel);
+    }
     if (B->h_ctl) (void)hipHostFree(B->h_ctl);
     if (B->h_last) (void)hipHostFree(B->h_last);
     hipEvent_t evs[] = {B->ev_in, B->ev_out, B->t0, B->t1, B->ev_fork, B->ev_join};
@@ -662,12 +755,14 @@ extern "C" int bgk_batch_step(bgk_batch* B, double* const* f, bgk_batch_stats* s
   });
 }
 
-extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads, int reps,
-                                    float* ms, bgk_stream_t stream_) {
+extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads, int lanes,
+                                    int reps, float* ms, bgk_stream_t stream_) {
   return guarded([&]() -> int {
     if (!B || !f || !ms || reps <= 0) return fail(BGK_E_INVALID, "bad arguments");
     if (threads <= 0 || threads % 64 || threads > 256)
       return fail(BGK_E_INVALID, "threads must be a multiple of 64 up to 256");
+    if (!valid_lanes(lanes))
+      return fail(BGK_E_INVALID, "lanes must be 0, 64 or a power of two up to 32");
     for (int i = 0; i < B->n; ++i)
       if (!f[i]) return fail(BGK_E_INVALID, "null f");
     const int n = B->n;
@@ -698,10 +793,12 @@ extern "C" int bgk_batch_time_sweep(bgk_batch* B, double* const* f, int threads,
     if (B->tab &&
         (rc = launch_tables_batch(B->dim, kin, c.done, B->tab_first, n, B->n_tab, B->stream)))
       return rc;
+    BatchWalk walk;
+    if ((rc = batch_walk(B, threads, lanes, &walk))) return rc;
     BGK_HIP(hipEventRecord(B->t0, B->stream));
     for (int r = 0; r < reps; ++r)
-      if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, B->map, B->nb2, B->nb1,
-                                   c.done, threads, B->stream, B->side, B->ev_fork, B->ev_join)))
+      if ((rc = launch_sweep_batch(B->dim, B->tab, B->sargs_tune, walk, c.done, B->stream,
+                                   B->side, B->ev_fork, B->ev_join)))
         return rc;
     BGK_HIP(hipEventRecord(B->t1, B->stream));
     BGK_HIP(hipEventSynchronize(B->t1));

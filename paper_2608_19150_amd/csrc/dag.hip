@@ -587,6 +587,16 @@ double velocity_key(const double* vj, int dim) {
          std::atan2(std::fabs(vj[2]), std::hypot(vj[0], vj[1]));
 }
 
+std::vector<int32_t> angular_order(const tgs_dag* D) {
+  std::vector<std::pair<double, int32_t>> key(D->n_v);
+  for (int j = 0; j < D->n_v; ++j)
+    key[j] = {velocity_key(&D->v_host[(size_t)j * D->dim], D->dim), j};
+  std::stable_sort(key.begin(), key.end());
+  std::vector<int32_t> out(D->n_v);
+  for (int j = 0; j < D->n_v; ++j) out[j] = key[j].second;
+  return out;
+}
+
 // Sorted positions 0..n-1 dealt to blocks: block b runs on XCD b % 8, and
 // sector x (positions [x n/8, (x+1) n/8)) goes to XCD x, so block b takes
 // the (b/8)-th position of sector b % 8 (sectors differ in size by at most

@@ -863,15 +863,17 @@ struct LanesCfg {
   static constexpr bool RING = RS >= 16;
 };
 
+// One 64-lane workgroup of the packed walk: lane group t sweeps velocity
+// vblock[t] (-1: none).
 template <int DIM, int ORDER, bool TAB, int L>
-__global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
+__device__ __forceinline__ void sweep_lanes_block(const SweepArgs& a,
+                                                  const int32_t* __restrict__ vblock,
+                                                  double* ring_all) {
   using C = LanesCfg<DIM, ORDER, L>;
-  constexpr int NP = C::NP, VPB = C::VPB, RS = C::RS;
-  __shared__ double ring_all[C::RING ? VPB * RS * NP : 1];
-  if (skip_launch(a.skip)) return;
+  constexpr int NP = C::NP, RS = C::RS;
   const int lane = threadIdx.x, t = lane / L, r = lane - t * L;
   double* ring = ring_all + t * RS * NP;
-  const int jj = a.vorder[blockIdx.x * VPB + t];   // the packed order, -1: none
+  const int jj = vblock[t];
   const int j = jj < 0 ? 0 : jj;
   double v[DIM], v2 = 0.0;
 #pragma unroll
@@ -924,6 +926,31 @@ __global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
   }
 }
 
+template <int DIM, int ORDER, bool TAB, int L>
+__global__ __launch_bounds__(64) void k_sweep_lanes(SweepArgs a) {
+  using C = LanesCfg<DIM, ORDER, L>;
+  __shared__ double ring_all[C::RING ? C::VPB * C::RS * C::NP : 1];
+  if (skip_launch(a.skip)) return;
+  sweep_lanes_block<DIM, ORDER, TAB, L>(a, a.vorder + blockIdx.x * C::VPB, ring_all);
+}
+
+// Batched packed walk: block b serves the 64/L velocities pvel[map[b].y ..]
+// of instance map[b].x, unless that instance is done.
+template <int DIM, int ORDER, bool TAB, int L>
+__global__ __launch_bounds__(64) void k_sweep_batch_lanes(const SweepArgs* __restrict__ args,
+                                                          const int2* __restrict__ map,
+                                                          const int32_t* __restrict__ pvel,
+                                                          const int32_t* __restrict__ done) {
+  using C = LanesCfg<DIM, ORDER, L>;
+  __shared__ double ring_all[C::RING ? C::VPB * C::RS * C::NP : 1];
+  const int2 m = map[blockIdx.x];
+  const int inst = __builtin_amdgcn_readfirstlane(m.x);
+  const int off = __builtin_amdgcn_readfirstlane(m.y);
+  if (done[inst]) return;
+  const SweepArgs a = args[inst];
+  sweep_lanes_block<DIM, ORDER, TAB, L>(a, pvel + off, ring_all);
+}
+
 // Batched FP64 sweep over many instances of one element type in one launch:
 // block b sweeps velocity map[b].y (a position in its instance's velocity
 // order) of instance map[b].x; instances flagged done skip.  One kernel per
@@ -949,39 +976,60 @@ __global__ __launch_bounds__(256, 2) void k_sweep_batch(const SweepArgs* __restr
 }
 
 template <int DIM, int ORDER>
-void launch_batch_kernel(bool tab, const SweepArgs* args, const int2* map, int nblocks,
-                         const int32_t* done, int threads, hipStream_t stream) {
-  if (tab)
-    hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, true>), dim3(nblocks), dim3(threads), 0, stream,
-                       args, map, done);
-  else
-    hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, false>), dim3(nblocks), dim3(threads), 0,
-                       stream, args, map, done);
+void launch_batch_kernel(bool tab, const SweepArgs* args, const BatchWalk& w, bool p1,
+                         const int32_t* done, hipStream_t stream) {
+  const int nb = p1 ? w.nb1 : w.nb2;
+  const int2* map = p1 ? w.map + w.nb2 : w.map;
+  if (w.lanes >= 64) {
+    if (tab)
+      hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, true>), dim3(nb), dim3(w.threads), 0, stream,
+                         args, map, done);
+    else
+      hipLaunchKernelGGL((k_sweep_batch<DIM, ORDER, false>), dim3(nb), dim3(w.threads), 0,
+                         stream, args, map, done);
+    return;
+  }
+#define BGK_BL(L_)                                                                           \
+  if (tab)                                                                                   \
+    hipLaunchKernelGGL((k_sweep_batch_lanes<DIM, ORDER, true, L_>), dim3(nb), dim3(64), 0,   \
+                       stream, args, map, w.pvel, done);                                     \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_sweep_batch_lanes<DIM, ORDER, false, L_>), dim3(nb), dim3(64), 0,  \
+                       stream, args, map, w.pvel, done);
+  switch (w.lanes) {
+    case 1: BGK_BL(1) break;
+    case 2: BGK_BL(2) break;
+    case 4: BGK_BL(4) break;
+    case 8: BGK_BL(8) break;
+    case 16: BGK_BL(16) break;
+    default: BGK_BL(32) break;
+  }
+#undef BGK_BL
 }
 
-int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nb2, int nb1,
-                       const int32_t* done, int threads, hipStream_t stream, hipStream_t side,
-                       hipEvent_t fork, hipEvent_t join) {
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const BatchWalk& w,
+                       const int32_t* done, hipStream_t stream, hipStream_t side, hipEvent_t fork,
+                       hipEvent_t join) {
   if (dim == 3) {
-    if (nb1 > 0) launch_batch_kernel<3, 1>(tab, args, map, nb1, done, threads, stream);
+    if (w.nb1 > 0) launch_batch_kernel<3, 1>(tab, args, w, true, done, stream);
     BGK_HIP(hipGetLastError());
     return BGK_OK;
   }
-  if (nb2 > 0 && nb1 > 0) {
+  if (w.nb2 > 0 && w.nb1 > 0) {
     // P1 instances on the side stream, forked from and joined back to the
     // main stream (under graph capture the two become parallel branches)
     BGK_HIP(hipEventRecord(fork, stream));
     BGK_HIP(hipStreamWaitEvent(side, fork, 0));
-    launch_batch_kernel<2, 1>(tab, args, map + nb2, nb1, done, threads, side);
+    launch_batch_kernel<2, 1>(tab, args, w, true, done, side);
     BGK_HIP(hipGetLastError());
-    launch_batch_kernel<2, 2>(tab, args, map, nb2, done, threads, stream);
+    launch_batch_kernel<2, 2>(tab, args, w, false, done, stream);
     BGK_HIP(hipGetLastError());
     BGK_HIP(hipEventRecord(join, side));
     BGK_HIP(hipStreamWaitEvent(stream, join, 0));
     return BGK_OK;
   }
-  if (nb2 > 0) launch_batch_kernel<2, 2>(tab, args, map, nb2, done, threads, stream);
-  if (nb1 > 0) launch_batch_kernel<2, 1>(tab, args, map + nb2, nb1, done, threads, stream);
+  if (w.nb2 > 0) launch_batch_kernel<2, 2>(tab, args, w, false, done, stream);
+  if (w.nb1 > 0) launch_batch_kernel<2, 1>(tab, args, w, true, done, stream);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

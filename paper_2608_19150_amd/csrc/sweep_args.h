@@ -1,5 +1,7 @@
 // Arguments of the sweep kernels (one instance, one sweep).
 #pragma once
+#include <vector>
+
 #include "internal.h"
 
 namespace bgk {
@@ -35,17 +37,32 @@ struct SweepArgs {
   const int32_t* skip;       // nonzero *skip: the launch does nothing (nullable)
 };
 
-// One batched FP64 sweep: block b sweeps velocity position map[b].y of
-// instance map[b].x with args[map[b].x], unless done[map[b].x].  The map
-// holds the blocks of P2 instances first (nb2 of them), then those of P1
-// instances (nb1; every 3D instance is P1); in 2D with both present the two
-// kernels run concurrently, the P1 one on `side` between the events fork
-// (recorded on stream) and join (recorded on side, waited for on stream).
-int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const int2* map, int nb2, int nb1,
-                       const int32_t* done, int threads, hipStream_t stream, hipStream_t side,
-                       hipEvent_t fork, hipEvent_t join);
+// The walk of a batched FP64 sweep.  lanes == 64: the workgroup walk, block
+// b sweeping velocity position map[b].y of instance map[b].x with `threads`
+// per workgroup.  lanes < 64: the packed walk, 64-lane block b serving the
+// 64/lanes velocities pvel[map[b].y ..] (-1: none) of instance map[b].x.
+// Either map holds the blocks of P2 instances first (nb2 of them), then
+// those of P1 instances (nb1; every 3D instance is P1).
+struct BatchWalk {
+  int threads;
+  int lanes;
+  const int2* map;
+  int nb2, nb1;
+  const int32_t* pvel;
+};
+
+// One batched FP64 sweep; instances with done[i] skip.  In 2D with both
+// element types present the two kernels run concurrently, the P1 one on
+// `side` between the events fork (recorded on stream) and join (recorded on
+// side, waited for on stream).
+int launch_sweep_batch(int dim, bool tab, const SweepArgs* args, const BatchWalk& w,
+                       const int32_t* done, hipStream_t stream, hipStream_t side, hipEvent_t fork,
+                       hipEvent_t join);
 SweepArgs make_sweep_args(const tgs_dag* d, const tgs_sweep_io* io,
                           const double* mtab, float* d32);
+// the DAG's velocities sorted by direction (dag.hip): angular neighbours
+// adjacent, the order the packed walk groups them in
+std::vector<int32_t> angular_order(const tgs_dag* d);
 // One single-instance sweep (sweep.hip): the DAG's walk, or the workgroup
 // walk with `threads` per workgroup when threads > 0.  A non-null `skip`
 // turns the launch into a no-op on the device while *skip is nonzero.

@@ -147,10 +147,52 @@ def test_time_sweep_and_autotuner(tmp_path):
     assert os.path.exists(cache)
     best2, _ = autotune.tune_sweep_threads(solvers, fs, cache_path=cache)
     assert best2 == best
+    walk, wms = autotune.tune_batch_walk(solvers, fs, cache_path=cache)
+    assert walk in autotune.BATCH_WALK_CANDIDATES and wms[walk] == min(wms.values())
+    assert all(torch.equal(a, b) for a, b in zip(fs, before))
     batch, t, _ = autotune.autotuned_batch(solvers, fs, cache_path=cache)
-    assert t == best
+    assert t == walk
     st = batch.step(fs)
     assert all(x["status"] == 0 for x in st)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batched_packed_walk_equals_single_instance_steps(dim):
+    """The batch's packed walk (64/L velocities of one instance per 64-lane
+    workgroup) gives the single-instance steps bit for bit, for every L,
+    eager and replayed from graphs."""
+    probs = _instances(dim, seed0=4500, count=4)
+    ref, ref_iters = [], []
+    for pr in probs:
+        s, f = _setup(pr)
+        ref_iters.append([s.step(f)["iters"] for _ in range(2)])
+        ref.append(f.clone())
+        del s
+    for lanes, graph in [(1, False), (2, True), (4, False), (8, True), (16, True), (32, False)]:
+        pairs = [_setup(pr) for pr in probs]
+        fs = [p[1] for p in pairs]
+        batch = B.Batch([p[0] for p in pairs], graph=graph, chunk_iters=3, sweep_lanes=lanes)
+        got = [[] for _ in probs]
+        for _ in range(2):
+            for i, x in enumerate(batch.step(fs)):
+                assert x["status"] == 0
+                got[i].append(x["iters"])
+        assert got == ref_iters, lanes
+        for i in range(len(probs)):
+            assert torch.equal(fs[i], ref[i]), (lanes, graph, i)
+
+
+def test_batch_walk_options_validated():
+    pairs = [_setup(pr) for pr in _instances(2, seed0=4600, count=2)]
+    solvers, fs = [p[0] for p in pairs], [p[1] for p in pairs]
+    for bad in (3, 48, 128, -1):
+        with pytest.raises(B.BGKError) as e:
+            B.Batch(solvers, sweep_lanes=bad)
+        assert e.value.code == B.BGK_E_INVALID
+    probe = B.Batch(solvers, graph=False)
+    with pytest.raises(B.BGKError) as e:
+        probe.time_sweep(fs, 128, lanes=12)
+    assert e.value.code == B.BGK_E_INVALID
 
 
 def _oracle_instance(pr):
