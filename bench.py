@@ -276,11 +276,12 @@ def run_c4(steps, warmup, tune_cache):
             "sequential_single_instance_ms_per_step": 1e3 * seq, "setup_s": setup_s}
 
 
-def run_c3(steps, warmup, kn, gen_stats=False):
+def run_c3(steps, warmup, kn, gen_stats=False, tune=None):
     """3D x 3D: ~55k tetrahedra, P1, 16^3 velocities, backward Euler."""
     import problems as P
     pr = P.config_c3(kn=kn)
-    r = run_gpu(pr, steps, warmup, 0, gen_stats=gen_stats, tune=gen_stats)
+    r = run_gpu(pr, steps, warmup, 0, gen_stats=gen_stats,
+                tune=gen_stats if tune is None else tune)
     sweep_s = r["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r["n_unknown"] / sweep_s / 1e9
     out = {"workload": pr.name, "kn": kn, "unknowns": r["n_unknown"],
@@ -719,11 +720,17 @@ SWEEP_KERNEL = "k_sweep<2, 2, false, true, true>"
 
 
 def sweep_source_digest():
+    """SHA-256 of the sweep's sources with comments and blank lines removed
+    (a change to a comment leaves the counters valid)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for path in SWEEP_SOURCES:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n")]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()
 
 
@@ -760,6 +767,9 @@ def main():
     ap.add_argument("--n-side", type=int, default=316,
                     help="mesh lattice size (2*n^2 triangles; 316 -> 199,712)")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the DAGs' default sweep walks (no walk autotuning), e.g. under a "
+                         "profiler, where the tuner's trial sweeps would mix into the averages")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-velocities", type=int, default=64)
     ap.add_argument("--no-c1", action="store_true", help="skip the small 2D case end to end")
@@ -825,7 +835,7 @@ def main():
     torch.cuda.set_device(0)
     pr = P.config_c2(args.n_side)
     print(f"[bench] workload {pr.name}: building", file=sys.stderr, flush=True)
-    r64 = run_gpu(pr, args.steps, args.warmup, 0, gen_stats=True, tune=True)
+    r64 = run_gpu(pr, args.steps, args.warmup, 0, gen_stats=True, tune=not args.no_tune)
     print(f"[bench] fp64 {r64['value']:.3e} unknowns/s, {r64['ms_per_step']:.1f} ms/step, "
           f"iters {r64['iters']}", file=sys.stderr, flush=True)
     fp32 = None
@@ -877,7 +887,8 @@ def main():
         for kn in [float(x) for x in args.c3_kn.split(",")]:
             st_, wu = runs.get(kn, (2, 1))
             c3[f"kn{kn:g}"] = section(
-                f"c3 kn={kn:g}", lambda: run_c3(st_, wu, kn, gen_stats=(kn == 1e-2)),
+                f"c3 kn={kn:g}", lambda: run_c3(st_, wu, kn, gen_stats=(kn == 1e-2),
+                                                 tune=(kn == 1e-2 and not args.no_tune)),
                 lambda c: f"{c['value']:.3e} unknowns/s, {c['ms_per_step']:.1f} ms/step, "
                           f"iters {c['picard_iters']}, sweep {c['kernel_ms']['sweep']:.2f} ms, "
                           f"G {c['max_generations']}")

@@ -1057,11 +1057,12 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {
-    // P1 triangles: 256 threads.  P2 triangles and tetrahedra (168 VGPRs):
-    // 128 threads, measured fastest on 200k P2 triangles x 1024 velocities
-    // (20.8 ms against 25.6 ms at 192 and 25.3 ms at 256) and on par on 55k
-    // tetrahedra x 4096 velocities; smaller workgroups keep more velocities
-    // per CU resident, and wider generations take a second pass
+    // P1 triangles: 256 threads.  P2 triangles and tetrahedra: 128 threads,
+    // the fastest measured on 200k P2 triangles x 1024 velocities (14.1 ms
+    // against 15.8 at 64, 15.5 at 192 and 14.8 at 256 threads) and on 55k
+    // tetrahedra x 4096 velocities (15.9 ms against 17.6, 16.9 and 16.5);
+    // smaller workgroups keep more velocities per CU resident, and wider
+    // generations take a second pass
     const bool small = d->dim == 2 && d->order == 1;
     threads = small ? 256 : 128;
   }
