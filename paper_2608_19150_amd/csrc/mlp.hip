@@ -2,17 +2,22 @@
 // (GELU hidden layers) run on BF16 MFMA with FP32 accumulation, trained on
 // the GPU with back-propagation and Adam on FP32 master weights.
 //
-// Matrix products use v_mfma_f32_16x16x16bf16_1k on 16-row tiles (one tile
-// per wavefront).  Operand fragments, lane l of 64:
-//   A (16 x 16, M x K): A[l % 16][4*(l/16) + i], i = 0..3
-//   B (16 x 16, K x N): B[4*(l/16) + i][l % 16]
-//   D (16 x 16, M x N): D[4*(l/16) + i][l % 16]
+// Matrix products run on 16-row tiles (one tile per wavefront).  Products
+// over the 64 hidden features use gfx950's v_mfma_f32_16x16x32_bf16 (two
+// K-steps of 32); those over 16 (the padded inputs, the padded outputs in
+// back-propagation, and the 16 rows of a tile in the weight gradients) use
+// v_mfma_f32_16x16x16bf16_1k.  Operand fragments, lane l of 64, q = l / 16:
+//   K = 32: A[l % 16][8q + i], B[8q + i][l % 16], i = 0..7
+//   K = 16: A[l % 16][4q + i], B[4q + i][l % 16], i = 0..3
+//   D (16 x 16, M x N): D[4q + i][l % 16], i = 0..3
+// (the instruction pairs a lane's i-th A value with the i-th B value of the
+// lanes of its column; any k order used alike by A and B is exact).
 // Weights are kept as FP32 masters in a padded layout (inputs 11 -> 16,
 // outputs 5 -> 16) and mirrored as BF16 B-operand fragments, both W (forward)
-// and W^T (back-propagation), so each lane reads its 4 values in one load.
-// Activations live in LDS rows padded to 68 bf16 (conflict-free fragment
-// reads).  Weight gradients are written per tile and summed over tiles in a
-// fixed order, so training is bitwise reproducible.
+// and W^T (back-propagation), so each lane reads its values in one load.
+// Activations live in LDS rows padded to 72 bf16 (16-byte aligned rows for
+// the 8-value fragment reads).  Weight gradients are written per tile and
+// summed over tiles in a fixed order, so training is bitwise reproducible.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,6 +29,7 @@ namespace bgk {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int NI = 11, NO = 5, HD = 64, K1 = 16, N4 = 16;
@@ -33,7 +39,7 @@ constexpr int OW1 = 0, OB1 = OW1 + K1 * HD, OW2 = OB1 + HD, OB2 = OW2 + HD * HD,
 // BF16 fragment buffer: forward W1, W2, W3, W4 then transposed W2, W3, W4
 constexpr int FW1 = 0, FW2 = FW1 + K1 * HD, FW3 = FW2 + HD * HD, FW4 = FW3 + HD * HD,
               TW2 = FW4 + HD * N4, TW3 = TW2 + HD * HD, TW4 = TW3 + HD * HD, NFRAG = TW4 + N4 * HD;
-constexpr int AST = 68;            // LDS row stride of activations (bf16)
+constexpr int AST = 72;            // LDS row stride of activations (bf16, 16-byte rows)
 constexpr int MLP_THREADS = 256;   // 4 wavefronts, one 16-row tile each
 constexpr int GRAD_BLOCKS = 1024;  // gradient launches: one accumulator per wavefront
 
@@ -61,18 +67,33 @@ __device__ __forceinline__ float gelu_grad(float z) {
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
-// D (16 x NT*16) = act (16 x KT*16, LDS) * W (fragments)
-template <int KT, int NT>
-__device__ __forceinline__ void mm_act_w(const uint16_t* act, const v4s* __restrict__ wf,
-                                         v4f (&acc)[NT], int lane) {
+// D (16 x NT*16) = act (16 x 16, LDS) * W (K = 16 fragments)
+template <int NT>
+__device__ __forceinline__ void mm_act_w16(const uint16_t* act, const uint16_t* __restrict__ frag,
+                                           v4f (&acc)[NT], int lane) {
+  const v4s* wf = reinterpret_cast<const v4s*>(frag);
+  const v4s a = *reinterpret_cast<const v4s*>(act + (lane % 16) * AST + 4 * (lane / 16));
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma(a, wf[nt * 64 + lane], v4f{0.f, 0.f, 0.f, 0.f});
+}
+
+// D (16 x NT*16) = act (16 x 64, LDS) * W (K = 32 fragments, two K-steps)
+template <int NT>
+__device__ __forceinline__ void mm_act_w64(const uint16_t* act, const uint16_t* __restrict__ frag,
+                                           v4f (&acc)[NT], int lane) {
+  const v8bf* wf = reinterpret_cast<const v8bf*>(frag);
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < KT; ++kt) {
-    const v4s a = *reinterpret_cast<const v4s*>(act + (lane % 16) * AST + kt * 16 + 4 * (lane / 16));
+  for (int kt = 0; kt < 2; ++kt) {
+    const v8bf a =
+        *reinterpret_cast<const v8bf*>(act + (lane % 16) * AST + kt * 32 + 8 * (lane / 16));
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma(a, wf[(kt * NT + nt) * 64 + lane], acc[nt]);
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma32(a, wf[(kt * NT + nt) * 64 + lane], acc[nt]);
   }
 }
 
@@ -99,7 +120,7 @@ __device__ __forceinline__ void mm_hT_g(const uint16_t* h, const uint16_t* g, in
 
 struct MlpArgs {
   const float* master;    // [NPAD]
-  const v4s* frag;        // [NFRAG/4]
+  const uint16_t* frag;   // [NFRAG] BF16 fragments
   const float* stats;     // mean_in[11], std_in[11], mean_out[5], std_out[5]
 };
 
@@ -128,14 +149,14 @@ __device__ __forceinline__ void hidden_epilogue(v4f (&acc)[4], const float* __re
 // (column = lane % 16).
 __device__ __forceinline__ v4f forward_tile(const MlpArgs& m, uint16_t* act, v4f (&z)[3][4],
                                             int lane) {
-  mm_act_w<1, 4>(act, m.frag + FW1 / 4, z[0], lane);
+  mm_act_w16<4>(act, m.frag + FW1, z[0], lane);
   hidden_epilogue(z[0], m.master + OB1, act + 16 * AST, lane);
-  mm_act_w<4, 4>(act + 16 * AST, m.frag + FW2 / 4, z[1], lane);
+  mm_act_w64<4>(act + 16 * AST, m.frag + FW2, z[1], lane);
   hidden_epilogue(z[1], m.master + OB2, act + 32 * AST, lane);
-  mm_act_w<4, 4>(act + 32 * AST, m.frag + FW3 / 4, z[2], lane);
+  mm_act_w64<4>(act + 32 * AST, m.frag + FW3, z[2], lane);
   hidden_epilogue(z[2], m.master + OB3, act + 48 * AST, lane);
   v4f out[1];
-  mm_act_w<4, 1>(act + 48 * AST, m.frag + FW4 / 4, out, lane);
+  mm_act_w64<1>(act + 48 * AST, m.frag + FW4, out, lane);
   const float b4 = m.master[OB4 + lane % 16];
   return out[0] + v4f{b4, b4, b4, b4};
 }
@@ -238,9 +259,9 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpArgs m, const float* __restr
       const int lay = 2 - L;  // hidden layer index of z (0-based)
       v4f dh[4];
       if (L == 0)
-        mm_act_w<1, 4>(g, m.frag + TW4 / 4, dh, lane);
+        mm_act_w16<4>(g, m.frag + TW4, dh, lane);
       else
-        mm_act_w<4, 4>(g, m.frag + (L == 1 ? TW3 : TW2) / 4, dh, lane);
+        mm_act_w64<4>(g, m.frag + (L == 1 ? TW3 : TW2), dh, lane);
       wave_sync();  // every lane has read g before it is overwritten
       const int obias = L == 0 ? OB3 : (L == 1 ? OB2 : OB1);
 #pragma unroll
@@ -325,11 +346,13 @@ __global__ void k_mlp_frag(const float* __restrict__ w, uint16_t* __restrict__ f
   else if (e < TW3) { base = TW2; K = HD; N = HD; ow = OW2; trans = true; }
   else if (e < TW4) { base = TW3; K = HD; N = HD; ow = OW3; trans = true; }
   else { base = TW4; K = N4; N = HD; ow = OW4; trans = true; }
+  // K = 64 layers: 8-value fragments of 32-deep K-steps; K = 16: 4-value
   const int loc = e - base;
-  const int i = loc % 4, lane = (loc / 4) % 64, tileidx = loc / 256;
+  const int V = K == HD ? 8 : 4;
+  const int i = loc % V, lane = (loc / V) % 64, tileidx = loc / (64 * V);
   const int NT = N / 16;
   const int kt = tileidx / NT, nt = tileidx % NT;
-  const int k = kt * 16 + 4 * (lane / 16) + i, nn = nt * 16 + lane % 16;
+  const int k = kt * 4 * V + V * (lane / 16) + i, nn = nt * 16 + lane % 16;
   // B operand value B[k][nn]: forward W[k][nn]; transposed W^T[k][nn] = W[nn][k]
   // (W stored [fan_in][fan_out] with row length N_out of that layer)
   float val;
@@ -535,7 +558,7 @@ int mlp_sync(bgk_mlp* m, hipStream_t s) {
   return BGK_OK;
 }
 MlpArgs margs(const bgk_mlp* m) {
-  return MlpArgs{m->master, reinterpret_cast<const v4s*>(m->frag), m->stats};
+  return MlpArgs{m->master, m->frag, m->stats};
 }
 int grid_tiles(int64_t ntiles) { return (int)std::max<int64_t>(1, std::min<int64_t>((ntiles + 3) / 4, 4096)); }
 }  // namespace
