@@ -243,7 +243,8 @@ struct GeoLayout {
 // cell's nodes' (E_0, nu) pairs, [n1][n_cells][s0]; then the product of the
 // other axes' factors as one table, [n1^(d-1)][n_cells][s1], row r = the
 // velocity's row-major index over axes 1..d-1 (s0, s1 = 2 n_p and n_p
-// rounded up to a power of 2).  A velocity's Maxwellian is then one
+// rounded up to a power of 2, doubled for P1 tetrahedra so that the padding
+// holds their geometry: TabGeo).  A velocity's Maxwellian is then one
 // multiply of two gathered factors in 2D and 3D alike.
 struct TabLayout {
   int64_t nc;
@@ -253,8 +254,14 @@ struct TabLayout {
     while (p < x) p *= 2;
     return p;
   }
+  __host__ __device__ static constexpr int stride0(int dim, int np) {
+    return dim == 3 && np == 4 ? 16 : pow2(2 * np);
+  }
+  __host__ __device__ static constexpr int stride1(int dim, int np) {
+    return dim == 3 && np == 4 ? 8 : pow2(np);
+  }
   __host__ __device__ TabLayout(int64_t n_cells, int n1_, int np_, int dim)
-      : nc(n_cells), n1(n1_), np(np_), s0(pow2(2 * np_)), s1(pow2(np_)),
+      : nc(n_cells), n1(n1_), np(np_), s0(stride0(dim, np_)), s1(stride1(dim, np_)),
         nr(dim == 3 ? n1_ * n1_ : n1_) {}
   // first double of cell c's record on row i of part al (0: axis 0, 1: the rest)
   __host__ __device__ int64_t at(int al, int i, int64_t c) const {
@@ -266,16 +273,20 @@ struct TabLayout {
   }
 };
 
-// P2 triangles: the padding of a cell's records carries its geometry, so the
-// sweep's table gathers bring it with no access of their own.  Axis 0's
-// record (16 doubles, 12 used) holds (|det J|-scaled volume, N_0, N_1.x) in
-// its last four doubles, the rest's record (8 doubles, 6 used) N_1.y in
-// double 6; the third facet's area-weighted normal is -(N_0 + N_1), the
-// normals of a closed triangle summing to zero.
+// P2 triangles and P1 tetrahedra: the padding of a cell's records carries its
+// geometry (volume and the area-weighted normals of all facets but the
+// last), so the sweep's table gathers bring it with no access of their own;
+// the last facet's normal is minus the sum of the others (the normals of a
+// closed simplex sum to zero).  Geometry doubles 0 .. E0_N-1 sit in axis
+// 0's record from double E0_AT, the next REST_N in the rest's record from
+// double REST_AT.  P2 triangles: records of 16 and 8 doubles (12 and 6
+// used), (volume, N_0, N_1.x) and N_1.y.  P1 tetrahedra: records of 16 and
+// 8 doubles (8 and 4 used), (volume, N_0, N_1, N_2.x) and N_2.yz.
 template <int DIM, int NP>
 struct TabGeo {
-  static constexpr bool ON = DIM == 2 && NP == 6;
-  static constexpr int E0_AT = 12, REST_AT = 6;
+  static constexpr bool ON = (DIM == 2 && NP == 6) || (DIM == 3 && NP == 4);
+  static constexpr int E0_AT = DIM == 2 ? 12 : 8, E0_N = DIM == 2 ? 4 : 8;
+  static constexpr int REST_AT = DIM == 2 ? 6 : 4, REST_N = DIM == 2 ? 1 : 2;
 };
 
 // threads of the table kernels: one per (part, cell, 16-byte chunk of the

@@ -678,7 +678,7 @@ __global__ void k_coef_from_prim(const double* __restrict__ prim, double* __rest
 // a chunk of the rest holds two nodes' entries.  Chunks are numbered
 // through axis 0's records first, then through the rest's.
 // Padding chunk h of cell c's record (axis 0 if first): zeros, or for P2
-// triangles the cell's geometry (TabGeo)
+// triangles and P1 tetrahedra the cell's geometry (TabGeo)
 template <int DIM>
 __device__ __forceinline__ double2 pad_chunk(const double* __restrict__ geo, int np, bool first,
                                              int h, int64_t c) {
@@ -686,6 +686,11 @@ __device__ __forceinline__ double2 pad_chunk(const double* __restrict__ geo, int
     const double* g = geo + c * GeoLayout<2>::STRIDE;
     if (first) return h == 6 ? make_double2(g[0], g[1]) : make_double2(g[2], g[3]);
     return make_double2(g[4], 0.0);
+  }
+  if (DIM == 3 && np == 4) {
+    const double* g = geo + c * GeoLayout<3>::STRIDE;
+    if (first) return make_double2(g[2 * (h - 4)], g[2 * (h - 4) + 1]);  // chunks 4..7
+    return h == 2 ? make_double2(g[8], g[9]) : make_double2(0.0, 0.0);
   }
   return make_double2(0.0, 0.0);
 }

@@ -175,6 +175,19 @@ struct Raw {
   double x[NX];
 };
 
+// Geometry taken from the table records (TabGeo): the last facet's
+// area-weighted normal, g[1 + DIM*DIM ..], is minus the sum of the others
+template <int DIM>
+__device__ __forceinline__ void last_normal(double* g) {
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    double s = g[1 + d];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) s += g[1 + k * DIM + d];
+    g[1 + DIM * DIM + d] = -s;
+  }
+}
+
 // Plain loads of the raw inputs of slot s (cell K); nodal arrays in the
 // internal cell order (no node map)
 template <int DIM, int ORDER, bool TAB>
@@ -194,7 +207,7 @@ __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s,
   for (int b = 0; b < NP; ++b) R.q[b] = q[b];
   const size_t u = (size_t)K;
   if constexpr (TAB) {
-    constexpr int S0 = TabLayout::pow2(2 * NP), S1 = TabLayout::pow2(NP);
+    constexpr int S0 = TabLayout::stride0(DIM, NP), S1 = TabLayout::stride1(DIM, NP);
     const double* __restrict__ e0 = mrow[0] + u * S0;
 #pragma unroll
     for (int b = 0; b < RW::NM; ++b) R.m[b] = e0[b];
@@ -203,8 +216,9 @@ __device__ __forceinline__ void load_raw(const SweepArgs& a, size_t base, int s,
     if constexpr (TG) {
       using T = TabGeo<DIM, NP>;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) R.g[i] = e0[T::E0_AT + i];
-      R.g[4] = mrow[1][u * S1 + T::REST_AT];
+      for (int i = 0; i < T::E0_N; ++i) R.g[i] = e0[T::E0_AT + i];
+#pragma unroll
+      for (int i = 0; i < T::REST_N; ++i) R.g[T::E0_N + i] = mrow[1][u * S1 + T::REST_AT + i];
     }
   } else {
 #pragma unroll
@@ -225,10 +239,7 @@ __device__ __forceinline__ void compute_prep(const SweepArgs& a, const double* v
   double g[RW::NG];
 #pragma unroll
   for (int i = 0; i < RW::NG; ++i) g[i] = R.g[i];
-  if constexpr (TAB && TabGeo<DIM, NP>::ON) {
-    g[5] = -(g[1] + g[3]);
-    g[6] = -(g[2] + g[4]);
-  }
+  if constexpr (TAB && TabGeo<DIM, NP>::ON) last_normal<DIM>(g);
   P.vol = g[0];
   double raw[NF];
   facet_flux_raw<DIM>(g, v, v2, P.fl, raw);
@@ -260,12 +271,13 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
   double gk[NG];
   if constexpr (TAB && TabGeo<DIM, NP>::ON) {
     using T = TabGeo<DIM, NP>;
-    const double* __restrict__ e0 = mrow[0] + u * TabLayout::pow2(2 * NP);
+    const double* __restrict__ e0 = mrow[0] + u * TabLayout::stride0(DIM, NP);
+    const double* __restrict__ er = mrow[1] + u * TabLayout::stride1(DIM, NP);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) gk[i] = e0[T::E0_AT + i];
-    gk[4] = mrow[1][u * TabLayout::pow2(NP) + T::REST_AT];
-    gk[5] = -(gk[1] + gk[3]);
-    gk[6] = -(gk[2] + gk[4]);
+    for (int i = 0; i < T::E0_N; ++i) gk[i] = e0[T::E0_AT + i];
+#pragma unroll
+    for (int i = 0; i < T::REST_N; ++i) gk[T::E0_N + i] = er[T::REST_AT + i];
+    last_normal<DIM>(gk);
   } else {
     const double* __restrict__ g = a.geo + (size_t)P.K * GeoLayout<DIM>::STRIDE;
 #pragma unroll
@@ -282,7 +294,7 @@ __device__ __forceinline__ void prepare(const SweepArgs& a, const double* v, dou
   if constexpr (TAB) {
     // tensor grid: M = E_0[i_0][node] * E_rest[i_1..i_{d-1}][node]; the
     // first factor is stored interleaved with nu, so one gather brings both
-    constexpr int S0 = TabLayout::pow2(2 * NP), S1 = TabLayout::pow2(NP);
+    constexpr int S0 = TabLayout::stride0(DIM, NP), S1 = TabLayout::stride1(DIM, NP);
     const double* __restrict__ e0 = mrow[0] + u * S0;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
