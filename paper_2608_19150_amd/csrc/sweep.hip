@@ -104,8 +104,10 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Unpivoted LU in place: the multipliers below the diagonal, the
+// reciprocal pivots on it, U above it.
 template <int N, typename T>
-__device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
+__device__ __forceinline__ void lu_factor(T (&A)[N][N]) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const T inv = recip(A[k][k]);
@@ -114,10 +116,19 @@ __device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
       const T l = A[i][k] * inv;
 #pragma unroll
       for (int c = k + 1; c < N; ++c) A[i][c] = fma(-l, A[k][c], A[i][c]);
-      b[i] = fma(-l, b[k], b[i]);
+      A[i][k] = l;
     }
     A[k][k] = inv;
   }
+}
+
+// Solves with lu_factor's result: forward elimination, back substitution
+template <int N, typename T>
+__device__ __forceinline__ void lu_apply(const T (&A)[N][N], T (&b)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) b[i] = fma(-A[i][k], b[k], b[i]);
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     T s = b[i];
@@ -125,6 +136,12 @@ __device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
     for (int c = i + 1; c < N; ++c) s = fma(-A[i][c], b[c], s);
     b[i] = s * A[i][i];
   }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void lu_solve(T (&A)[N][N], T (&b)[N]) {
+  lu_factor<N, T>(A);
+  lu_apply<N, T>(A, b);
 }
 
 // A cell prepared for its solve: everything but the upwind values.
@@ -464,8 +481,9 @@ __device__ __forceinline__ void solve64_fetched(const Prep<DIM, ORDER>& P, doubl
   constexpr int NP = S::NP, NF = S::NF, NFP = S::NFP;
   double A[NP][NP];
   assemble<DIM, ORDER>(P, A, rhs);
-  // keep the assembly ahead of the first use of the upwind values: the waits
-  // for their loads then come after it
+  // the matrix does not depend on the upwind values: assemble and factor it
+  // ahead of their first use, so the waits for their loads come after it
+  lu_factor<NP, double>(A);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
@@ -481,7 +499,7 @@ __device__ __forceinline__ void solve64_fetched(const Prep<DIM, ORDER>& P, doubl
       rhs[ra] = fma(inflow, r, rhs[ra]);
     }
   }
-  lu_solve<NP, double>(A, rhs);
+  lu_apply<NP, double>(A, rhs);
   if constexpr (RING) {
     double* rg = ring + (P.s & rmask) * NP;
 #pragma unroll
