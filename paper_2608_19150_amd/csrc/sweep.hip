@@ -852,12 +852,13 @@ __device__ __forceinline__ void sweep_velocity(
   }
 }
 
-// Register budget: P1 triangles fit 4 waves per SIMD; P2 triangles and
-// tetrahedra get 2 (up to 256 VGPRs, no spills): a sweep has at most a few
-// velocities per CU resident anyway, and the spill-free kernel is faster
-// (200k P2 triangles x 1024 velocities: 17.6 ms against 20.1 ms at 3).
+// Register budget: the plain P1-triangle walk fits 4 waves per SIMD; the
+// pipelined walks and the other plain walks get 2 (up to 256 VGPRs, no
+// spills): a sweep has at most a few velocities per CU resident anyway, and
+// the spill-free kernel is faster (200k P2 triangles x 1024 velocities:
+// 17.6 ms against 20.1 ms at 3, on the plain walk).
 template <int DIM, int ORDER, bool F32, bool TAB, bool PIPE>
-__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1) ? 4 : 2) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(256, (DIM == 2 && ORDER == 1 && !PIPE) ? 4 : 2) void k_sweep(SweepArgs a) {
   constexpr int RS = SweepCfg<DIM, ORDER>::RS, NP = SweepCfg<DIM, ORDER>::NP;
   using RT = typename std::conditional<F32, float, double>::type;
   __shared__ RT ring[RS * NP];
@@ -1087,14 +1088,15 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
   const bool fp32 = io->precision == TGS_FP32_CORRECTION;
   if (threads <= 0) threads = d->sweep_threads;
   if (threads <= 0) {
-    // P1 triangles: 256 threads.  P2 triangles and tetrahedra: 128 threads,
-    // the fastest measured on 200k P2 triangles x 1024 velocities (14.1 ms
-    // against 15.8 at 64, 15.5 at 192 and 14.8 at 256 threads) and on 55k
-    // tetrahedra x 4096 velocities (15.9 ms against 17.6, 16.9 and 16.5);
-    // smaller workgroups keep more velocities per CU resident, and wider
-    // generations take a second pass
-    const bool small = d->dim == 2 && d->order == 1;
-    threads = small ? 256 : 128;
+    // 128 threads: the fastest measured on 200k P2 triangles x 1024
+    // velocities (14.1 ms against 15.8 at 64, 15.5 at 192 and 14.8 at 256
+    // threads), on 55k tetrahedra x 4096 velocities (15.9 ms against 17.6,
+    // 16.9 and 16.5) and, pipelined, on 200k P1 triangles x 1024 velocities
+    // (10.42 ms against 10.79, 12.31 and 10.46); smaller workgroups keep
+    // more velocities per CU resident, and wider generations take a second
+    // pass.  The plain P1-triangle walk (FP32 form, node coefficients): 256
+    const bool plain_p1 = d->dim == 2 && d->order == 1 && (fp32 || !mtab);
+    threads = plain_p1 ? 256 : 128;
   }
   if (!fp32 && d->sweep_lanes < 64) {
     SweepArgs ap = a;
@@ -1127,21 +1129,19 @@ int launch_sweep(const tgs_dag* d, const tgs_sweep_io* io, const double* mtab, f
     return BGK_OK;
   }
   const dim3 grid(d->n_v), block(threads);
-  // FP64 sweeps on factorised tables take the pipelined walk (P1 triangles
-  // keep the plain walk: their 4-waves-per-SIMD register budget has no room
-  // for a second cell's inputs; so do sweeps that evaluate the Maxwellian
-  // from node coefficients, whose inputs do not fit twice in registers)
-  const bool pipe = !fp32 && !(d->dim == 2 && d->order == 1);
+  // FP64 sweeps on factorised tables take the pipelined walk (sweeps that
+  // evaluate the Maxwellian from node coefficients keep the plain walk:
+  // their inputs do not fit twice in registers).  P1 triangles run it at
+  // three waves per SIMD (165 registers) instead of the plain walk's four:
+  // 10.5 against 12.4 ms on 200k P1 triangles x 1024 velocities, 0.74
+  // against 0.80 ms per step on the 512-triangle case
 #define BGK_LAUNCH(D_, O_)                                                                 \
   if (fp32 && mtab)                                                                        \
     hipLaunchKernelGGL((k_sweep<D_, O_, true, true, false>), grid, block, 0, stream, a);   \
   else if (fp32)                                                                           \
     hipLaunchKernelGGL((k_sweep<D_, O_, true, false, false>), grid, block, 0, stream, a);  \
-  else if (mtab && pipe)                                                                   \
-    hipLaunchKernelGGL((k_sweep<D_, O_, false, true, (D_ != 2 || O_ != 1)>), grid, block, 0, \
-                       stream, a);                                                         \
   else if (mtab)                                                                           \
-    hipLaunchKernelGGL((k_sweep<D_, O_, false, true, false>), grid, block, 0, stream, a);  \
+    hipLaunchKernelGGL((k_sweep<D_, O_, false, true, true>), grid, block, 0, stream, a);   \
   else                                                                                     \
     hipLaunchKernelGGL((k_sweep<D_, O_, false, false, false>), grid, block, 0, stream, a);
   if (d->dim == 2 && d->order == 1) {
