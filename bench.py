@@ -16,8 +16,10 @@ swept per second over the timed steps = N_c * N_p * N_v * (sweeps) / time.
 Extra JSON fields: the FP32-solve + FP64-refinement form on the same
 workload (its rate, iterations and the moment error against the FP64 run),
 the sweep kernel's roofline (algorithmic 16 B per unknown: read the stage
-source, write the new iterate) from HIP events inside the library, and the
-FP64 CPU oracle's sweep rate on a bounded sample of velocities.  Further
+source, write the new iterate) from HIP events inside the library, against
+the published HBM peak and against a measured device copy, the rates of the
+sweep kernel alone, of whole Picard iterations and of whole steps (`rates`),
+and the FP64 CPU oracle's sweep rate on a bounded sample of velocities.  Further
 sections (each skippable): the 3D workload (c3_3d), batched uneven
 instances (c4_batched), the learned Picard guess (c5_learned_guess), the
 Q2 Gauss-Legendre velocity space with the projected Maxwellian
@@ -698,6 +700,30 @@ def moment_error(U, Uref, dim):
     return errs
 
 
+def copy_bandwidth(gib=4, reps=5):
+    """Device copy bandwidth (GB/s, bytes read + written) of `gib` GiB, timed
+    with HIP events: the faster of the runtime's device-to-device copy and an
+    elementwise kernel (multiply by 1), the practical ceiling beside the
+    published HBM peak."""
+    import torch
+    n = gib * (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    for op in (lambda: dst.copy_(src), lambda: torch.mul(src, 1.0, out=dst)):
+        op()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            op()
+        t1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * n * 8 * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
 def calibrate_copy(mib):
     """A plain device copy of known size (read mib MiB, write mib MiB) for
     scaling the profiler's FETCH_SIZE / WRITE_SIZE counters."""
@@ -842,7 +868,8 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(pr, args.steps, args.warmup, 1)
         fp32 = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "iters": r32["iters"],
-                "sweep_ms_avg": r32["sweep_ms_avg"],
+                "sweep_ms_avg": r32["sweep_ms_avg"], "moments_ms_avg": r32["moments_ms_avg"],
+                "maxwellian_ms_avg": r32["maxwellian_ms_avg"],
                 "moment_err_vs_fp64": moment_error(r32["U"], r64["U"], 2)}
         print(f"[bench] fp32+refine {r32['value']:.3e} unknowns/s, {r32['ms_per_step']:.1f} ms/step",
               file=sys.stderr, flush=True)
@@ -909,6 +936,20 @@ def main():
                                f"{c['heldout_iters_after_first_step']}")
     sweep_s = r64["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r64["n_unknown"] / sweep_s / 1e9
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    def rates(r):
+        # unknowns per second of the sweep kernel alone, of a whole Picard
+        # iteration's kernels (Maxwellian and tables, sweep, moments and norms)
+        # and of whole steps
+        it_ms = r["sweep_ms_avg"] + r["moments_ms_avg"] + r["maxwellian_ms_avg"]
+        return {"sweep_kernel": r64["n_unknown"] / (r["sweep_ms_avg"] * 1e-3),
+                "picard_iteration": r64["n_unknown"] / (it_ms * 1e-3), "step": r["value"]}
+
+    rate = {"fp64": rates(r64)}
+    if fp32:
+        rate["fp32_refine"] = rates(fp32)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pr, args.cpu_velocities, r64["dt"])
@@ -929,8 +970,10 @@ def main():
         "kernel_ms": {"sweep": r64["sweep_ms_avg"], "moments": r64["moments_ms_avg"],
                       "maxwellian": r64["maxwellian_ms_avg"]},
         "fp32_refine": fp32,
+        "rates": rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "kernel": SWEEP_KERNEL,
                      "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},
         "cpu_baseline": cpu,
