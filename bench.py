@@ -111,8 +111,15 @@ def cpu_baseline(pr, n_vel, dt):
         mtimes = pool.map(_oracle_moments, [(j,) for j in js])
         wall = time.perf_counter() - t0
     unknowns = geo.n_cells * geo.n_p * n_vel
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": unknowns / wall, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "extrapolated": True,
+            "cpu_model": model, "host_cpus": len(os.sched_getaffinity(0)), "extrapolated": True,
             "sample": f"FP64 NumPy oracle sweep and moment pass of {n_vel} sampled velocities "
                       f"on the full mesh ({geo.n_cells} cells, P{pr.order}), one velocity per "
                       f"process; {sum(times):.1f} s (sweep) + {sum(mtimes):.2f} s (moments) of "
