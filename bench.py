@@ -943,6 +943,7 @@ def main():
                                f"{c['heldout_iters_after_first_step']}")
     sweep_s = r64["sweep_ms_avg"] * 1e-3
     achieved = SWEEP_BYTES_PER_UNKNOWN * r64["n_unknown"] / sweep_s / 1e9
+    traffic = measured_traffic()
     copy_gbs = copy_bandwidth()
     print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
@@ -979,7 +980,8 @@ def main():
         "fp32_refine": fp32,
         "rates": rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": traffic / sweep_s / 1e9 if traffic else None,
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "kernel": SWEEP_KERNEL,
                      "bytes_per_unknown": SWEEP_BYTES_PER_UNKNOWN},

@@ -902,15 +902,17 @@ int launch_nodal_rows(const tgs_dag* d, const double* src, double* dst, int row,
   return BGK_OK;
 }
 
-// velocity lanes per cell for the moment kernel: enough blocks to fill the chip
-// velocity lanes per cell.  Fewer lanes put more consecutive cells of one
-// velocity in a wavefront (their slots cluster, so the gathers coalesce
-// better); more lanes give more threads on small meshes.  Measured: 3072
-// P1 triangles x 36,864 velocities 1.7 ms at 64 lanes against 2.4 at 16;
-// 10,523 tetrahedra x 110,592 velocities 19.6 ms at 4 against 24.1 at 16
+// Velocity lanes per cell for the moment kernel.  Fewer lanes put more
+// consecutive cells of one velocity in a wavefront (their slots cluster, so
+// the gathers coalesce better); more lanes give more threads, which the
+// kernel needs to keep enough gathers in flight.  Measured: 3072 P1
+// triangles x 36,864 velocities 1.7 ms at 64 lanes against 2.4 at 16;
+// 10,523 tetrahedra x 110,592 velocities 19.6 ms at 4 against 24.1 at 16;
+// 54,651 tetrahedra x 4096 velocities 3.00 ms at 4 against 3.22 at 1 and
+// 3.90 at 16; 199,712 P2 triangles x 1024 velocities 3.43 ms at 4 against
+// 3.68 at 1 and 4.20 at 16
 int moment_vl(const tgs_dag* d) {
   const int64_t nc = d->n_cells;
-  if (nc >= 65536) return 1;
   if (nc >= 16384) return 4;
   if (nc >= 4096) return d->n_v >= 65536 ? 4 : 16;
   return d->n_v < 2048 ? 16 : 64;
