@@ -154,38 +154,6 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments(MomArgs a) {
   moments_block<DIM, NP, VL>(a, blockIdx.x, smem);
 }
 
-// Final reduction of the block pieces in a fixed order; writes
-// out[0..2] = ratios, out[3] = max ratio.
-__device__ __forceinline__ void ratio_block(const double* __restrict__ partial, int nblk,
-                                            double* out, double (*s)[256]) {
-  const int tid = threadIdx.x;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = tid; b < nblk; b += 256)
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] += partial[(size_t)b * 6 + i];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) s[i][tid] = acc[i];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off)
-#pragma unroll
-      for (int i = 0; i < 6; ++i) s[i][tid] += s[i][tid + off];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double n0 = sqrt(s[3][0]);
-    double mx = 0.0;
-    for (int m = 0; m < 3; ++m) {
-      double den = sqrt(s[3 + m][0]);
-      if (m == 1) den = fmax(den, n0);
-      const double r = sqrt(s[m][0]) / den;
-      out[m] = r;
-      mx = fmax(mx, r);
-    }
-    out[3] = mx;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_ratio(const double* __restrict__ partial, int nblk,
                                                double* out, const int32_t* skip) {
   __shared__ double s[6][256];

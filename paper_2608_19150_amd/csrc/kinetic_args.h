@@ -75,6 +75,38 @@ int launch_tables_batch(int dim, const BatchKin* kin, const int32_t* done,
 int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const int32_t* done,
                          const int32_t* blk_first, int n_inst, int n_blocks, bool with_ratio,
                          hipStream_t stream);
+// Final reduction of the block pieces in a fixed order; writes
+// out[0..2] = ratios, out[3] = max ratio.
+__device__ __forceinline__ void ratio_block(const double* __restrict__ partial, int nblk,
+                                            double* out, double (*s)[256]) {
+  const int tid = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < nblk; b += 256)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += partial[(size_t)b * 6 + i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i][tid] = acc[i];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) s[i][tid] += s[i][tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double n0 = sqrt(s[3][0]);
+    double mx = 0.0;
+    for (int m = 0; m < 3; ++m) {
+      double den = sqrt(s[3 + m][0]);
+      if (m == 1) den = fmax(den, n0);
+      const double r = sqrt(s[m][0]) / den;
+      out[m] = r;
+      mx = fmax(mx, r);
+    }
+    out[3] = mx;
+  }
+}
+
 int moment_vl(const tgs_dag* d);
 int moment_blocks(const tgs_dag* d);
 

@@ -95,10 +95,16 @@ __global__ void k_reset(int32_t* status, unsigned long long* numax, const int32_
   }
 }
 
-// control block of the chunked iteration at the start of a stage
-__global__ void k_ctl_init(int32_t* ctl) {
+// control block of the chunked iteration at the start of a stage, and the
+// status words of its first iteration
+__global__ void k_ctl_init(int32_t* ctl, int32_t* status, unsigned long long* numax) {
   if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
-  if (threadIdx.x == 0) reinterpret_cast<double*>(ctl)[4] = 0.0;
+  if (threadIdx.x == 0) {
+    reinterpret_cast<double*>(ctl)[4] = 0.0;
+    status[0] = 0;
+    status[1] = 0;
+    *numax = 0ull;
+  }
 }
 
 // The stopping test of one Picard iteration on the device (the host loop's
@@ -106,18 +112,30 @@ __global__ void k_ctl_init(int32_t* ctl) {
 // fixed_iters the count decides, else the max ratio of eq.
 // convergence-criteria against tau / max(1, max nu dt); l_max iterations
 // without stopping fail).  Once ctl[0] is set, later iterations skip.
-__global__ void k_converge1(int32_t* ctl, const int32_t* __restrict__ status,
-                            const unsigned long long* __restrict__ numax,
-                            const double* __restrict__ ratio, double tau, double dt,
-                            int fixed_iters, int l_max) {
-  if (threadIdx.x != 0 || ctl[0] != 0) return;
+// In the chunked iteration it first reduces the moment kernel's block pieces
+// of the norms into the ratios (as k_ratio does) and afterwards clears the
+// status words for the next iteration (the host loop's k_reset), so an
+// iteration takes two launches fewer.
+__global__ __launch_bounds__(256) void k_ratio_converge(
+    int32_t* ctl, int32_t* __restrict__ status, unsigned long long* __restrict__ numax,
+    const double* __restrict__ partial, int nblk, double* __restrict__ ratio, double tau,
+    double dt, int fixed_iters, int l_max) {
+  __shared__ double s[6][256];
+  if (skip_launch(ctl)) return;
+  ratio_block(partial, nblk, ratio, s);
+  if (threadIdx.x != 0) return;
+  const int32_t st0 = status[0], st1 = status[1];
+  const unsigned long long nmax = *numax;
+  status[0] = 0;
+  status[1] = 0;
+  *numax = 0ull;
   const int it = ctl[1] + 1;
   ctl[1] = it;
-  ctl[2] += status[0];
-  if (status[1] > 0) {
+  ctl[2] += st0;
+  if (st1 > 0) {
     ctl[0] = 2;
     ctl[3] = BGK_E_NONPHYSICAL;
-    ctl[4] = status[1];
+    ctl[4] = st1;
     return;
   }
   const double last = ratio[3];
@@ -133,7 +151,7 @@ __global__ void k_converge1(int32_t* ctl, const int32_t* __restrict__ status,
       return;
     }
   } else {
-    const double nm = __longlong_as_double((long long)numax[0]);
+    const double nm = __longlong_as_double((long long)nmax);
     if (last < tau / fmax(1.0, nm * dt)) {
       ctl[0] = 1;
       return;
@@ -384,6 +402,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         return rc;
     }
     const int K = o.chunk_iters > 1 ? o.chunk_iters : 1;
+    const int nblk = moment_blocks(d);  // block pieces of the norms per moment pass
     // the buffer a Picard iteration writes, given the one it reads: with
     // lagged facets or the FP32 form the previous iterate must survive the
     // sweep, so iterates alternate between the stage's output and fping
@@ -411,7 +430,9 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       const auto enqueue_iter = [&](hipStream_t sm, int uc, const double* prv, double* cur,
                                     const int32_t* skip) -> int {
         int r;
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, sm, s->status, s->numax, skip);
+        // the chunked iteration clears the status words and reduces the
+        // norms in its stopping-test kernel
+        if (!skip) hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, sm, s->status, s->numax, skip);
         if (o.timing) BGK_HIP(hipEventRecord(s->ev[0], sm));
         if ((r = launch_maxwellian(d, o.maxw_mode, s->U[uc], &o.nu_model, s->mcoef, s->nu,
                                    nullptr, s->status, s->numax, s->sticky, sm, skip)))
@@ -436,8 +457,8 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         io.f_out = cur;
         if ((r = launch_sweep(d, &io, s->mtab, s->d32, sm, 0, skip))) return r;
         if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], sm));
-        if ((r = launch_moments(d, cur, s->U[uc ^ 1], s->U[uc], s->partial, s->ratio, sm, false,
-                                skip)))
+        if ((r = launch_moments(d, cur, s->U[uc ^ 1], s->U[uc], s->partial,
+                                skip ? nullptr : s->ratio, sm, false, skip)))
           return r;
         if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], sm));
         return BGK_OK;
@@ -448,8 +469,9 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
           double* cur = next_out(prv, out);
           int r = enqueue_iter(sm, uc, prv, cur, s->ctl);
           if (r) return r;
-          hipLaunchKernelGGL(k_converge1, dim3(1), dim3(64), 0, sm, s->ctl, s->status, s->numax,
-                             s->ratio, o.tau, o.dt, o.fixed_iters, o.l_max);
+          hipLaunchKernelGGL(k_ratio_converge, dim3(1), dim3(256), 0, sm, s->ctl, s->status,
+                             s->numax, s->partial, nblk, s->ratio, o.tau, o.dt, o.fixed_iters,
+                             o.l_max);
           BGK_HIP(hipGetLastError());
           uc ^= 1;
           prv = cur;
@@ -513,7 +535,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
           }
         }
       } else {
-        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, s->ctl);
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, s->ctl, s->status, s->numax);
         BGK_HIP(hipGetLastError());
         int32_t done = 0;
         while (done == 0) {
