@@ -248,9 +248,9 @@ int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev
 /* moments() for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same kernels and results, bit for bit, with no hipMalloc/hipFree or
- * allocating call.  The ratio scratch (6 doubles per moment block, 256
- * cells per block on meshes of 65,536 cells or more, at most 1024 blocks
- * below) lives in a fixed 2 MiB device array per GPU, held until the
+ * allocating call.  The ratio scratch (6 doubles per moment block, 64
+ * cells per block on meshes of 16,384 cells or more, at most 1024 blocks
+ * below) lives in a fixed 8 MiB device array per GPU, held until the
  * process ends and shared by every call on that GPU: calls that overlap on
  * one GPU race on it and must be ordered by the caller (one stream, or
  * events).  Nothing in it needs clearing between calls.  BGK_E_INVALID when

@@ -1125,7 +1125,7 @@ int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const
 // One copy per device, held until the process ends.  Host code never uses
 // the array's name as an address: it takes the device address from
 // hipGetSymbolAddress once per device (noalloc_scratch below).
-constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 18;  // 2 MiB
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 20;  // 8 MiB
 static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
 
 namespace {
