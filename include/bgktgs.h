@@ -248,14 +248,16 @@ int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev
 /* moments() for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same kernels and results, bit for bit, with no hipMalloc/hipFree or
- * allocating call.  The ratio scratch (6 doubles per moment block, 64
- * cells per block on meshes of 16,384 cells or more, at most 1024 blocks
- * below) lives in a fixed 8 MiB device array per GPU, held until the
- * process ends and shared by every call on that GPU: calls that overlap on
- * one GPU race on it and must be ordered by the caller (one stream, or
- * events).  Nothing in it needs clearing between calls.  BGK_E_INVALID when
- * U_prev is given and the mesh needs more scratch than that (about 11
- * million cells); without U_prev no scratch is used. */
+ * allocating call.  The scratch (the chunk sums of a velocity-split moment
+ * pass, at most 2^21 doubles, used on meshes of 4096 to 16,383 cells with
+ * 8192 velocities or more; with U_prev, 6 doubles per moment block, 64
+ * cells per block on meshes of 16,384 cells or more and in split passes,
+ * at most 1024 blocks otherwise) lives in a fixed 32 MiB device array per
+ * GPU, held until the process ends and shared by every call on that GPU:
+ * calls that overlap on one GPU race on it and must be ordered by the
+ * caller (one stream, or events).  Nothing in it needs clearing between calls.  BGK_E_INVALID when
+ * the mesh needs more scratch than that (with U_prev, about 44 million
+ * cells). */
 int moments_noalloc(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
                     double* rel3, bgk_stream_t stream);
 
@@ -423,7 +425,9 @@ int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out
  * once in a hipGraph and replayed until every instance has stopped; the
  * host polls a small control block once per chunk.  Per instance the
  * arithmetic is bgk_step's, so results equal single-instance steps bit for
- * bit.  Requirements: all solvers share the dimension and the tableau, use
+ * bit, except for an instance of 4096 to 16,383 cells with 8192 velocities
+ * or more: bgk_step splits its moment sums over velocity chunks, the batch
+ * does not, and the two agree to rounding.  Requirements: all solvers share the dimension and the tableau, use
  * the FP64 sweep and have acyclic sweep graphs (else BGK_E_UNSUPPORTED).
  * The batch borrows the solvers (and their DAGs): destroy it first. */
 typedef struct bgk_batch bgk_batch;

@@ -29,21 +29,15 @@ struct MomSmem {
   static constexpr int TOTAL = RED + 6 * CB;
 };
 
-// One block of the moment kernel: block `blk` of the instance; `smem` holds
-// MomSmem<DIM, NP, VL>::TOTAL doubles of LDS.
+// Sum over the velocities j0 + lane, j0 + lane + VL, ... below j1, in
+// increasing order, of w_j e(v_j) times cell K's nodal values at its slot of
+// velocity j.  UNR velocities' gathers (pos, then the NP values at that slot)
+// are issued before any is summed, so each lane has UNR independent load
+// chains in flight; the summation order is unchanged.
 template <int DIM, int NP, int VL>
-__device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double* smem) {
-  constexpr int CB = MOM_THREADS / VL, NM = DIM + 2;
-  double* s_red = smem;
-  double* s_norm = smem + MomSmem<DIM, NP, VL>::RED;  // [6][CB]
-  const int tid = threadIdx.x, c = tid % CB, lane = tid / CB;
-  const int K = blk * CB + c;
-  const bool valid = K < a.n_cells;
-  double acc[NP][NM];
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+__device__ __forceinline__ void mom_accumulate(const MomArgs& a, int K, int lane, int j0, int j1,
+                                               double (&acc)[NP][DIM + 2]) {
+  constexpr int NM = DIM + 2;
   // the weights w_j e_m(v_j) of velocity j applied to one cell's nodal values
   auto accumulate = [&](int j, const double* fv) {
     const double wj = a.w[j];
@@ -62,54 +56,67 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
 #pragma unroll
       for (int m = 0; m < NM; ++m) acc[p][m] = fma(e[m], fv[p], acc[p][m]);
   };
-  if (valid) {
-    // UNR velocities' gathers (pos, then the cell's NP values at that slot)
-    // are issued before any is summed, so each lane has UNR independent
-    // load chains in flight; the summation order is unchanged
-    constexpr int UNR = 8;
-    int j = lane;
-    for (; j + (UNR - 1) * VL < a.n_v; j += UNR * VL) {
-      double fv[UNR][NP];
-      size_t slot[UNR];
+  constexpr int UNR = 8;
+  int j = j0 + lane;
+  for (; j + (UNR - 1) * VL < j1; j += UNR * VL) {
+    double fv[UNR][NP];
+    size_t slot[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
-        slot[u] = (size_t)a.pos[(size_t)(j + u * VL) * a.n_cells + K];
+    for (int u = 0; u < UNR; ++u)
+      slot[u] = (size_t)a.pos[(size_t)(j + u * VL) * a.n_cells + K];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const double* fp = a.f + ((size_t)(j + u * VL) * a.n_cells + slot[u]) * NP;
+    for (int u = 0; u < UNR; ++u) {
+      const double* fp = a.f + ((size_t)(j + u * VL) * a.n_cells + slot[u]) * NP;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) fv[u][p] = fp[p];
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) accumulate(j + u * VL, fv[u]);
+      for (int p = 0; p < NP; ++p) fv[u][p] = fp[p];
     }
-    for (; j < a.n_v; j += VL) {
-      const size_t slot = (size_t)a.pos[(size_t)j * a.n_cells + K];
-      const double* fp = a.f + ((size_t)j * a.n_cells + slot) * NP;
-      double fv[NP];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) fv[p] = fp[p];
-      accumulate(j, fv);
-    }
+    for (int u = 0; u < UNR; ++u) accumulate(j + u * VL, fv[u]);
   }
-  if (VL > 1) {
-    if (lane > 0) {
+  for (; j < j1; j += VL) {
+    const size_t slot = (size_t)a.pos[(size_t)j * a.n_cells + K];
+    const double* fp = a.f + ((size_t)j * a.n_cells + slot) * NP;
+    double fv[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) fv[p] = fp[p];
+    accumulate(j, fv);
+  }
+}
+
+// The VL lanes' partial sums of cell c added in lane order through LDS
+// (s_red: (VL - 1) * CB * NP * (DIM + 2) doubles); lane 0 ends with the sum.
+template <int DIM, int NP, int VL, int CB>
+__device__ __forceinline__ void mom_lanes(double* s_red, int c, int lane,
+                                          double (&acc)[NP][DIM + 2]) {
+  constexpr int NM = DIM + 2;
+  if (lane > 0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) s_red[(((lane - 1) * CB + c) * NP + p) * NM + m] = acc[p][m];
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll 1
+    for (int l = 1; l < VL; ++l)
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int m = 0; m < NM; ++m) s_red[(((lane - 1) * CB + c) * NP + p) * NM + m] = acc[p][m];
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll 1
-      for (int l = 1; l < VL; ++l)
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc[p][m] += s_red[(((l - 1) * CB + c) * NP + p) * NM + m];
-    }
+        for (int m = 0; m < NM; ++m) acc[p][m] += s_red[(((l - 1) * CB + c) * NP + p) * NM + m];
   }
-  if (lane == 0) {
+}
+
+// U of the block's CB cells (written by the threads that hold a cell's sum,
+// threadIdx.x < CB) and, with U_prev, the block's piece of the convergence
+// norms, reduced over the CB cells by a fixed-order tree (s_norm: 6 * CB
+// doubles).
+template <int DIM, int NP, int CB>
+__device__ __forceinline__ void mom_finish(const MomArgs& a, int blk, int K, bool valid,
+                                           bool writer, int c, const double (&acc)[NP][DIM + 2],
+                                           double* s_norm) {
+  constexpr int NM = DIM + 2;
+  const int tid = threadIdx.x;
+  if (writer) {
     double nrm[6] = {0, 0, 0, 0, 0, 0};
     if (valid) {
       const size_t u = a.uid ? (size_t)a.uid[K] : (size_t)K;
@@ -122,10 +129,10 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
           const double* Uo = a.U_prev + (u * NP + p) * NM;
 #pragma unroll
           for (int m = 0; m < NM; ++m) {
-            const int blk = m == 0 ? 0 : (m == NM - 1 ? 2 : 1);
+            const int b = m == 0 ? 0 : (m == NM - 1 ? 2 : 1);
             const double dd = acc[p][m] - Uo[m];
-            nrm[blk] = fma(dd, dd, nrm[blk]);
-            nrm[3 + blk] = fma(Uo[m], Uo[m], nrm[3 + blk]);
+            nrm[b] = fma(dd, dd, nrm[b]);
+            nrm[3 + b] = fma(Uo[m], Uo[m], nrm[3 + b]);
           }
         }
       }
@@ -145,6 +152,80 @@ __device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double*
     }
     if (tid < 6) a.partial[(size_t)blk * 6 + tid] = s_norm[tid * CB];
   }
+}
+
+// One block of the moment kernel: block `blk` of the instance; `smem` holds
+// MomSmem<DIM, NP, VL>::TOTAL doubles of LDS.
+template <int DIM, int NP, int VL>
+__device__ __forceinline__ void moments_block(const MomArgs& a, int blk, double* smem) {
+  constexpr int CB = MOM_THREADS / VL, NM = DIM + 2;
+  double* s_red = smem;
+  double* s_norm = smem + MomSmem<DIM, NP, VL>::RED;  // [6][CB]
+  const int tid = threadIdx.x, c = tid % CB, lane = tid / CB;
+  const int K = blk * CB + c;
+  const bool valid = K < a.n_cells;
+  double acc[NP][NM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+  if (valid) mom_accumulate<DIM, NP, VL>(a, K, lane, 0, a.n_v, acc);
+  if (VL > 1) mom_lanes<DIM, NP, VL, CB>(s_red, c, lane, acc);
+  mom_finish<DIM, NP, CB>(a, blk, K, valid, lane == 0, c, acc, s_norm);
+}
+
+// Velocity-split moments for meshes with few cells and many velocities:
+// block (b, v) sums the velocities of chunk v (jc of them, a multiple of
+// the 4 lanes) for the 64 cells of block b, as moments_block does for all
+// velocities, and writes the chunk's sums to split[v][cell]; k_moments_fold
+// then adds the chunks in order and finishes as moments_block does.  The
+// grid holds vb times the blocks, so such meshes still fill the GPU with
+// wavefronts of 64 consecutive cells.
+template <int DIM, int NP>
+__global__ __launch_bounds__(MOM_THREADS) void k_moments_split(MomArgs a) {
+  constexpr int VL = 4, CB = MOM_THREADS / VL, NM = DIM + 2;
+  __shared__ double s_red[(VL - 1) * CB * NP * NM];
+  if (skip_launch(a.skip)) return;
+  const int tid = threadIdx.x, c = tid % CB, lane = tid / CB;
+  const int K = blockIdx.x * CB + c;
+  const int j0 = blockIdx.y * a.jc, j1 = min(a.n_v, j0 + a.jc);
+  double acc[NP][NM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+  if (K < a.n_cells) mom_accumulate<DIM, NP, VL>(a, K, lane, j0, j1, acc);
+  mom_lanes<DIM, NP, VL, CB>(s_red, c, lane, acc);
+  if (lane == 0 && K < a.n_cells) {
+    double* P = a.split + ((size_t)blockIdx.y * a.n_cells + K) * NP * NM;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) P[p * NM + m] = acc[p][m];
+  }
+}
+
+template <int DIM, int NP>
+__global__ __launch_bounds__(64) void k_moments_fold(MomArgs a) {
+  constexpr int CB = 64, NM = DIM + 2;
+  __shared__ double s_norm[6 * CB];
+  if (skip_launch(a.skip)) return;
+  const int c = threadIdx.x, K = blockIdx.x * CB + c;
+  const bool valid = K < a.n_cells;
+  double acc[NP][NM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[p][m] = 0.0;
+  if (valid)
+    for (int v = 0; v < a.vb; ++v) {
+      const double* P = a.split + ((size_t)v * a.n_cells + K) * NP * NM;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[p][m] += P[p * NM + m];
+    }
+  mom_finish<DIM, NP, CB>(a, blockIdx.x, K, valid, true, c, acc, s_norm);
 }
 
 template <int DIM, int NP, int VL>
@@ -892,14 +973,74 @@ int moment_blocks(const tgs_dag* d) {
   return (int)((d->n_cells + cb - 1) / cb);
 }
 
+// Velocity chunks of the split moment reduction (1: none).  Meshes of 4096
+// to 16,383 cells with 8192 velocities or more get enough chunks for about
+// 4096 wavefronts of 64 cells (at least 256 velocities a chunk, at most 64
+// chunks, at most MOM_SPLIT_DOUBLES of chunk sums).  Measured: 10,523
+// tetrahedra x 110,592 velocities 17.6 ms in 7 chunks against 19.7 unsplit;
+// 3072 P1 triangles x 36,864 velocities 1.84 ms in 22 chunks against 1.75
+// unsplit at 64 lanes per cell, so smaller meshes stay unsplit.
+int moment_split(const tgs_dag* d) {
+  const int64_t nc = d->n_cells;
+  if (nc < 4096 || nc >= 16384 || d->n_v < 8192) return 1;
+  const int64_t blocks = (nc + 63) / 64;
+  int64_t vb = (4096 + blocks * 4 - 1) / (blocks * 4);
+  vb = std::min<int64_t>(vb, d->n_v / 256);
+  vb = std::min<int64_t>(vb, 64);
+  vb = std::min<int64_t>(vb, MOM_SPLIT_DOUBLES / (d->n_nodes * (d->dim + 2)));
+  return vb < 2 ? 1 : (int)vb;
+}
+
+// velocities per chunk (a multiple of the 4 lanes) and the chunk count
+static void split_chunks(const tgs_dag* d, int vb, int* jc, int* nchunks) {
+  int c = (d->n_v + vb - 1) / vb;
+  c = (c + 3) / 4 * 4;
+  *jc = c;
+  *nchunks = (d->n_v + c - 1) / c;
+}
+
+int64_t moment_split_doubles(const tgs_dag* d) {
+  const int vb = moment_split(d);
+  if (vb < 2) return 0;
+  int jc, nch;
+  split_chunks(d, vb, &jc, &nch);
+  return (int64_t)nch * d->n_nodes * (d->dim + 2);
+}
+
+int moment_partials(const tgs_dag* d) {
+  return moment_split(d) > 1 ? (int)((d->n_cells + 63) / 64) : moment_blocks(d);
+}
+
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                    double* partial, double* ratio_out, hipStream_t stream, bool user_order,
-                   const int32_t* skip) {
+                   double* split, const int32_t* skip) {
   MomArgs a{f,      d->d_pos, user_order ? d->d_uid : nullptr, d->d_v, d->d_w, U, U_prev, partial,
             (int)d->n_cells, d->n_v, skip};
-  const int vl = moment_vl(d);
-  const int nblk = moment_blocks(d);
-  const dim3 grid((unsigned)nblk), block(MOM_THREADS);
+  const int vb = moment_split(d);
+  const int nblk = moment_partials(d);
+  if (vb > 1) {
+    BGK_CHECK(split != nullptr, BGK_E_INVALID, "split moment reduction without its scratch");
+    int jc, nch;
+    split_chunks(d, vb, &jc, &nch);
+    a.split = split;
+    a.jc = jc;
+    a.vb = nch;
+    const dim3 grid((unsigned)nblk, (unsigned)nch), block(MOM_THREADS);
+#define BGK_MOMS(D_, P_)                                                                    \
+  do {                                                                                      \
+    hipLaunchKernelGGL((k_moments_split<D_, P_>), grid, block, 0, stream, a);             \
+    hipLaunchKernelGGL((k_moments_fold<D_, P_>), dim3((unsigned)nblk), dim3(64), 0, stream, a); \
+  } while (0)
+    if (d->dim == 2 && d->order == 1)
+      BGK_MOMS(2, 3);
+    else if (d->dim == 2)
+      BGK_MOMS(2, 6);
+    else
+      BGK_MOMS(3, 4);
+#undef BGK_MOMS
+  } else {
+    const int vl = moment_vl(d);
+    const dim3 grid((unsigned)nblk), block(MOM_THREADS);
 #define BGK_MOM(D_, P_)                                                                         \
   do {                                                                                          \
     if (vl == 1) hipLaunchKernelGGL((k_moments<D_, P_, 1>), grid, block, 0, stream, a);   \
@@ -907,13 +1048,14 @@ int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U
     else if (vl == 16) hipLaunchKernelGGL((k_moments<D_, P_, 16>), grid, block, 0, stream, a); \
     else hipLaunchKernelGGL((k_moments<D_, P_, 64>), grid, block, 0, stream, a);          \
   } while (0)
-  if (d->dim == 2 && d->order == 1)
-    BGK_MOM(2, 3);
-  else if (d->dim == 2)
-    BGK_MOM(2, 6);
-  else
-    BGK_MOM(3, 4);
+    if (d->dim == 2 && d->order == 1)
+      BGK_MOM(2, 3);
+    else if (d->dim == 2)
+      BGK_MOM(2, 6);
+    else
+      BGK_MOM(3, 4);
 #undef BGK_MOM
+  }
   BGK_HIP(hipGetLastError());
   if (U_prev && ratio_out) {
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, stream, partial, nblk, ratio_out, skip);
@@ -1121,11 +1263,12 @@ int launch_moments_batch(int dim, const BatchKin* kin, const int32_t* par, const
 }
 
 // Scratch of the allocation-free moments entry point (moments_noalloc):
-// the per-block partial norms of the convergence ratios, then the ratios.
+// the chunk sums of a velocity-split moment pass, the per-block partial
+// norms of the convergence ratios, then the ratios.
 // One copy per device, held until the process ends.  Host code never uses
 // the array's name as an address: it takes the device address from
 // hipGetSymbolAddress once per device (noalloc_scratch below).
-constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 20;  // 8 MiB
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 22;  // 32 MiB
 static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
 
 namespace {
@@ -1163,20 +1306,29 @@ extern "C" int moments(const tgs_dag* d, const double* f, double* U, const doubl
       return fail(BGK_E_INVALID, "U_prev and rel3 go together");
     double* partial = nullptr;
     double* ratio = nullptr;
+    double* split = nullptr;
     hipStream_t s = (hipStream_t)stream;
-    if (U_prev) {
-      if (hipMallocAsync((void**)&partial, (size_t)moment_blocks(d) * 6 * sizeof(double), s) !=
+    const auto release = [&]() {
+      if (partial) (void)hipFreeAsync(partial, s);
+      if (ratio) (void)hipFreeAsync(ratio, s);
+      if (split) (void)hipFreeAsync(split, s);
+    };
+    const int64_t nsplit = moment_split_doubles(d);
+    if ((U_prev &&
+         (hipMallocAsync((void**)&partial, (size_t)moment_partials(d) * 6 * sizeof(double), s) !=
               hipSuccess ||
-          hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)
-        return fail(BGK_E_NOMEM, "scratch allocation failed");
+          hipMallocAsync((void**)&ratio, 4 * sizeof(double), s) != hipSuccess)) ||
+        (nsplit > 0 &&
+         hipMallocAsync((void**)&split, (size_t)nsplit * sizeof(double), s) != hipSuccess)) {
+      release();
+      return fail(BGK_E_NOMEM, "scratch allocation failed");
     }
-    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
+    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true, split);
     if (rc == BGK_OK && U_prev) {
       if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
         rc = fail(BGK_E_HIP, "copy of ratios failed");
     }
-    if (partial) (void)hipFreeAsync(partial, s);
-    if (ratio) (void)hipFreeAsync(ratio, s);
+    release();
     return rc;
   });
 }
@@ -1190,24 +1342,31 @@ extern "C" int moments_noalloc(const tgs_dag* d, const double* f, double* U,
     hipStream_t s = (hipStream_t)stream;
     double* partial = nullptr;
     double* ratio = nullptr;
-    if (U_prev) {
-      // partial norms: 6 per moment block; the ratios after them, 256-byte aligned
-      const int64_t need = (int64_t)moment_blocks(d) * 6;
-      const int64_t at = (need + 31) / 32 * 32;
-      if (at + 4 > NOALLOC_SCRATCH_DOUBLES)
-        return fail(BGK_E_INVALID,
-                    "moments_noalloc: the mesh needs " + std::to_string(at + 4) +
-                        " doubles of ratio scratch, above the fixed " +
-                        std::to_string(NOALLOC_SCRATCH_DOUBLES) + " (use moments)");
+    double* split = nullptr;
+    // the scratch, each part 256-byte aligned: the chunk sums of a
+    // velocity-split pass, the partial norms (6 per piece), the ratios
+    const int64_t nsplit = moment_split_doubles(d);
+    const int64_t at_part = (nsplit + 31) / 32 * 32;
+    const int64_t need = U_prev ? (int64_t)moment_partials(d) * 6 : 0;
+    const int64_t at_ratio = at_part + (need + 31) / 32 * 32;
+    const int64_t total = at_ratio + (U_prev ? 4 : 0);
+    if (total > NOALLOC_SCRATCH_DOUBLES)
+      return fail(BGK_E_INVALID, "moments_noalloc: the mesh needs " + std::to_string(total) +
+                                     " doubles of scratch, above the fixed " +
+                                     std::to_string(NOALLOC_SCRATCH_DOUBLES) + " (use moments)");
+    if (total > 0) {
       double* base = nullptr;
       int rc = noalloc_scratch(&base);
       if (rc) return rc;
-      partial = base;
-      ratio = base + at;
+      if (nsplit > 0) split = base;
+      if (U_prev) {
+        partial = base + at_part;
+        ratio = base + at_ratio;
+      }
     }
-    // every block writes its own 6 partial norms before k_ratio reads them:
+    // every chunk sum and every partial norm is written before it is read:
     // nothing in the scratch needs clearing
-    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true);
+    int rc = launch_moments(d, f, U, U_prev, partial, ratio, s, true, split);
     if (rc == BGK_OK && U_prev) {
       if (hipMemcpyAsync(rel3, ratio, 3 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
         rc = fail(BGK_E_HIP, "copy of ratios failed");

@@ -18,6 +18,9 @@ struct MomArgs {
   int n_cells;
   int n_v;
   const int32_t* skip;  // nonzero *skip: the launch does nothing (nullable)
+  double* split;        // velocity-split reduction: chunk sums [vb][cell][node][m]
+  int jc;               // velocities per chunk
+  int vb;               // chunks
 };
 
 struct MaxwArgs {
@@ -108,13 +111,24 @@ __device__ __forceinline__ void ratio_block(const double* __restrict__ partial, 
 }
 
 int moment_vl(const tgs_dag* d);
-int moment_blocks(const tgs_dag* d);
+int moment_blocks(const tgs_dag* d);  // blocks of the unsplit kernel (the batch's)
+
+// The single-instance moment pass of a mesh with few cells and many velocities
+// splits the velocities into chunks (moment_split > 1): its chunk sums take
+// moment_split_doubles doubles of scratch (at most MOM_SPLIT_DOUBLES), and its
+// norms come in moment_partials pieces (moment_blocks without the split).
+constexpr int64_t MOM_SPLIT_DOUBLES = (int64_t)1 << 21;
+int moment_split(const tgs_dag* d);
+int64_t moment_split_doubles(const tgs_dag* d);
+int moment_partials(const tgs_dag* d);
 
 // Single-instance launchers (kinetic.hip).  A non-null `skip` turns the
-// launch into a no-op on the device while *skip is nonzero.
+// launch into a no-op on the device while *skip is nonzero.  `split` is
+// the chunk-sum scratch (moment_split_doubles; null when that is 0);
+// `partial` holds 6 doubles per moment_partials piece.
 int launch_moments(const tgs_dag* d, const double* f, double* U, const double* U_prev,
                    double* partial, double* ratio_out, hipStream_t stream, bool user_order,
-                   const int32_t* skip = nullptr);
+                   double* split, const int32_t* skip = nullptr);
 int launch_maxwellian(const tgs_dag* d, int mode, const double* U, const tgs_nu_model* nm,
                       double* coef, double* nu, double* M_dense, int32_t* status,
                       unsigned long long* numax, uint8_t* sticky, hipStream_t stream,

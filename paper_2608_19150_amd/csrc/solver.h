@@ -37,6 +37,7 @@ struct bgk_solver {
   double* bcd = nullptr;         // dense boundary data [n_bfaces][n_fp][n_v]
   double* nu = nullptr;
   double* partial = nullptr;
+  double* msplit = nullptr;      // chunk sums of the velocity-split moment pass (or null)
   double* ratio = nullptr;       // [4]
   int32_t* status = nullptr;     // [2]
   unsigned long long* numax = nullptr;

@@ -320,7 +320,9 @@ extern "C" int bgk_solver_create(const tgs_dag* d, const bgk_solver_opts* o, bgk
     if (!rc && o->maxw_mode == BGK_MAXW_PROJECTED) rc = dmalloc(&s->pr, proj_scratch_size(d));
     if (!rc) rc = dmalloc(&s->bcd, std::max<size_t>(1, (size_t)d->n_bfaces * d->n_fp * d->n_v));
     if (!rc) rc = dmalloc(&s->nu, (size_t)d->n_nodes);
-    if (!rc) rc = dmalloc(&s->partial, (size_t)moment_blocks(d) * 6);
+    if (!rc) rc = dmalloc(&s->partial, (size_t)moment_partials(d) * 6);
+    if (!rc && moment_split_doubles(d) > 0)
+      rc = dmalloc(&s->msplit, (size_t)moment_split_doubles(d));
     if (!rc) rc = dmalloc(&s->ratio, 4);
     if (!rc) rc = dmalloc(&s->status, 2);
     if (!rc) rc = dmalloc(&s->numax, 1);
@@ -349,7 +351,7 @@ extern "C" int bgk_solver_destroy(bgk_solver* s) {
     void* ptrs[] = {s->fk,    s->fst[0], s->fst[1], s->fst[2], s->fst[3], s->fping,
                     s->q,     s->d32,    s->U[0],   s->U[1],   s->mcoef,  s->mtab,
                     s->nu,    s->partial, s->ratio, s->status, s->numax, s->sticky, s->pr,
-                    s->bcd,   s->ctl};
+                    s->bcd,   s->ctl,    s->msplit};
     for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
     if (s->cap) (void)hipStreamDestroy(s->cap);
     for (void* p : ptrs)
@@ -398,11 +400,12 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
     if (U_guess) {
       if ((rc = launch_nodal_perm(d, U_guess, s->U[0], 1, stream))) return rc;
     } else {
-      if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false)))
+      if ((rc = launch_moments(d, fk, s->U[0], nullptr, nullptr, nullptr, stream, false,
+                               s->msplit)))
         return rc;
     }
     const int K = o.chunk_iters > 1 ? o.chunk_iters : 1;
-    const int nblk = moment_blocks(d);  // block pieces of the norms per moment pass
+    const int nblk = moment_partials(d);  // pieces of the norms per moment pass
     // the buffer a Picard iteration writes, given the one it reads: with
     // lagged facets or the FP32 form the previous iterate must survive the
     // sweep, so iterates alternate between the stage's output and fping
@@ -458,7 +461,7 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
         if ((r = launch_sweep(d, &io, s->mtab, s->d32, sm, 0, skip))) return r;
         if (o.timing) BGK_HIP(hipEventRecord(s->ev[2], sm));
         if ((r = launch_moments(d, cur, s->U[uc ^ 1], s->U[uc], s->partial,
-                                skip ? nullptr : s->ratio, sm, false, skip)))
+                                skip ? nullptr : s->ratio, sm, false, s->msplit, skip)))
           return r;
         if (o.timing) BGK_HIP(hipEventRecord(s->ev[3], sm));
         return BGK_OK;
@@ -614,7 +617,8 @@ extern "C" int bgk_step(bgk_solver* s, double* f, const double* U_guess, double*
       const double* xs[5] = {fk, fst[0], fst[1], fst[2], fst[3]};
       if ((rc = combine(f, xs, s->ncoef, s->S + 1, nf, stream))) return rc;
       if (U_out &&
-          (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false)))
+          (rc = launch_moments(d, f, s->U[ucur], nullptr, nullptr, nullptr, stream, false,
+                               s->msplit)))
         return rc;
     }
     if (U_out && (rc = launch_nodal_perm(d, s->U[ucur], U_out, 0, stream))) return rc;

@@ -1,8 +1,9 @@
 """The allocation-free moments entry point (moments_noalloc) against the
 allocating one (moments), through the C ABI: the same kernels, so U and the
-three convergence ratios must be equal bit for bit.  Two calls in a row, the
-second on a smaller mesh (the fixed scratch keeps the first call's contents
-and must not leak into the second), plus a call without U_prev."""
+three convergence ratios must be equal bit for bit.  Calls in a row, each on
+a mesh needing less scratch than the one before (the fixed scratch keeps the
+previous call's contents and must not leak into the next), the first with
+the velocity-split reduction, plus a call without U_prev."""
 import numpy as np
 import pytest
 
@@ -27,9 +28,12 @@ def _case(pr, seed):
 
 
 def test_moments_noalloc_equals_moments_on_consecutive_calls():
+    # 8281 velocities on 4232 triangles: the velocity-split reduction, whose
+    # chunk sums also live in the fixed scratch
+    split = P.small_problem(dim=2, order=1, n_side=46, n_1d=91, seed=10)
     big = P.small_problem(dim=3, order=1, n_side=4, n_1d=8, seed=11)      # more moment blocks
     small = P.small_problem(dim=2, order=2, n_side=3, n_1d=6, seed=12)    # fewer
-    for pr, seed in ((big, 1), (small, 2)):
+    for pr, seed in ((split, 3), (big, 1), (small, 2)):
         d, fs, U_old = _case(pr, seed)
         U_ref, r_ref = B.moments(d, fs, U_prev=U_old)
         U = torch.full_like(U_ref, float("nan"))
