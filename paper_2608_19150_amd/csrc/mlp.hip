@@ -304,20 +304,31 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpArgs m, const float* __restr
   }
 }
 
-// grad[p] = sum over wavefront accumulators (slot order), loss likewise
-__global__ void k_mlp_reduce(const float* __restrict__ partial, const float* __restrict__ ploss,
-                             int64_t nslots, float* __restrict__ grad, float* __restrict__ loss) {
+// grad[p] = sum over wavefront accumulators (slot order), loss likewise.
+// The loads of 16 slots are issued before they are added (in slot order),
+// so each thread keeps 16 loads in flight; 64-thread blocks spread the
+// parameters over more compute units.
+__global__ __launch_bounds__(64) void k_mlp_reduce(const float* __restrict__ partial,
+                                                   const float* __restrict__ ploss,
+                                                   int64_t nslots, float* __restrict__ grad,
+                                                   float* __restrict__ loss) {
+  constexpr int U = 16;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < NPAD) {
+  const auto ordered_sum = [&](const float* __restrict__ base, size_t stride) {
     float s = 0.0f;
-    for (int64_t t = 0; t < nslots; ++t) s += partial[(size_t)t * NPAD + p];
-    grad[p] = s;
-  }
-  if (p == NPAD && loss) {
-    float s = 0.0f;
-    for (int64_t t = 0; t < nslots; ++t) s += ploss[t];
-    *loss = s;
-  }
+    int64_t t = 0;
+    for (; t + U <= nslots; t += U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = base[(size_t)(t + u) * stride];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; t < nslots; ++t) s += base[(size_t)t * stride];
+    return s;
+  };
+  if (p < NPAD) grad[p] = ordered_sum(partial + p, NPAD);
+  if (p == NPAD && loss) *loss = ordered_sum(ploss, 1);
 }
 
 __global__ void k_mlp_adam(float* __restrict__ w, float* __restrict__ mo, float* __restrict__ ve,
@@ -669,7 +680,7 @@ int mlp_grad(bgk_mlp* m, const float* X, const float* T, int64_t n, float* loss,
   hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(64), 0, s, margs(m), X, T, n,
                      m->partial, m->ploss);
   BGK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPAD + 1 + 255) / 256), dim3(256), 0, s, m->partial,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPAD + 1 + 63) / 64), dim3(64), 0, s, m->partial,
                      m->ploss, nslots, m->grad, loss);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
