@@ -251,13 +251,13 @@ int moments(const tgs_dag* dag, const double* f, double* U, const double* U_prev
  * allocating call.  The scratch (the chunk sums of a velocity-split moment
  * pass, at most 2^21 doubles, used on meshes of 4096 to 16,383 cells with
  * 8192 velocities or more; with U_prev, 6 doubles per moment block, 64
- * cells per block on meshes of 16,384 cells or more and in split passes,
- * at most 1024 blocks otherwise) lives in a fixed 32 MiB device array per
- * GPU, held until the process ends and shared by every call on that GPU:
- * calls that overlap on one GPU race on it and must be ordered by the
- * caller (one stream, or events).  Nothing in it needs clearing between calls.  BGK_E_INVALID when
- * the mesh needs more scratch than that (with U_prev, about 44 million
- * cells). */
+ * cells per block on meshes of 16,384 cells or more and in split passes
+ * (256 on such tetrahedral meshes), at most 1024 blocks otherwise) lives
+ * in a fixed 32 MiB device array per GPU, held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU race on
+ * it and must be ordered by the caller (one stream, or events).  Nothing
+ * in it needs clearing between calls.  BGK_E_INVALID when the mesh needs
+ * more scratch than that (with U_prev, about 44 million cells). */
 int moments_noalloc(const tgs_dag* dag, const double* f, double* U, const double* U_prev,
                     double* rel3, bgk_stream_t stream);
 

@@ -287,9 +287,10 @@ def test_sweep_with_lagged_facets_matches_oracle(dim, order):
 
 # then: a few cells with thousands of velocities (64 velocity lanes per cell
 # in the moment kernel); 4232 cells with 8281 velocities (the velocity-split
-# reduction: chunk sums, then their ordered sum)
+# reduction: chunk sums, then their ordered sum); 22,999 tetrahedra (the
+# 256-cell blocks of large tetrahedral meshes)
 @pytest.mark.parametrize("dim,order,n_side,n1", CASES + [(2, 2, 3, 48), (3, 1, 2, 14),
-                                                         (2, 1, 46, 91)])
+                                                         (2, 1, 46, 91), (3, 1, 15, 4)])
 def test_moments_and_ratios_match_oracle(dim, order, n_side, n1):
     pr = _problem(dim, order, n_side, n1)
     d = B.Dag.from_problem(pr)

@@ -31,9 +31,11 @@ def test_moments_noalloc_equals_moments_on_consecutive_calls():
     # 8281 velocities on 4232 triangles: the velocity-split reduction, whose
     # chunk sums also live in the fixed scratch
     split = P.small_problem(dim=2, order=1, n_side=46, n_1d=91, seed=10)
+    # 22,999 tetrahedra: 256-cell moment blocks
+    wide = P.small_problem(dim=3, order=1, n_side=15, n_1d=4, seed=13)
     big = P.small_problem(dim=3, order=1, n_side=4, n_1d=8, seed=11)      # more moment blocks
     small = P.small_problem(dim=2, order=2, n_side=3, n_1d=6, seed=12)    # fewer
-    for pr, seed in ((split, 3), (big, 1), (small, 2)):
+    for pr, seed in ((split, 3), (wide, 4), (big, 1), (small, 2)):
         d, fs, U_old = _case(pr, seed)
         U_ref, r_ref = B.moments(d, fs, U_prev=U_old)
         U = torch.full_like(U_ref, float("nan"))
