@@ -427,7 +427,9 @@ int bgk_step(bgk_solver* solver, double* f, const double* U_guess, double* U_out
  * arithmetic is bgk_step's, so results equal single-instance steps bit for
  * bit, except for an instance of 4096 to 16,383 cells with 8192 velocities
  * or more: bgk_step splits its moment sums over velocity chunks, the batch
- * does not, and the two agree to rounding.  Requirements: all solvers share the dimension and the tableau, use
+ * does not, and the two agree to rounding.  (On tetrahedral instances of
+ * 16,384 cells or more bgk_step sums the convergence norms over wider
+ * blocks: equal moments, ratios equal to rounding.)  Requirements: all solvers share the dimension and the tableau, use
  * the FP64 sweep and have acyclic sweep graphs (else BGK_E_UNSUPPORTED).
  * The batch borrows the solvers (and their DAGs): destroy it first. */
 typedef struct bgk_batch bgk_batch;
